@@ -1,0 +1,309 @@
+/*
+ * kde_oracle.c -- plain, slow, FP64 CPU reference for the KDE heat map of
+ * Huang, Li, Zhang and Liu, "GPU-Accelerated Compression and Visualization of
+ * Large-Scale Vessel Trajectories in Maritime IoT Industries" (arXiv 2004.13653).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or call
+ * this file; only tests/, the smoke check and the CPU-baseline leg of the bench
+ * do.  It shares no code, header, table or constant with the HIP library.
+ *
+ * What it computes (Sec. III-C, Eq. (7)-(8), Table I), in the reading that the
+ * kernel argument is s = (grid node - point) / h with support |s| <= 1:
+ *
+ *   S[j][i] = sum_p k((gx_i - x_p)/hx) * k((gy_j - y_p)/hy)      (Table I: every
+ *             kernel is a product f(s,t) = k(s) k(t))
+ *   f[j][i] = S[j][i] / (n * hx * hy)                             (density)
+ *
+ * Grid nodes: gx_i = xmin + i*dx, dx = (xmax - xmin)/(nx - 1), i = 0..nx-1, the
+ * node spacing of Eq. (5)-(6) with both box edges on nodes.  Output is row-major
+ * out[j*nx + i], x fastest, the index order of Algorithm 3's density matrix.
+ *
+ * Every per-output sum runs over points (or pairs) in index order, one term at a
+ * time, in double precision; threads split outputs, never a sum, so the result
+ * does not depend on the thread count.
+ *
+ * "Grid-unit" entry points take the FP32 pixel coordinates X_p = fl32((x_p -
+ * xmin)/dx) and FP32 bandwidths Hx = fl32(hx/dx) that a GPU is fed, and evaluate
+ * everything else in FP64 with node i at X = i: this is the parity mode.  The
+ * support test there is |i - X_p| <= Hx on the exact difference.
+ *
+ * Differentiation (not in the paper): the vector-Jacobian product of the map and
+ * the least-squares cross-validation (LSCV) bandwidth objective of Rudemo (1982)
+ * and Bowman (1984), both written from their definitions below.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+
+#define KO_UNIFORM 0
+#define KO_TRIANGULAR 1
+#define KO_EPANECHNIKOV 2
+#define KO_QUARTIC 3
+#define KO_TRIWEIGHT 4
+#define KO_TRICUBE 5
+#define KO_GAUSSIAN 6
+#define KO_COSINE 7
+
+static const double PI = 3.14159265358979323846;
+
+/* One-dimensional factor k(u) of the Table I product kernels, in Table I order.
+ * The indicator I(u) is 1 for |u| <= 1 (inclusive) and the Gaussian has none. */
+double ko_k(int kernel, double u)
+{
+    double a = fabs(u);
+    if (kernel == KO_GAUSSIAN) return exp(-0.5 * u * u) / sqrt(2.0 * PI);
+    if (a > 1.0) return 0.0;
+    switch (kernel) {
+    case KO_UNIFORM: return 0.5;
+    case KO_TRIANGULAR: return 1.0 - a;
+    case KO_EPANECHNIKOV: return 0.75 * (1.0 - u * u);
+    case KO_QUARTIC: { double w = 1.0 - u * u; return (15.0 / 16.0) * w * w; }
+    case KO_TRIWEIGHT: { double w = 1.0 - u * u; return (35.0 / 32.0) * w * w * w; }
+    case KO_TRICUBE: { double w = 1.0 - a * a * a; return (70.0 / 81.0) * w * w * w; }
+    case KO_COSINE: return (PI / 4.0) * cos(0.5 * PI * u);
+    default: return NAN;
+    }
+}
+
+/* dk/du, taken from the formula inside the support (|u| <= 1), 0 outside; at the
+ * kink u = 0 of the triangular kernel the two one-sided slopes average to 0. */
+double ko_dk(int kernel, double u)
+{
+    double a = fabs(u);
+    if (kernel == KO_GAUSSIAN) return -u * exp(-0.5 * u * u) / sqrt(2.0 * PI);
+    if (a > 1.0) return 0.0;
+    switch (kernel) {
+    case KO_UNIFORM: return 0.0;
+    case KO_TRIANGULAR: return u > 0.0 ? -1.0 : (u < 0.0 ? 1.0 : 0.0);
+    case KO_EPANECHNIKOV: return -1.5 * u;
+    case KO_QUARTIC: return (15.0 / 16.0) * 2.0 * (1.0 - u * u) * (-2.0 * u);
+    case KO_TRIWEIGHT: { double w = 1.0 - u * u; return (35.0 / 32.0) * 3.0 * w * w * (-2.0 * u); }
+    case KO_TRICUBE: { double w = 1.0 - a * a * a; return (70.0 / 81.0) * 3.0 * w * w * (-3.0 * u * a); }
+    case KO_COSINE: return -(PI / 4.0) * (0.5 * PI) * sin(0.5 * PI * u);
+    default: return NAN;
+    }
+}
+
+/* Autoconvolution kbar = k * k (the integral of k(v) k(u - v) dv) and its
+ * derivative, for the kernels whose LSCV the oracle supports: Gaussian
+ * (kbar is the N(0, 2) density) and Epanechnikov (piecewise polynomial on
+ * |u| <= 2).  Returns NAN for other kernels. */
+double ko_kbar(int kernel, double u)
+{
+    double a = fabs(u);
+    if (kernel == KO_GAUSSIAN) return exp(-0.25 * u * u) / (2.0 * sqrt(PI));
+    if (kernel == KO_EPANECHNIKOV) {
+        if (a > 2.0) return 0.0;
+        double b = 2.0 - a;
+        return (3.0 / 160.0) * b * b * b * (a * a + 6.0 * a + 4.0);
+    }
+    return NAN;
+}
+
+double ko_dkbar(int kernel, double u)
+{
+    double a = fabs(u);
+    if (kernel == KO_GAUSSIAN) return -0.5 * u * exp(-0.25 * u * u) / (2.0 * sqrt(PI));
+    if (kernel == KO_EPANECHNIKOV) {
+        if (a > 2.0) return 0.0;
+        double b = 2.0 - a;
+        return -(3.0 / 32.0) * u * (a + 4.0) * b * b;
+    }
+    return NAN;
+}
+
+void ko_k_array(int kernel, const double *u, int64_t n, double *out)
+{
+    for (int64_t q = 0; q < n; ++q) out[q] = ko_k(kernel, u[q]);
+}
+
+void ko_dk_array(int kernel, const double *u, int64_t n, double *out)
+{
+    for (int64_t q = 0; q < n; ++q) out[q] = ko_dk(kernel, u[q]);
+}
+
+void ko_kbar_array(int kernel, const double *u, int64_t n, double *out)
+{
+    for (int64_t q = 0; q < n; ++q) out[q] = ko_kbar(kernel, u[q]);
+}
+
+void ko_dkbar_array(int kernel, const double *u, int64_t n, double *out)
+{
+    for (int64_t q = 0; q < n; ++q) out[q] = ko_dkbar(kernel, u[q]);
+}
+
+/* World mode: points xy[n][2] (x, y) in world units, grid box and size as above.
+ * Writes the window rows j0..j1-1, columns i0..i1-1 into out[(j-j0)*(i1-i0) +
+ * (i-i0)].  raw != 0 gives S; otherwise the density S/(n hx hy). */
+void ko_map_world(const double *xy, int64_t n, int kernel, double hx, double hy,
+                  double xmin, double xmax, double ymin, double ymax, int nx, int ny,
+                  int i0, int i1, int j0, int j1, int raw, double *out)
+{
+    double dx = (xmax - xmin) / (double)(nx - 1);
+    double dy = (ymax - ymin) / (double)(ny - 1);
+    int w = i1 - i0, h = j1 - j0;
+    double scale = raw ? 1.0 : 1.0 / ((double)n * hx * hy);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int r = 0; r < h * w; ++r) {
+        int j = j0 + r / w, i = i0 + r % w;
+        double gx = xmin + i * dx, gy = ymin + j * dy;
+        double s = 0.0;
+        for (int64_t p = 0; p < n; ++p)
+            s += ko_k(kernel, (gx - xy[2 * p]) / hx) * ko_k(kernel, (gy - xy[2 * p + 1]) / hy);
+        out[r] = s * scale;
+    }
+}
+
+/* One factor in grid units: node index i against FP32 coordinate X with FP32
+ * bandwidth H.  For compact kernels the support test is |i - X| <= H on the
+ * exact difference, then k((i - X)/H). */
+static double unit_factor(int kernel, int i, float X, float H)
+{
+    double d = (double)i - (double)X;
+    if (kernel != KO_GAUSSIAN && fabs(d) > (double)H) return 0.0;
+    return ko_k(kernel, d / (double)H); /* |d| <= H implies |d/H| <= 1 */
+}
+
+static double unit_dfactor(int kernel, int i, float X, float H)
+{
+    double d = (double)i - (double)X;
+    if (kernel != KO_GAUSSIAN && fabs(d) > (double)H) return 0.0;
+    return ko_dk(kernel, d / (double)H);
+}
+
+/* Parity mode: XY[n][2] FP32 pixel coordinates, Hx, Hy FP32 pixel bandwidths.
+ * Raw sum S over the window (density scaling is a separate FP64 factor). */
+void ko_map_units(const float *XY, int64_t n, int kernel, float Hx, float Hy,
+                  int i0, int i1, int j0, int j1, double *out)
+{
+    int w = i1 - i0, h = j1 - j0;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int r = 0; r < h * w; ++r) {
+        int j = j0 + r / w, i = i0 + r % w;
+        double s = 0.0;
+        for (int64_t p = 0; p < n; ++p)
+            s += unit_factor(kernel, i, XY[2 * p], Hx) * unit_factor(kernel, j, XY[2 * p + 1], Hy);
+        out[r] = s;
+    }
+}
+
+/* Parity mode at a list of pixels ij[m][2] = (i, j): raw sums. */
+void ko_map_units_at(const float *XY, int64_t n, int kernel, float Hx, float Hy,
+                     const int32_t *ij, int64_t m, double *out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < m; ++r) {
+        int i = ij[2 * r], j = ij[2 * r + 1];
+        double s = 0.0;
+        for (int64_t p = 0; p < n; ++p)
+            s += unit_factor(kernel, i, XY[2 * p], Hx) * unit_factor(kernel, j, XY[2 * p + 1], Hy);
+        out[r] = s;
+    }
+}
+
+/* Vector-Jacobian product of the raw map in grid units.  Given gbar[ny][nx]
+ * (dL/dS), for each selected point p = sel[r] (r = 0..m-1):
+ *   g[r][0]  = dL/dX_p = sum_{j,i} gbar[j][i] * k'((i-X_p)/Hx) * (-1/Hx) * k((j-Y_p)/Hy)
+ *   g[r][1]  = dL/dY_p   (the same with the roles of x and y swapped)
+ *   gh[r][0] = sum_{j,i} gbar[j][i] * k'(s) * (-s/Hx) * k(t),  s = (i-X_p)/Hx, t = (j-Y_p)/Hy
+ *   gh[r][1] = sum_{j,i} gbar[j][i] * k(s) * k'(t) * (-t/Hy)
+ * gh is point p's share of dL/dHx and dL/dHy; summed over all points it is the
+ * bandwidth gradient.  Each sum runs over pixels j-major, i fastest. */
+void ko_vjp_units(const float *XY, int64_t n, int kernel, float Hx, float Hy,
+                  int nx, int ny, const double *gbar, const int64_t *sel, int64_t m,
+                  double *g, double *gh)
+{
+    (void)n;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < m; ++r) {
+        int64_t p = sel[r];
+        double X = (double)XY[2 * p], Y = (double)XY[2 * p + 1];
+        double gx = 0.0, gy = 0.0, hx = 0.0, hy = 0.0;
+        for (int j = 0; j < ny; ++j) {
+            double ky = unit_factor(kernel, j, XY[2 * p + 1], Hy);
+            double dky = unit_dfactor(kernel, j, XY[2 * p + 1], Hy);
+            double t = ((double)j - Y) / (double)Hy;
+            for (int i = 0; i < nx; ++i) {
+                double gb = gbar[(int64_t)j * nx + i];
+                double kx = unit_factor(kernel, i, XY[2 * p], Hx);
+                double dkx = unit_dfactor(kernel, i, XY[2 * p], Hx);
+                double s = ((double)i - X) / (double)Hx;
+                gx += gb * dkx * (-1.0 / (double)Hx) * ky;
+                gy += gb * kx * dky * (-1.0 / (double)Hy);
+                hx += gb * dkx * (-s / (double)Hx) * ky;
+                hy += gb * kx * dky * (-t / (double)Hy);
+            }
+        }
+        g[2 * r] = gx;
+        g[2 * r + 1] = gy;
+        gh[2 * r] = hx;
+        gh[2 * r + 1] = hy;
+    }
+}
+
+/* LSCV objective in world units for points xy[n][2] (n >= 2):
+ *   LSCV(hx, hy) = A - B
+ *   A = 1/(n^2 hx hy)        * sum_{p,q}     kbar(dx_pq/hx) kbar(dy_pq/hy)   (= integral of f^2)
+ *   B = 2/(n (n-1) hx hy)    * sum_{p != q}  k(dx_pq/hx)    k(dy_pq/hy)      (leave-one-out term)
+ * with dx_pq = x_p - x_q.  grad[2] = (dLSCV/dhx, dLSCV/dhy) uses
+ *   d/dh [g(a/h)/h] = -(g(u) + u g'(u)) / h^2,  u = a/h.
+ * The pair sums run q fastest inside p, p in order.  Supported kernels:
+ * Gaussian and Epanechnikov; returns NAN otherwise. */
+void ko_lscv_world(const double *xy, int64_t n, int kernel, double hx, double hy,
+                   double *value, double *grad)
+{
+    double *pa = (double *)malloc(sizeof(double) * 6 * (size_t)(n > 0 ? n : 1));
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t p = 0; p < n; ++p) {
+        double sa = 0.0, sb = 0.0, sax = 0.0, say = 0.0, sbx = 0.0, sby = 0.0;
+        for (int64_t q = 0; q < n; ++q) {
+            double u = (xy[2 * p] - xy[2 * q]) / hx;
+            double v = (xy[2 * p + 1] - xy[2 * q + 1]) / hy;
+            double ku = ko_kbar(kernel, u), kv = ko_kbar(kernel, v);
+            sa += ku * kv;
+            sax += (ku + u * ko_dkbar(kernel, u)) * kv;
+            say += ku * (kv + v * ko_dkbar(kernel, v));
+            if (q != p) {
+                double lu = ko_k(kernel, u), lv = ko_k(kernel, v);
+                sb += lu * lv;
+                sbx += (lu + u * ko_dk(kernel, u)) * lv;
+                sby += lu * (lv + v * ko_dk(kernel, v));
+            }
+        }
+        pa[6 * p + 0] = sa;
+        pa[6 * p + 1] = sb;
+        pa[6 * p + 2] = sax;
+        pa[6 * p + 3] = say;
+        pa[6 * p + 4] = sbx;
+        pa[6 * p + 5] = sby;
+    }
+    double SA = 0, SB = 0, SAX = 0, SAY = 0, SBX = 0, SBY = 0;
+    for (int64_t p = 0; p < n; ++p) {
+        SA += pa[6 * p + 0];
+        SB += pa[6 * p + 1];
+        SAX += pa[6 * p + 2];
+        SAY += pa[6 * p + 3];
+        SBX += pa[6 * p + 4];
+        SBY += pa[6 * p + 5];
+    }
+    free(pa);
+    double nn = (double)n;
+    double ca = 1.0 / (nn * nn), cb = 2.0 / (nn * (nn - 1.0));
+    *value = ca * SA / (hx * hy) - cb * SB / (hx * hy);
+    /* A = ca * SA/(hx hy): dA/dhx = ca * sum -(kbar(u) + u kbar'(u)) kbar(v) / (hx^2 hy) */
+    grad[0] = -ca * SAX / (hx * hx * hy) + cb * SBX / (hx * hx * hy);
+    grad[1] = -ca * SAY / (hx * hy * hy) + cb * SBY / (hx * hy * hy);
+}
+
+/* LSCV in grid units (parity mode): FP32 pixel coordinates and bandwidths, FP64
+ * arithmetic.  Same sums as ko_lscv_world with dx_pq = X_p - X_q and h = H; the
+ * value and gradient are returned in grid units (multiply by 1/(dx dy) and
+ * 1/(dx^2 dy), 1/(dx dy^2) for world units). */
+void ko_lscv_units(const float *XY, int64_t n, int kernel, float Hx, float Hy,
+                   double *value, double *grad)
+{
+    double *xy = (double *)malloc(sizeof(double) * 2 * (size_t)(n > 0 ? n : 1));
+    for (int64_t q = 0; q < 2 * n; ++q) xy[q] = (double)XY[q];
+    ko_lscv_world(xy, n, kernel, (double)Hx, (double)Hy, value, grad);
+    free(xy);
+}

@@ -1,0 +1,397 @@
+"""Pins of the FP64 oracle against what the paper and mathematics fix.
+
+Nothing here compares the oracle with itself: every check is a printed value
+(Table I), a closed form (unit mass, moments, roughness, single-point map), an
+independent library routine (scipy.stats densities), a numerical integral, an
+exact symmetry of the definition, or a finite difference of an already pinned
+function.  A dropped term, a wrong sign, exponent or index, or transposed x/y
+in the oracle fails at least one of them.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate, stats
+
+import oracle
+from oracle import GAUSSIAN, Grid
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+K = list(range(8))
+COMPACT = [0, 1, 2, 3, 4, 5, 7]
+
+
+def _golden_table1():
+    rows = {}
+    env = {"__builtins__": {}, "pi": math.pi, "sqrt": math.sqrt, "exp": math.exp, "cos": math.cos}
+    with open(os.path.join(HERE, "golden", "table1_kernel_constants.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            name, f00, fhalf = line.split()
+            rows[name] = (eval(f00.replace("^", "**"), env), eval(fhalf.replace("^", "**"), env))
+    return rows
+
+
+# --------------------------------------------------------------------- 1-D factors
+@pytest.mark.parametrize("kernel", K)
+def test_table1_printed_values(kernel):
+    """f(0,0) and f(1/2,1/2) of Table I equal k(0)^2 and k(1/2)^2."""
+    f00, fhalf = _golden_table1()[oracle.KERNELS[kernel]]
+    k0, kh = oracle.k(kernel, [0.0, 0.5])
+    assert k0 * k0 == pytest.approx(f00, rel=1e-15)
+    assert kh * kh == pytest.approx(fhalf, rel=1e-14)
+
+
+# Closed forms: second moment mu2 = int u^2 k and roughness R = int k^2 of the
+# textbook kernels with support [-1, 1] (Gaussian: whole line).
+MU2 = [1 / 3, 1 / 6, 1 / 5, 1 / 7, 1 / 9, 35 / 243, 1.0, 1 - 8 / math.pi ** 2]
+ROUGH = [1 / 2, 2 / 3, 3 / 5, 5 / 7, 350 / 429, 175 / 247, 1 / (2 * math.sqrt(math.pi)), math.pi ** 2 / 16]
+
+
+def _quad(fn, kernel):
+    lim = (-40.0, 40.0) if kernel == GAUSSIAN else (-1.0, 1.0)
+    pts = None if kernel == GAUSSIAN else [0.0]
+    v, _ = integrate.quad(fn, *lim, points=pts, epsabs=1e-14, epsrel=1e-13, limit=400)
+    return v
+
+
+@pytest.mark.parametrize("kernel", K)
+def test_unit_mass(kernel):
+    assert _quad(lambda u: oracle.k(kernel, [u])[0], kernel) == pytest.approx(1.0, abs=1e-12)
+
+
+@pytest.mark.parametrize("kernel", K)
+def test_first_and_second_moment(kernel):
+    assert abs(_quad(lambda u: u * oracle.k(kernel, [u])[0], kernel)) < 1e-13
+    assert _quad(lambda u: u * u * oracle.k(kernel, [u])[0], kernel) == pytest.approx(MU2[kernel], rel=1e-11)
+
+
+@pytest.mark.parametrize("kernel", K)
+def test_roughness(kernel):
+    assert _quad(lambda u: oracle.k(kernel, [u])[0] ** 2, kernel) == pytest.approx(ROUGH[kernel], rel=1e-11)
+
+
+@pytest.mark.parametrize("kernel", COMPACT)
+def test_support_edge(kernel):
+    """Indicator of Eq. (8) read as |u| <= 1 inclusive: zero just outside, the
+    boundary value at +-1 (1/2 for the uniform kernel, 0 otherwise)."""
+    out = oracle.k(kernel, [-1.0 - 1e-12, 1.0 + 1e-12, 3.0, -7.5])
+    assert np.all(out == 0.0)
+    edge = oracle.k(kernel, [-1.0, 1.0])
+    want = 0.5 if kernel == 0 else 0.0
+    assert np.allclose(edge, want, atol=1e-15)
+
+
+def test_library_densities():
+    """Six of the eight factors are textbook densities in scipy.stats: uniform,
+    symmetric triangular, Beta(a, a) on [-1, 1] for a = 2, 3, 4 (Epanechnikov,
+    quartic, triweight) and the standard normal."""
+    u = np.linspace(-1.3, 1.3, 1041)
+    lib = {
+        0: stats.uniform(loc=-1, scale=2).pdf(u),
+        1: stats.triang(c=0.5, loc=-1, scale=2).pdf(u),
+        2: stats.beta(2, 2, loc=-1, scale=2).pdf(u),
+        3: stats.beta(3, 3, loc=-1, scale=2).pdf(u),
+        4: stats.beta(4, 4, loc=-1, scale=2).pdf(u),
+        6: stats.norm.pdf(u),
+    }
+    inside = np.abs(np.abs(u) - 1.0) > 1e-9  # the libraries differ on the closed/open end
+    for kernel, ref in lib.items():
+        np.testing.assert_allclose(oracle.k(kernel, u)[inside], ref[inside], rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("kernel", K)
+def test_derivative_matches_difference(kernel):
+    u = np.array([-0.93, -0.51, -0.2, 0.13, 0.47, 0.88, 1.7, -2.4])
+    eps = 1e-6
+    fd = (oracle.k(kernel, u + eps) - oracle.k(kernel, u - eps)) / (2 * eps)
+    np.testing.assert_allclose(oracle.dk(kernel, u), fd, rtol=1e-7, atol=1e-8)
+
+
+@pytest.mark.parametrize("kernel", [2, GAUSSIAN])
+def test_autoconvolution(kernel):
+    """kbar(u) = int k(v) k(u - v) dv by quadrature of the pinned factor; kbar(0)
+    is the roughness; derivative against a central difference."""
+    for u in (0.0, 0.3, 0.9, 1.5, 1.99, 2.5):
+        conv = _quad(lambda v: oracle.k(kernel, [v])[0] * oracle.k(kernel, [u - v])[0], kernel) \
+            if kernel == GAUSSIAN else integrate.quad(
+                lambda v: oracle.k(kernel, [v])[0] * oracle.k(kernel, [u - v])[0], -1, 1,
+                points=[u - 1, u + 1] if abs(u) < 2 else None, epsabs=1e-14, epsrel=1e-12, limit=200)[0]
+        assert oracle.kbar(kernel, [u])[0] == pytest.approx(conv, rel=1e-10, abs=1e-14)
+    assert oracle.kbar(kernel, [0.0])[0] == pytest.approx(ROUGH[kernel], rel=1e-14)
+    u = np.array([-1.7, -0.4, 0.25, 1.1, 1.9])
+    fd = (oracle.kbar(kernel, u + 1e-6) - oracle.kbar(kernel, u - 1e-6)) / 2e-6
+    np.testing.assert_allclose(oracle.dkbar(kernel, u), fd, rtol=1e-7, atol=1e-9)
+
+
+# --------------------------------------------------------------------- maps
+G_ASYM = Grid(10.0, 11.0, 20.0, 20.6, 21, 13)  # dx = 0.05, dy = 0.05
+
+
+@pytest.mark.parametrize("kernel", K)
+def test_single_point_at_node(kernel):
+    """n = 1 at node (i, j) = (7, 4): the density is the outer product
+    k((gy - y)/hy) k((gx - x)/hx) / (hx hy), peak k(0)^2/(hx hy) at row 4, col 7."""
+    g = G_ASYM
+    gx, gy = g.nodes()
+    xy = np.array([[gx[7], gy[4]]])
+    hx, hy = 0.17, 0.11
+    m = oracle.map_world(xy, kernel, hx, hy, g)
+    assert m.shape == (g.ny, g.nx)
+    k0 = _golden_table1()[oracle.KERNELS[kernel]][0]
+    assert m[4, 7] == pytest.approx(k0 / (hx * hy), rel=1e-13)
+    assert m[4, 7] == m.max()
+    if kernel != 0:  # the uniform kernel is flat on its support
+        assert np.unravel_index(np.argmax(m), m.shape) == (4, 7)
+    # row 4 is k((gx - x)/hx) k(0) / (hx hy): half-widths differ, so a transpose fails
+    assert np.count_nonzero(m[4] > 1e-300) != np.count_nonzero(m[:, 7] > 1e-300) or kernel == GAUSSIAN
+
+
+def _unit_mass_tol(kernel):
+    return {0: 3e-2, 1: 2e-3, 7: 2e-3, 2: 2e-3}.get(kernel, 1e-4)
+
+
+@pytest.mark.parametrize("kernel", K)
+def test_map_unit_integral_and_moments(kernel):
+    """The density integrates to 1 over the plane; its mean is the point mean
+    and its per-axis variance the sample variance plus mu2 h^2 (Riemann sums on a
+    fine grid whose box holds the whole support)."""
+    rng = np.random.default_rng(7)
+    g = Grid(0.0, 4.0, -1.0, 2.0, 401, 301)  # spacing 0.01
+    xy = np.column_stack([rng.uniform(1.2, 2.8, 9), rng.uniform(0.0, 1.0, 9)])
+    hx, hy = (0.15, 0.12) if kernel == GAUSSIAN else (0.31, 0.23)
+    m = oracle.map_world(xy, kernel, hx, hy, g)
+    gx, gy = g.nodes()
+    w = g.dx * g.dy
+    mass = m.sum() * w
+    assert mass == pytest.approx(1.0, abs=_unit_mass_tol(kernel))
+    mx = (m.sum(0) * gx).sum() * w / mass
+    my = (m.sum(1) * gy).sum() * w / mass
+    mtol = 3e-3 if kernel == 0 else 2e-4  # the uniform kernel's jumps: Riemann error O(spacing)
+    assert mx == pytest.approx(xy[:, 0].mean(), abs=mtol)
+    assert my == pytest.approx(xy[:, 1].mean(), abs=mtol)
+    vx = (m.sum(0) * (gx - mx) ** 2).sum() * w / mass
+    vy = (m.sum(1) * (gy - my) ** 2).sum() * w / mass
+    tol = 2e-2 if kernel == 0 else 3e-3
+    assert vx == pytest.approx(xy[:, 0].var() + MU2[kernel] * hx * hx, rel=tol)
+    assert vy == pytest.approx(xy[:, 1].var() + MU2[kernel] * hy * hy, rel=tol)
+
+
+def _pts(seed, n, g):
+    rng = np.random.default_rng(seed)
+    return np.column_stack([rng.uniform(g.xmin, g.xmax, n), rng.uniform(g.ymin, g.ymax, n)])
+
+
+@pytest.mark.parametrize("kernel", K)
+def test_reflection_transpose_translation_permutation(kernel):
+    g = Grid(0.0, 3.0, 0.0, 2.0, 31, 21)  # spacing 0.1
+    xy = _pts(3, 17, g)
+    hx, hy = 0.37, 0.23
+    m = oracle.map_world(xy, kernel, hx, hy, g)
+    # reflection x -> xmin + xmax - x flips the columns
+    r = xy.copy()
+    r[:, 0] = g.xmin + g.xmax - r[:, 0]
+    np.testing.assert_allclose(oracle.map_world(r, kernel, hx, hy, g)[:, ::-1], m, rtol=1e-9, atol=1e-12)
+    # swapping the axes transposes the map
+    gt = Grid(g.ymin, g.ymax, g.xmin, g.xmax, g.ny, g.nx)
+    mt = oracle.map_world(xy[:, ::-1], kernel, hy, hx, gt)
+    np.testing.assert_allclose(mt.T, m, rtol=1e-12, atol=1e-14)
+    # shifting every point by 3 columns and 2 rows shifts the map
+    s = xy + np.array([3 * g.dx, 2 * g.dy])
+    ms = oracle.map_world(s, kernel, hx, hy, g)
+    np.testing.assert_allclose(ms[2:, 3:], m[:-2, :-3], rtol=1e-9, atol=1e-12)
+    # permutation invariance
+    perm = np.random.default_rng(1).permutation(xy.shape[0])
+    np.testing.assert_allclose(oracle.map_world(xy[perm], kernel, hx, hy, g), m, rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("kernel", K)
+def test_raw_sum_linearity_and_scaling(kernel):
+    g = Grid(0.0, 3.0, 0.0, 2.0, 31, 21)
+    a, b = _pts(4, 11, g), _pts(5, 6, g)
+    hx, hy = 0.4, 0.3
+    ma = oracle.map_world(a, kernel, hx, hy, g, raw=True)
+    mb = oracle.map_world(b, kernel, hx, hy, g, raw=True)
+    mab = oracle.map_world(np.vstack([a, b]), kernel, hx, hy, g, raw=True)
+    np.testing.assert_allclose(mab, ma + mb, rtol=1e-13, atol=1e-15)
+    dens = oracle.map_world(a, kernel, hx, hy, g)
+    np.testing.assert_allclose(dens, ma / (a.shape[0] * hx * hy), rtol=1e-14)
+    # scaling coordinates, grid and h by c scales the density by 1/c^2
+    c = 2.5
+    gc = Grid(g.xmin * c, g.xmax * c, g.ymin * c, g.ymax * c, g.nx, g.ny)
+    np.testing.assert_allclose(oracle.map_world(a * c, kernel, hx * c, hy * c, gc), dens / c ** 2, rtol=1e-9,
+                               atol=1e-12)
+
+
+def test_brute_force_against_library_densities():
+    """Tiny map computed point by point from scipy.stats densities."""
+    g = Grid(-1.0, 1.0, -0.5, 0.7, 7, 6)
+    xy = _pts(11, 5, g)
+    hx, hy = 0.45, 0.35
+    gx, gy = g.nodes()
+    dists = {
+        0: lambda: stats.uniform(loc=-1, scale=2), 1: lambda: stats.triang(c=0.5, loc=-1, scale=2),
+        2: lambda: stats.beta(2, 2, loc=-1, scale=2), 3: lambda: stats.beta(3, 3, loc=-1, scale=2),
+        4: lambda: stats.beta(4, 4, loc=-1, scale=2), 6: lambda: stats.norm(),
+    }
+    for kernel, dist in dists.items():
+        d = dist()
+        ref = np.zeros((g.ny, g.nx))
+        for (x, y) in xy:
+            ref += np.outer(d.pdf((gy - y) / hy) / hy, d.pdf((gx - x) / hx) / hx)
+        ref /= xy.shape[0]
+        np.testing.assert_allclose(oracle.map_world(xy, kernel, hx, hy, g), ref, rtol=1e-12, atol=1e-13)
+
+
+@pytest.mark.parametrize("kernel", K)
+def test_units_mode_equals_world_mode(kernel):
+    """With a grid of spacing 1 from the origin and points on FP32-exact
+    coordinates, grid units and world units coincide."""
+    rng = np.random.default_rng(kernel)
+    XY = (rng.integers(0, 40 * 256, (23, 2)) / 256.0).astype(np.float32)
+    g = Grid(0.0, 39.0, 0.0, 29.0, 40, 30)
+    H = (np.float32(2.75), np.float32(3.5))
+    np.testing.assert_array_equal(oracle.to_units(XY.astype(np.float64), g), XY)
+    w = oracle.map_world(XY.astype(np.float64), kernel, float(H[0]), float(H[1]), g, raw=True)
+    u = oracle.map_units(XY, kernel, H[0], H[1], (0, 40, 0, 30))
+    np.testing.assert_allclose(u, w, rtol=1e-14, atol=1e-15)
+    ij = np.array([[0, 0], [39, 29], [17, 3], [5, 22]])
+    np.testing.assert_allclose(oracle.map_units_at(XY, kernel, H[0], H[1], ij), w[ij[:, 1], ij[:, 0]], rtol=1e-14,
+                               atol=1e-15)
+
+
+def test_units_support_boundary_inclusive():
+    """A point exactly Hx from a node contributes there (|i - X| <= Hx)."""
+    XY = np.array([[5.0, 5.0]], dtype=np.float32)
+    s = oracle.map_units(XY, 0, np.float32(2.0), np.float32(2.0), (0, 11, 0, 11))
+    assert s[5, 3] == 0.25 and s[5, 7] == 0.25 and s[3, 3] == 0.25
+    assert s[5, 2] == 0.0 and s[8, 5] == 0.0
+
+
+@pytest.mark.parametrize("kernel", K)
+def test_separable_form_equals_plain_loops(kernel):
+    rng = np.random.default_rng(100 + kernel)
+    XY = rng.uniform(-3, 35, (300, 2)).astype(np.float32)
+    win = (2, 31, 5, 27)
+    plain = oracle.map_units(XY, kernel, np.float32(2.3), np.float32(3.1), win)
+    sep = oracle.map_units_separable(XY, kernel, np.float32(2.3), np.float32(3.1), win, chunk=77)
+    np.testing.assert_allclose(sep, plain, rtol=1e-13, atol=1e-15 * plain.max())
+
+
+def test_to_units_rounding():
+    """FP64 subtract and divide, then one rounding to FP32 (nearest even)."""
+    g = Grid(122.0, 123.0, 30.0, 31.0, 1024, 1024)
+    xy = np.array([[122.5, 30.25], [122.0, 31.0], [123.0, 30.0]])
+    XY = oracle.to_units(xy, g)
+    assert XY.dtype == np.float32
+    assert XY[0, 0] == np.float32(0.5 * 1023) and XY[0, 1] == np.float32(0.25 * 1023)
+    assert XY[1, 0] == 0.0 and XY[1, 1] == np.float32(1023.0) and XY[2, 0] == np.float32(1023.0)
+
+
+# --------------------------------------------------------------------- adjoint
+def _map_units_f64(XY64, kernel, Hx, Hy, nx, ny):
+    g = Grid(0.0, nx - 1.0, 0.0, ny - 1.0, nx, ny)
+    return oracle.map_world(XY64, kernel, Hx, Hy, g, raw=True)
+
+
+@pytest.mark.parametrize("kernel", [2, 3, 4, GAUSSIAN, 7])
+def test_vjp_against_finite_differences(kernel):
+    """dL/dX_p, dL/dY_p and dL/dHx, dL/dHy of L = <gbar, S> against central
+    differences of the FP64 map (step 1e-6)."""
+    rng = np.random.default_rng(20 + kernel)
+    nx, ny = 24, 19
+    XY = rng.uniform(3, 16, (6, 2)).astype(np.float32)
+    Hx, Hy = np.float32(2.5), np.float32(3.25)
+    gbar = rng.standard_normal((ny, nx))
+    g, gh = oracle.vjp_units(XY, kernel, Hx, Hy, gbar)
+    base = XY.astype(np.float64)
+    eps = 1e-6
+
+    def L(pts, hx=float(Hx), hy=float(Hy)):
+        return float((gbar * _map_units_f64(pts, kernel, hx, hy, nx, ny)).sum())
+
+    for p in range(XY.shape[0]):
+        for c in range(2):
+            a, b = base.copy(), base.copy()
+            a[p, c] += eps
+            b[p, c] -= eps
+            fd = (L(a) - L(b)) / (2 * eps)
+            assert g[p, c] == pytest.approx(fd, rel=2e-5, abs=2e-7)
+    fdx = (L(base, hx=float(Hx) + eps) - L(base, hx=float(Hx) - eps)) / (2 * eps)
+    fdy = (L(base, hy=float(Hy) + eps) - L(base, hy=float(Hy) - eps)) / (2 * eps)
+    assert gh[:, 0].sum() == pytest.approx(fdx, rel=2e-5, abs=2e-7)
+    assert gh[:, 1].sum() == pytest.approx(fdy, rel=2e-5, abs=2e-7)
+
+
+@pytest.mark.parametrize("kernel", [2, GAUSSIAN])
+def test_vjp_separable_equals_plain(kernel):
+    rng = np.random.default_rng(40 + kernel)
+    nx, ny = 33, 27
+    XY = rng.uniform(-2, 34, (90, 2)).astype(np.float32)
+    gbar = rng.standard_normal((ny, nx))
+    g, gh = oracle.vjp_units(XY, kernel, np.float32(2.2), np.float32(1.7), gbar)
+    g2, gh2 = oracle.vjp_units_separable(XY, kernel, np.float32(2.2), np.float32(1.7), gbar, chunk=31)
+    scale = np.abs(g).max()
+    np.testing.assert_allclose(g2, g, rtol=1e-11, atol=1e-13 * scale)
+    np.testing.assert_allclose(gh2, gh, rtol=1e-11, atol=1e-13 * np.abs(gh).max())
+
+
+# --------------------------------------------------------------------- LSCV
+@pytest.mark.parametrize("kernel", [2, GAUSSIAN])
+def test_lscv_against_its_definition(kernel):
+    """LSCV(h) = int f^2 - (2/n) sum_p f_{-p}(x_p): the first term by quadrature
+    of the pinned density on a fine grid, the second from leave-one-out maps
+    evaluated at each point (a grid with a node on the point)."""
+    rng = np.random.default_rng(60 + kernel)
+    n = 7
+    xy = np.column_stack([rng.uniform(0.4, 0.6, n), rng.uniform(0.3, 0.5, n)])
+    hx, hy = 0.05, 0.04
+    g = Grid(0.0, 1.0, 0.0, 0.8, 1001, 801)
+    f = oracle.map_world(xy, kernel, hx, hy, g)
+    int_f2 = (f * f).sum() * g.dx * g.dy
+    loo = 0.0
+    for p in range(n):
+        others = np.delete(xy, p, axis=0)
+        gp = Grid(xy[p, 0], xy[p, 0] + 1.0, xy[p, 1], xy[p, 1] + 1.0, 2, 2)
+        loo += oracle.map_world(others, kernel, hx, hy, gp)[0, 0]
+    ref = int_f2 - 2.0 / n * loo
+    val, _ = oracle.lscv_world(xy, kernel, hx, hy)
+    assert val == pytest.approx(ref, rel=2e-4 if kernel == 2 else 1e-8)
+
+
+@pytest.mark.parametrize("kernel", [2, GAUSSIAN])
+def test_lscv_gradient_against_finite_differences(kernel):
+    rng = np.random.default_rng(80 + kernel)
+    xy = np.column_stack([rng.uniform(0, 1, 40), rng.uniform(0, 1, 40)])
+    hx, hy = 0.09, 0.13
+    _, grad = oracle.lscv_world(xy, kernel, hx, hy)
+    eps = 1e-6
+    fx = (oracle.lscv_world(xy, kernel, hx + eps, hy)[0] - oracle.lscv_world(xy, kernel, hx - eps, hy)[0]) / (2 * eps)
+    fy = (oracle.lscv_world(xy, kernel, hx, hy + eps)[0] - oracle.lscv_world(xy, kernel, hx, hy - eps)[0]) / (2 * eps)
+    assert grad[0] == pytest.approx(fx, rel=1e-6)
+    assert grad[1] == pytest.approx(fy, rel=1e-6)
+
+
+def test_lscv_two_points_gaussian_closed_form():
+    """n = 2 Gaussian: int f^2 is a sum of N(0, 2h^2) densities and the
+    leave-one-out density of each point is the other point's kernel."""
+    xy = np.array([[0.0, 0.0], [0.3, -0.2]])
+    hx, hy = 0.25, 0.5
+    dx, dy = 0.3, -0.2
+    phi2 = lambda d, h: math.exp(-d * d / (4 * h * h)) / math.sqrt(4 * math.pi * h * h)
+    phi1 = lambda d, h: math.exp(-d * d / (2 * h * h)) / math.sqrt(2 * math.pi * h * h)
+    int_f2 = 0.25 * (2 * phi2(0, hx) * phi2(0, hy) + 2 * phi2(dx, hx) * phi2(dy, hy))
+    loo = phi1(dx, hx) * phi1(dy, hy)
+    val, _ = oracle.lscv_world(xy, GAUSSIAN, hx, hy)
+    assert val == pytest.approx(int_f2 - 2 * loo, rel=1e-13)
+
+
+def test_errors_measure():
+    r = np.array([0.0, 1.0, 2.0, 4.0])
+    y = np.array([0.0, 1.0, 2.0, 4.4])
+    e = oracle.errors(y, r)
+    assert e["e_inf"] == pytest.approx(0.1)
+    assert e["e_2"] == pytest.approx(0.4 / math.sqrt(21))
+    assert e["e_rel"] == pytest.approx(0.1)
