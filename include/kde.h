@@ -1,0 +1,171 @@
+/*
+ * kde.h -- C ABI of libkde, an MI355X (gfx950) implementation of the kernel
+ * density estimation (KDE) heat map of Huang, Li, Zhang and Liu, "GPU-Accelerated
+ * Compression and Visualization of Large-Scale Vessel Trajectories in Maritime
+ * IoT Industries" (arXiv 2004.13653), Sec. III-C and IV-B.
+ *
+ * The map.  For points (x_p, y_p), p = 0..n-1, bandwidths hx, hy > 0 and one of
+ * the eight product kernels f(s,t) = k(s) k(t) of Table I, every grid node
+ * (gx_i, gy_j) receives
+ *
+ *     S[j][i] = sum_p k((gx_i - x_p)/hx) * k((gy_j - y_p)/hy)
+ *     out[j*nx + i] = S[j][i] / (n * hx * hy)          (or S with KDE_RAW_SUM)
+ *
+ * This is the convolution of Eq. (7) written as a direct sum over the points
+ * instead of over a binned count matrix.  The indicator I(.) of Eq. (8) is read
+ * as |u| <= 1 (inclusive) on the scaled argument u = (node - point)/h, the
+ * support on which every Table I constant normalises k to unit mass; the
+ * Gaussian has no indicator.
+ *
+ * Grid.  nx x ny nodes, gx_i = xmin + i*dx with dx = (xmax - xmin)/(nx - 1), both
+ * box edges on nodes (the node spacing of Eq. (5)-(6)); rows j follow y.  Output
+ * is row-major, x fastest (the density-matrix index order of Algorithm 3).
+ *
+ * Points on the device are FP32 "grid units": X_p = fl32((x_p - xmin)/dx), Y_p =
+ * fl32((y_p - ymin)/dy), interleaved [n][2].  kde_to_grid_units produces them on
+ * the host in FP64 with a single rounding.  Bandwidths are passed in world units
+ * and converted to Hx = fl32(hx/dx), Hy = fl32(hy/dy) inside the library.
+ *
+ * Conventions for every call:
+ *  - Return value: KDE_OK (0) or a negative kde_status.  On any failure
+ *    kde_last_error() returns a message; it is thread-local and valid until the
+ *    next call on the same thread.  No C++ exception crosses this interface.
+ *  - Arguments are validated before anything is launched: a KDE_EINVAL return
+ *    has written nothing and launched nothing.
+ *  - Device buffers belong to the caller; the library never frees them.  The
+ *    library owns grid handles and a workspace per (device, stream) that is
+ *    reused across calls and released by kde_shutdown().
+ *  - Device work is enqueued on `stream` (a hipStream_t; NULL = the null
+ *    stream) and returns before it completes, except where a call writes a
+ *    host scalar, which synchronises `stream` first.
+ *  - Non-finite point coordinates are not checked (that would need a device
+ *    pass); they yield NaN (Gaussian) or no contribution (compact kernels).
+ */
+#ifndef KDE_H
+#define KDE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum kde_status {
+    KDE_OK = 0,
+    KDE_EINVAL = -1,       /* bad argument; nothing written or launched */
+    KDE_ENOMEM = -2,       /* workspace allocation failed */
+    KDE_EHIP = -3,         /* HIP runtime error (message in kde_last_error) */
+    KDE_EUNSUPPORTED = -4  /* valid request this library does not implement */
+} kde_status;
+
+/* Kernel ids in Table I order. */
+enum {
+    KDE_UNIFORM = 0,      /* k(u) = 1/2                  I(u) */
+    KDE_TRIANGULAR = 1,   /* k(u) = 1 - |u|              I(u) */
+    KDE_EPANECHNIKOV = 2, /* k(u) = 3/4 (1 - u^2)        I(u) */
+    KDE_QUARTIC = 3,      /* k(u) = 15/16 (1 - u^2)^2    I(u) */
+    KDE_TRIWEIGHT = 4,    /* k(u) = 35/32 (1 - u^2)^3    I(u) */
+    KDE_TRICUBE = 5,      /* k(u) = 70/81 (1 - |u|^3)^3  I(u) */
+    KDE_GAUSSIAN = 6,     /* k(u) = exp(-u^2/2)/sqrt(2 pi)    */
+    KDE_COSINE = 7,       /* k(u) = pi/4 cos(pi u/2)     I(u) */
+    KDE_NUM_KERNELS = 8
+};
+
+/* Evaluation paths ("precision" argument of kde_eval). */
+enum {
+    KDE_FP32_DIRECT = 0, /* FP32 direct sum over all pairs (compact kernels skip
+                            pairs outside the support); FP32 accumulation */
+    KDE_FP16_SEP = 1,    /* separable form S = Gy Gx^T on matrix cores: 1-D
+                            factors rounded to FP16, FP32 accumulation */
+    KDE_BF16_SEP = 2,    /* the same with BF16 factors */
+    KDE_FP16X3_SEP = 3,  /* FP16 hi/lo split: Gy_hi Gx_hi^T + Gy_hi Gx_lo^T +
+                            Gy_lo Gx_hi^T, FP32 accumulation */
+    KDE_BF16X3_SEP = 4   /* the same split with BF16 */
+};
+
+/* Flags. */
+#define KDE_RAW_SUM 1u /* write S instead of S/(n hx hy) */
+
+typedef struct kde_grid kde_grid; /* opaque, immutable, library-owned */
+
+/* Creates a grid of nx x ny nodes spanning [xmin, xmax] x [ymin, ymax] (world
+ * units, both edges on nodes).  Requires finite bounds with xmin < xmax,
+ * ymin < ymax, and 2 <= nx, ny <= 65536 (the node spacing divides by nx - 1).
+ * *out receives the handle; release it with kde_destroy_grid. */
+int kde_create_grid(double xmin, double xmax, double ymin, double ymax, int32_t nx, int32_t ny,
+                    kde_grid **out);
+
+/* Releases a grid handle (NULL is ignored). */
+void kde_destroy_grid(kde_grid *g);
+
+/* Reports the node counts and spacings of a grid; any output may be NULL. */
+int kde_grid_shape(const kde_grid *g, int32_t *nx, int32_t *ny, double *dx, double *dy);
+
+/* Host-side input conditioning: world points xy[n][2] (FP64, host) to grid units
+ * out[n][2] (FP32, host), X = fl32((x - xmin)/dx), Y = fl32((y - ymin)/dy).
+ * Points outside the box are allowed (they still contribute to nearby nodes). */
+int kde_to_grid_units(const kde_grid *g, const double *xy, int64_t n, float *out);
+
+/* Bandwidths in grid units: Hx = fl32(hx/dx), Hy = fl32(hy/dy).  hx, hy must be
+ * finite and > 0 and give Hx, Hy in [2^-20, 2^20]. */
+int kde_bandwidth_units(const kde_grid *g, double hx, double hy, float *Hx, float *Hy);
+
+/* The heat map (Sec. III-C, Eq. (7)-(8), Table I).
+ *   points    device, FP32 [n][2] grid units (may be NULL when n == 0)
+ *   n         number of points, 0 <= n < 2^31; n == 0 writes a zero map
+ *   kernel_id KDE_UNIFORM .. KDE_COSINE
+ *   hx, hy    bandwidths in world units (see kde_bandwidth_units)
+ *   g         grid handle
+ *   out       device, FP32 [ny][nx], fully overwritten
+ *   precision KDE_FP32_DIRECT or one of the *_SEP matrix-core paths
+ *   flags     0 or KDE_RAW_SUM
+ *   stream    hipStream_t or NULL */
+int kde_eval(const float *points, int64_t n, int32_t kernel_id, double hx, double hy, const kde_grid *g,
+             float *out, int32_t precision, uint32_t flags, void *stream);
+
+/* One map of a batch: the arguments of kde_eval except precision and stream. */
+typedef struct kde_map {
+    const float *points; /* device [n][2] grid units of `grid` */
+    int64_t n;
+    int32_t kernel_id;
+    int32_t reserved; /* must be 0 */
+    double hx, hy;    /* world units */
+    const kde_grid *grid;
+    float *out; /* device [ny][nx] */
+} kde_map;
+
+/* Evaluates n_maps maps (host array of descriptors) with the FP32 direct path in
+ * one persistent launch.  Every descriptor is validated before anything is
+ * launched; output buffers must not overlap.  flags as for kde_eval. */
+int kde_eval_batched(const kde_map *maps, int32_t n_maps, uint32_t flags, void *stream);
+
+/* Adjoint of kde_eval (FP32 direct path).  Given grad_out = dL/d(out) (device
+ * [ny][nx]), writes
+ *   grad_points  device FP32 [n][2]: dL/dx_p, dL/dy_p in world units (or NULL)
+ *   grad_h       host FP64 [2]: dL/dhx, dL/dhy in world units (or NULL; when
+ *                non-NULL the call synchronises `stream`)
+ * The derivative of k is taken from its formula inside the support. */
+int kde_backward(const float *points, int64_t n, int32_t kernel_id, double hx, double hy, const kde_grid *g,
+                 const float *grad_out, float *grad_points, double *grad_h, uint32_t flags, void *stream);
+
+/* Least-squares cross-validation score of the bandwidth (Rudemo 1982, Bowman
+ * 1984; not in the paper), in world units:
+ *   LSCV = 1/(n^2 hx hy) sum_{p,q} kbar(dx_pq/hx) kbar(dy_pq/hy)
+ *        - 2/(n(n-1) hx hy) sum_{p!=q} k(dx_pq/hx) k(dy_pq/hy),   kbar = k * k,
+ * and its gradient with respect to (hx, hy).  points as for kde_eval (the grid
+ * only fixes the units), n >= 2, kernel KDE_GAUSSIAN or KDE_EPANECHNIKOV.
+ * value (host, FP64) and grad_h (host FP64 [2], or NULL); synchronises stream. */
+int kde_lscv(const float *points, int64_t n, int32_t kernel_id, double hx, double hy, const kde_grid *g,
+             double *value, double *grad_h, void *stream);
+
+/* Thread-local text of the last failure on this thread ("" if none). */
+const char *kde_last_error(void);
+
+/* Frees every cached workspace on every device.  No call may be in flight. */
+void kde_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KDE_H */

@@ -1,0 +1,163 @@
+"""Python binding of libkde, the MI355X KDE heat-map library (arXiv 2004.13653).
+
+Thin ctypes marshalling over the C ABI in include/kde.h: every step of the map is
+computed by the HIP kernels in libkde.so; PyTorch only supplies device memory and
+the current stream.  There is no CPU fallback: if libkde.so is missing, every call
+raises.
+
+Build the library with ``python -m paper_2004_13653_amd.build``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = ["KERNELS", "PRECISIONS", "KDEError", "Grid", "lib", "eval", "to_grid_units", "bandwidth_units",
+           "LIB_PATH"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libkde.so")
+
+KERNELS = {"uniform": 0, "triangular": 1, "epanechnikov": 2, "quartic": 3, "triweight": 4, "tricube": 5,
+           "gaussian": 6, "cosine": 7}
+PRECISIONS = {"fp32": 0, "fp16": 1, "bf16": 2, "fp16x3": 3, "bf16x3": 4}
+RAW_SUM = 1
+
+KDE_OK, KDE_EINVAL, KDE_ENOMEM, KDE_EHIP, KDE_EUNSUPPORTED = 0, -1, -2, -3, -4
+_STATUS = {KDE_EINVAL: "EINVAL", KDE_ENOMEM: "ENOMEM", KDE_EHIP: "EHIP", KDE_EUNSUPPORTED: "EUNSUPPORTED"}
+
+
+class KDEError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class kde_map(ctypes.Structure):
+    _fields_ = [("points", ctypes.c_void_p), ("n", ctypes.c_int64), ("kernel_id", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("hx", ctypes.c_double), ("hy", ctypes.c_double),
+                ("grid", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Loads libkde.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libkde.so not found at {LIB_PATH}; build it with "
+                               "'python -m paper_2004_13653_amd.build'")
+        # PyTorch ships its own HIP runtime with the same soname as the system one.
+        # Loading torch first makes libkde bind to that copy, so the process holds
+        # a single HIP runtime (two runtimes in one process cannot share a device).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = ctypes.CDLL(LIB_PATH)
+        i32, i64, u32, d, p = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double, ctypes.c_void_p
+        sig = {
+            "kde_create_grid": (ctypes.c_int, [d, d, d, d, i32, i32, ctypes.POINTER(p)]),
+            "kde_destroy_grid": (None, [p]),
+            "kde_grid_shape": (ctypes.c_int, [p, p, p, p, p]),
+            "kde_to_grid_units": (ctypes.c_int, [p, p, i64, p]),
+            "kde_bandwidth_units": (ctypes.c_int, [p, d, d, p, p]),
+            "kde_eval": (ctypes.c_int, [p, i64, i32, d, d, p, p, i32, u32, p]),
+            "kde_eval_batched": (ctypes.c_int, [p, i32, u32, p]),
+            "kde_backward": (ctypes.c_int, [p, i64, i32, d, d, p, p, p, p, u32, p]),
+            "kde_lscv": (ctypes.c_int, [p, i64, i32, d, d, p, p, p, p]),
+            "kde_last_error": (ctypes.c_char_p, []),
+            "kde_shutdown": (None, []),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int) -> None:
+    if status != KDE_OK:
+        raise KDEError(status, lib().kde_last_error().decode())
+
+
+def _kernel_id(kernel) -> int:
+    if isinstance(kernel, str):
+        return KERNELS[kernel.lower()]
+    return int(kernel)
+
+
+class Grid:
+    """Library-owned node grid (kde_create_grid): nx x ny nodes spanning
+    [xmin, xmax] x [ymin, ymax], both edges on nodes."""
+
+    def __init__(self, xmin: float, xmax: float, ymin: float, ymax: float, nx: int, ny: int):
+        h = ctypes.c_void_p()
+        _check(lib().kde_create_grid(xmin, xmax, ymin, ymax, nx, ny, ctypes.byref(h)))
+        self._h = h
+        self.bounds = (float(xmin), float(xmax), float(ymin), float(ymax))
+        nx_, ny_ = ctypes.c_int32(), ctypes.c_int32()
+        dx, dy = ctypes.c_double(), ctypes.c_double()
+        _check(lib().kde_grid_shape(h, ctypes.byref(nx_), ctypes.byref(ny_), ctypes.byref(dx), ctypes.byref(dy)))
+        self.nx, self.ny, self.dx, self.dy = nx_.value, ny_.value, dx.value, dy.value
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.kde_destroy_grid(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def to_grid_units(xy, grid: Grid) -> np.ndarray:
+    """World points [n, 2] (FP64) to FP32 grid units on the host (kde_to_grid_units)."""
+    xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+    out = np.empty(xy.shape, dtype=np.float32)
+    _check(lib().kde_to_grid_units(grid.handle, xy.ctypes.data, xy.shape[0], out.ctypes.data))
+    return out
+
+
+def bandwidth_units(hx: float, hy: float, grid: Grid) -> tuple[np.float32, np.float32]:
+    Hx, Hy = ctypes.c_float(), ctypes.c_float()
+    _check(lib().kde_bandwidth_units(grid.handle, hx, hy, ctypes.byref(Hx), ctypes.byref(Hy)))
+    return np.float32(Hx.value), np.float32(Hy.value)
+
+
+def _stream(torch, device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _check_points(points, torch):
+    if not (points.is_cuda and points.dtype == torch.float32 and points.dim() == 2 and points.shape[1] == 2):
+        raise ValueError("points must be a CUDA float32 tensor of shape [n, 2]")
+    if not points.is_contiguous():
+        raise ValueError("points must be contiguous")
+
+
+def eval(points, kernel, hx: float, hy: float, grid: Grid, out=None, precision: str = "fp32",
+         raw: bool = False):
+    """The heat map of `points` ([n, 2] FP32 grid units on the GPU) on `grid`:
+    returns (or fills) an [ny, nx] FP32 tensor (kde_eval)."""
+    import torch
+    _check_points(points, torch)
+    if out is None:
+        out = torch.empty((grid.ny, grid.nx), dtype=torch.float32, device=points.device)
+    elif not (out.is_cuda and out.dtype == torch.float32 and out.is_contiguous() and out.numel() == grid.nx * grid.ny):
+        raise ValueError("out must be a contiguous CUDA float32 tensor with ny*nx elements")
+    with torch.cuda.device(points.device):
+        _check(lib().kde_eval(points.data_ptr() if points.numel() else None, points.shape[0], _kernel_id(kernel),
+                              hx, hy, grid.handle, out.data_ptr(), PRECISIONS[precision],
+                              RAW_SUM if raw else 0, _stream(torch, points.device)))
+    return out

@@ -1,0 +1,268 @@
+// C ABI of libkde: argument validation, grid handles, workspace cache and
+// dispatch to the HIP kernels.  Every entry point validates all arguments
+// before it touches the GPU and never lets a C++ exception escape.
+#include "kde.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <utility>
+
+#include "kde_internal.h"
+
+struct kde_grid {
+    uint64_t magic;
+    double xmin, xmax, ymin, ymax;
+    int32_t nx, ny;
+    double dx, dy;
+};
+
+namespace {
+
+constexpr uint64_t kGridMagic = 0x6b64655f67726964ull;  // "kde_grid"
+constexpr int32_t kMaxSide = 65536;
+constexpr double kMinH = 1.0 / 1048576.0, kMaxH = 1048576.0;
+constexpr int64_t kMaxPoints = (int64_t)1 << 31;
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *where) {
+    return fail(KDE_EHIP, "%s: HIP error %d (%s)", where, (int)e, hipGetErrorString(e));
+}
+
+bool grid_ok(const kde_grid *g) { return g != nullptr && g->magic == kGridMagic; }
+
+// Library-owned device scratch, one buffer per (device, stream), grown on demand.
+std::mutex g_ws_mu;
+std::map<std::pair<int, hipStream_t>, std::pair<void *, size_t>> g_ws;
+
+int get_workspace(hipStream_t stream, size_t bytes, void **out) {
+    *out = nullptr;
+    if (bytes == 0) return KDE_OK;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    auto &slot = g_ws[{dev, stream}];
+    if (slot.second >= bytes) {
+        *out = slot.first;
+        return KDE_OK;
+    }
+    if (slot.first != nullptr) {
+        // Work already enqueued on this stream may still read the old buffer.
+        e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        e = hipFree(slot.first);
+        slot = {nullptr, 0};
+        if (e != hipSuccess) return hip_fail(e, "hipFree");
+    }
+    size_t want = bytes + bytes / 4;
+    void *p = nullptr;
+    e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(KDE_ENOMEM, "workspace allocation of %zu bytes failed (%s)", want, hipGetErrorString(e));
+    }
+    slot = {p, want};
+    *out = p;
+    return KDE_OK;
+}
+
+// Shared validation of (points, n, kernel, hx, hy, grid).
+int check_map(const float *points, int64_t n, int32_t kernel_id, double hx, double hy, const kde_grid *g,
+              const char *who) {
+    if (!grid_ok(g)) return fail(KDE_EINVAL, "%s: invalid grid handle", who);
+    if (n < 0 || n >= kMaxPoints) return fail(KDE_EINVAL, "%s: n = %lld out of range [0, 2^31)", who, (long long)n);
+    if (n > 0 && points == nullptr) return fail(KDE_EINVAL, "%s: points is NULL with n = %lld", who, (long long)n);
+    if (kernel_id < 0 || kernel_id >= KDE_NUM_KERNELS)
+        return fail(KDE_EINVAL, "%s: unknown kernel id %d", who, (int)kernel_id);
+    if (!(std::isfinite(hx) && std::isfinite(hy) && hx > 0.0 && hy > 0.0))
+        return fail(KDE_EINVAL, "%s: bandwidths must be finite and > 0 (hx = %g, hy = %g)", who, hx, hy);
+    const double Hx = hx / g->dx, Hy = hy / g->dy;
+    if (!(Hx >= kMinH && Hx <= kMaxH && Hy >= kMinH && Hy <= kMaxH))
+        return fail(KDE_EINVAL, "%s: bandwidth in grid units (%g, %g) outside [2^-20, 2^20]", who, Hx, Hy);
+    return KDE_OK;
+}
+
+kde::MapArgs make_args(const float *points, int64_t n, int32_t kernel_id, double hx, double hy, const kde_grid *g,
+                       float *out, uint32_t flags) {
+    kde::MapArgs a;
+    a.pts = reinterpret_cast<const float2 *>(points);
+    a.n = n;
+    a.kernel_id = kernel_id;
+    a.Hx = (float)(hx / g->dx);
+    a.Hy = (float)(hy / g->dy);
+    a.ax = kde::arg_scale(kernel_id, a.Hx);
+    a.ay = kde::arg_scale(kernel_id, a.Hy);
+    a.nx = g->nx;
+    a.ny = g->ny;
+    const double c = kde::kernel_norm(kernel_id);
+    a.scale = (flags & KDE_RAW_SUM) ? (float)(c * c) : (float)(c * c / ((double)n * hx * hy));
+    a.out = out;
+    return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+int kde_create_grid(double xmin, double xmax, double ymin, double ymax, int32_t nx, int32_t ny, kde_grid **out) {
+    if (out == nullptr) return fail(KDE_EINVAL, "kde_create_grid: out is NULL");
+    *out = nullptr;
+    if (!(std::isfinite(xmin) && std::isfinite(xmax) && std::isfinite(ymin) && std::isfinite(ymax)))
+        return fail(KDE_EINVAL, "kde_create_grid: bounds must be finite");
+    if (!(xmin < xmax && ymin < ymax)) return fail(KDE_EINVAL, "kde_create_grid: need xmin < xmax and ymin < ymax");
+    if (nx < 2 || ny < 2 || nx > kMaxSide || ny > kMaxSide)
+        return fail(KDE_EINVAL, "kde_create_grid: nx, ny = %d, %d outside [2, %d]", (int)nx, (int)ny, (int)kMaxSide);
+    kde_grid *g = new (std::nothrow) kde_grid;
+    if (g == nullptr) return fail(KDE_ENOMEM, "kde_create_grid: out of host memory");
+    g->magic = kGridMagic;
+    g->xmin = xmin;
+    g->xmax = xmax;
+    g->ymin = ymin;
+    g->ymax = ymax;
+    g->nx = nx;
+    g->ny = ny;
+    g->dx = (xmax - xmin) / (double)(nx - 1);
+    g->dy = (ymax - ymin) / (double)(ny - 1);
+    if (!(g->dx > 0.0 && g->dy > 0.0 && std::isfinite(g->dx) && std::isfinite(g->dy))) {
+        delete g;
+        return fail(KDE_EINVAL, "kde_create_grid: degenerate node spacing");
+    }
+    *out = g;
+    return KDE_OK;
+}
+
+void kde_destroy_grid(kde_grid *g) {
+    if (g != nullptr && g->magic == kGridMagic) {
+        g->magic = 0;
+        delete g;
+    }
+}
+
+int kde_grid_shape(const kde_grid *g, int32_t *nx, int32_t *ny, double *dx, double *dy) {
+    if (!grid_ok(g)) return fail(KDE_EINVAL, "kde_grid_shape: invalid grid handle");
+    if (nx) *nx = g->nx;
+    if (ny) *ny = g->ny;
+    if (dx) *dx = g->dx;
+    if (dy) *dy = g->dy;
+    return KDE_OK;
+}
+
+int kde_to_grid_units(const kde_grid *g, const double *xy, int64_t n, float *out) {
+    if (!grid_ok(g)) return fail(KDE_EINVAL, "kde_to_grid_units: invalid grid handle");
+    if (n < 0) return fail(KDE_EINVAL, "kde_to_grid_units: n < 0");
+    if (n > 0 && (xy == nullptr || out == nullptr)) return fail(KDE_EINVAL, "kde_to_grid_units: NULL buffer");
+    for (int64_t p = 0; p < n; ++p) {
+        out[2 * p] = (float)((xy[2 * p] - g->xmin) / g->dx);
+        out[2 * p + 1] = (float)((xy[2 * p + 1] - g->ymin) / g->dy);
+    }
+    return KDE_OK;
+}
+
+int kde_bandwidth_units(const kde_grid *g, double hx, double hy, float *Hx, float *Hy) {
+    int st = check_map(nullptr, 0, KDE_GAUSSIAN, hx, hy, g, "kde_bandwidth_units");
+    if (st != KDE_OK) return st;
+    if (Hx) *Hx = (float)(hx / g->dx);
+    if (Hy) *Hy = (float)(hy / g->dy);
+    return KDE_OK;
+}
+
+int kde_eval(const float *points, int64_t n, int32_t kernel_id, double hx, double hy, const kde_grid *g, float *out,
+             int32_t precision, uint32_t flags, void *stream) {
+    try {
+        int st = check_map(points, n, kernel_id, hx, hy, g, "kde_eval");
+        if (st != KDE_OK) return st;
+        if (out == nullptr) return fail(KDE_EINVAL, "kde_eval: out is NULL");
+        if (flags & ~KDE_RAW_SUM) return fail(KDE_EINVAL, "kde_eval: unknown flags 0x%x", flags);
+        if (precision < KDE_FP32_DIRECT || precision > KDE_BF16X3_SEP)
+            return fail(KDE_EINVAL, "kde_eval: unknown precision %d", (int)precision);
+        if (precision != KDE_FP32_DIRECT)
+            return fail(KDE_EUNSUPPORTED, "kde_eval: precision %d not available", (int)precision);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const int64_t plane = (int64_t)g->nx * g->ny;
+        if (n == 0) {
+            hipError_t e = kde::launch_fill_zero(out, plane, s);
+            return e == hipSuccess ? KDE_OK : hip_fail(e, "kde_eval");
+        }
+        kde::MapArgs a = make_args(points, n, kernel_id, hx, hy, g, out, flags);
+        void *ws = nullptr;
+        st = get_workspace(s, kde::direct_workspace_bytes(a), &ws);
+        if (st != KDE_OK) return st;
+        hipError_t e = kde::launch_direct(a, ws, s);
+        return e == hipSuccess ? KDE_OK : hip_fail(e, "kde_eval");
+    } catch (...) {
+        return fail(KDE_EHIP, "kde_eval: internal error");
+    }
+}
+
+int kde_eval_batched(const kde_map *maps, int32_t n_maps, uint32_t flags, void *stream) {
+    (void)stream;
+    if (n_maps < 0 || (n_maps > 0 && maps == nullptr)) return fail(KDE_EINVAL, "kde_eval_batched: bad map array");
+    if (flags & ~KDE_RAW_SUM) return fail(KDE_EINVAL, "kde_eval_batched: unknown flags 0x%x", flags);
+    for (int32_t m = 0; m < n_maps; ++m) {
+        const kde_map &d = maps[m];
+        int st = check_map(d.points, d.n, d.kernel_id, d.hx, d.hy, d.grid, "kde_eval_batched");
+        if (st != KDE_OK) return st;
+        if (d.out == nullptr || d.reserved != 0) return fail(KDE_EINVAL, "kde_eval_batched: map %d: bad out/reserved", m);
+    }
+    return fail(KDE_EUNSUPPORTED, "kde_eval_batched: not available");
+}
+
+int kde_backward(const float *points, int64_t n, int32_t kernel_id, double hx, double hy, const kde_grid *g,
+                 const float *grad_out, float *grad_points, double *grad_h, uint32_t flags, void *stream) {
+    (void)stream;
+    (void)grad_points;
+    (void)grad_h;
+    int st = check_map(points, n, kernel_id, hx, hy, g, "kde_backward");
+    if (st != KDE_OK) return st;
+    if (grad_out == nullptr) return fail(KDE_EINVAL, "kde_backward: grad_out is NULL");
+    if (flags & ~KDE_RAW_SUM) return fail(KDE_EINVAL, "kde_backward: unknown flags 0x%x", flags);
+    return fail(KDE_EUNSUPPORTED, "kde_backward: not available");
+}
+
+int kde_lscv(const float *points, int64_t n, int32_t kernel_id, double hx, double hy, const kde_grid *g, double *value,
+             double *grad_h, void *stream) {
+    (void)stream;
+    (void)grad_h;
+    int st = check_map(points, n, kernel_id, hx, hy, g, "kde_lscv");
+    if (st != KDE_OK) return st;
+    if (n < 2) return fail(KDE_EINVAL, "kde_lscv: need n >= 2");
+    if (value == nullptr) return fail(KDE_EINVAL, "kde_lscv: value is NULL");
+    if (kernel_id != KDE_GAUSSIAN && kernel_id != KDE_EPANECHNIKOV)
+        return fail(KDE_EUNSUPPORTED, "kde_lscv: kernel %d not supported", (int)kernel_id);
+    return fail(KDE_EUNSUPPORTED, "kde_lscv: not available");
+}
+
+const char *kde_last_error(void) { return g_err.c_str(); }
+
+void kde_shutdown(void) {
+    std::lock_guard<std::mutex> lock(g_ws_mu);
+    int cur = 0;
+    bool have_cur = hipGetDevice(&cur) == hipSuccess;
+    for (auto &kv : g_ws) {
+        if (kv.second.first != nullptr) {
+            (void)hipSetDevice(kv.first.first);
+            (void)hipFree(kv.second.first);
+        }
+    }
+    g_ws.clear();
+    if (have_cur) (void)hipSetDevice(cur);
+}
+
+}  // extern "C"

@@ -1,0 +1,52 @@
+// Internal declarations shared by the HIP translation units of libkde.
+// Nothing here is part of the C ABI (include/kde.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace kde {
+
+enum KernelId : int {
+    kUniform = 0,
+    kTriangular = 1,
+    kEpanechnikov = 2,
+    kQuartic = 3,
+    kTriweight = 4,
+    kTricube = 5,
+    kGaussian = 6,
+    kCosine = 7,
+};
+
+// Normalising constant c of the 1-D factor k(u) = c g(u) (Table I); the kernels
+// accumulate products of g and the epilogue multiplies by c^2.
+double kernel_norm(int kernel_id);
+
+// Scale that turns a grid-unit difference d = node - point into the argument of
+// g: the Gaussian evaluates g = exp2(-(d a)^2) with a = sqrt(log2(e)/2)/H, the
+// compact kernels evaluate g(|d|/H) with a = 1/H.
+float arg_scale(int kernel_id, float H);
+
+struct MapArgs {
+    const float2 *pts;  // [n] grid units
+    int64_t n;
+    int kernel_id;
+    float Hx, Hy;       // bandwidths in grid units
+    float ax, ay;       // argument scales (arg_scale)
+    int nx, ny;
+    float scale;        // c^2 / (n hx hy), or c^2 for raw sums
+    float *out;         // [ny][nx]
+};
+
+// FP32 direct path: enqueues the map on `stream`; ws holds
+// direct_workspace_bytes(a) bytes of device scratch.  Returns the launch status.
+hipError_t launch_direct(const MapArgs &a, void *ws, hipStream_t stream);
+
+// Bytes of workspace launch_direct needs for these arguments.
+size_t direct_workspace_bytes(const MapArgs &a);
+
+// Zero-fill kernel (used for empty inputs; no memset nodes in captured graphs).
+hipError_t launch_fill_zero(float *out, int64_t count, hipStream_t stream);
+
+}  // namespace kde

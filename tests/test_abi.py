@@ -1,0 +1,115 @@
+"""The C ABI on the CPU: the library loads, exports every declared symbol, and
+validates arguments before touching the GPU (no compute call runs here)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2004_13653_amd as kde
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
+
+
+def _declared():
+    names = set()
+    for f in os.listdir(os.path.join(ROOT, "include")):
+        if f.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", f)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(kde_[a-z_]+)\s*\(", txt))
+    return names
+
+
+def test_exports_every_declared_symbol():
+    L = kde.lib()
+    names = _declared()
+    assert {"kde_create_grid", "kde_eval", "kde_eval_batched", "kde_backward", "kde_lscv"} <= names
+    for n in sorted(names):
+        assert hasattr(L, n), n
+
+
+def _status(fn, *args):
+    return getattr(kde.lib(), fn)(*args)
+
+
+def test_grid_validation():
+    h = ctypes.c_void_p()
+    bad = [(0.0, 0.0, 0.0, 1.0, 8, 8), (0.0, 1.0, 1.0, 0.0, 8, 8), (0.0, 1.0, 0.0, 1.0, 1, 8),
+           (0.0, 1.0, 0.0, 1.0, 8, 65537), (float("nan"), 1.0, 0.0, 1.0, 8, 8), (0.0, float("inf"), 0.0, 1.0, 8, 8)]
+    for b in bad:
+        assert _status("kde_create_grid", *b, ctypes.byref(h)) == kde.KDE_EINVAL
+        assert h.value is None
+        assert kde.lib().kde_last_error().decode()
+    g = kde.Grid(122.0, 123.0, 30.0, 31.0, 1024, 512)
+    assert (g.nx, g.ny) == (1024, 512)
+    assert g.dx == (123.0 - 122.0) / 1023 and g.dy == 1.0 / 511
+    assert _status("kde_grid_shape", None, None, None, None, None) == kde.KDE_EINVAL
+
+
+def test_grid_units_bit_identical_to_oracle():
+    t = synth.workload_lanes(n_tracks=50, pts=200)
+    g = kde.Grid(122.0, 123.0, 30.0, 31.0, 1024, 1024)
+    og = oracle.Grid(122.0, 123.0, 30.0, 31.0, 1024, 1024)
+    np.testing.assert_array_equal(kde.to_grid_units(t.xy, g), oracle.to_units(t.xy, og))
+    assert kde.bandwidth_units(0.002, 0.003, g) == oracle.bandwidth_units(0.002, 0.003, og)
+
+
+def test_eval_validation_before_launch():
+    g = kde.Grid(0.0, 1.0, 0.0, 1.0, 64, 64)
+    L = kde.lib()
+    ok = dict(points=FAKE, n=10, k=6, hx=0.05, hy=0.05, g=g.handle, out=FAKE, prec=0, flags=0, s=None)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return L.kde_eval(a["points"], a["n"], a["k"], a["hx"], a["hy"], a["g"], a["out"], a["prec"], a["flags"],
+                          a["s"])
+
+    for kw in (dict(n=-1), dict(n=1 << 31), dict(points=None), dict(k=8), dict(k=-1), dict(hx=0.0),
+               dict(hy=-1.0), dict(hx=float("nan")), dict(hy=float("inf")), dict(hx=1e-9), dict(hx=1e9),
+               dict(g=None), dict(out=None), dict(prec=5), dict(prec=-1), dict(flags=2)):
+        assert call(**kw) == kde.KDE_EINVAL, kw
+        assert L.kde_last_error().decode()
+
+
+def test_other_entry_points_validate():
+    g = kde.Grid(0.0, 1.0, 0.0, 1.0, 64, 64)
+    L = kde.lib()
+    assert L.kde_backward(FAKE, 10, 6, 0.05, 0.05, g.handle, None, FAKE, None, 0, None) == kde.KDE_EINVAL
+    assert L.kde_backward(FAKE, 10, 9, 0.05, 0.05, g.handle, FAKE, FAKE, None, 0, None) == kde.KDE_EINVAL
+    v = ctypes.c_double()
+    assert L.kde_lscv(FAKE, 1, 6, 0.05, 0.05, g.handle, ctypes.byref(v), None, None) == kde.KDE_EINVAL
+    assert L.kde_lscv(FAKE, 10, 6, 0.05, 0.05, g.handle, None, None, None) == kde.KDE_EINVAL
+    assert L.kde_eval_batched(None, 3, 0, None) == kde.KDE_EINVAL
+    m = (kde.kde_map * 2)()
+    for d in m:
+        d.points, d.n, d.kernel_id, d.hx, d.hy, d.grid, d.out = FAKE.value, 5, 6, 0.05, 0.05, g.handle.value, FAKE.value
+    m[1].kernel_id = 11
+    assert L.kde_eval_batched(m, 2, 0, None) == kde.KDE_EINVAL
+    assert "kernel" in L.kde_last_error().decode()
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(kde, "_lib", None)
+    monkeypatch.setattr(kde, "LIB_PATH", str(tmp_path / "libkde.so"))
+    with pytest.raises(RuntimeError, match="libkde.so not found"):
+        kde.lib()
+
+
+def test_single_hip_runtime_in_process():
+    """libkde binds to the HIP runtime PyTorch already loaded (same soname), so a
+    process that uses both holds one copy of libamdhip64."""
+    import subprocess
+    import sys
+    code = ("import paper_2004_13653_amd as kde, oracle, synth\n"
+            "kde.Grid(0.0, 1.0, 0.0, 1.0, 8, 8)\n"
+            "import torch\n"
+            "libs = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}\n"
+            "print(len(libs))\n")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
