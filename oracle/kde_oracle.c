@@ -114,21 +114,25 @@ double ko_dkbar(int kernel, double u)
 
 void ko_k_array(int kernel, const double *u, int64_t n, double *out)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t q = 0; q < n; ++q) out[q] = ko_k(kernel, u[q]);
 }
 
 void ko_dk_array(int kernel, const double *u, int64_t n, double *out)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t q = 0; q < n; ++q) out[q] = ko_dk(kernel, u[q]);
 }
 
 void ko_kbar_array(int kernel, const double *u, int64_t n, double *out)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t q = 0; q < n; ++q) out[q] = ko_kbar(kernel, u[q]);
 }
 
 void ko_dkbar_array(int kernel, const double *u, int64_t n, double *out)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t q = 0; q < n; ++q) out[q] = ko_dkbar(kernel, u[q]);
 }
 

@@ -192,8 +192,6 @@ int kde_eval(const float *points, int64_t n, int32_t kernel_id, double hx, doubl
         if (flags & ~KDE_RAW_SUM) return fail(KDE_EINVAL, "kde_eval: unknown flags 0x%x", flags);
         if (precision < KDE_FP32_DIRECT || precision > KDE_BF16X3_SEP)
             return fail(KDE_EINVAL, "kde_eval: unknown precision %d", (int)precision);
-        if (precision != KDE_FP32_DIRECT)
-            return fail(KDE_EUNSUPPORTED, "kde_eval: precision %d not available", (int)precision);
         hipStream_t s = static_cast<hipStream_t>(stream);
         const int64_t plane = (int64_t)g->nx * g->ny;
         if (n == 0) {
@@ -201,10 +199,11 @@ int kde_eval(const float *points, int64_t n, int32_t kernel_id, double hx, doubl
             return e == hipSuccess ? KDE_OK : hip_fail(e, "kde_eval");
         }
         kde::MapArgs a = make_args(points, n, kernel_id, hx, hy, g, out, flags);
+        const bool direct = precision == KDE_FP32_DIRECT;
         void *ws = nullptr;
-        st = get_workspace(s, kde::direct_workspace_bytes(a), &ws);
+        st = get_workspace(s, direct ? kde::direct_workspace_bytes(a) : kde::sep_workspace_bytes(a, precision), &ws);
         if (st != KDE_OK) return st;
-        hipError_t e = kde::launch_direct(a, ws, s);
+        hipError_t e = direct ? kde::launch_direct(a, ws, s) : kde::launch_sep(a, precision, ws, s);
         return e == hipSuccess ? KDE_OK : hip_fail(e, "kde_eval");
     } catch (...) {
         return fail(KDE_EHIP, "kde_eval: internal error");

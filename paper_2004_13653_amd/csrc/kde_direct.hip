@@ -297,9 +297,14 @@ hipError_t launch_direct(const MapArgs &a, void *ws, hipStream_t stream) {
     default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess || pl.splits == 1) return e;
-    const int64_t plane = (int64_t)a.nx * a.ny;
-    hipLaunchKernelGGL(reduce_splits_kernel, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, stream,
-                       static_cast<const float *>(ws), pl.splits, plane, a.scale, a.out);
+    return launch_reduce_splits(static_cast<const float *>(ws), pl.splits, (int64_t)a.nx * a.ny, a.scale, a.out,
+                                stream);
+}
+
+hipError_t launch_reduce_splits(const float *part, int splits, int64_t plane, float scale, float *out,
+                                hipStream_t stream) {
+    hipLaunchKernelGGL(reduce_splits_kernel, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, stream, part,
+                       splits, plane, scale, out);
     return hipGetLastError();
 }
 

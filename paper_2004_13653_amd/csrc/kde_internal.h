@@ -8,6 +8,15 @@
 
 namespace kde {
 
+// Evaluation paths (the precision argument of kde_eval).
+enum Precision : int {
+    kPrecFp32Direct = 0,
+    kPrecFp16 = 1,
+    kPrecBf16 = 2,
+    kPrecFp16x3 = 3,
+    kPrecBf16x3 = 4,
+};
+
 enum KernelId : int {
     kUniform = 0,
     kTriangular = 1,
@@ -45,6 +54,14 @@ hipError_t launch_direct(const MapArgs &a, void *ws, hipStream_t stream);
 
 // Bytes of workspace launch_direct needs for these arguments.
 size_t direct_workspace_bytes(const MapArgs &a);
+
+// Matrix-core separable path (precision kPrecFp16 .. kPrecBf16x3).
+hipError_t launch_sep(const MapArgs &a, int precision, void *ws, hipStream_t stream);
+size_t sep_workspace_bytes(const MapArgs &a, int precision);
+
+// out[i] = scale * sum_{s < splits} part[s * plane + i], summed in split order.
+hipError_t launch_reduce_splits(const float *part, int splits, int64_t plane, float scale, float *out,
+                                hipStream_t stream);
 
 // Zero-fill kernel (used for empty inputs; no memset nodes in captured graphs).
 hipError_t launch_fill_zero(float *out, int64_t count, hipStream_t stream);
