@@ -53,6 +53,8 @@ def lib():
         L = ctypes.CDLL(_SO)
         d, i, i64, p = ctypes.c_double, ctypes.c_int, ctypes.c_int64, ctypes.c_void_p
         f = ctypes.c_float
+        L.ko_num_threads.restype = ctypes.c_int
+        L.ko_num_threads.argtypes = []
         L.ko_k.restype = d
         L.ko_k.argtypes = [i, d]
         L.ko_dk.restype = d
@@ -71,6 +73,11 @@ def lib():
             getattr(L, name).restype = None
         _lib = L
     return _lib
+
+
+def num_threads() -> int:
+    """Threads the oracle's parallel loops use (OpenMP)."""
+    return int(lib().ko_num_threads())
 
 
 def _ptr(a: np.ndarray) -> int:

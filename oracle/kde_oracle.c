@@ -34,6 +34,9 @@
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define KO_UNIFORM 0
 #define KO_TRIANGULAR 1
@@ -45,6 +48,16 @@
 #define KO_COSINE 7
 
 static const double PI = 3.14159265358979323846;
+
+/* Number of threads the parallel loops below use. */
+int ko_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* One-dimensional factor k(u) of the Table I product kernels, in Table I order.
  * The indicator I(u) is 1 for |u| <= 1 (inclusive) and the Gaussian has none. */
