@@ -84,7 +84,8 @@ enum {
 };
 
 /* Flags. */
-#define KDE_RAW_SUM 1u /* write S instead of S/(n hx hy) */
+#define KDE_RAW_SUM 1u          /* the map is S instead of S/(n hx hy) */
+#define KDE_GRID_UNIT_GRADS 2u  /* kde_backward: grad_points as dL/dX_p, dL/dY_p in grid units */
 
 typedef struct kde_grid kde_grid; /* opaque, immutable, library-owned */
 
@@ -139,12 +140,16 @@ typedef struct kde_map {
  * launched; output buffers must not overlap.  flags as for kde_eval. */
 int kde_eval_batched(const kde_map *maps, int32_t n_maps, uint32_t flags, void *stream);
 
-/* Adjoint of kde_eval (FP32 direct path).  Given grad_out = dL/d(out) (device
- * [ny][nx]), writes
- *   grad_points  device FP32 [n][2]: dL/dx_p, dL/dy_p in world units (or NULL)
- *   grad_h       host FP64 [2]: dL/dhx, dL/dhy in world units (or NULL; when
- *                non-NULL the call synchronises `stream`)
- * The derivative of k is taken from its formula inside the support. */
+/* Adjoint of kde_eval (vector-Jacobian product; not in the paper).  Given
+ * grad_out = dL/d(out) (device FP32 [ny][nx]) for the map kde_eval produces with
+ * the same points, kernel, bandwidths, grid and KDE_RAW_SUM flag, writes
+ *   grad_points  device FP32 [n][2]: dL/dx_p, dL/dy_p in world units (dL/dX_p,
+ *                dL/dY_p in grid units with KDE_GRID_UNIT_GRADS), or NULL
+ *   grad_h       host FP64 [2]: dL/dhx, dL/dhy in world units, or NULL; when
+ *                non-NULL the call synchronises `stream`
+ * Per pair FP32; bandwidth sums reduced in FP64 in a fixed order.  The
+ * derivative of k is taken from its formula inside the support (at the kink
+ * u = 0 of the triangular kernel, 0).  flags: KDE_RAW_SUM | KDE_GRID_UNIT_GRADS. */
 int kde_backward(const float *points, int64_t n, int32_t kernel_id, double hx, double hy, const kde_grid *g,
                  const float *grad_out, float *grad_points, double *grad_h, uint32_t flags, void *stream);
 

@@ -14,8 +14,8 @@ import os
 
 import numpy as np
 
-__all__ = ["KERNELS", "PRECISIONS", "KDEError", "Grid", "lib", "eval", "to_grid_units", "bandwidth_units",
-           "LIB_PATH"]
+__all__ = ["KERNELS", "PRECISIONS", "KDEError", "Grid", "lib", "eval", "backward", "lscv", "kde_map", "kde_lscv",
+           "to_grid_units", "bandwidth_units", "LIB_PATH"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libkde.so")
 
@@ -161,3 +161,93 @@ def eval(points, kernel, hx: float, hy: float, grid: Grid, out=None, precision: 
                               hx, hy, grid.handle, out.data_ptr(), PRECISIONS[precision],
                               RAW_SUM if raw else 0, _stream(torch, points.device)))
     return out
+
+
+GRID_UNIT_GRADS = 2
+
+
+def backward(points, kernel, hx: float, hy: float, grid: Grid, grad_out, raw: bool = False,
+             grid_units: bool = False, want_points: bool = True, want_h: bool = True):
+    """Vector-Jacobian product of `eval` (kde_backward).  Returns (grad_points
+    [n, 2] FP32 tensor or None, (dL/dhx, dL/dhy) floats or None)."""
+    import torch
+    _check_points(points, torch)
+    if not (grad_out.is_cuda and grad_out.dtype == torch.float32 and grad_out.is_contiguous()
+            and grad_out.numel() == grid.nx * grid.ny):
+        raise ValueError("grad_out must be a contiguous CUDA float32 tensor with ny*nx elements")
+    gp = torch.empty_like(points) if want_points else None
+    gh = (ctypes.c_double * 2)() if want_h else None
+    flags = (RAW_SUM if raw else 0) | (GRID_UNIT_GRADS if grid_units else 0)
+    with torch.cuda.device(points.device):
+        _check(lib().kde_backward(points.data_ptr() if points.numel() else None, points.shape[0],
+                                  _kernel_id(kernel), hx, hy, grid.handle, grad_out.data_ptr(),
+                                  gp.data_ptr() if gp is not None and points.numel() else None, gh, flags,
+                                  _stream(torch, points.device)))
+    return gp, ((gh[0], gh[1]) if gh is not None else None)
+
+
+def lscv(points, kernel, hx: float, hy: float, grid: Grid):
+    """Least-squares cross-validation score and its gradient w.r.t. (hx, hy)
+    (kde_lscv).  Returns (value, (dLSCV/dhx, dLSCV/dhy))."""
+    import torch
+    _check_points(points, torch)
+    v = ctypes.c_double()
+    gh = (ctypes.c_double * 2)()
+    with torch.cuda.device(points.device):
+        _check(lib().kde_lscv(points.data_ptr(), points.shape[0], _kernel_id(kernel), hx, hy, grid.handle,
+                              ctypes.byref(v), gh, _stream(torch, points.device)))
+    return v.value, (gh[0], gh[1])
+
+
+def _autograd():
+    import torch
+
+    class KDEMap(torch.autograd.Function):
+        """out = eval(points, kernel, hx, hy, grid); gradients w.r.t. the grid-unit
+        points and the world-unit bandwidths come from kde_backward."""
+
+        @staticmethod
+        def forward(ctx, points, hx, hy, kernel, grid, raw):
+            ctx.save_for_backward(points)
+            ctx.args = (kernel, float(hx), float(hy), grid, raw)
+            return eval(points, kernel, float(hx), float(hy), grid, raw=raw)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            (points,) = ctx.saved_tensors
+            kernel, hx, hy, grid, raw = ctx.args
+            want_h = ctx.needs_input_grad[1] or ctx.needs_input_grad[2]
+            gp, gh = backward(points, kernel, hx, hy, grid, grad_out.contiguous(), raw=raw, grid_units=True,
+                              want_points=ctx.needs_input_grad[0], want_h=want_h)
+            ghx = torch.tensor(gh[0], dtype=torch.float64) if want_h else None
+            ghy = torch.tensor(gh[1], dtype=torch.float64) if want_h else None
+            return gp, ghx, ghy, None, None, None
+
+    class KDELSCV(torch.autograd.Function):
+        """LSCV(hx, hy) of fixed points; gradient w.r.t. the bandwidths."""
+
+        @staticmethod
+        def forward(ctx, points, hx, hy, kernel, grid):
+            value, grad = lscv(points, kernel, float(hx), float(hy), grid)
+            ctx.grad = grad
+            return torch.tensor(value, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, g):
+            gx, gy = ctx.grad
+            return None, g * gx, g * gy, None, None
+
+    return KDEMap, KDELSCV
+
+
+def kde_map(points, hx, hy, kernel, grid: Grid, raw: bool = False):
+    """Differentiable heat map: points [n, 2] grid units (CUDA FP32), hx, hy world
+    units (Python floats or 0-d tensors)."""
+    KDEMap, _ = _autograd()
+    return KDEMap.apply(points, hx, hy, kernel, grid, raw)
+
+
+def kde_lscv(points, hx, hy, kernel, grid: Grid):
+    """Differentiable LSCV score as a 0-d FP64 tensor (gradients w.r.t. hx, hy)."""
+    _, KDELSCV = _autograd()
+    return KDELSCV.apply(points, hx, hy, kernel, grid)

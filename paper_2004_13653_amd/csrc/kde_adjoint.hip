@@ -1,0 +1,331 @@
+// Adjoints of the KDE heat map on gfx950 (FP32 per pair, FP64 final sums).
+//
+// 1. Vector-Jacobian product of the map.  With S[j][i] = sum_p g(s_ip) g(t_jp),
+//    s_ip = (i - X_p)/Hx, t_jp = (j - Y_p)/Hy (grid units) and a cotangent
+//    Gbar[j][i], every point needs the bilinear sums
+//      Tx_p = sum_{j,i} Gbar g'(s) g(t)      Ty_p = sum Gbar g(s) g'(t)
+//      Ux_p = sum Gbar s g'(s) g(t)          Uy_p = sum Gbar g(s) t g'(t)
+//      Q_p  = sum Gbar g(s) g(t)
+//    from which the host-side chain rule forms dL/dX_p, dL/dY_p and the
+//    bandwidth gradient (see kde_api.cpp).
+//    Layout: one thread per point (a workgroup owns 256 consecutive points), so
+//    no sum is shared between threads.  The grid is swept in strips of 32
+//    columns: each thread keeps its point's 32 column factors g, g' and s g' in
+//    registers, the workgroup stages the strip's Gbar rows in LDS, and every row
+//    costs 96 FMAs against three LDS broadcast rows plus one row factor pair.
+//    Compact kernels sweep only the strips and rows that the workgroup's points
+//    can reach (their bounding box widened by the support).
+//
+// 2. Least-squares cross-validation sums over ordered point pairs (p, q):
+//      SA = sum kb(u) kb(v)   SAX = sum (kb(u) + u kb'(u)) kb(v)   SAY likewise
+//      SB = sum g(u) g(v)     SBX = sum (g(u) + u g'(u)) g(v)      SBY likewise
+//    with u = (X_p - X_q)/Hx, v = (Y_p - Y_q)/Hy, kb the autoconvolution of g
+//    (normalising constants are applied on the host).  One thread per p, q
+//    streamed through LDS 256 at a time; FP32 partials per q tile are added to
+//    FP64 accumulators and reduced per workgroup in FP64 in a fixed order.  The
+//    p == q terms are included here and removed on the host (each contributes
+//    exactly 1 to SB, SBX and SBY).
+#include "kde_internal.h"
+
+#include <cmath>
+
+namespace kde {
+
+namespace {
+
+constexpr int kAdjThreads = 256;
+constexpr int kStrip = 32;        // columns per strip
+constexpr int kRowChunk = 256;    // Gbar rows staged per LDS fill
+constexpr float kFarAdj = 1.0e30f;
+
+// g, g' and the support test for grid-unit difference d (u = d / H).
+template <int K>
+__device__ __forceinline__ void gdg(float d, float H, float inv, float &g, float &dg) {
+    const float u = d * inv;
+    if constexpr (K == kGaussian) {
+        g = __builtin_amdgcn_exp2f(-0.72134752044448170368f * u * u);  // exp(-u^2/2)
+        dg = -u * g;
+        return;
+    } else {
+        const bool in = fabsf(d) <= H;
+        const float a = fminf(fabsf(u), 1.0f);
+        const float sg = u < 0.0f ? -1.0f : (u > 0.0f ? 1.0f : 0.0f);
+        float v, w;
+        if constexpr (K == kUniform) {
+            v = 1.0f;
+            w = 0.0f;
+        } else if constexpr (K == kTriangular) {
+            v = 1.0f - a;
+            w = -sg;
+        } else if constexpr (K == kEpanechnikov) {
+            v = 1.0f - a * a;
+            w = -2.0f * sg * a;
+        } else if constexpr (K == kQuartic) {
+            const float q = 1.0f - a * a;
+            v = q * q;
+            w = -4.0f * sg * a * q;
+        } else if constexpr (K == kTriweight) {
+            const float q = 1.0f - a * a;
+            v = q * q * q;
+            w = -6.0f * sg * a * q * q;
+        } else if constexpr (K == kTricube) {
+            const float q = 1.0f - a * a * a;
+            v = q * q * q;
+            w = -9.0f * sg * a * a * q * q;
+        } else {  // cosine: g = cos(pi u / 2), g' = -(pi/2) sin(pi u / 2)
+            v = __builtin_amdgcn_cosf(a * 0.25f);
+            w = -1.57079632679489662f * sg * __builtin_amdgcn_sinf(a * 0.25f);
+        }
+        g = in ? v : 0.0f;
+        dg = in ? w : 0.0f;
+    }
+}
+
+struct VjpLaunch {
+    const float2 *pts;
+    int64_t n;
+    const float *gbar;  // [ny][nx]
+    int nx, ny;
+    float Hx, Hy, ix, iy;  // bandwidths and their inverses (grid units)
+    float fx, fy;          // output scales for dL/dX and dL/dY (host chain rule)
+    float *grad;           // [n][2] or null
+    double *part;          // [gridDim.x][3]: per-workgroup sums of Ux, Uy, Q
+};
+
+template <int K>
+__global__ __launch_bounds__(kAdjThreads) void vjp_kernel(VjpLaunch p) {
+    __shared__ float gs[kRowChunk][kStrip];
+    __shared__ float box[4][kAdjThreads / 64];
+    __shared__ double red[3][kAdjThreads];
+
+    const int tid = threadIdx.x;
+    const int64_t q = (int64_t)blockIdx.x * kAdjThreads + tid;
+    const bool active = q < p.n;
+    const float2 pt = active ? p.pts[q] : make_float2(kFarAdj, kFarAdj);
+
+    // Reach of this workgroup's points (compact kernels only).
+    int cx0 = 0, cx1 = p.nx - 1, ry0 = 0, ry1 = p.ny - 1;
+    if constexpr (K != kGaussian) {
+        float lox = active ? pt.x : 3.0e38f, hix = active ? pt.x : -3.0e38f;
+        float loy = active ? pt.y : 3.0e38f, hiy = active ? pt.y : -3.0e38f;
+        for (int off = 32; off > 0; off >>= 1) {
+            lox = fminf(lox, __shfl_xor(lox, off));
+            hix = fmaxf(hix, __shfl_xor(hix, off));
+            loy = fminf(loy, __shfl_xor(loy, off));
+            hiy = fmaxf(hiy, __shfl_xor(hiy, off));
+        }
+        if ((tid & 63) == 0) {
+            box[0][tid >> 6] = lox;
+            box[1][tid >> 6] = hix;
+            box[2][tid >> 6] = loy;
+            box[3][tid >> 6] = hiy;
+        }
+        __syncthreads();
+        for (int w = 0; w < kAdjThreads / 64; ++w) {
+            lox = fminf(lox, box[0][w]);
+            hix = fmaxf(hix, box[1][w]);
+            loy = fminf(loy, box[2][w]);
+            hiy = fmaxf(hiy, box[3][w]);
+        }
+        // Nodes within H of the box (clamped to the grid; empty if none).
+        cx0 = (int)fmaxf(0.0f, ceilf(lox - p.Hx));
+        cx1 = (int)fminf((float)(p.nx - 1), floorf(hix + p.Hx));
+        ry0 = (int)fmaxf(0.0f, ceilf(loy - p.Hy));
+        ry1 = (int)fminf((float)(p.ny - 1), floorf(hiy + p.Hy));
+    }
+
+    float Tx = 0.0f, Ty = 0.0f, Ux = 0.0f, Uy = 0.0f, Q = 0.0f;
+    if (cx0 <= cx1 && ry0 <= ry1) {
+        const int s0 = cx0 / kStrip, s1 = cx1 / kStrip;
+        for (int s = s0; s <= s1; ++s) {
+            const int i0 = s * kStrip;
+            // Column factors of this thread's point for the strip.
+            float gx[kStrip], dgx[kStrip], sdgx[kStrip];
+#pragma unroll
+            for (int c = 0; c < kStrip; ++c) {
+                const float d = (float)(i0 + c) - pt.x;
+                float g, dg;
+                gdg<K>(d, p.Hx, p.ix, g, dg);
+                const bool in = i0 + c < p.nx;
+                gx[c] = in ? g : 0.0f;
+                dgx[c] = in ? dg : 0.0f;
+                sdgx[c] = in ? d * p.ix * dg : 0.0f;
+            }
+            for (int r0 = ry0; r0 <= ry1; r0 += kRowChunk) {
+                const int rows = min(kRowChunk, ry1 - r0 + 1);
+                __syncthreads();  // previous chunk consumed
+                for (int e = tid; e < rows * kStrip; e += kAdjThreads) {
+                    const int rr = e / kStrip, cc = e % kStrip;
+                    const int col = i0 + cc;
+                    gs[rr][cc] = col < p.nx ? p.gbar[(int64_t)(r0 + rr) * p.nx + col] : 0.0f;
+                }
+                __syncthreads();
+                for (int rr = 0; rr < rows; ++rr) {
+                    float a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+#pragma unroll
+                    for (int c = 0; c < kStrip; c += 4) {
+                        const float4 gb = *reinterpret_cast<const float4 *>(&gs[rr][c]);
+                        a1 = fmaf(gb.x, dgx[c], a1);
+                        a2 = fmaf(gb.x, gx[c], a2);
+                        a3 = fmaf(gb.x, sdgx[c], a3);
+                        a1 = fmaf(gb.y, dgx[c + 1], a1);
+                        a2 = fmaf(gb.y, gx[c + 1], a2);
+                        a3 = fmaf(gb.y, sdgx[c + 1], a3);
+                        a1 = fmaf(gb.z, dgx[c + 2], a1);
+                        a2 = fmaf(gb.z, gx[c + 2], a2);
+                        a3 = fmaf(gb.z, sdgx[c + 2], a3);
+                        a1 = fmaf(gb.w, dgx[c + 3], a1);
+                        a2 = fmaf(gb.w, gx[c + 3], a2);
+                        a3 = fmaf(gb.w, sdgx[c + 3], a3);
+                    }
+                    const float dy = (float)(r0 + rr) - pt.y;
+                    float gy, dgy;
+                    gdg<K>(dy, p.Hy, p.iy, gy, dgy);
+                    Tx = fmaf(gy, a1, Tx);
+                    Ux = fmaf(gy, a3, Ux);
+                    Q = fmaf(gy, a2, Q);
+                    Ty = fmaf(dgy, a2, Ty);
+                    Uy = fmaf(dy * p.iy * dgy, a2, Uy);
+                }
+            }
+        }
+    }
+    if (active && p.grad != nullptr) {
+        p.grad[2 * q] = p.fx * Tx;
+        p.grad[2 * q + 1] = p.fy * Ty;
+    }
+    // Bandwidth sums: FP64 tree over the workgroup, fixed order.
+    red[0][tid] = active ? (double)Ux : 0.0;
+    red[1][tid] = active ? (double)Uy : 0.0;
+    red[2][tid] = active ? (double)Q : 0.0;
+    __syncthreads();
+    for (int w = kAdjThreads / 2; w > 0; w >>= 1) {
+        if (tid < w) {
+            red[0][tid] += red[0][tid + w];
+            red[1][tid] += red[1][tid + w];
+            red[2][tid] += red[2][tid + w];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        p.part[3 * blockIdx.x + 0] = red[0][0];
+        p.part[3 * blockIdx.x + 1] = red[1][0];
+        p.part[3 * blockIdx.x + 2] = red[2][0];
+    }
+}
+
+struct LscvLaunch {
+    const float2 *pts;
+    int64_t n;
+    float ix2, iy2;   // 1/H^2 (grid units)
+    double *part;     // [gridDim.x][6]
+};
+
+// Per pair and axis: squared scaled distance w = (d/H)^2 and the four factors
+// kb, kb + u kb', g, g + u g' (without normalising constants).
+template <int K>
+__device__ __forceinline__ void lscv_axis(float d, float i2, float &kb, float &kbd, float &g, float &gd) {
+    const float w = fminf(d * d * i2, 1.0e4f);  // u^2, capped: every factor is 0 there and stays finite
+    if constexpr (K == kGaussian) {
+        kb = __builtin_amdgcn_exp2f(-0.36067376022224085f * w);  // exp(-u^2/4)
+        g = kb * kb;                                              // exp(-u^2/2)
+        kbd = kb * fmaf(-0.5f, w, 1.0f);                          // (1 - u^2/2) kb
+        gd = g * (1.0f - w);                                      // (1 - u^2) g
+    } else {  // Epanechnikov: kb ~ (2-a)^3 (a^2 + 6a + 4) on a <= 2, g = 1 - u^2 on a <= 1
+        const float a = sqrtf(w);
+        const float b = fmaxf(2.0f - a, 0.0f);
+        const float b2 = b * b;
+        kb = b2 * b * (w + 6.0f * a + 4.0f);
+        kbd = kb - 5.0f * w * (a + 4.0f) * b2;
+        const bool in = w <= 1.0f;
+        g = in ? 1.0f - w : 0.0f;
+        gd = in ? 1.0f - 3.0f * w : 0.0f;
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(kAdjThreads) void lscv_kernel(LscvLaunch p) {
+    __shared__ float2 qs[kAdjThreads];
+    __shared__ double red[6][kAdjThreads];
+    const int tid = threadIdx.x;
+    const int64_t pi = (int64_t)blockIdx.x * kAdjThreads + tid;
+    const bool active = pi < p.n;
+    const float2 me = active ? p.pts[pi] : make_float2(0.0f, 0.0f);
+    double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t base = 0; base < p.n; base += kAdjThreads) {
+        __syncthreads();
+        const int64_t qi = base + tid;
+        qs[tid] = qi < p.n ? p.pts[qi] : make_float2(kFarAdj, kFarAdj);
+        __syncthreads();
+        float sa = 0.0f, sax = 0.0f, say = 0.0f, sb = 0.0f, sbx = 0.0f, sby = 0.0f;
+        for (int k = 0; k < kAdjThreads; ++k) {
+            const float2 o = qs[k];
+            float kbx, kbdx, gx, gdx, kby, kbdy, gy, gdy;
+            lscv_axis<K>(me.x - o.x, p.ix2, kbx, kbdx, gx, gdx);
+            lscv_axis<K>(me.y - o.y, p.iy2, kby, kbdy, gy, gdy);
+            sa = fmaf(kbx, kby, sa);
+            sax = fmaf(kbdx, kby, sax);
+            say = fmaf(kbx, kbdy, say);
+            sb = fmaf(gx, gy, sb);
+            sbx = fmaf(gdx, gy, sbx);
+            sby = fmaf(gx, gdy, sby);
+        }
+        S[0] += sa;
+        S[1] += sax;
+        S[2] += say;
+        S[3] += sb;
+        S[4] += sbx;
+        S[5] += sby;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) red[k][tid] = active ? S[k] : 0.0;
+    __syncthreads();
+    for (int w = kAdjThreads / 2; w > 0; w >>= 1) {
+        if (tid < w) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) red[k][tid] += red[k][tid + w];
+        }
+        __syncthreads();
+    }
+    if (tid < 6) p.part[6 * blockIdx.x + tid] = red[tid][0];
+}
+
+}  // namespace
+
+int64_t vjp_blocks(int64_t n) { return (n + kAdjThreads - 1) / kAdjThreads; }
+
+hipError_t launch_vjp(const float2 *pts, int64_t n, int kernel_id, float Hx, float Hy, const float *gbar, int nx,
+                      int ny, float fx, float fy, float *grad, double *part, hipStream_t stream) {
+    VjpLaunch p{pts, n, gbar, nx, ny, Hx, Hy, (float)(1.0 / (double)Hx), (float)(1.0 / (double)Hy), fx, fy, grad,
+                part};
+    const dim3 grid((unsigned)vjp_blocks(n));
+    switch (kernel_id) {
+    case kUniform: hipLaunchKernelGGL(vjp_kernel<kUniform>, grid, dim3(kAdjThreads), 0, stream, p); break;
+    case kTriangular: hipLaunchKernelGGL(vjp_kernel<kTriangular>, grid, dim3(kAdjThreads), 0, stream, p); break;
+    case kEpanechnikov: hipLaunchKernelGGL(vjp_kernel<kEpanechnikov>, grid, dim3(kAdjThreads), 0, stream, p); break;
+    case kQuartic: hipLaunchKernelGGL(vjp_kernel<kQuartic>, grid, dim3(kAdjThreads), 0, stream, p); break;
+    case kTriweight: hipLaunchKernelGGL(vjp_kernel<kTriweight>, grid, dim3(kAdjThreads), 0, stream, p); break;
+    case kTricube: hipLaunchKernelGGL(vjp_kernel<kTricube>, grid, dim3(kAdjThreads), 0, stream, p); break;
+    case kGaussian: hipLaunchKernelGGL(vjp_kernel<kGaussian>, grid, dim3(kAdjThreads), 0, stream, p); break;
+    case kCosine: hipLaunchKernelGGL(vjp_kernel<kCosine>, grid, dim3(kAdjThreads), 0, stream, p); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int64_t lscv_blocks(int64_t n) { return (n + kAdjThreads - 1) / kAdjThreads; }
+
+hipError_t launch_lscv(const float2 *pts, int64_t n, int kernel_id, float Hx, float Hy, double *part,
+                       hipStream_t stream) {
+    LscvLaunch p{pts, n, (float)(1.0 / ((double)Hx * Hx)), (float)(1.0 / ((double)Hy * Hy)), part};
+    const dim3 grid((unsigned)lscv_blocks(n));
+    if (kernel_id == kGaussian)
+        hipLaunchKernelGGL(lscv_kernel<kGaussian>, grid, dim3(kAdjThreads), 0, stream, p);
+    else if (kernel_id == kEpanechnikov)
+        hipLaunchKernelGGL(lscv_kernel<kEpanechnikov>, grid, dim3(kAdjThreads), 0, stream, p);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace kde

@@ -12,6 +12,7 @@
 #include <new>
 #include <string>
 #include <utility>
+#include <vector>
 
 #include "kde_internal.h"
 
@@ -225,27 +226,100 @@ int kde_eval_batched(const kde_map *maps, int32_t n_maps, uint32_t flags, void *
 
 int kde_backward(const float *points, int64_t n, int32_t kernel_id, double hx, double hy, const kde_grid *g,
                  const float *grad_out, float *grad_points, double *grad_h, uint32_t flags, void *stream) {
-    (void)stream;
-    (void)grad_points;
-    (void)grad_h;
-    int st = check_map(points, n, kernel_id, hx, hy, g, "kde_backward");
-    if (st != KDE_OK) return st;
-    if (grad_out == nullptr) return fail(KDE_EINVAL, "kde_backward: grad_out is NULL");
-    if (flags & ~KDE_RAW_SUM) return fail(KDE_EINVAL, "kde_backward: unknown flags 0x%x", flags);
-    return fail(KDE_EUNSUPPORTED, "kde_backward: not available");
+    try {
+        int st = check_map(points, n, kernel_id, hx, hy, g, "kde_backward");
+        if (st != KDE_OK) return st;
+        if (grad_out == nullptr) return fail(KDE_EINVAL, "kde_backward: grad_out is NULL");
+        if (flags & ~(KDE_RAW_SUM | KDE_GRID_UNIT_GRADS))
+            return fail(KDE_EINVAL, "kde_backward: unknown flags 0x%x", flags);
+        if (grad_points == nullptr && grad_h == nullptr) return KDE_OK;
+        if (n == 0) {
+            if (grad_h) grad_h[0] = grad_h[1] = 0.0;
+            return KDE_OK;
+        }
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const bool raw = (flags & KDE_RAW_SUM) != 0;
+        const float Hx = (float)(hx / g->dx), Hy = (float)(hy / g->dy);
+        const double c = kde::kernel_norm(kernel_id);
+        // out = sigma * S: sigma = c^2 (raw) or c^2 / (n hx hy) (density).
+        const double sigma = raw ? c * c : c * c / ((double)n * hx * hy);
+        // dL/dX_p = sigma * (-1/Hx) * Tx_p; world units divide by dx once more.
+        const bool grid_units = (flags & KDE_GRID_UNIT_GRADS) != 0;
+        const double fx = -sigma / (double)Hx / (grid_units ? 1.0 : g->dx);
+        const double fy = -sigma / (double)Hy / (grid_units ? 1.0 : g->dy);
+        const int64_t blocks = kde::vjp_blocks(n);
+        void *ws = nullptr;
+        st = get_workspace(s, (size_t)blocks * 3 * sizeof(double), &ws);
+        if (st != KDE_OK) return st;
+        hipError_t e = kde::launch_vjp(reinterpret_cast<const float2 *>(points), n, kernel_id, Hx, Hy, grad_out,
+                                       g->nx, g->ny, (float)fx, (float)fy, grad_points, static_cast<double *>(ws), s);
+        if (e != hipSuccess) return hip_fail(e, "kde_backward");
+        if (grad_h != nullptr) {
+            std::vector<double> part((size_t)blocks * 3);
+            e = hipMemcpyAsync(part.data(), ws, part.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return hip_fail(e, "kde_backward");
+            double ux = 0.0, uy = 0.0, q = 0.0;
+            for (int64_t b = 0; b < blocks; ++b) {
+                ux += part[3 * b];
+                uy += part[3 * b + 1];
+                q += part[3 * b + 2];
+            }
+            // d out/dhx = sigma/dx * dS/dHx (+ dsigma/dhx S for densities); with
+            // Hx dS/dHx = -sum Gbar s g'(s) g(t) = -Ux and dsigma/dhx = -sigma/hx.
+            grad_h[0] = -sigma * ux / ((double)Hx * g->dx) - (raw ? 0.0 : sigma * q / hx);
+            grad_h[1] = -sigma * uy / ((double)Hy * g->dy) - (raw ? 0.0 : sigma * q / hy);
+        }
+        return KDE_OK;
+    } catch (...) {
+        return fail(KDE_EHIP, "kde_backward: internal error");
+    }
 }
 
 int kde_lscv(const float *points, int64_t n, int32_t kernel_id, double hx, double hy, const kde_grid *g, double *value,
              double *grad_h, void *stream) {
-    (void)stream;
-    (void)grad_h;
-    int st = check_map(points, n, kernel_id, hx, hy, g, "kde_lscv");
-    if (st != KDE_OK) return st;
-    if (n < 2) return fail(KDE_EINVAL, "kde_lscv: need n >= 2");
-    if (value == nullptr) return fail(KDE_EINVAL, "kde_lscv: value is NULL");
-    if (kernel_id != KDE_GAUSSIAN && kernel_id != KDE_EPANECHNIKOV)
-        return fail(KDE_EUNSUPPORTED, "kde_lscv: kernel %d not supported", (int)kernel_id);
-    return fail(KDE_EUNSUPPORTED, "kde_lscv: not available");
+    try {
+        int st = check_map(points, n, kernel_id, hx, hy, g, "kde_lscv");
+        if (st != KDE_OK) return st;
+        if (n < 2) return fail(KDE_EINVAL, "kde_lscv: need n >= 2");
+        if (value == nullptr) return fail(KDE_EINVAL, "kde_lscv: value is NULL");
+        if (kernel_id != KDE_GAUSSIAN && kernel_id != KDE_EPANECHNIKOV)
+            return fail(KDE_EUNSUPPORTED, "kde_lscv: kernel %d not supported (Gaussian and Epanechnikov are)",
+                        (int)kernel_id);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const float Hx = (float)(hx / g->dx), Hy = (float)(hy / g->dy);
+        const int64_t blocks = kde::lscv_blocks(n);
+        void *ws = nullptr;
+        st = get_workspace(s, (size_t)blocks * 6 * sizeof(double), &ws);
+        if (st != KDE_OK) return st;
+        hipError_t e = kde::launch_lscv(reinterpret_cast<const float2 *>(points), n, kernel_id, Hx, Hy,
+                                        static_cast<double *>(ws), s);
+        if (e != hipSuccess) return hip_fail(e, "kde_lscv");
+        std::vector<double> part((size_t)blocks * 6);
+        e = hipMemcpyAsync(part.data(), ws, part.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "kde_lscv");
+        double S[6] = {0, 0, 0, 0, 0, 0};
+        for (int64_t b = 0; b < blocks; ++b)
+            for (int k = 0; k < 6; ++k) S[k] += part[6 * b + k];
+        // Remove the p == q terms of the leave-one-out sums (each exactly 1).
+        const double nn = (double)n;
+        S[3] -= nn;
+        S[4] -= nn;
+        S[5] -= nn;
+        const double pi = 3.14159265358979323846;
+        const double c = kde::kernel_norm(kernel_id);  // k = c g
+        const double cb = kernel_id == KDE_GAUSSIAN ? 1.0 / (2.0 * std::sqrt(pi)) : 3.0 / 160.0;  // kbar = cb kb
+        const double ca = cb * cb / (nn * nn), cbb = 2.0 * c * c / (nn * (nn - 1.0));
+        *value = (ca * S[0] - cbb * S[3]) / (hx * hy);
+        if (grad_h != nullptr) {
+            grad_h[0] = (-ca * S[1] + cbb * S[4]) / (hx * hx * hy);
+            grad_h[1] = (-ca * S[2] + cbb * S[5]) / (hx * hy * hy);
+        }
+        return KDE_OK;
+    } catch (...) {
+        return fail(KDE_EHIP, "kde_lscv: internal error");
+    }
 }
 
 const char *kde_last_error(void) { return g_err.c_str(); }

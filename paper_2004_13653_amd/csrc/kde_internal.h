@@ -59,6 +59,17 @@ size_t direct_workspace_bytes(const MapArgs &a);
 hipError_t launch_sep(const MapArgs &a, int precision, void *ws, hipStream_t stream);
 size_t sep_workspace_bytes(const MapArgs &a, int precision);
 
+// Adjoints.  launch_vjp writes grad[n][2] = (fx Tx_p, fy Ty_p) (if grad is not
+// null) and per-workgroup FP64 sums (Ux, Uy, Q) into part[vjp_blocks(n)][3];
+// launch_lscv writes per-workgroup FP64 sums (SA, SAX, SAY, SB, SBX, SBY) into
+// part[lscv_blocks(n)][6].  See kde_adjoint.hip for the definitions.
+int64_t vjp_blocks(int64_t n);
+hipError_t launch_vjp(const float2 *pts, int64_t n, int kernel_id, float Hx, float Hy, const float *gbar, int nx,
+                      int ny, float fx, float fy, float *grad, double *part, hipStream_t stream);
+int64_t lscv_blocks(int64_t n);
+hipError_t launch_lscv(const float2 *pts, int64_t n, int kernel_id, float Hx, float Hy, double *part,
+                       hipStream_t stream);
+
 // out[i] = scale * sum_{s < splits} part[s * plane + i], summed in split order.
 hipError_t launch_reduce_splits(const float *part, int splits, int64_t plane, float scale, float *out,
                                 hipStream_t stream);

@@ -13,10 +13,11 @@
 // Workgroup: 4 waves, a 256 x 256 output tile (wave w owns the 128 x 128 block
 // (w >> 1, w & 1): 4 x 4 MFMA tiles, 256 accumulator registers per lane).  The
 // points stream through in chunks of KC: for each chunk the workgroup writes the
-// 256 x KC slices of Gy and Gx into LDS in the exact lane order the MFMA operand
-// registers use (one 16-byte LDS word per lane and MFMA tile, conflict-free
-// linear reads), double-buffered so that factor generation for chunk c + 1
-// (VALU, v_exp_f32) and the MFMAs of chunk c come from the same basic block.
+// 256 x KC slices of Gy and Gx into LDS as row-major rows of 16-byte words (8
+// factors each, one pad word per row so that neither the stores nor the MFMA
+// fragment reads conflict on LDS banks), double-buffered in two arrays so that
+// factor generation for chunk c + 1 (VALU) and the MFMAs of chunk c share a basic
+// block and can interleave.
 //
 // Gaussian factors are evaluated tile-relative: with a = sqrt(log2(e)/2)/H,
 // g = exp2(-(m a - (X - x0) a)^2) for node x0 + m, keeping every argument small.
@@ -29,6 +30,7 @@
 #include "kde_internal.h"
 
 #include <algorithm>
+#include <cmath>
 
 namespace kde {
 
@@ -37,6 +39,7 @@ namespace {
 constexpr int kTile = 256;     // output tile side (rows and columns)
 constexpr int kThreadsSep = 256;
 constexpr float kFar = 1.0e30f;
+constexpr float kMaxRecurScale = 0.8f;
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -67,6 +70,7 @@ struct SepLaunch {
     int64_t n;
     int64_t per_split;  // points per split, multiple of the chunk size
     float ax, ay;       // Gaussian argument scales sqrt(log2(e)/2)/H
+    float kappa_x, kappa_y;  // Gaussian run ratio exp2(-2 a^2)
     float Hx, Hy;       // compact kernels: support half-widths
     float ix, iy;       // compact kernels: 1/H
     int nx, ny, tiles_x;
@@ -152,92 +156,156 @@ __device__ __forceinline__ f32x16 mfma(uint4 a, uint4 b, f32x16 c) {
 template <int P>
 struct SepConfig {
     static constexpr bool kSplit = PrecTraits<P>::kSplit;
-    static constexpr int KC = kSplit ? 32 : 64;         // points per chunk
-    static constexpr int G = KC / 8;                    // 8-point groups per chunk
-    static constexpr int KK = KC / 16;                  // MFMA k-steps per chunk
-    static constexpr int kWords = (kTile / 32) * KK * 64;  // 16-byte LDS words per operand slice
-    static constexpr int kRowsPerThread = G;            // rows (and columns) each thread generates
-    static constexpr int kRowStride = kTile / G;
+#ifndef KDE_SEP_KC
+    static constexpr int KC = kSplit ? 32 : 64;            // points per chunk
+#else
+    static constexpr int KC = KDE_SEP_KC;
+#endif
+    static constexpr int G = KC / 8;                       // 8-point groups per chunk
+    static constexpr int KK = KC / 16;                     // MFMA k-steps per chunk
+    // Operand slice in LDS: row-major [kTile rows][G + 1] 16-byte words (8 factors
+    // each); the one-word pad per row makes both the generators' stores (8
+    // consecutive rows per thread, lanes varying the point group) and the MFMA
+    // fragment reads (lanes varying the row) hit distinct bank groups.
+    static constexpr int kRowWords = G + 1;
+    static constexpr int kWords = kTile * kRowWords;  // 16-byte LDS words per operand slice
+    static constexpr int R = G;                            // consecutive rows (and columns) per thread
 };
 
-// Generates chunk `c` of this split into LDS buffer words: A (rows, from Y) and B
-// (columns, from X), hi and optionally lo.
-template <int K, int P>
-__device__ __forceinline__ void generate_chunk(const SepLaunch &p, int64_t beg, int64_t end, int64_t c, int tid,
-                                               float x0, float y0, const float (&mrow)[SepConfig<P>::G],
-                                               const float (&mcol)[SepConfig<P>::G], uint4 *Ahi, uint4 *Bhi,
-                                               uint4 *Alo, uint4 *Blo) {
-    using Cfg = SepConfig<P>;
-    constexpr bool kBf16 = PrecTraits<P>::kBf16;
-    const int g = tid % Cfg::G, s = tid / Cfg::G;
-    const int64_t q0 = beg + c * Cfg::KC + 8 * g;
-    float px[8], py[8];
+// The 8 points of group g in chunk c.  Indices past the split end load the
+// split's last point and are pushed far away (all their factors are 0); adding
+// the offset instead of selecting keeps every load unconditional, so the loads
+// are issued a whole chunk ahead without branches.
+__device__ __forceinline__ void load_points(const SepLaunch &p, int64_t q0, int64_t end, float2 (&v)[8]) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         const int64_t q = q0 + k;
-        float2 v = make_float2(kFar, kFar);
-        if (q < end) v = p.pts[q];
-        if constexpr (K == kGaussian) {
-            px[k] = (v.x - x0) * p.ax;
-            py[k] = (v.y - y0) * p.ay;
-        } else {
-            px[k] = v.x - x0;
-            py[k] = v.y - y0;
-        }
+        const float2 w = p.pts[q < end ? q : end - 1];
+        const float off = q < end ? 0.0f : kFar;
+        v[k] = make_float2(w.x + off, w.y + off);
     }
-    const int kk = g >> 1, hh = g & 1;
-#pragma unroll
-    for (int r = 0; r < Cfg::G; ++r) {
-        const int m = s + Cfg::kRowStride * r;  // row (A) and column (B) index within the tile
-        const int word = ((m >> 5) * Cfg::KK + kk) * 64 + (m & 31) + 32 * hh;
-        float va[8], vb[8];
+}
+
+// Writes one row (A) or column (B) of 8 factors: hi, and lo for splits.
+template <int P>
+__device__ __forceinline__ void put8(const float (&v)[8], uint4 *hi, uint4 *lo, int word) {
+    constexpr bool kBf16 = PrecTraits<P>::kBf16;
+    const uint4 h = pack8<kBf16>(v);
+    hi[word] = h;
+    if constexpr (PrecTraits<P>::kSplit) {
+        float l[8];
+        residual8<kBf16>(v, h, l);
+        lo[word] = pack8<kBf16>(l);
+    }
+}
+
+// Factors of one operand slice for this thread: R consecutive nodes m0 .. m0+R-1
+// (rows of A or columns of B) against the 8 points `pr` (tile-relative; Gaussian
+// scaled by a).  kRecur (Gaussian, a <= 0.8): one exp2 for g(m0) and one for the
+// ratio rho = g(m0+1)/g(m0) = exp2(-2 a t0 - a^2) per point, then
+// g(m+1) = g(m) rho(m), rho(m+1) = rho(m) kappa with kappa = exp2(-2 a^2).
+// With a <= 0.8 and R <= 8, a start value that underflows implies every value of
+// the run is below 2^-31 of the peak, and rho is clamped to stay finite, so the
+// run never turns a zero into a non-zero or produces NaN.
+template <int K, int P, bool kRecur>
+__device__ __forceinline__ void gen_slice(const float (&pr)[8], float m0, float a, float kappa, float H,
+                                          float inv, uint4 *hi, uint4 *lo, int word0, int stride) {
+    constexpr int R = SepConfig<P>::R;
+    if constexpr (kRecur) {
+        float e[8], rho[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            va[k] = sep_factor<K>(mrow[r], py[k], p.Hy, p.iy);
-            vb[k] = sep_factor<K>(mcol[r], px[k], p.Hx, p.ix);
+            const float t0 = m0 - pr[k];
+            e[k] = __builtin_amdgcn_exp2f(-t0 * t0);
+            rho[k] = __builtin_amdgcn_exp2f(fminf(fmaf(-2.0f * a, t0, -a * a), 126.0f));
         }
-        const uint4 ha = pack8<kBf16>(va), hb = pack8<kBf16>(vb);
-        Ahi[word] = ha;
-        Bhi[word] = hb;
-        if constexpr (Cfg::kSplit) {
-            float la[8], lb[8];
-            residual8<kBf16>(va, ha, la);
-            residual8<kBf16>(vb, hb, lb);
-            Alo[word] = pack8<kBf16>(la);
-            Blo[word] = pack8<kBf16>(lb);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            put8<P>(e, hi, lo, word0 + r * stride);
+            if (r + 1 < R) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) e[k] *= rho[k];
+            }
+            if (r + 2 < R) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) rho[k] *= kappa;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const float m = K == kGaussian ? m0 + (float)r * a : m0 + (float)r;
+            float v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = sep_factor<K>(m, pr[k], H, inv);
+            put8<P>(v, hi, lo, word0 + r * stride);
         }
     }
 }
 
-template <int K, int P>
+// Generates one chunk (8 points per thread, given) into an LDS buffer: A (rows,
+// from Y) and B (columns, from X).
+template <int K, int P, bool kRecur>
+__device__ __forceinline__ void generate_chunk(const SepLaunch &p, const float2 (&v)[8], int tid, float x0,
+                                               float y0, float mrow0, float mcol0, uint4 *Ahi, uint4 *Bhi,
+                                               uint4 *Alo, uint4 *Blo) {
+    using Cfg = SepConfig<P>;
+    const int g = tid % Cfg::G, s = tid / Cfg::G;
+    const int m = Cfg::R * s;  // first row / column of this thread; R consecutive ones, within one 32-block
+    const int word0 = m * Cfg::kRowWords + g;
+    float px[8], py[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if constexpr (K == kGaussian) {
+            px[k] = (v[k].x - x0) * p.ax;
+            py[k] = (v[k].y - y0) * p.ay;
+        } else {
+            px[k] = v[k].x - x0;
+            py[k] = v[k].y - y0;
+        }
+    }
+    const float ga_y = K == kGaussian ? p.ay : 1.0f, ga_x = K == kGaussian ? p.ax : 1.0f;
+    gen_slice<K, P, kRecur>(py, mrow0, ga_y, p.kappa_y, p.Hy, p.iy, Ahi, Alo, word0, Cfg::kRowWords);
+    gen_slice<K, P, kRecur>(px, mcol0, ga_x, p.kappa_x, p.Hx, p.ix, Bhi, Blo, word0, Cfg::kRowWords);
+}
+
+// Scheduling hint for the chunk loop: spread the factor generation (VALU, LDS
+// writes) and the fragment reads between the MFMAs, so the one wave per SIMD keeps
+// the matrix core busy while it computes the next chunk's factors.
+template <int NM, int NV, int KK>
+__device__ __forceinline__ void interleave_hint() {
+    constexpr int per_kk = NM / KK;  // MFMAs per k-step
+    __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);  // fragments of the first k-step
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x002, NV, 0);  // VALU (factor generation)
+        if (i % per_kk < 8 && i < NM - per_kk) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // next fragments
+        if (i % 4 == 3) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // factor stores
+    }
+}
+
+template <int K, int P, bool kRecur>
 __global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p) {
     using Cfg = SepConfig<P>;
     constexpr bool kBf16 = PrecTraits<P>::kBf16;
     constexpr int W = Cfg::kWords;
     constexpr int kOps = Cfg::kSplit ? 4 : 2;  // operand slices per buffer
-    __shared__ uint4 lds[2 * kOps * W];
+    // Two separate LDS buffers, so the compiler can see that the factor stores of
+    // one chunk never alias the fragment reads of the other and may interleave them.
+    __shared__ uint4 lds0[kOps * W];
+    __shared__ uint4 lds1[kOps * W];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int tx = blockIdx.x % p.tiles_x, ty = blockIdx.x / p.tiles_x;
     const int col0 = tx * kTile, row0 = ty * kTile;
     const float x0 = (float)col0, y0 = (float)row0;
 
-    // Node offsets of the rows/columns this thread generates.
-    float mrow[Cfg::G], mcol[Cfg::G];
-    {
-        const int s = tid / Cfg::G;
-#pragma unroll
-        for (int r = 0; r < Cfg::G; ++r) {
-            const float m = (float)(s + Cfg::kRowStride * r);
-            if constexpr (K == kGaussian) {
-                mrow[r] = m * p.ay;
-                mcol[r] = m * p.ax;
-            } else {
-                mrow[r] = m;
-                mcol[r] = m;
-            }
-        }
-    }
+    // First node offset of the rows / columns this thread generates (Gaussian:
+    // pre-multiplied by a).
+    const float m0 = (float)(Cfg::R * (tid / Cfg::G));
+    const float mrow0 = K == kGaussian ? m0 * p.ay : m0;
+    const float mcol0 = K == kGaussian ? m0 * p.ax : m0;
 
     f32x16 acc[4][4];
 #pragma unroll
@@ -250,39 +318,34 @@ __global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p) {
     const int64_t beg = (int64_t)blockIdx.y * p.per_split;
     const int64_t end = min(p.n, beg + p.per_split);
     const int64_t nch = (end - beg + Cfg::KC - 1) / Cfg::KC;
+    const int64_t qg = beg + 8 * (tid % Cfg::G);  // first point of this thread's group in chunk 0
+    const int ta0 = 4 * (wave >> 1), tb0 = 4 * (wave & 1);  // first MFMA row / column tile of this wave
+    // Fragment word of lane `lane` for MFMA tile t (32 rows) and k-step kk: row
+    // 32 t + lane % 32, point group 2 kk + lane / 32.
+    const int frag0 = (lane & 31) * Cfg::kRowWords + (lane >> 5);
+    auto frag = [&](int t, int kk) { return frag0 + 32 * t * Cfg::kRowWords + 2 * kk; };
 
-    auto slices = [&](int buf, uint4 *&Ah, uint4 *&Bh, uint4 *&Al, uint4 *&Bl) {
-        uint4 *base = lds + buf * kOps * W;
-        Ah = base;
-        Bh = base + W;
-        Al = Cfg::kSplit ? base + 2 * W : nullptr;
-        Bl = Cfg::kSplit ? base + 3 * W : nullptr;
-    };
-
-    {
-        uint4 *Ah, *Bh, *Al, *Bl;
-        slices(0, Ah, Bh, Al, Bl);
-        generate_chunk<K, P>(p, beg, end, 0, tid, x0, y0, mrow, mcol, Ah, Bh, Al, Bl);
-    }
+    float2 pts[8], nxt[8];
+    load_points(p, qg, end, pts);
+    load_points(p, qg + Cfg::KC, end, nxt);
+    generate_chunk<K, P, kRecur>(p, pts, tid, x0, y0, mrow0, mcol0, lds0, lds0 + W, lds0 + 2 * W, lds0 + 3 * W);
     __syncthreads();
 
-    const int ta0 = 4 * (wave >> 1), tb0 = 4 * (wave & 1);  // first MFMA row / column tile of this wave
-    for (int64_t c = 0; c < nch; ++c) {
-        const int cur = (int)(c & 1);
-        {
-            uint4 *Ah, *Bh, *Al, *Bl;
-            slices(cur ^ 1, Ah, Bh, Al, Bl);
-            generate_chunk<K, P>(p, beg, end, c + 1, tid, x0, y0, mrow, mcol, Ah, Bh, Al, Bl);
-        }
-        uint4 *Ah, *Bh, *Al, *Bl;
-        slices(cur, Ah, Bh, Al, Bl);
+    // One chunk: generate chunk c + 1 into `gen` while the MFMAs consume chunk c
+    // from `use`.
+    auto step = [&](int64_t c, uint4 *gen, const uint4 *use) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) pts[k] = nxt[k];
+        load_points(p, qg + (c + 2) * Cfg::KC, end, nxt);  // consumed one chunk later
+        generate_chunk<K, P, kRecur>(p, pts, tid, x0, y0, mrow0, mcol0, gen, gen + W, gen + 2 * W, gen + 3 * W);
+        const uint4 *Ah = use, *Bh = use + W, *Al = use + 2 * W, *Bl = use + 3 * W;
 #pragma unroll
         for (int kk = 0; kk < Cfg::KK; ++kk) {
             uint4 fa[4], fb[4];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) fa[a] = Ah[((ta0 + a) * Cfg::KK + kk) * 64 + lane];
+            for (int a = 0; a < 4; ++a) fa[a] = Ah[frag(ta0 + a, kk)];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) fb[b] = Bh[((tb0 + b) * Cfg::KK + kk) * 64 + lane];
+            for (int b = 0; b < 4; ++b) fb[b] = Bh[frag(tb0 + b, kk)];
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -290,9 +353,9 @@ __global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p) {
             if constexpr (Cfg::kSplit) {
                 uint4 la[4], lb[4];
 #pragma unroll
-                for (int a = 0; a < 4; ++a) la[a] = Al[((ta0 + a) * Cfg::KK + kk) * 64 + lane];
+                for (int a = 0; a < 4; ++a) la[a] = Al[frag(ta0 + a, kk)];
 #pragma unroll
-                for (int b = 0; b < 4; ++b) lb[b] = Bl[((tb0 + b) * Cfg::KK + kk) * 64 + lane];
+                for (int b = 0; b < 4; ++b) lb[b] = Bl[frag(tb0 + b, kk)];
 #pragma unroll
                 for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -302,7 +365,15 @@ __global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p) {
                     }
             }
         }
+#ifdef KDE_SEP_HINT
+        interleave_hint<Cfg::kSplit ? 96 : 64, Cfg::kSplit ? 5 : 6, Cfg::KK>();
+#endif
         __syncthreads();
+    };
+
+    for (int64_t c = 0; c < nch; c += 2) {
+        step(c, lds1, lds0);
+        if (c + 1 < nch) step(c + 1, lds0, lds1);
     }
 
     // Epilogue: register r of lane l in a 32 x 32 tile holds row 8 (r / 4) + 4 (l / 32) + r % 4,
@@ -364,6 +435,8 @@ hipError_t launch_sep_kp(const MapArgs &a, const SepPlan &pl, float *dst, hipStr
     p.per_split = pl.per_split;
     p.ax = arg_scale(kGaussian, a.Hx);
     p.ay = arg_scale(kGaussian, a.Hy);
+    p.kappa_x = std::exp2(-2.0f * p.ax * p.ax);
+    p.kappa_y = std::exp2(-2.0f * p.ay * p.ay);
     p.Hx = a.Hx;
     p.Hy = a.Hy;
     p.ix = (float)(1.0 / (double)a.Hx);
@@ -374,7 +447,18 @@ hipError_t launch_sep_kp(const MapArgs &a, const SepPlan &pl, float *dst, hipStr
     p.dst = dst;
     p.scale = a.scale;
     p.plane = (int64_t)a.nx * a.ny;
-    hipLaunchKernelGGL((sep_mfma_kernel<K, P>), dim3(pl.tiles, pl.splits), dim3(kThreadsSep), 0, stream, p);
+    // The Gaussian's multiplicative runs need a <= 0.8 (H >= 1.05 px); narrower
+    // bandwidths evaluate every factor with its own exp2.
+    bool recur = false;
+    if constexpr (K == kGaussian) recur = p.ax <= kMaxRecurScale && p.ay <= kMaxRecurScale;
+    if constexpr (K == kGaussian) {
+        if (recur) {
+            hipLaunchKernelGGL((sep_mfma_kernel<K, P, true>), dim3(pl.tiles, pl.splits), dim3(kThreadsSep), 0,
+                               stream, p);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((sep_mfma_kernel<K, P, false>), dim3(pl.tiles, pl.splits), dim3(kThreadsSep), 0, stream, p);
     return hipGetLastError();
 }
 

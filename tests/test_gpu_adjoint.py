@@ -1,0 +1,181 @@
+"""Parity of the adjoints (kde_backward, kde_lscv) with the FP64 oracle.
+
+Gates: point gradients relative L2 <= 1e-4, bandwidth gradients and LSCV
+relative error <= 1e-4.  The oracle's gradients are themselves pinned against
+central finite differences in tests/test_oracle_pins.py."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2004_13653_amd as kde
+import synth
+from tests import kdetest as kt
+
+pytestmark = pytest.mark.gpu
+
+GRAD_GATE = 1e-4
+
+
+def _rel_l2(y, r):
+    """||y - r|| / ||r||; for an all-zero reference, ||y|| itself."""
+    y = np.asarray(y, np.float64)
+    nr = np.linalg.norm(r)
+    return float(np.linalg.norm(y - r) / nr) if nr > 0 else float(np.linalg.norm(y))
+
+
+def _rel(y, r):
+    y, r = np.asarray(y, np.float64), np.asarray(r, np.float64)
+    return np.where(r != 0, np.abs(y - r) / np.where(r != 0, np.abs(r), 1.0), np.abs(y))
+
+
+def _expected_vjp(XY, kernel, hx, hy, og, gbar, raw):
+    """World-unit dL/dx_p, dL/dy_p and dL/dhx, dL/dhy of L = <gbar, out> from the
+    oracle's raw-sum VJP (k includes its constant)."""
+    Hx, Hy = oracle.bandwidth_units(hx, hy, og)
+    g, gh = oracle.vjp_units_separable(XY, kernel, Hx, Hy, gbar)
+    n = XY.shape[0]
+    sigma = 1.0 if raw else oracle.density_scale(n, hx, hy)
+    gp = np.column_stack([g[:, 0] * sigma / og.dx, g[:, 1] * sigma / og.dy])
+    dhx = sigma * gh[:, 0].sum() / og.dx
+    dhy = sigma * gh[:, 1].sum() / og.dy
+    if not raw:
+        S = oracle.map_units_separable(XY, kernel, Hx, Hy, (0, og.nx, 0, og.ny))
+        q = float((gbar * S).sum())
+        dhx -= sigma * q / hx
+        dhy -= sigma * q / hy
+    return gp, np.array([dhx, dhy])
+
+
+def _gpu_vjp(XY, kernel, hx, hy, g, gbar, raw=False, grid_units=False):
+    import torch
+    pts = kt.to_device(XY)
+    go = torch.from_numpy(np.ascontiguousarray(gbar, dtype=np.float32)).to(kt.device())
+    gp, gh = kde.backward(pts, kernel, hx, hy, g, go, raw=raw, grid_units=grid_units)
+    torch.cuda.synchronize()
+    return gp.cpu().numpy().astype(np.float64), np.array(gh)
+
+
+@pytest.mark.parametrize("kernel", list(range(8)))
+@pytest.mark.parametrize("raw", [False, True])
+def test_vjp_all_kernels(kernel, raw):
+    """2,000 lane points, 150 x 97 grid (ragged strips), random cotangent."""
+    t = kt.lanes(20, 100)
+    g, og = kt.grids(synth.BOX_C2, 150, 97)
+    XY = kde.to_grid_units(t.xy, g)
+    rng = np.random.default_rng(kernel)
+    gbar = rng.standard_normal((97, 150))
+    h = 0.02
+    gp, gh = _gpu_vjp(XY, kernel, h, 0.7 * h, g, gbar, raw=raw)
+    rp, rh = _expected_vjp(XY, kernel, h, 0.7 * h, og, gbar, raw)
+    e_p = _rel_l2(gp, rp)
+    e_h = _rel(gh, rh)
+    kt.log(f"kernel={kernel} raw={raw}: points rel-L2 {e_p:.2e}, h rel {e_h}")
+    assert e_p <= GRAD_GATE
+    assert np.all(e_h <= GRAD_GATE)
+
+
+def test_vjp_grid_units_and_l2_loss():
+    """L2 loss against a target map: gbar = 2 (f - T), T the map of the
+    Douglas-Peucker-compressed points, gradients for the raw points."""
+    import torch
+    t = kt.lanes(40, 200)
+    tc = synth.dp_compress(t, 50.0)
+    g, og = kt.grids(synth.BOX_C2, 256, 256)
+    XY = kde.to_grid_units(t.xy, g)
+    XYc = kde.to_grid_units(tc.xy, g)
+    h = 0.006
+    f = kt.gpu_map(XY, 6, h, h, g)
+    T = kt.gpu_map(XYc, 6, h, h, g)
+    gbar = 2.0 * (f - T)
+    gp, gh = _gpu_vjp(XY, 6, h, h, g, gbar, grid_units=True)
+    rp, rh = _expected_vjp(XY, 6, h, h, og, gbar, False)
+    rp_units = rp * np.array([og.dx, og.dy])
+    assert _rel_l2(gp, rp_units) <= GRAD_GATE
+    assert np.all(np.abs(gh - rh) / np.abs(rh) <= GRAD_GATE)
+
+
+def test_autograd_function_matches_backward():
+    import torch
+    t = kt.lanes(20, 100)
+    g, og = kt.grids(synth.BOX_C2, 96, 80)
+    XY = kde.to_grid_units(t.xy, g)
+    pts = kt.to_device(XY).requires_grad_(True)
+    hx = torch.tensor(0.02, dtype=torch.float64, requires_grad=True)
+    hy = torch.tensor(0.015, dtype=torch.float64, requires_grad=True)
+    out = kde.kde_map(pts, hx, hy, "epanechnikov", g)
+    w = torch.linspace(-1, 1, out.numel(), device=out.device).reshape(out.shape)
+    (out * w).sum().backward()
+    rp, rh = _expected_vjp(XY, 2, 0.02, 0.015, og, w.cpu().numpy().astype(np.float64), False)
+    assert _rel_l2(pts.grad.cpu().numpy(), rp * np.array([og.dx, og.dy])) <= GRAD_GATE
+    assert abs(hx.grad.item() - rh[0]) <= GRAD_GATE * abs(rh[0])
+    assert abs(hy.grad.item() - rh[1]) <= GRAD_GATE * abs(rh[1])
+
+
+@pytest.mark.parametrize("kernel", [6, 2])
+@pytest.mark.parametrize("hdeg", [0.001, 0.004, 0.01])
+def test_lscv_value_and_gradient(kernel, hdeg):
+    """20,000 lane points, LSCV over all ordered pairs against the oracle in
+    parity mode (FP32 grid-unit inputs, FP64 arithmetic)."""
+    import torch
+    t = kt.lanes(100, 200)
+    g, og = kt.grids(synth.BOX_C2, 512, 512)
+    XY = kde.to_grid_units(t.xy, g)
+    Hx, Hy = oracle.bandwidth_units(hdeg, 1.3 * hdeg, og)
+    vu, gu = oracle.lscv_units(XY, kernel, Hx, Hy)
+    hx, hy = hdeg, 1.3 * hdeg
+    ref_v = vu * float(Hx) * float(Hy) / (hx * hy)
+    ref_g = np.array([gu[0] * float(Hx) ** 2 * float(Hy) / (hx * hx * hy),
+                      gu[1] * float(Hx) * float(Hy) ** 2 / (hx * hy * hy)])
+    v, gh = kde.lscv(kt.to_device(XY), kernel, hx, hy, g)
+    torch.cuda.synchronize()
+    kt.log(f"lscv kernel={kernel} h={hdeg}: value {v:.6e} ref {ref_v:.6e}; grad {gh} ref {ref_g}")
+    assert abs(v - ref_v) <= GRAD_GATE * abs(ref_v)
+    assert np.all(np.abs(np.array(gh) - ref_g) <= GRAD_GATE * np.abs(ref_g))
+
+
+def test_lscv_autograd_and_edge_cases():
+    import torch
+    g = kde.Grid(0.0, 1.0, 0.0, 1.0, 64, 64)
+    og = oracle.Grid(0.0, 1.0, 0.0, 1.0, 64, 64)
+    XY = np.array([[10.0, 12.0], [13.5, 11.25]], dtype=np.float32)  # n = 2
+    hx = torch.tensor(0.05, dtype=torch.float64, requires_grad=True)
+    hy = torch.tensor(0.04, dtype=torch.float64, requires_grad=True)
+    val = kde.kde_lscv(kt.to_device(XY), hx, hy, "gaussian", g)
+    val.backward()
+    Hx, Hy = oracle.bandwidth_units(0.05, 0.04, og)
+    vu, gu = oracle.lscv_units(XY, 6, Hx, Hy)
+    assert val.item() == pytest.approx(vu * float(Hx) * float(Hy) / (0.05 * 0.04), rel=1e-5)
+    assert hx.grad.item() == pytest.approx(gu[0] * float(Hx) ** 2 * float(Hy) / (0.05 ** 2 * 0.04), rel=1e-4)
+    with pytest.raises(kde.KDEError):
+        kde.lscv(kt.to_device(XY[:1]), "gaussian", 0.05, 0.04, g)
+    with pytest.raises(kde.KDEError, match="EUNSUPPORTED"):
+        kde.lscv(kt.to_device(XY), "cosine", 0.05, 0.04, g)
+
+
+def test_full_size_adjoint_runs_and_is_deterministic():
+    """250,000 points on 512 x 512 (Gaussian and Epanechnikov): VJP and LSCV are
+    bitwise reproducible and finite; for the Gaussian, L = sum(out) does not
+    change when one interior point moves (a lattice sum of a smooth Gaussian is
+    translation invariant to far below FP32), so its point gradients vanish next
+    to those of a random cotangent."""
+    import torch
+    t = kt.lanes(500, 500)
+    g, og = kt.grids(synth.BOX_C2, 512, 512)
+    XY = kde.to_grid_units(t.xy, g)
+    pts = kt.to_device(XY)
+    ones = torch.ones((512, 512), device=kt.device())
+    for kernel, h in ((6, 0.004), (2, 0.004)):
+        a, ha = kde.backward(pts, kernel, h, h, g, ones, raw=True, grid_units=True)
+        b, hb = kde.backward(pts, kernel, h, h, g, ones, raw=True, grid_units=True)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b) and ha == hb
+        assert torch.isfinite(a).all()
+        va, ga = kde.lscv(pts, kernel, h, h, g)
+        vb, gb = kde.lscv(pts, kernel, h, h, g)
+        assert va == vb and ga == gb and np.isfinite(va)
+        if kernel == 6:
+            inside = (XY[:, 0] > 20) & (XY[:, 0] < 490) & (XY[:, 1] > 20) & (XY[:, 1] < 490)
+            rnd = torch.randn((512, 512), device=kt.device(), generator=torch.Generator(kt.device()).manual_seed(3))
+            c, _ = kde.backward(pts, kernel, h, h, g, rnd, raw=True, grid_units=True, want_h=False)
+            torch.cuda.synchronize()
+            assert np.abs(a.cpu().numpy()[inside]).max() < 1e-4 * np.abs(c.cpu().numpy()).max()
