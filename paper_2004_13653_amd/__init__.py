@@ -34,7 +34,9 @@ class KDEError(RuntimeError):
         self.status = status
 
 
-class kde_map(ctypes.Structure):
+class MapDesc(ctypes.Structure):
+    """ctypes image of struct kde_map (one descriptor of kde_eval_batched)."""
+
     _fields_ = [("points", ctypes.c_void_p), ("n", ctypes.c_int64), ("kernel_id", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("hx", ctypes.c_double), ("hy", ctypes.c_double),
                 ("grid", ctypes.c_void_p), ("out", ctypes.c_void_p)]

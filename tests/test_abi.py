@@ -85,7 +85,7 @@ def test_other_entry_points_validate():
     assert L.kde_lscv(FAKE, 1, 6, 0.05, 0.05, g.handle, ctypes.byref(v), None, None) == kde.KDE_EINVAL
     assert L.kde_lscv(FAKE, 10, 6, 0.05, 0.05, g.handle, None, None, None) == kde.KDE_EINVAL
     assert L.kde_eval_batched(None, 3, 0, None) == kde.KDE_EINVAL
-    m = (kde.kde_map * 2)()
+    m = (kde.MapDesc * 2)()
     for d in m:
         d.points, d.n, d.kernel_id, d.hx, d.hy, d.grid, d.out = FAKE.value, 5, 6, 0.05, 0.05, g.handle.value, FAKE.value
     m[1].kernel_id = 11
