@@ -97,6 +97,85 @@ def cpu_baseline(XY, y_maps, og, budget_s: float):
     return base, errs, crop, win
 
 
+def bench_adjoint(torch, kde, synth, steps: int):
+    """Adjoint workload: 250,000 points on 512 x 512, Gaussian and Epanechnikov,
+    hx = hy = 0.004 degrees: the map VJP (L2 loss against the map of the
+    Douglas-Peucker-compressed points) and the LSCV score with its gradient."""
+    t = synth.workload_lanes(n_tracks=500, pts=500, seed_index=3)
+    tc = synth.dp_compress(t, 50.0)
+    b = synth.BOX_C2
+    g = kde.Grid(b.lon0, b.lon1, b.lat0, b.lat1, 512, 512)
+    pts = torch.from_numpy(kde.to_grid_units(t.xy, g)).cuda()
+    ptc = torch.from_numpy(kde.to_grid_units(tc.xy, g)).cuda()
+    n = pts.shape[0]
+    res = {"points": n, "grid": [512, 512], "h_deg": 0.004, "target_points": int(ptc.shape[0])}
+    for kname in ("gaussian", "epanechnikov"):
+        f = kde.eval(pts, kname, 0.004, 0.004, g)
+        T = kde.eval(ptc, kname, 0.004, 0.004, g)
+        gbar = (2.0 * (f - T)).contiguous()
+        tot, _ = timed_steps(torch, lambda: kde.backward(pts, kname, 0.004, 0.004, g, gbar, want_h=False), steps, 1)
+        ms_vjp = tot / steps
+        # with the bandwidth gradient (synchronises for the two host scalars)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            kde.backward(pts, kname, 0.004, 0.004, g, gbar)
+        ms_vjp_h = (time.perf_counter() - t0) * 1e3 / steps
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            kde.lscv(pts, kname, 0.004, 0.004, g)
+        ms_lscv = (time.perf_counter() - t0) * 1e3 / steps
+        res[kname] = {"vjp_ms": ms_vjp, "vjp_pairs_per_s": n * 512 * 512 / (ms_vjp * 1e-3),
+                      "vjp_with_h_ms": ms_vjp_h, "lscv_ms": ms_lscv,
+                      "lscv_pairs_per_s": n * n / (ms_lscv * 1e-3)}
+        log(f"adjoint {kname}: vjp {ms_vjp:.2f} ms, lscv {ms_lscv:.2f} ms")
+    return res
+
+
+def bench_batched(torch, kde, synth, steps: int):
+    """Batch workload: 256 maps, point counts log-uniform in [1k, 200k] (time
+    windows of a 4M-point pool), grids from {256^2, 512^2, 1024^2}, h ~ U(0.001,
+    0.008) degrees, kernels uniform over the eight: one graph-replayed persistent
+    launch against 256 separate kde_eval launches."""
+    t = synth.workload_lanes(n_tracks=N_TRACKS, pts=PTS_PER_TRACK, seed_index=2)
+    b = synth.BOX_C2
+    grids = {s: kde.Grid(b.lon0, b.lon1, b.lat0, b.lat1, s, s) for s in (256, 512, 1024)}
+    dev_pts = {s: torch.from_numpy(kde.to_grid_units(t.xy, grids[s])).cuda() for s in grids}
+    specs = synth.batch_specs(256, t.n)
+    maps = [(dev_pts[sp.side][sp.start:sp.start + sp.count], sp.kernel, sp.h_deg, sp.h_deg, grids[sp.side],
+             torch.empty((sp.side, sp.side), device="cuda")) for sp in specs]
+    pairs = float(sum(sp.count * sp.side * sp.side for sp in specs))
+    gauss_pairs = float(sum(sp.count * sp.side * sp.side for sp in specs if sp.kernel == 6))
+    tot_b, _ = timed_steps(torch, lambda: kde.eval_batched(maps), steps, 2)
+    ms_b = tot_b / steps
+
+    def separate():
+        for (p, k, hx, hy, g, o) in maps:
+            kde.eval(p, k, hx, hy, g, out=o)
+    tot_s, _ = timed_steps(torch, separate, max(1, steps // 2), 1)
+    ms_s = tot_s / max(1, steps // 2)
+    log(f"batched: {ms_b:.2f} ms vs separate {ms_s:.2f} ms")
+    return {"maps": 256, "logical_pairs": pairs, "gaussian_pairs": gauss_pairs, "batched_ms": ms_b,
+            "separate_ms": ms_s, "batched_pairs_per_s": pairs / (ms_b * 1e-3),
+            "separate_pairs_per_s": pairs / (ms_s * 1e-3), "speedup": ms_s / ms_b}
+
+
+def bench_compact(torch, kde, synth, steps: int):
+    """The eight kernels on the FP32 direct path: 1,000,000 points (2,000 tracks x
+    500) on 1024 x 1024, h = 0.002 degrees."""
+    t = synth.workload_lanes(n_tracks=2000, pts=500, seed_index=1)
+    b = synth.BOX_C2
+    g = kde.Grid(b.lon0, b.lon1, b.lat0, b.lat1, 1024, 1024)
+    pts = torch.from_numpy(kde.to_grid_units(t.xy, g)).cuda()
+    out = torch.empty((1024, 1024), device="cuda")
+    res = {}
+    for kname, kid in kde.KERNELS.items():
+        tot, _ = timed_steps(torch, lambda: kde.eval(pts, kid, 0.002, 0.002, g, out=out), steps, 1)
+        ms = tot / steps
+        res[kname] = {"ms": ms, "logical_pairs_per_s": pts.shape[0] * 1024 * 1024 / (ms * 1e-3)}
+    log("compact kernels: " + ", ".join(f"{k} {v['ms']:.2f} ms" for k, v in res.items()))
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +184,8 @@ def main() -> int:
     ap.add_argument("--direct-steps", type=int, default=3, help="timed steps of the FP32 direct path")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sections", default="adjoint,batched,kernels",
+                    help="extra measured sections beside the headline: adjoint, batched, kernels (or none)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the KDE map runs on a single MI355X here "
@@ -172,6 +253,13 @@ def main() -> int:
                                      "unit": "TFLOP/s", "frac": d["fp32_tflops"] / PEAK_FP32_VECTOR_TFLOPS}},
         "paths": results,
     }
+    extra = [x for x in args.sections.split(",") if x and x != "none"]
+    if "adjoint" in extra:
+        line["adjoint"] = bench_adjoint(torch, kde, synth, 5)
+    if "batched" in extra:
+        line["batched"] = bench_batched(torch, kde, synth, 6)
+    if "kernels" in extra:
+        line["fp32_direct_kernels"] = bench_compact(torch, kde, synth, 5)
     if not args.no_cpu_baseline:
         og_mod = __import__("oracle")
         og = og_mod.Grid(b.lon0, b.lon1, b.lat0, b.lat1, SIDE, SIDE)

@@ -86,6 +86,7 @@ enum {
 /* Flags. */
 #define KDE_RAW_SUM 1u          /* the map is S instead of S/(n hx hy) */
 #define KDE_GRID_UNIT_GRADS 2u  /* kde_backward: grad_points as dL/dX_p, dL/dY_p in grid units */
+#define KDE_BATCH_EAGER 4u      /* kde_eval_batched: launch directly instead of replaying a graph */
 
 typedef struct kde_grid kde_grid; /* opaque, immutable, library-owned */
 
@@ -136,8 +137,18 @@ typedef struct kde_map {
 } kde_map;
 
 /* Evaluates n_maps maps (host array of descriptors) with the FP32 direct path in
- * one persistent launch.  Every descriptor is validated before anything is
- * launched; output buffers must not overlap.  flags as for kde_eval. */
+ * one persistent launch (not in the paper, which maps one data set at a time):
+ * the batch is cut into (map, pixel tile, point range) items, longest first,
+ * pulled by persistent workgroups from an atomic counter; each map's output
+ * equals what kde_eval(..., KDE_FP32_DIRECT, ...) computes up to FP32 rounding
+ * order.  Every descriptor is validated before anything is launched; output
+ * buffers must not overlap each other or any point buffer.  By default the
+ * upload + launch sequence is captured into a hipGraph the first time a batch
+ * shape (item list, kernels, grid sizes, point counts) is seen and replayed
+ * afterwards; the library keeps one device buffer and pinned staging buffer per
+ * captured shape until kde_shutdown().  A call on a shape that is still running
+ * waits for that run to finish before reusing its staging buffer.  flags:
+ * KDE_RAW_SUM, KDE_BATCH_EAGER (no graph; the call synchronises `stream`). */
 int kde_eval_batched(const kde_map *maps, int32_t n_maps, uint32_t flags, void *stream);
 
 /* Adjoint of kde_eval (vector-Jacobian product; not in the paper).  Given

@@ -15,7 +15,7 @@ import os
 import numpy as np
 
 __all__ = ["KERNELS", "PRECISIONS", "KDEError", "Grid", "lib", "eval", "backward", "lscv", "kde_map", "kde_lscv",
-           "to_grid_units", "bandwidth_units", "LIB_PATH"]
+           "eval_batched", "to_grid_units", "bandwidth_units", "LIB_PATH"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libkde.so")
 
@@ -253,3 +253,33 @@ def kde_lscv(points, hx, hy, kernel, grid: Grid):
     """Differentiable LSCV score as a 0-d FP64 tensor (gradients w.r.t. hx, hy)."""
     _, KDELSCV = _autograd()
     return KDELSCV.apply(points, hx, hy, kernel, grid)
+
+
+BATCH_EAGER = 4
+
+
+def eval_batched(maps, raw: bool = False, eager: bool = False, stream_device=None):
+    """Many maps in one persistent launch (kde_eval_batched).  `maps` is a list of
+    (points [n, 2] CUDA FP32 grid units, kernel, hx, hy, Grid, out [ny, nx] CUDA
+    FP32) tuples; outputs are written in place."""
+    import torch
+    descs = (MapDesc * len(maps))()
+    dev = None
+    for d, (pts, kernel, hx, hy, grid, out) in zip(descs, maps):
+        _check_points(pts, torch)
+        if not (out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()
+                and out.numel() == grid.nx * grid.ny):
+            raise ValueError("out must be a contiguous CUDA float32 tensor with ny*nx elements")
+        dev = pts.device if dev is None else dev
+        d.points = pts.data_ptr() if pts.numel() else None
+        d.n = pts.shape[0]
+        d.kernel_id = _kernel_id(kernel)
+        d.reserved = 0
+        d.hx, d.hy = float(hx), float(hy)
+        d.grid = grid.handle.value
+        d.out = out.data_ptr()
+    if dev is None:
+        return
+    flags = (RAW_SUM if raw else 0) | (BATCH_EAGER if eager else 0)
+    with torch.cuda.device(dev):
+        _check(lib().kde_eval_batched(descs, len(maps), flags, _stream(torch, dev)))

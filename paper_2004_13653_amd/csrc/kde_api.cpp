@@ -212,16 +212,40 @@ int kde_eval(const float *points, int64_t n, int32_t kernel_id, double hx, doubl
 }
 
 int kde_eval_batched(const kde_map *maps, int32_t n_maps, uint32_t flags, void *stream) {
-    (void)stream;
-    if (n_maps < 0 || (n_maps > 0 && maps == nullptr)) return fail(KDE_EINVAL, "kde_eval_batched: bad map array");
-    if (flags & ~KDE_RAW_SUM) return fail(KDE_EINVAL, "kde_eval_batched: unknown flags 0x%x", flags);
-    for (int32_t m = 0; m < n_maps; ++m) {
-        const kde_map &d = maps[m];
-        int st = check_map(d.points, d.n, d.kernel_id, d.hx, d.hy, d.grid, "kde_eval_batched");
-        if (st != KDE_OK) return st;
-        if (d.out == nullptr || d.reserved != 0) return fail(KDE_EINVAL, "kde_eval_batched: map %d: bad out/reserved", m);
+    try {
+        if (n_maps < 0 || (n_maps > 0 && maps == nullptr)) return fail(KDE_EINVAL, "kde_eval_batched: bad map array");
+        if (flags & ~(KDE_RAW_SUM | KDE_BATCH_EAGER))
+            return fail(KDE_EINVAL, "kde_eval_batched: unknown flags 0x%x", flags);
+        for (int32_t m = 0; m < n_maps; ++m) {
+            const kde_map &d = maps[m];
+            int st = check_map(d.points, d.n, d.kernel_id, d.hx, d.hy, d.grid, "kde_eval_batched");
+            if (st != KDE_OK) return fail(st, "kde_eval_batched: map %d: %s", m, g_err.c_str());
+            if (d.out == nullptr || d.reserved != 0)
+                return fail(KDE_EINVAL, "kde_eval_batched: map %d: out is NULL or reserved != 0", m);
+        }
+        if (n_maps == 0) return KDE_OK;
+        std::vector<kde::MapArgs> args((size_t)n_maps);
+        for (int32_t m = 0; m < n_maps; ++m) {
+            const kde_map &d = maps[m];
+            args[m] = make_args(d.points, d.n, d.kernel_id, d.hx, d.hy, d.grid, d.out, flags);
+            if (d.n == 0) args[m].scale = 0.0f;  // zero map
+        }
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const bool eager = (flags & KDE_BATCH_EAGER) != 0;
+        void *ws = nullptr;
+        size_t bytes = 0;
+        if (eager) {
+            bytes = kde::batched_workspace_bytes(args.data(), n_maps);
+            int st = get_workspace(s, bytes, &ws);
+            if (st != KDE_OK) return st;
+        }
+        hipError_t e = kde::run_batched(args.data(), n_maps, !eager, ws, bytes, s);
+        return e == hipSuccess ? KDE_OK : hip_fail(e, "kde_eval_batched");
+    } catch (const std::bad_alloc &) {
+        return fail(KDE_ENOMEM, "kde_eval_batched: out of host memory");
+    } catch (...) {
+        return fail(KDE_EHIP, "kde_eval_batched: internal error");
     }
-    return fail(KDE_EUNSUPPORTED, "kde_eval_batched: not available");
 }
 
 int kde_backward(const float *points, int64_t n, int32_t kernel_id, double hx, double hy, const kde_grid *g,
@@ -335,6 +359,7 @@ void kde_shutdown(void) {
         }
     }
     g_ws.clear();
+    kde::release_batched_graphs();
     if (have_cur) (void)hipSetDevice(cur);
 }
 

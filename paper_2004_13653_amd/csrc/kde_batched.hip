@@ -1,0 +1,351 @@
+// Many heat maps in one persistent launch (FP32 direct path).
+//
+// The work of a batch is cut into items (map, pixel tile, point range): tiles
+// of the per-kernel register-block shape, and Gaussian tiles whose point count
+// would make one item long are split into point ranges of about 2^26 pairs.
+// Items are sorted by estimated cost, longest first.  A persistent grid of
+// workgroups (about one per SIMD slot the kernel can occupy) pulls item indices
+// from an atomic counter until the list is exhausted, so uneven maps balance
+// across the CUs.  An item that covers a whole tile writes the scaled tile to
+// its map; split items write raw partial tiles, and the last of a tile's splits
+// to finish (a per-tile atomic count, with device-scope fences) adds the
+// partials in split order and writes the scaled tile: results do not depend on
+// which workgroup finishes last.
+//
+// Host side: the descriptors and the item list live in one pinned staging
+// buffer that a single copy moves to the device, followed by a counter reset
+// kernel and the persistent kernel.  That sequence is captured once per batch
+// shape (the item list and the static map fields) into a hipGraph and replayed
+// for later calls with new pointers and bandwidths.
+#include "kde_tile.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+namespace kde {
+
+namespace {
+
+using tile::kPointTile;
+using tile::kThreads;
+
+constexpr int64_t kPairsPerItem = int64_t(1) << 26;
+
+struct BMap {
+    const float2 *pts;
+    float *out;
+    int64_t n;
+    int kernel;
+    int nx, ny, tiles_x;
+    float Hx, Hy, ax, ay, scale;
+};
+
+struct BItem {
+    int map, tile, split, nsplit;
+    int64_t p0, p1;
+    int64_t slot;      // index of this split's partial tile (split items only)
+    int tile_global;   // index of the tile's finish counter (split items only)
+    int pad;
+};
+
+struct BatchLaunch {
+    const BMap *maps;
+    const BItem *items;
+    int n_items;
+    int *counter;   // [1 + n_split_tiles]: next item, then per-tile finish counts
+    float *partials;
+};
+
+template <int K>
+__device__ __forceinline__ void run_item(const BMap &m, const BItem &w, const BatchLaunch &b, float2 *sp,
+                                         int *swave, int *s_last) {
+    using S = tile::Shape<K>;
+    const int tid = threadIdx.x;
+    const int tx = w.tile % m.tiles_x, ty = w.tile / m.tiles_x;
+    const int x0 = tx * S::TW, y0 = ty * S::TH;
+    const int lib = (tid & 15) * S::C, ljb = (tid >> 4) * S::R;  // tile-local block origin
+    const int ib = x0 + lib, jb = y0 + ljb;
+    float tot[S::R][S::C];
+    tile::tile_sums<K, S::R, S::C, S::kCull>(m.pts, w.p0, w.p1, m.Hx, m.Hy, m.ax, m.ay, ib, jb, (float)x0,
+                                             (float)(min(x0 + S::TW, m.nx) - 1), (float)y0,
+                                             (float)(min(y0 + S::TH, m.ny) - 1), sp, swave, tot);
+    if (w.nsplit == 1) {
+        tile::store_block<S::R, S::C>(tot, m.out, m.nx, m.ny, ib, jb, m.scale);
+        return;
+    }
+    // Partial tile, row-major TW x TH.
+    constexpr int kTileElems = S::TW * S::TH;
+    float *mine = b.partials + w.slot * kTileElems;
+#pragma unroll
+    for (int r = 0; r < S::R; ++r)
+#pragma unroll
+        for (int c = 0; c < S::C; ++c) mine[(ljb + r) * S::TW + lib + c] = tot[r][c];
+    __threadfence();  // release the partial before counting this split as done
+    __syncthreads();
+    if (tid == 0) *s_last = atomicAdd(b.counter + 1 + w.tile_global, 1) == w.nsplit - 1;
+    __syncthreads();
+    if (!*s_last) return;
+    __threadfence();  // acquire the other splits' partials
+    const float *first = b.partials + (w.slot - w.split) * kTileElems;
+#pragma unroll
+    for (int r = 0; r < S::R; ++r)
+#pragma unroll
+        for (int c = 0; c < S::C; ++c) {
+            float v = 0.0f;
+            for (int s = 0; s < w.nsplit; ++s) v += first[s * kTileElems + (ljb + r) * S::TW + lib + c];
+            tot[r][c] = v;
+        }
+    tile::store_block<S::R, S::C>(tot, m.out, m.nx, m.ny, ib, jb, m.scale);
+}
+
+__global__ __launch_bounds__(kThreads) void batched_kernel(BatchLaunch b) {
+    __shared__ float2 sp[kPointTile];
+    __shared__ int swave[kThreads / 64];
+    __shared__ int s_item, s_last;
+    for (;;) {
+        __syncthreads();  // every thread has read the previous s_item
+        if (threadIdx.x == 0) s_item = atomicAdd(b.counter, 1);
+        __syncthreads();
+        const int it = s_item;
+        if (it >= b.n_items) return;  // the counter only grows: every workgroup reaches this
+        const BItem w = b.items[it];
+        const BMap m = b.maps[w.map];
+        switch (m.kernel) {
+        case kUniform: run_item<kUniform>(m, w, b, sp, swave, &s_last); break;
+        case kTriangular: run_item<kTriangular>(m, w, b, sp, swave, &s_last); break;
+        case kEpanechnikov: run_item<kEpanechnikov>(m, w, b, sp, swave, &s_last); break;
+        case kQuartic: run_item<kQuartic>(m, w, b, sp, swave, &s_last); break;
+        case kTriweight: run_item<kTriweight>(m, w, b, sp, swave, &s_last); break;
+        case kTricube: run_item<kTricube>(m, w, b, sp, swave, &s_last); break;
+        case kGaussian: run_item<kGaussian>(m, w, b, sp, swave, &s_last); break;
+        default: run_item<kCosine>(m, w, b, sp, swave, &s_last); break;
+        }
+    }
+}
+
+__global__ void zero_ints_kernel(int *p, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0;
+}
+
+// ------------------------------------------------------------------ host side
+
+int tile_w(int kernel) { return kernel == kGaussian ? tile::Shape<kGaussian>::TW : tile::Shape<kUniform>::TW; }
+int tile_h(int kernel) { return kernel == kGaussian ? tile::Shape<kGaussian>::TH : tile::Shape<kUniform>::TH; }
+
+struct Plan {
+    std::vector<BMap> maps;
+    std::vector<BItem> items;
+    int n_split_tiles = 0;
+    int64_t n_slots = 0;
+    std::string signature;  // item list and static map fields
+};
+
+Plan make_plan(const MapArgs *args, int n_maps) {
+    Plan pl;
+    pl.maps.resize(n_maps);
+    struct Costed {
+        double cost;
+        int order;
+        BItem item;
+    };
+    std::vector<Costed> cs;
+    for (int m = 0; m < n_maps; ++m) {
+        const MapArgs &a = args[m];
+        const int TW = tile_w(a.kernel_id), TH = tile_h(a.kernel_id);
+        BMap &bm = pl.maps[m];
+        bm.pts = a.pts;
+        bm.out = a.out;
+        bm.n = a.n;
+        bm.kernel = a.kernel_id;
+        bm.nx = a.nx;
+        bm.ny = a.ny;
+        bm.tiles_x = (a.nx + TW - 1) / TW;
+        bm.Hx = a.Hx;
+        bm.Hy = a.Hy;
+        bm.ax = a.ax;
+        bm.ay = a.ay;
+        bm.scale = a.scale;
+        const int tiles = bm.tiles_x * ((a.ny + TH - 1) / TH);
+        const bool dense = a.kernel_id == kGaussian;
+        int64_t per = a.n;
+        if (dense) {
+            per = std::max<int64_t>(kPointTile, kPairsPerItem / ((int64_t)TW * TH));
+            per = (per + kPointTile - 1) / kPointTile * kPointTile;
+        }
+        const int nsplit = a.n == 0 ? 1 : (int)((a.n + per - 1) / per);
+        for (int t = 0; t < tiles; ++t) {
+            const int tg = nsplit > 1 ? pl.n_split_tiles++ : -1;
+            for (int s = 0; s < nsplit; ++s) {
+                BItem it{};
+                it.map = m;
+                it.tile = t;
+                it.split = s;
+                it.nsplit = nsplit;
+                it.p0 = std::min<int64_t>(a.n, s * per);
+                it.p1 = std::min<int64_t>(a.n, (s + 1) * per);
+                it.slot = nsplit > 1 ? pl.n_slots++ : -1;
+                it.tile_global = tg;
+                // Dense tiles cost pairs; culled tiles cost the scan plus a small
+                // share of in-support work.
+                const double npts = (double)(it.p1 - it.p0);
+                const double cost = dense ? npts * TW * TH : npts * 64.0;
+                cs.push_back({cost, (int)cs.size(), it});
+            }
+        }
+    }
+    std::stable_sort(cs.begin(), cs.end(), [](const Costed &x, const Costed &y) { return x.cost > y.cost; });
+    pl.items.reserve(cs.size());
+    for (const auto &c : cs) pl.items.push_back(c.item);
+    // Signature: everything the captured launch depends on except the values
+    // re-uploaded each call (pointers, bandwidth-dependent scalars).
+    pl.signature.assign(reinterpret_cast<const char *>(pl.items.data()), pl.items.size() * sizeof(BItem));
+    for (const BMap &bm : pl.maps) {
+        const int32_t st[5] = {bm.kernel, bm.nx, bm.ny, bm.tiles_x, (int32_t)(bm.n & 0x7fffffff)};
+        pl.signature.append(reinterpret_cast<const char *>(st), sizeof st);
+    }
+    return pl;
+}
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+struct Layout {
+    size_t maps_off, items_off, stage_bytes;  // staged (copied) part
+    size_t counters_off, partials_off, total;
+    int n_counters;
+};
+
+Layout layout_of(const Plan &pl) {
+    Layout L;
+    L.maps_off = 0;
+    L.items_off = align256(pl.maps.size() * sizeof(BMap));
+    L.stage_bytes = align256(L.items_off + pl.items.size() * sizeof(BItem));
+    L.counters_off = L.stage_bytes;
+    L.n_counters = 1 + pl.n_split_tiles;
+    L.partials_off = align256(L.counters_off + (size_t)L.n_counters * sizeof(int));
+    const size_t tile_elems = (size_t)tile::Shape<kGaussian>::TW * tile::Shape<kGaussian>::TH;
+    L.total = align256(L.partials_off + (size_t)pl.n_slots * tile_elems * sizeof(float));
+    return L;
+}
+
+int persistent_grid(int n_items) {
+    // Workgroups of 256 threads; the kernel's register use allows about 3 per CU.
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                                                                        dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    return std::max(1, std::min(n_items, 3 * cus));
+}
+
+hipError_t enqueue(const Plan &pl, const Layout &L, const void *host_stage, char *dev, hipStream_t s) {
+    hipError_t e = hipMemcpyAsync(dev, host_stage, L.stage_bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(zero_ints_kernel, dim3((L.n_counters + 255) / 256), dim3(256), 0, s,
+                       reinterpret_cast<int *>(dev + L.counters_off), L.n_counters);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    BatchLaunch b;
+    b.maps = reinterpret_cast<const BMap *>(dev + L.maps_off);
+    b.items = reinterpret_cast<const BItem *>(dev + L.items_off);
+    b.n_items = (int)pl.items.size();
+    b.counter = reinterpret_cast<int *>(dev + L.counters_off);
+    b.partials = reinterpret_cast<float *>(dev + L.partials_off);
+    hipLaunchKernelGGL(batched_kernel, dim3(persistent_grid(b.n_items)), dim3(kThreads), 0, s, b);
+    return hipGetLastError();
+}
+
+void fill_stage(const Plan &pl, const Layout &L, char *stage) {
+    std::memcpy(stage + L.maps_off, pl.maps.data(), pl.maps.size() * sizeof(BMap));
+    std::memcpy(stage + L.items_off, pl.items.data(), pl.items.size() * sizeof(BItem));
+}
+
+// A captured batch: device buffer, pinned staging buffer, executable graph.
+struct Captured {
+    char *dev = nullptr;
+    char *stage = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;
+    Layout L;
+    ~Captured() {
+        if (done) (void)hipEventSynchronize(done);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (done) (void)hipEventDestroy(done);
+        if (stage) (void)hipHostFree(stage);
+        if (dev) (void)hipFree(dev);
+    }
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, std::string>, std::unique_ptr<Captured>> g_graphs;  // (device, signature)
+
+}  // namespace
+
+hipError_t run_batched(const MapArgs *args, int n_maps, bool use_graph, void *ws_eager, size_t ws_bytes,
+                       hipStream_t stream) {
+    const Plan pl = make_plan(args, n_maps);
+    if (pl.items.empty()) return hipSuccess;
+    const Layout L = layout_of(pl);
+    if (!use_graph) {
+        if (ws_bytes < L.total) return hipErrorInvalidValue;
+        std::vector<char> stage(L.stage_bytes);
+        fill_stage(pl, L, stage.data());
+        hipError_t e = enqueue(pl, L, stage.data(), static_cast<char *>(ws_eager), stream);
+        if (e != hipSuccess) return e;
+        return hipStreamSynchronize(stream);  // the pageable staging buffer dies here
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto &slot = g_graphs[{dev, pl.signature}];
+    if (!slot) {
+        auto c = std::make_unique<Captured>();
+        c->L = L;
+        if ((e = hipMalloc(&c->dev, L.total)) != hipSuccess) return e;
+        if ((e = hipHostMalloc(&c->stage, L.stage_bytes, hipHostMallocDefault)) != hipSuccess) return e;
+        if ((e = hipEventCreateWithFlags(&c->done, hipEventDisableTiming)) != hipSuccess) return e;
+        hipStream_t cap = nullptr;
+        if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess) return e;
+        hipGraph_t graph = nullptr;
+        e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            const hipError_t e1 = enqueue(pl, L, c->stage, c->dev, cap);
+            e = hipStreamEndCapture(cap, &graph);
+            if (e1 != hipSuccess) e = e1;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&c->exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipStreamDestroy(cap);
+        if (e != hipSuccess) return e;
+        slot = std::move(c);
+    }
+    Captured &c = *slot;
+    // The previous replay's copy must have read the staging buffer before it is
+    // overwritten.
+    if ((e = hipEventSynchronize(c.done)) != hipSuccess) return e;
+    fill_stage(pl, c.L, c.stage);
+    if ((e = hipGraphLaunch(c.exec, stream)) != hipSuccess) return e;
+    return hipEventRecord(c.done, stream);
+}
+
+size_t batched_workspace_bytes(const MapArgs *args, int n_maps) {
+    const Plan pl = make_plan(args, n_maps);
+    return pl.items.empty() ? 0 : layout_of(pl).total;
+}
+
+void release_batched_graphs() {
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_graphs.clear();
+}
+
+}  // namespace kde

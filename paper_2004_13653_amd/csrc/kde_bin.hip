@@ -1,0 +1,297 @@
+// Support binning for the compact kernels (FP32 direct path).
+//
+// A point contributes only to nodes within H of it, so each 64 x 64 output tile
+// needs only the points whose support square [X +- Hx] x [Y +- Hy] reaches one
+// of its nodes.  Instead of every tile scanning all points, the points are
+// counting-sorted into per-tile bins:
+//
+//   1. count:   every point adds 1 to cnt[tile][w] for each tile it reaches,
+//               where w is its 64-point wave block (integer atomics: the counts
+//               do not depend on their order);
+//   2. scan:    exclusive prefix sum over cnt in tile-major order gives each
+//               (tile, wave block) its first slot (the paper's work-efficient
+//               scan pattern, Sec. IV-A: per-block scans, a scan of the block
+//               totals, then a propagation pass);
+//   3. scatter: each wave walks its 64 points and their tiles in a fixed order
+//               and assigns slots with ballots (lanes with the same tile take
+//               consecutive slots in lane order), so the bin contents and their
+//               order are the same on every run;
+//   4. gather:  one workgroup per (tile, split) sums its share of the tile's bin
+//               with the register-tiled kernel of the direct path (no culling
+//               needed; the per-pair support test remains), partial maps are
+//               added in split order.
+#include "kde_tile.h"
+
+#include <algorithm>
+
+namespace kde {
+
+namespace {
+
+constexpr int kBinTile = tile::Shape<kUniform>::TW;  // 64, the compact kernels' tile side
+constexpr int kScanBlock = 1024;
+
+struct BinGeom {
+    int nx, ny, tiles_x, tiles_y;
+    float Hx, Hy;
+    int64_t n, wblocks;  // points, 64-point wave blocks
+};
+
+// Tile rectangle a point reaches (empty when tx0 > tx1 or ty0 > ty1).
+__device__ __forceinline__ void reach(const BinGeom &g, float2 v, int &tx0, int &tx1, int &ty0, int &ty1) {
+    const float i0 = fmaxf(0.0f, ceilf(v.x - g.Hx)), i1 = fminf((float)(g.nx - 1), floorf(v.x + g.Hx));
+    const float j0 = fmaxf(0.0f, ceilf(v.y - g.Hy)), j1 = fminf((float)(g.ny - 1), floorf(v.y + g.Hy));
+    if (!(i0 <= i1 && j0 <= j1)) {  // also false for NaN coordinates
+        tx0 = ty0 = 1;
+        tx1 = ty1 = 0;
+        return;
+    }
+    tx0 = (int)i0 / kBinTile;
+    tx1 = (int)i1 / kBinTile;
+    ty0 = (int)j0 / kBinTile;
+    ty1 = (int)j1 / kBinTile;
+}
+
+__global__ __launch_bounds__(256) void bin_count_kernel(BinGeom g, const float2 *__restrict__ pts,
+                                                        unsigned *__restrict__ cnt) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= g.n) return;
+    const int64_t w = p >> 6;
+    int tx0, tx1, ty0, ty1;
+    reach(g, pts[p], tx0, tx1, ty0, ty1);
+    for (int ty = ty0; ty <= ty1; ++ty)
+        for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&cnt[(int64_t)(ty * g.tiles_x + tx) * g.wblocks + w], 1u);
+}
+
+// Exclusive scan, pass 1: each block scans kScanBlock entries in place and
+// stores its total.
+__global__ __launch_bounds__(256) void scan_blocks_kernel(unsigned *__restrict__ a, int64_t len,
+                                                          unsigned *__restrict__ totals) {
+    __shared__ unsigned s[256];
+    const int tid = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock + 4 * tid;
+    unsigned v[4], sum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[k] = base + k < len ? a[base + k] : 0u;
+        sum += v[k];
+    }
+    s[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {  // inclusive Hillis-Steele over thread sums
+        const unsigned t = tid >= off ? s[tid - off] : 0u;
+        __syncthreads();
+        s[tid] += t;
+        __syncthreads();
+    }
+    unsigned run = s[tid] - sum;  // exclusive prefix of this thread
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (base + k < len) a[base + k] = run;
+        run += v[k];
+    }
+    if (tid == 255) totals[blockIdx.x] = s[255];
+}
+
+// Pass 2: exclusive scan of the block totals by one workgroup (sequential over
+// 256-entry segments); writes the grand total to totals[nblocks].
+__global__ __launch_bounds__(256) void scan_totals_kernel(unsigned *__restrict__ totals, int64_t nblocks) {
+    __shared__ unsigned s[256];
+    __shared__ unsigned carry;
+    const int tid = threadIdx.x;
+    if (tid == 0) carry = 0;
+    __syncthreads();
+    for (int64_t seg = 0; seg < nblocks; seg += 256) {
+        const int64_t i = seg + tid;
+        const unsigned v = i < nblocks ? totals[i] : 0u;
+        s[tid] = v;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
+            const unsigned t = tid >= off ? s[tid - off] : 0u;
+            __syncthreads();
+            s[tid] += t;
+            __syncthreads();
+        }
+        if (i < nblocks) totals[i] = carry + s[tid] - v;
+        __syncthreads();
+        if (tid == 0) carry += s[255];
+        __syncthreads();
+    }
+    if (tid == 0) totals[nblocks] = carry;
+}
+
+// Pass 3: add each block's offset.
+__global__ __launch_bounds__(256) void scan_add_kernel(unsigned *__restrict__ a, int64_t len,
+                                                       const unsigned *__restrict__ totals) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) a[i] += totals[i / kScanBlock];
+}
+
+// Scatter: one wave per 64-point block.  off[] holds the (tile, block) start
+// slots and is advanced in place (each column belongs to one wave), so that
+// afterwards off[t][w] is the end of segment (t, w).
+__global__ __launch_bounds__(256) void bin_scatter_kernel(BinGeom g, const float2 *__restrict__ pts,
+                                                          unsigned *__restrict__ off, float2 *__restrict__ bins) {
+    const int lane = threadIdx.x & 63;
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= g.wblocks) return;  // whole wave
+    const int64_t p = w * 64 + lane;
+    const bool valid = p < g.n;
+    const float2 v = valid ? pts[p] : make_float2(0.0f, 0.0f);
+    int tx0 = 1, tx1 = 0, ty0 = 1, ty1 = 0;
+    if (valid) reach(g, v, tx0, tx1, ty0, ty1);
+    const int ncols = tx1 >= tx0 ? tx1 - tx0 + 1 : 0;
+    const int ntl = ncols > 0 && ty1 >= ty0 ? ncols * (ty1 - ty0 + 1) : 0;
+    int most = ntl;
+    for (int o = 32; o > 0; o >>= 1) most = max(most, __shfl_xor(most, o));
+    for (int j = 0; j < most; ++j) {  // j-th tile of every lane, raster order within its rectangle
+        int key = -1;
+        if (j < ntl) key = (ty0 + j / ncols) * g.tiles_x + tx0 + j % ncols;
+        uint64_t pending = __ballot(key >= 0);
+        while (pending) {
+            const int leader = __ffsll((unsigned long long)pending) - 1;
+            const int lkey = __shfl(key, leader);
+            const uint64_t same = __ballot(key == lkey);
+            // Only this wave touches column w, so the atomic just returns the
+            // current cursor and advances it, in this wave's program order.
+            unsigned base = 0;
+            if (lane == leader) base = atomicAdd(&off[(int64_t)lkey * g.wblocks + w], (unsigned)__popcll(same));
+            base = __shfl(base, leader);
+            if (key == lkey) bins[base + (unsigned)__popcll(same & ((1ull << lane) - 1ull))] = v;
+            pending &= ~same;
+        }
+    }
+}
+
+struct GatherLaunch {
+    const float2 *bins;
+    const unsigned *end;  // after the scatter, end[t * wblocks + wblocks - 1] is the end of tile t's bin
+    int64_t wblocks;
+    float Hx, Hy, ax, ay;
+    int nx, ny, tiles_x;
+    float *dst;   // final map (one split) or partials [splits][ny][nx]
+    float scale;
+    int64_t plane;
+};
+
+template <int K>
+__global__ __launch_bounds__(tile::kThreads) void bin_gather_kernel(GatherLaunch p) {
+    using S = tile::Shape<K>;
+    __shared__ float2 sp[tile::kPointTile];
+    __shared__ int swave[tile::kThreads / 64];
+    const int t = blockIdx.x, tid = threadIdx.x;
+    const int64_t e = p.end[(int64_t)t * p.wblocks + p.wblocks - 1];
+    const int64_t b = t > 0 ? (int64_t)p.end[(int64_t)t * p.wblocks - 1] : 0;
+    const int64_t len = e - b, parts = gridDim.y;
+    const int64_t lo = b + len * blockIdx.y / parts, hi = b + len * (blockIdx.y + 1) / parts;
+    const int x0 = (t % p.tiles_x) * S::TW, y0 = (t / p.tiles_x) * S::TH;
+    const int ib = x0 + (tid & 15) * S::C, jb = y0 + (tid >> 4) * S::R;
+    float tot[S::R][S::C];
+    tile::tile_sums<K, S::R, S::C, false>(p.bins, lo, hi, p.Hx, p.Hy, p.ax, p.ay, ib, jb, 0.0f, 0.0f, 0.0f, 0.0f,
+                                          sp, swave, tot);
+    tile::store_block<S::R, S::C>(tot, p.dst + (int64_t)blockIdx.y * p.plane, p.nx, p.ny, ib, jb,
+                                  gridDim.y == 1 ? p.scale : 1.0f);
+}
+
+struct BinPlan {
+    BinGeom g;
+    int64_t cnt_len, scan_blocks, max_entries;
+    int splits;
+    size_t off_bytes, totals_bytes, bins_bytes, part_bytes;
+};
+
+BinPlan bin_plan(const MapArgs &a) {
+    BinPlan pl;
+    pl.g.nx = a.nx;
+    pl.g.ny = a.ny;
+    pl.g.tiles_x = (a.nx + kBinTile - 1) / kBinTile;
+    pl.g.tiles_y = (a.ny + kBinTile - 1) / kBinTile;
+    pl.g.Hx = a.Hx;
+    pl.g.Hy = a.Hy;
+    pl.g.n = a.n;
+    pl.g.wblocks = (a.n + 63) / 64;
+    pl.cnt_len = (int64_t)pl.g.tiles_x * pl.g.tiles_y * pl.g.wblocks;
+    pl.scan_blocks = (pl.cnt_len + kScanBlock - 1) / kScanBlock;
+    // Tiles a point can reach per axis: its support spans at most 2H + 1 nodes.
+    const int64_t rx = std::min<int64_t>(pl.g.tiles_x, (int64_t)(2.0f * a.Hx) / kBinTile + 2);
+    const int64_t ry = std::min<int64_t>(pl.g.tiles_y, (int64_t)(2.0f * a.Hy) / kBinTile + 2);
+    pl.max_entries = a.n * rx * ry;
+    const int64_t tiles = (int64_t)pl.g.tiles_x * pl.g.tiles_y;
+    pl.splits = (int)std::max<int64_t>(1, std::min<int64_t>(8, 2048 / std::max<int64_t>(1, tiles)));
+    pl.off_bytes = (size_t)pl.cnt_len * sizeof(unsigned);
+    pl.totals_bytes = (size_t)(pl.scan_blocks + 1) * sizeof(unsigned);
+    pl.bins_bytes = (size_t)pl.max_entries * sizeof(float2);
+    pl.part_bytes = pl.splits > 1 ? (size_t)pl.splits * a.nx * a.ny * sizeof(float) : 0;
+    return pl;
+}
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+template <int K>
+hipError_t launch_gather(const GatherLaunch &p, int tiles, int splits, hipStream_t s) {
+    hipLaunchKernelGGL(bin_gather_kernel<K>, dim3(tiles, splits), dim3(tile::kThreads), 0, s, p);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool binning_applies(const MapArgs &a) {
+    if (a.kernel_id == kGaussian || a.n < 4096) return false;
+    if (a.Hx > (float)kBinTile || a.Hy > (float)kBinTile) return false;  // at most 3 x 3 tiles per point
+    const BinPlan pl = bin_plan(a);
+    return pl.cnt_len <= (int64_t(1) << 26) && pl.max_entries <= (int64_t(1) << 30);
+}
+
+size_t binned_workspace_bytes(const MapArgs &a) {
+    const BinPlan pl = bin_plan(a);
+    return align256(pl.off_bytes) + align256(pl.totals_bytes) + align256(pl.bins_bytes) + pl.part_bytes;
+}
+
+hipError_t launch_binned(const MapArgs &a, void *ws, hipStream_t s) {
+    const BinPlan pl = bin_plan(a);
+    char *w = static_cast<char *>(ws);
+    unsigned *off = reinterpret_cast<unsigned *>(w);
+    unsigned *totals = reinterpret_cast<unsigned *>(w + align256(pl.off_bytes));
+    float2 *bins = reinterpret_cast<float2 *>(w + align256(pl.off_bytes) + align256(pl.totals_bytes));
+    float *part = reinterpret_cast<float *>(w + align256(pl.off_bytes) + align256(pl.totals_bytes) +
+                                            align256(pl.bins_bytes));
+    hipError_t e = launch_fill_zero(reinterpret_cast<float *>(off), pl.cnt_len, s);  // 0.0f is all-zero bits
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(bin_count_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, pl.g, a.pts, off);
+    hipLaunchKernelGGL(scan_blocks_kernel, dim3((unsigned)pl.scan_blocks), dim3(256), 0, s, off, pl.cnt_len, totals);
+    hipLaunchKernelGGL(scan_totals_kernel, dim3(1), dim3(256), 0, s, totals, pl.scan_blocks);
+    hipLaunchKernelGGL(scan_add_kernel, dim3((unsigned)((pl.cnt_len + 255) / 256)), dim3(256), 0, s, off,
+                       pl.cnt_len, static_cast<const unsigned *>(totals));
+    hipLaunchKernelGGL(bin_scatter_kernel, dim3((unsigned)((pl.g.wblocks + 3) / 4)), dim3(256), 0, s, pl.g, a.pts,
+                       off, bins);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    GatherLaunch p;
+    p.bins = bins;
+    p.end = off;
+    p.wblocks = pl.g.wblocks;
+    p.Hx = a.Hx;
+    p.Hy = a.Hy;
+    p.ax = a.ax;
+    p.ay = a.ay;
+    p.nx = a.nx;
+    p.ny = a.ny;
+    p.tiles_x = pl.g.tiles_x;
+    p.dst = pl.splits > 1 ? part : a.out;
+    p.scale = a.scale;
+    p.plane = (int64_t)a.nx * a.ny;
+    const int tiles = pl.g.tiles_x * pl.g.tiles_y;
+    switch (a.kernel_id) {
+    case kUniform: e = launch_gather<kUniform>(p, tiles, pl.splits, s); break;
+    case kTriangular: e = launch_gather<kTriangular>(p, tiles, pl.splits, s); break;
+    case kEpanechnikov: e = launch_gather<kEpanechnikov>(p, tiles, pl.splits, s); break;
+    case kQuartic: e = launch_gather<kQuartic>(p, tiles, pl.splits, s); break;
+    case kTriweight: e = launch_gather<kTriweight>(p, tiles, pl.splits, s); break;
+    case kTricube: e = launch_gather<kTricube>(p, tiles, pl.splits, s); break;
+    case kCosine: e = launch_gather<kCosine>(p, tiles, pl.splits, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess || pl.splits == 1) return e;
+    return launch_reduce_splits(part, pl.splits, (int64_t)a.nx * a.ny, a.scale, a.out, s);
+}
+
+}  // namespace kde

@@ -19,7 +19,7 @@
 // points across workgroups ("splits"); a second kernel adds the per-split
 // partial maps in split order and applies the density scale.  The order of every
 // sum is fixed by the launch shape, so results are bitwise reproducible.
-#include "kde_internal.h"
+#include "kde_tile.h"
 
 #include <algorithm>
 #include <cmath>
@@ -28,39 +28,8 @@ namespace kde {
 
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kPointTile = 256;
-
-// g(d) for grid-unit difference d = node - point.  a is arg_scale(kernel, H).
-template <int K>
-__device__ __forceinline__ float factor(float d, float a, float H) {
-    if constexpr (K == kGaussian) {
-        const float t = d * a;
-        return __builtin_amdgcn_exp2f(-t * t);
-    } else {
-        const float u = fminf(fabsf(d) * a, 1.0f);  // |u|, clamped against rounding past 1
-        float v;
-        if constexpr (K == kUniform) {
-            v = 1.0f;
-        } else if constexpr (K == kTriangular) {
-            v = 1.0f - u;
-        } else if constexpr (K == kEpanechnikov) {
-            v = 1.0f - u * u;
-        } else if constexpr (K == kQuartic) {
-            const float w = 1.0f - u * u;
-            v = w * w;
-        } else if constexpr (K == kTriweight) {
-            const float w = 1.0f - u * u;
-            v = w * w * w;
-        } else if constexpr (K == kTricube) {
-            const float w = 1.0f - u * u * u;
-            v = w * w * w;
-        } else {  // cosine: v_cos_f32 takes revolutions, cos(pi u / 2) = cos(2 pi (u / 4))
-            v = __builtin_amdgcn_cosf(u * 0.25f);
-        }
-        return fabsf(d) <= H ? v : 0.0f;
-    }
-}
+using tile::kPointTile;
+using tile::kThreads;
 
 struct DirectLaunch {
     const float2 *pts;
@@ -73,114 +42,24 @@ struct DirectLaunch {
     int64_t plane;      // nx * ny
 };
 
-template <int R, int C>
-__device__ __forceinline__ void store_block(float (&v)[R][C], float *dst, int nx, int ny, int ib, int jb,
-                                            float scale) {
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int j = jb + r;
-        if (j >= ny) break;
-        float *row = dst + (int64_t)j * nx;
-        if ((nx & 3) == 0 && ib + C <= nx && (C % 4) == 0) {
-#pragma unroll
-            for (int c = 0; c < C; c += 4) {
-                float4 w = make_float4(v[r][c] * scale, v[r][c + 1] * scale, v[r][c + 2] * scale,
-                                       v[r][c + 3] * scale);
-                *reinterpret_cast<float4 *>(row + ib + c) = w;
-            }
-        } else {
-#pragma unroll
-            for (int c = 0; c < C; ++c)
-                if (ib + c < nx) row[ib + c] = v[r][c] * scale;
-        }
-    }
-}
-
 // One workgroup: pixel tile blockIdx.x, point split blockIdx.y.
-template <int K, int R, int C, bool kCull>
-__global__ __launch_bounds__(kThreads) void direct_fp32_kernel(DirectLaunch p) {
-    constexpr int TW = 16 * C, TH = 16 * R;
-    __shared__ float2 sp[kPointTile];
-    __shared__ int swave[kThreads / 64];
-
+template <int K>
+__global__ __launch_bounds__(tile::kThreads) void direct_fp32_kernel(DirectLaunch p) {
+    using S = tile::Shape<K>;
+    __shared__ float2 sp[tile::kPointTile];
+    __shared__ int swave[tile::kThreads / 64];
     const int tid = threadIdx.x;
-    const int lx = tid & 15, ly = tid >> 4;
     const int tx = blockIdx.x % p.tiles_x, ty = blockIdx.x / p.tiles_x;
-    const int x0 = tx * TW, y0 = ty * TH;
-    const int ib = x0 + lx * C, jb = y0 + ly * R;
-
-    // Node coordinates of the block's first column and row; the others are these
-    // plus small integers, and (node - X) stays exact in FP32 for |X| < 2^24.
-    const float fib = (float)ib, fjb = (float)jb;
-
-    // Reach of the tile for culling: nodes x0 .. x1, y0 .. y1.
-    const float bx0 = (float)x0, bx1 = (float)(min(x0 + TW, p.nx) - 1);
-    const float by0 = (float)y0, by1 = (float)(min(y0 + TH, p.ny) - 1);
-
-    float tot[R][C];
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int c = 0; c < C; ++c) tot[r][c] = 0.0f;
-
+    const int x0 = tx * S::TW, y0 = ty * S::TH;
+    const int ib = x0 + (tid & 15) * S::C, jb = y0 + (tid >> 4) * S::R;
     const int64_t beg = (int64_t)blockIdx.y * p.per_split;
     const int64_t end = min(p.n, beg + p.per_split);
-    for (int64_t base = beg; base < end; base += kPointTile) {
-        const int64_t q = base + tid;
-        float2 v = make_float2(0.0f, 0.0f);
-        if (q < end) v = p.pts[q];
-        int cnt;
-        __syncthreads();  // previous tile fully consumed
-        if constexpr (kCull) {
-            const bool keep = q < end && v.x + p.Hx >= bx0 && v.x - p.Hx <= bx1 && v.y + p.Hy >= by0 &&
-                              v.y - p.Hy <= by1;
-            const uint64_t m = __ballot(keep);
-            const int lane = tid & 63, w = tid >> 6;
-            const int before = __popcll(m & ((1ull << lane) - 1ull));
-            if (lane == 0) swave[w] = __popcll(m);
-            __syncthreads();
-            int off = 0;
-            cnt = 0;
-#pragma unroll
-            for (int k = 0; k < kThreads / 64; ++k) {
-                off += (k < w) ? swave[k] : 0;
-                cnt += swave[k];
-            }
-            if (keep) sp[off + before] = v;  // survivors keep their index order
-        } else {
-            sp[tid] = v;
-            cnt = (int)min((int64_t)kPointTile, end - base);
-        }
-        __syncthreads();
-        if (cnt == 0) continue;
-
-        float acc[R][C];
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-            for (int c = 0; c < C; ++c) acc[r][c] = 0.0f;
-
-        for (int k = 0; k < cnt; ++k) {
-            const float2 pt = sp[k];
-            const float dx0 = fib - pt.x, dy0 = fjb - pt.y;
-            float kx[C], ky[R];
-#pragma unroll
-            for (int c = 0; c < C; ++c) kx[c] = factor<K>(dx0 + (float)c, p.ax, p.Hx);
-#pragma unroll
-            for (int r = 0; r < R; ++r) ky[r] = factor<K>(dy0 + (float)r, p.ay, p.Hy);
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-#pragma unroll
-                for (int c = 0; c < C; ++c) acc[r][c] = fmaf(ky[r], kx[c], acc[r][c]);
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-            for (int c = 0; c < C; ++c) tot[r][c] += acc[r][c];
-    }
-
+    float tot[S::R][S::C];
+    tile::tile_sums<K, S::R, S::C, S::kCull>(p.pts, beg, end, p.Hx, p.Hy, p.ax, p.ay, ib, jb, (float)x0,
+                                             (float)(min(x0 + S::TW, p.nx) - 1), (float)y0,
+                                             (float)(min(y0 + S::TH, p.ny) - 1), sp, swave, tot);
     float *dst = p.dst + (int64_t)blockIdx.y * p.plane;
-    store_block<R, C>(tot, dst, p.nx, p.ny, ib, jb, gridDim.y == 1 ? p.scale : 1.0f);
+    tile::store_block<S::R, S::C>(tot, dst, p.nx, p.ny, ib, jb, gridDim.y == 1 ? p.scale : 1.0f);
 }
 
 // out[i] = scale * sum_s part[s][i], s in order.
@@ -199,16 +78,14 @@ __global__ __launch_bounds__(256) void fill_zero_kernel(float *out, int64_t coun
     if (i < count) out[i] = 0.0f;
 }
 
-struct Shape {
+struct ShapeInfo {
     int R, C;
     bool cull;
 };
 
-Shape shape_for(int kernel_id) {
-    // Gaussian: every pair counts, large register blocks amortise the factors.
-    // Compact kernels: smaller tiles so that culling skips more.
-    if (kernel_id == kGaussian) return {8, 8, false};
-    return {4, 4, true};
+ShapeInfo shape_for(int kernel_id) {
+    if (kernel_id == kGaussian) return {tile::Shape<kGaussian>::R, tile::Shape<kGaussian>::C, false};
+    return {tile::Shape<kUniform>::R, tile::Shape<kUniform>::C, true};
 }
 
 struct Plan {
@@ -218,7 +95,7 @@ struct Plan {
 };
 
 Plan plan_for(const MapArgs &a) {
-    const Shape s = shape_for(a.kernel_id);
+    const ShapeInfo s = shape_for(a.kernel_id);
     const int TW = 16 * s.C, TH = 16 * s.R;
     Plan pl;
     pl.tiles_x = (a.nx + TW - 1) / TW;
@@ -237,14 +114,10 @@ Plan plan_for(const MapArgs &a) {
 
 template <int K>
 hipError_t launch_k(const MapArgs &a, const Plan &pl, float *dst, hipStream_t stream) {
-    const Shape s = shape_for(K);
     DirectLaunch p{a.pts, a.n, pl.per_split, a.Hx, a.Hy, a.ax, a.ay, a.nx, a.ny, pl.tiles_x, dst, a.scale,
                    (int64_t)a.nx * a.ny};
     dim3 grid(pl.tiles, pl.splits);
-    if (s.cull)
-        hipLaunchKernelGGL((direct_fp32_kernel<K, 4, 4, true>), grid, dim3(kThreads), 0, stream, p);
-    else
-        hipLaunchKernelGGL((direct_fp32_kernel<K, 8, 8, false>), grid, dim3(kThreads), 0, stream, p);
+    hipLaunchKernelGGL((direct_fp32_kernel<K>), grid, dim3(kThreads), 0, stream, p);
     return hipGetLastError();
 }
 
@@ -271,6 +144,7 @@ float arg_scale(int kernel_id, float H) {
 }
 
 size_t direct_workspace_bytes(const MapArgs &a) {
+    if (binning_applies(a)) return binned_workspace_bytes(a);
     const Plan pl = plan_for(a);
     return pl.splits > 1 ? (size_t)pl.splits * a.nx * a.ny * sizeof(float) : 0;
 }
@@ -282,6 +156,7 @@ hipError_t launch_fill_zero(float *out, int64_t count, hipStream_t stream) {
 }
 
 hipError_t launch_direct(const MapArgs &a, void *ws, hipStream_t stream) {
+    if (binning_applies(a)) return launch_binned(a, ws, stream);
     const Plan pl = plan_for(a);
     float *dst = pl.splits > 1 ? static_cast<float *>(ws) : a.out;
     hipError_t e;

@@ -55,9 +55,22 @@ hipError_t launch_direct(const MapArgs &a, void *ws, hipStream_t stream);
 // Bytes of workspace launch_direct needs for these arguments.
 size_t direct_workspace_bytes(const MapArgs &a);
 
+// Support binning for the compact kernels (FP32 direct path): used when the
+// support reaches at most 3 x 3 tiles per point and the count table stays small.
+bool binning_applies(const MapArgs &a);
+size_t binned_workspace_bytes(const MapArgs &a);
+hipError_t launch_binned(const MapArgs &a, void *ws, hipStream_t stream);
+
 // Matrix-core separable path (precision kPrecFp16 .. kPrecBf16x3).
 hipError_t launch_sep(const MapArgs &a, int precision, void *ws, hipStream_t stream);
 size_t sep_workspace_bytes(const MapArgs &a, int precision);
+
+// Batched maps (FP32 direct path) in one persistent launch; use_graph captures
+// the launch sequence once per batch shape and replays it (ws unused then).
+hipError_t run_batched(const MapArgs *args, int n_maps, bool use_graph, void *ws_eager, size_t ws_bytes,
+                       hipStream_t stream);
+size_t batched_workspace_bytes(const MapArgs *args, int n_maps);
+void release_batched_graphs();
 
 // Adjoints.  launch_vjp writes grad[n][2] = (fx Tx_p, fy Ty_p) (if grad is not
 // null) and per-workgroup FP64 sums (Ux, Uy, Q) into part[vjp_blocks(n)][3];

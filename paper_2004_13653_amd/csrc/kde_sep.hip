@@ -70,7 +70,6 @@ struct SepLaunch {
     int64_t n;
     int64_t per_split;  // points per split, multiple of the chunk size
     float ax, ay;       // Gaussian argument scales sqrt(log2(e)/2)/H
-    float kappa_x, kappa_y;  // Gaussian run ratio exp2(-2 a^2)
     float Hx, Hy;       // compact kernels: support half-widths
     float ix, iy;       // compact kernels: 1/H
     int nx, ny, tiles_x;
@@ -201,34 +200,39 @@ __device__ __forceinline__ void put8(const float (&v)[8], uint4 *hi, uint4 *lo, 
 
 // Factors of one operand slice for this thread: R consecutive nodes m0 .. m0+R-1
 // (rows of A or columns of B) against the 8 points `pr` (tile-relative; Gaussian
-// scaled by a).  kRecur (Gaussian, a <= 0.8): one exp2 for g(m0) and one for the
-// ratio rho = g(m0+1)/g(m0) = exp2(-2 a t0 - a^2) per point, then
-// g(m+1) = g(m) rho(m), rho(m+1) = rho(m) kappa with kappa = exp2(-2 a^2).
-// With a <= 0.8 and R <= 8, a start value that underflows implies every value of
-// the run is below 2^-31 of the peak, and rho is clamped to stay finite, so the
-// run never turns a zero into a non-zero or produces NaN.
+// scaled by a).
+//
+// kRecur (Gaussian, a <= 0.8): with the run centre c = m0 + (R-1)/2, t_c =
+// (c - X) a and offsets rho_r = r - (R-1)/2,
+//     g(m0 + r) = exp2(-(t_c + rho_r a)^2) = P_r q_r,
+//     P_r = exp2(-t_c^2 - 2 t_c a rho_r),   q_r = exp2(-(rho_r a)^2).
+// q_r depends only on the node's position in its run (row or column index mod
+// R), so it factors out of the contraction and is applied once per output in
+// the epilogue; the operands carry P_r = P_0 B^r, B = exp2(-2 a t_c): two exp2
+// per point and run, then one multiply per factor.  P_r <= g q_r^-1 <= 2^((R-1)^2
+// a^2 / 4) stays inside FP16 range; a start value P_0 that underflows implies
+// every factor of the run is below 2^-31 of the peak, and B is clamped to stay
+// finite, so a run never turns a zero into a non-zero or produces NaN.
 template <int K, int P, bool kRecur>
-__device__ __forceinline__ void gen_slice(const float (&pr)[8], float m0, float a, float kappa, float H,
-                                          float inv, uint4 *hi, uint4 *lo, int word0, int stride) {
+__device__ __forceinline__ void gen_slice(const float (&pr)[8], float m0, float a, float H, float inv, uint4 *hi,
+                                          uint4 *lo, int word0, int stride) {
     constexpr int R = SepConfig<P>::R;
     if constexpr (kRecur) {
-        float e[8], rho[8];
+        const float mc = m0 + 0.5f * (float)(R - 1) * a;  // centre node (times a)
+        const float span = (float)(R - 1) * a;
+        float e[8], ratio[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            const float t0 = m0 - pr[k];
-            e[k] = __builtin_amdgcn_exp2f(-t0 * t0);
-            rho[k] = __builtin_amdgcn_exp2f(fminf(fmaf(-2.0f * a, t0, -a * a), 126.0f));
+            const float tc = mc - pr[k];
+            e[k] = __builtin_amdgcn_exp2f(tc * (span - tc));  // -t_c^2 + (R-1) a t_c
+            ratio[k] = __builtin_amdgcn_exp2f(fminf(-2.0f * a * tc, 126.0f));
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             put8<P>(e, hi, lo, word0 + r * stride);
             if (r + 1 < R) {
 #pragma unroll
-                for (int k = 0; k < 8; ++k) e[k] *= rho[k];
-            }
-            if (r + 2 < R) {
-#pragma unroll
-                for (int k = 0; k < 8; ++k) rho[k] *= kappa;
+                for (int k = 0; k < 8; ++k) e[k] *= ratio[k];
             }
         }
     } else {
@@ -265,8 +269,8 @@ __device__ __forceinline__ void generate_chunk(const SepLaunch &p, const float2 
         }
     }
     const float ga_y = K == kGaussian ? p.ay : 1.0f, ga_x = K == kGaussian ? p.ax : 1.0f;
-    gen_slice<K, P, kRecur>(py, mrow0, ga_y, p.kappa_y, p.Hy, p.iy, Ahi, Alo, word0, Cfg::kRowWords);
-    gen_slice<K, P, kRecur>(px, mcol0, ga_x, p.kappa_x, p.Hx, p.ix, Bhi, Blo, word0, Cfg::kRowWords);
+    gen_slice<K, P, kRecur>(py, mrow0, ga_y, p.Hy, p.iy, Ahi, Alo, word0, Cfg::kRowWords);
+    gen_slice<K, P, kRecur>(px, mcol0, ga_x, p.Hx, p.ix, Bhi, Blo, word0, Cfg::kRowWords);
 }
 
 // Scheduling hint for the chunk loop: spread the factor generation (VALU, LDS
@@ -377,9 +381,20 @@ __global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p) {
     }
 
     // Epilogue: register r of lane l in a 32 x 32 tile holds row 8 (r / 4) + 4 (l / 32) + r % 4,
-    // column l % 32.
+    // column l % 32.  Gaussian runs: multiply by q(row mod R) q(column mod R).
     float *dst = p.dst + (int64_t)blockIdx.y * p.plane;
     const float sc = gridDim.y == 1 ? p.scale : 1.0f;
+    float qcol = 1.0f, qrow[4] = {1.0f, 1.0f, 1.0f, 1.0f};
+    if constexpr (kRecur) {
+        constexpr float hc = 0.5f * (float)(Cfg::R - 1);
+        const float rc = ((float)(lane % Cfg::R) - hc) * p.ax;
+        qcol = __builtin_amdgcn_exp2f(-rc * rc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float rr = ((float)((4 * (lane >> 5) + r) % Cfg::R) - hc) * p.ay;
+            qrow[r] = __builtin_amdgcn_exp2f(-rr * rr);
+        }
+    }
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
 #pragma unroll
@@ -388,7 +403,8 @@ __global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int row = row0 + 32 * (ta0 + a) + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                if (row < p.ny && col < p.nx) dst[(int64_t)row * p.nx + col] = acc[a][b][r] * sc;
+                if (row < p.ny && col < p.nx)
+                    dst[(int64_t)row * p.nx + col] = acc[a][b][r] * (qrow[r & 3] * qcol * sc);
             }
         }
     }
@@ -435,8 +451,6 @@ hipError_t launch_sep_kp(const MapArgs &a, const SepPlan &pl, float *dst, hipStr
     p.per_split = pl.per_split;
     p.ax = arg_scale(kGaussian, a.Hx);
     p.ay = arg_scale(kGaussian, a.Hy);
-    p.kappa_x = std::exp2(-2.0f * p.ax * p.ax);
-    p.kappa_y = std::exp2(-2.0f * p.ay * p.ay);
     p.Hx = a.Hx;
     p.Hy = a.Hy;
     p.ix = (float)(1.0 / (double)a.Hx);

@@ -236,3 +236,31 @@ def dp_compress(tracks: Tracks, eps_m: float) -> Tracks:
 def compression_ratio(original: Tracks, compressed: Tracks) -> float:
     """CR = (1 - N_c / N_o) x 100 % (Eq. (14))."""
     return (1.0 - compressed.n / original.n) * 100.0
+
+
+# ---------------------------------------------------------------------------
+# Batches of maps ("time windows" of one large pool of tracks).
+
+@dataclass
+class MapSpec:
+    start: int      # first point of the contiguous slice of the pool
+    count: int      # number of points
+    side: int       # grid is side x side over the pool's box
+    h_deg: float    # hx = hy
+    kernel: int     # Table I kernel id
+
+
+def batch_specs(n_maps: int, pool_points: int, seed: int = SEED0 + 4, min_points: int = 1000,
+                max_points: int = 200_000, sides=(256, 512, 1024), h_range=(0.001, 0.008)) -> list[MapSpec]:
+    """Per-map point counts log-uniform in [min_points, max_points], grid sides
+    drawn uniformly from `sides`, bandwidth U(h_range), kernel uniform over the
+    eight; each map is a contiguous slice (a time window) of the pool."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    specs = []
+    for _ in range(n_maps):
+        count = int(round(math.exp(rng.uniform(math.log(min_points), math.log(max_points)))))
+        count = min(count, pool_points)
+        start = int(rng.integers(0, pool_points - count + 1))
+        specs.append(MapSpec(start, count, int(rng.choice(sides)), float(rng.uniform(*h_range)),
+                             int(rng.integers(0, 8))))
+    return specs

@@ -147,3 +147,19 @@ def test_raw_sum_and_determinism():
         np.testing.assert_array_equal(a, b)
         raw = kt.gpu_map(XY, kernel, 0.005, 0.005, g, raw=True)
         np.testing.assert_allclose(raw / (XY.shape[0] * 0.005 * 0.005), a, rtol=3e-7, atol=1e-30)
+
+
+@pytest.mark.parametrize("kernel", [0, 1, 5, 7])
+@pytest.mark.parametrize("H", [1.3, 60.0, 70.0])
+def test_binned_and_scanned_compact_paths(kernel, H):
+    """Compact kernels with n >= 4096 go through support binning when H <= 64 px
+    and through per-tile culling scans otherwise; points also lie outside the
+    grid on every side."""
+    rng = np.random.default_rng(int(H) + 10 * kernel)
+    XY = np.column_stack([rng.uniform(-90, 290, 50000), rng.uniform(-90, 240, 50000)]).astype(np.float32)
+    g, og = kde.Grid(0.0, 199.0, 0.0, 149.0, 200, 150), oracle.Grid(0.0, 199.0, 0.0, 149.0, 200, 150)
+    y = kt.gpu_map(XY, kernel, H, 0.9 * H, g)
+    r = kt.oracle_density_window(XY, kernel, H, 0.9 * H, og, (0, 200, 0, 150))
+    assert kt.peak_error(y, r) <= kt.FP32_GATE
+    y2 = kt.gpu_map(XY, kernel, H, 0.9 * H, g)
+    np.testing.assert_array_equal(y, y2)
