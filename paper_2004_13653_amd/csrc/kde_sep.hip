@@ -66,9 +66,10 @@ struct PrecTraits<kPrecBf16x3> {
 };
 
 struct SepLaunch {
-    const float2 *pts;
+    const float2 *pts;  // padded copy: split s owns [s * pad_stride, (s + 1) * pad_stride)
     int64_t n;
     int64_t per_split;  // points per split, multiple of the chunk size
+    int64_t pad_stride; // per_split + 2 chunks of far-away points
     float ax, ay;       // Gaussian argument scales sqrt(log2(e)/2)/H
     float Hx, Hy;       // compact kernels: support half-widths
     float ix, iy;       // compact kernels: 1/H
@@ -169,20 +170,37 @@ struct SepConfig {
     static constexpr int kRowWords = G + 1;
     static constexpr int kWords = kTile * kRowWords;  // 16-byte LDS words per operand slice
     static constexpr int R = G;                            // consecutive rows (and columns) per thread
+    // VALU instructions the scheduler places after each MFMA in the Gaussian
+    // runs' phases (0: no placement hints).
+#if defined(KDE_SEP_HINT_SINGLE) && defined(KDE_SEP_HINT_SPLIT)
+    static constexpr int kHintValu = kSplit ? KDE_SEP_HINT_SPLIT : KDE_SEP_HINT_SINGLE;
+#else
+    static constexpr int kHintValu = !kSplit ? 0 : PrecTraits<P>::kBf16 ? 6 : 3;
+#endif
 };
 
-// The 8 points of group g in chunk c.  Indices past the split end load the
-// split's last point and are pushed far away (all their factors are 0); adding
-// the offset instead of selecting keeps every load unconditional, so the loads
-// are issued a whole chunk ahead without branches.
-__device__ __forceinline__ void load_points(const SepLaunch &p, int64_t q0, int64_t end, float2 (&v)[8]) {
+// The 8 points of one group: 64 contiguous bytes of the padded copy (points
+// past the split's end are far away, so every factor they produce is 0).
+__device__ __forceinline__ void load_points(const float2 *q, float2 (&v)[8]) {
+    const float4 *q4 = reinterpret_cast<const float4 *>(q);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const int64_t q = q0 + k;
-        const float2 w = p.pts[q < end ? q : end - 1];
-        const float off = q < end ? 0.0f : kFar;
-        v[k] = make_float2(w.x + off, w.y + off);
+    for (int k = 0; k < 4; ++k) {
+        const float4 w = q4[k];
+        v[2 * k] = make_float2(w.x, w.y);
+        v[2 * k + 1] = make_float2(w.z, w.w);
     }
+}
+
+// Copies each split's points into a padded array: split s gets [s * stride,
+// (s + 1) * stride), its points first, then far-away points up to the stride.
+__global__ __launch_bounds__(256) void pad_points_kernel(const float2 *__restrict__ pts, int64_t n,
+                                                         int64_t per_split, int64_t stride, int64_t total,
+                                                         float2 *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int64_t s = i / stride, k = i - s * stride;
+    const int64_t q = s * per_split + k;
+    out[i] = (k < per_split && q < n) ? pts[q] : make_float2(kFar, kFar);
 }
 
 // Writes one row (A) or column (B) of 8 factors: hi, and lo for splits.
@@ -247,6 +265,38 @@ __device__ __forceinline__ void gen_slice(const float (&pr)[8], float m0, float 
     }
 }
 
+// One thread's Gaussian run for one operand slice, emitted row by row so that
+// the emission can be spread over the MFMA phases of a chunk (see gen_slice for
+// the recurrence and why it is safe).
+template <int P>
+struct GaussRun {
+    float e[8], ratio[8];
+    uint4 *hi, *lo;
+    int word, stride;
+
+    __device__ __forceinline__ void start(const float (&pr)[8], float m0, float a, uint4 *h, uint4 *l, int w,
+                                          int st) {
+        constexpr int R = SepConfig<P>::R;
+        const float mc = m0 + 0.5f * (float)(R - 1) * a, span = (float)(R - 1) * a;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const float tc = mc - pr[k];
+            e[k] = __builtin_amdgcn_exp2f(tc * (span - tc));
+            ratio[k] = __builtin_amdgcn_exp2f(fminf(-2.0f * a * tc, 126.0f));
+        }
+        hi = h;
+        lo = l;
+        word = w;
+        stride = st;
+    }
+    __device__ __forceinline__ void emit() {
+        put8<P>(e, hi, lo, word);
+        word += stride;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) e[k] *= ratio[k];
+    }
+};
+
 // Generates one chunk (8 points per thread, given) into an LDS buffer: A (rows,
 // from Y) and B (columns, from X).
 template <int K, int P, bool kRecur>
@@ -271,22 +321,6 @@ __device__ __forceinline__ void generate_chunk(const SepLaunch &p, const float2 
     const float ga_y = K == kGaussian ? p.ay : 1.0f, ga_x = K == kGaussian ? p.ax : 1.0f;
     gen_slice<K, P, kRecur>(py, mrow0, ga_y, p.Hy, p.iy, Ahi, Alo, word0, Cfg::kRowWords);
     gen_slice<K, P, kRecur>(px, mcol0, ga_x, p.Hx, p.ix, Bhi, Blo, word0, Cfg::kRowWords);
-}
-
-// Scheduling hint for the chunk loop: spread the factor generation (VALU, LDS
-// writes) and the fragment reads between the MFMAs, so the one wave per SIMD keeps
-// the matrix core busy while it computes the next chunk's factors.
-template <int NM, int NV, int KK>
-__device__ __forceinline__ void interleave_hint() {
-    constexpr int per_kk = NM / KK;  // MFMAs per k-step
-    __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);  // fragments of the first k-step
-#pragma unroll
-    for (int i = 0; i < NM; ++i) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
-        __builtin_amdgcn_sched_group_barrier(0x002, NV, 0);  // VALU (factor generation)
-        if (i % per_kk < 8 && i < NM - per_kk) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // next fragments
-        if (i % 4 == 3) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);  // factor stores
-    }
 }
 
 template <int K, int P, bool kRecur>
@@ -322,7 +356,7 @@ __global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p) {
     const int64_t beg = (int64_t)blockIdx.y * p.per_split;
     const int64_t end = min(p.n, beg + p.per_split);
     const int64_t nch = (end - beg + Cfg::KC - 1) / Cfg::KC;
-    const int64_t qg = beg + 8 * (tid % Cfg::G);  // first point of this thread's group in chunk 0
+    const float2 *qg = p.pts + blockIdx.y * p.pad_stride + 8 * (tid % Cfg::G);  // this thread's group, chunk 0
     const int ta0 = 4 * (wave >> 1), tb0 = 4 * (wave & 1);  // first MFMA row / column tile of this wave
     // Fragment word of lane `lane` for MFMA tile t (32 rows) and k-step kk: row
     // 32 t + lane % 32, point group 2 kk + lane / 32.
@@ -330,17 +364,86 @@ __global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p) {
     auto frag = [&](int t, int kk) { return frag0 + 32 * t * Cfg::kRowWords + 2 * kk; };
 
     float2 pts[8], nxt[8];
-    load_points(p, qg, end, pts);
-    load_points(p, qg + Cfg::KC, end, nxt);
+    load_points(qg, pts);
+    load_points(qg + Cfg::KC, nxt);
     generate_chunk<K, P, kRecur>(p, pts, tid, x0, y0, mrow0, mcol0, lds0, lds0 + W, lds0 + 2 * W, lds0 + 3 * W);
     __syncthreads();
 
     // One chunk: generate chunk c + 1 into `gen` while the MFMAs consume chunk c
     // from `use`.
+    // Gaussian runs: the chunk is cut into KK phases, each reading one k-step of
+    // fragments, issuing its MFMAs and emitting a share of the next chunk's
+    // factor rows; scheduling barriers keep the phases apart so that every
+    // MFMA group has generation work to overlap with.
+    auto step_phased = [&](int64_t c, uint4 *gen, const uint4 *use) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) pts[k] = nxt[k];
+        load_points(qg + (c + 2) * Cfg::KC, nxt);  // consumed one chunk later
+        float px[8], py[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            px[k] = (pts[k].x - x0) * p.ax;
+            py[k] = (pts[k].y - y0) * p.ay;
+        }
+        const int g8 = tid % Cfg::G, mrun = Cfg::R * (tid / Cfg::G);
+        const int word0 = mrun * Cfg::kRowWords + g8;
+        GaussRun<P> ra, rb;
+        const uint4 *Ah = use, *Bh = use + W, *Al = use + 2 * W, *Bl = use + 3 * W;
+        // Emission plan (rows of A and B per phase), R rows each.
+        constexpr int KKp = Cfg::KK;
+        constexpr int ea[4] = {Cfg::R / KKp, Cfg::R / KKp, Cfg::R / KKp, Cfg::R / KKp};
+        constexpr int eb[4] = {0, KKp == 4 ? 3 : Cfg::R, KKp == 4 ? 3 : 0, KKp == 4 ? 2 : 0};
+#pragma unroll
+        for (int kk = 0; kk < KKp; ++kk) {
+            if (kk == 0) ra.start(py, mrow0, p.ay, gen, gen + 2 * W, word0, Cfg::kRowWords);
+            if (kk == 1) rb.start(px, mcol0, p.ax, gen + W, gen + 3 * W, word0, Cfg::kRowWords);
+            uint4 fa[4], fb[4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a) fa[a] = Ah[frag(ta0 + a, kk)];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) fb[b] = Bh[frag(tb0 + b, kk)];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = mfma<kBf16>(fa[a], fb[b], acc[a][b]);
+            if constexpr (Cfg::kSplit) {
+                uint4 la[4], lb[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) la[a] = Al[frag(ta0 + a, kk)];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) lb[b] = Bl[frag(tb0 + b, kk)];
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        acc[a][b] = mfma<kBf16>(fa[a], lb[b], acc[a][b]);
+                        acc[a][b] = mfma<kBf16>(la[a], fb[b], acc[a][b]);
+                    }
+            }
+#pragma unroll
+            for (int r = 0; r < ea[kk]; ++r) ra.emit();
+#pragma unroll
+            for (int r = 0; r < eb[kk]; ++r) rb.emit();
+            // Split precisions: fragments first, then each MFMA followed by a
+            // slice of the VALU work (the compiler otherwise bunches the MFMAs).
+            if constexpr (Cfg::kHintValu > 0) {
+                __builtin_amdgcn_sched_group_barrier(0x100, Cfg::kSplit ? 16 : 8, 0);
+#pragma unroll
+                for (int i = 0; i < (Cfg::kSplit ? 48 : 16); ++i) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x002, Cfg::kHintValu, 0);
+                    if (i % 4 == 3) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        __syncthreads();
+    };
+
     auto step = [&](int64_t c, uint4 *gen, const uint4 *use) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) pts[k] = nxt[k];
-        load_points(p, qg + (c + 2) * Cfg::KC, end, nxt);  // consumed one chunk later
+        load_points(qg + (c + 2) * Cfg::KC, nxt);  // consumed one chunk later
         generate_chunk<K, P, kRecur>(p, pts, tid, x0, y0, mrow0, mcol0, gen, gen + W, gen + 2 * W, gen + 3 * W);
         const uint4 *Ah = use, *Bh = use + W, *Al = use + 2 * W, *Bl = use + 3 * W;
 #pragma unroll
@@ -369,15 +472,18 @@ __global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p) {
                     }
             }
         }
-#ifdef KDE_SEP_HINT
-        interleave_hint<Cfg::kSplit ? 96 : 64, Cfg::kSplit ? 5 : 6, Cfg::KK>();
-#endif
         __syncthreads();
     };
 
+    constexpr bool kPhased = kRecur;  // phases pace the Gaussian runs' emission
     for (int64_t c = 0; c < nch; c += 2) {
-        step(c, lds1, lds0);
-        if (c + 1 < nch) step(c + 1, lds0, lds1);
+        if constexpr (kPhased) {
+            step_phased(c, lds1, lds0);
+            if (c + 1 < nch) step_phased(c + 1, lds0, lds1);
+        } else {
+            step(c, lds1, lds0);
+            if (c + 1 < nch) step(c + 1, lds0, lds1);
+        }
     }
 
     // Epilogue: register r of lane l in a 32 x 32 tile holds row 8 (r / 4) + 4 (l / 32) + r % 4,
@@ -413,6 +519,8 @@ __global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p) {
 struct SepPlan {
     int tiles_x, tiles, splits;
     int64_t per_split;
+    int64_t pad_stride;   // padded points per split
+    size_t partial_bytes; // split partial planes (0 with one split), 256-byte aligned
 };
 
 SepPlan sep_plan(const MapArgs &a, int kc) {
@@ -426,8 +534,13 @@ SepPlan sep_plan(const MapArgs &a, int kc) {
     per = (per + kc - 1) / kc * kc;
     pl.splits = (int)std::max<int64_t>(1, (a.n + per - 1) / per);
     pl.per_split = per;
+    // Two extra chunks: the point loads run two chunks ahead of the MFMAs.
+    pl.pad_stride = per + 2 * kc;
+    pl.partial_bytes = pl.splits > 1 ? ((size_t)pl.splits * a.nx * a.ny * sizeof(float) + 255) / 256 * 256 : 0;
     return pl;
 }
+
+size_t padded_bytes(const SepPlan &pl) { return (size_t)pl.splits * pl.pad_stride * sizeof(float2); }
 
 template <int P>
 int chunk_of() {
@@ -444,11 +557,13 @@ int chunk_for(int precision) {
 }
 
 template <int K, int P>
-hipError_t launch_sep_kp(const MapArgs &a, const SepPlan &pl, float *dst, hipStream_t stream) {
+hipError_t launch_sep_kp(const MapArgs &a, const SepPlan &pl, const float2 *padded, float *dst,
+                         hipStream_t stream) {
     SepLaunch p;
-    p.pts = a.pts;
+    p.pts = padded;
     p.n = a.n;
     p.per_split = pl.per_split;
+    p.pad_stride = pl.pad_stride;
     p.ax = arg_scale(kGaussian, a.Hx);
     p.ay = arg_scale(kGaussian, a.Hy);
     p.Hx = a.Hx;
@@ -477,16 +592,17 @@ hipError_t launch_sep_kp(const MapArgs &a, const SepPlan &pl, float *dst, hipStr
 }
 
 template <int P>
-hipError_t launch_sep_p(const MapArgs &a, const SepPlan &pl, float *dst, hipStream_t stream) {
+hipError_t launch_sep_p(const MapArgs &a, const SepPlan &pl, const float2 *padded, float *dst,
+                        hipStream_t stream) {
     switch (a.kernel_id) {
-    case kUniform: return launch_sep_kp<kUniform, P>(a, pl, dst, stream);
-    case kTriangular: return launch_sep_kp<kTriangular, P>(a, pl, dst, stream);
-    case kEpanechnikov: return launch_sep_kp<kEpanechnikov, P>(a, pl, dst, stream);
-    case kQuartic: return launch_sep_kp<kQuartic, P>(a, pl, dst, stream);
-    case kTriweight: return launch_sep_kp<kTriweight, P>(a, pl, dst, stream);
-    case kTricube: return launch_sep_kp<kTricube, P>(a, pl, dst, stream);
-    case kGaussian: return launch_sep_kp<kGaussian, P>(a, pl, dst, stream);
-    case kCosine: return launch_sep_kp<kCosine, P>(a, pl, dst, stream);
+    case kUniform: return launch_sep_kp<kUniform, P>(a, pl, padded, dst, stream);
+    case kTriangular: return launch_sep_kp<kTriangular, P>(a, pl, padded, dst, stream);
+    case kEpanechnikov: return launch_sep_kp<kEpanechnikov, P>(a, pl, padded, dst, stream);
+    case kQuartic: return launch_sep_kp<kQuartic, P>(a, pl, padded, dst, stream);
+    case kTriweight: return launch_sep_kp<kTriweight, P>(a, pl, padded, dst, stream);
+    case kTricube: return launch_sep_kp<kTricube, P>(a, pl, padded, dst, stream);
+    case kGaussian: return launch_sep_kp<kGaussian, P>(a, pl, padded, dst, stream);
+    case kCosine: return launch_sep_kp<kCosine, P>(a, pl, padded, dst, stream);
     default: return hipErrorInvalidValue;
     }
 }
@@ -495,18 +611,24 @@ hipError_t launch_sep_p(const MapArgs &a, const SepPlan &pl, float *dst, hipStre
 
 size_t sep_workspace_bytes(const MapArgs &a, int precision) {
     const SepPlan pl = sep_plan(a, chunk_for(precision));
-    return pl.splits > 1 ? (size_t)pl.splits * a.nx * a.ny * sizeof(float) : 0;
+    return pl.partial_bytes + padded_bytes(pl);
 }
 
+// Workspace: [split partial planes][padded points].
 hipError_t launch_sep(const MapArgs &a, int precision, void *ws, hipStream_t stream) {
     const SepPlan pl = sep_plan(a, chunk_for(precision));
     float *dst = pl.splits > 1 ? static_cast<float *>(ws) : a.out;
-    hipError_t e;
+    float2 *padded = reinterpret_cast<float2 *>(static_cast<char *>(ws) + pl.partial_bytes);
+    const int64_t total = (int64_t)pl.splits * pl.pad_stride;
+    hipLaunchKernelGGL(pad_points_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, a.pts, a.n,
+                       pl.per_split, pl.pad_stride, total, padded);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     switch (precision) {
-    case kPrecFp16: e = launch_sep_p<kPrecFp16>(a, pl, dst, stream); break;
-    case kPrecBf16: e = launch_sep_p<kPrecBf16>(a, pl, dst, stream); break;
-    case kPrecFp16x3: e = launch_sep_p<kPrecFp16x3>(a, pl, dst, stream); break;
-    case kPrecBf16x3: e = launch_sep_p<kPrecBf16x3>(a, pl, dst, stream); break;
+    case kPrecFp16: e = launch_sep_p<kPrecFp16>(a, pl, padded, dst, stream); break;
+    case kPrecBf16: e = launch_sep_p<kPrecBf16>(a, pl, padded, dst, stream); break;
+    case kPrecFp16x3: e = launch_sep_p<kPrecFp16x3>(a, pl, padded, dst, stream); break;
+    case kPrecBf16x3: e = launch_sep_p<kPrecBf16x3>(a, pl, padded, dst, stream); break;
     default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess || pl.splits == 1) return e;
