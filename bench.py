@@ -28,28 +28,44 @@ UNIT = "pixel×point evals/s"
 PEAK_MFMA_TFLOPS = {"fp16": 2500.0, "bf16": 2500.0, "fp16x3": 2500.0, "bf16x3": 2500.0}
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 N_TRACKS, PTS_PER_TRACK, SIDE, H_DEG = 8000, 500, 2048, 0.002
+# HBM-side bytes per launch of the FP16 contraction kernel at this workload, from
+# two rocprofv3 counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors a
+# plain 256 MiB elementwise copy gives), profiles/kde_map_gaussian_4M_2048_fp16_traffic.txt.
+# Set to None whenever that kernel changes until the counters are taken again.
+TRAFFIC_FP16 = 342.1e6
 
 
 def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def timed_steps(torch, fn, steps: int, warmup: int):
+def timed_steps(torch, fn, steps: int, warmup: int, kde=None):
     """Runs warmup untimed calls, then `steps` calls, each bracketed by HIP events
-    on the current stream (the stream the library launches on).  Returns
-    (total ms, per-step ms list)."""
+    on the current stream (the stream the library launches on).  With `kde`, every
+    timed call also has the library record a second pair of events around its main
+    kernel alone (kde_time_next_main_kernel).  Returns (total ms, per-step ms list,
+    per-step main-kernel ms list or None)."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    kev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    if kde is not None:
+        for a, b in kev:  # materialise the HIP events before the timed region
+            a.record(stream)
+            b.record(stream)
+        torch.cuda.synchronize()
     ev[0].record(stream)
     for i in range(steps):
+        if kde is not None:
+            kde.time_next_main_kernel(*kev[i])
         fn()
         ev[i + 1].record(stream)
     torch.cuda.synchronize()
     per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
-    return ev[0].elapsed_time(ev[-1]), per
+    kern = [a.elapsed_time(b) for a, b in kev] if kde is not None else None
+    return ev[0].elapsed_time(ev[-1]), per, kern
 
 
 def cpu_baseline(XY, y_maps, og, budget_s: float):
@@ -113,7 +129,8 @@ def bench_adjoint(torch, kde, synth, steps: int):
         f = kde.eval(pts, kname, 0.004, 0.004, g)
         T = kde.eval(ptc, kname, 0.004, 0.004, g)
         gbar = (2.0 * (f - T)).contiguous()
-        tot, _ = timed_steps(torch, lambda: kde.backward(pts, kname, 0.004, 0.004, g, gbar, want_h=False), steps, 1)
+        tot, _, _ = timed_steps(torch, lambda: kde.backward(pts, kname, 0.004, 0.004, g, gbar, want_h=False),
+                                steps, 1)
         ms_vjp = tot / steps
         # with the bandwidth gradient (synchronises for the two host scalars)
         t0 = time.perf_counter()
@@ -145,13 +162,13 @@ def bench_batched(torch, kde, synth, steps: int):
              torch.empty((sp.side, sp.side), device="cuda")) for sp in specs]
     pairs = float(sum(sp.count * sp.side * sp.side for sp in specs))
     gauss_pairs = float(sum(sp.count * sp.side * sp.side for sp in specs if sp.kernel == 6))
-    tot_b, _ = timed_steps(torch, lambda: kde.eval_batched(maps), steps, 2)
+    tot_b, _, _ = timed_steps(torch, lambda: kde.eval_batched(maps), steps, 2)
     ms_b = tot_b / steps
 
     def separate():
         for (p, k, hx, hy, g, o) in maps:
             kde.eval(p, k, hx, hy, g, out=o)
-    tot_s, _ = timed_steps(torch, separate, max(1, steps // 2), 1)
+    tot_s, _, _ = timed_steps(torch, separate, max(1, steps // 2), 1)
     ms_s = tot_s / max(1, steps // 2)
     log(f"batched: {ms_b:.2f} ms vs separate {ms_s:.2f} ms")
     return {"maps": 256, "logical_pairs": pairs, "gaussian_pairs": gauss_pairs, "batched_ms": ms_b,
@@ -169,7 +186,7 @@ def bench_compact(torch, kde, synth, steps: int):
     out = torch.empty((1024, 1024), device="cuda")
     res = {}
     for kname, kid in kde.KERNELS.items():
-        tot, _ = timed_steps(torch, lambda: kde.eval(pts, kid, 0.002, 0.002, g, out=out), steps, 1)
+        tot, _, _ = timed_steps(torch, lambda: kde.eval(pts, kid, 0.002, 0.002, g, out=out), steps, 1)
         ms = tot / steps
         res[kname] = {"ms": ms, "logical_pairs_per_s": pts.shape[0] * 1024 * 1024 / (ms * 1e-3)}
     log("compact kernels: " + ", ".join(f"{k} {v['ms']:.2f} ms" for k, v in res.items()))
@@ -184,6 +201,9 @@ def main() -> int:
     ap.add_argument("--direct-steps", type=int, default=3, help="timed steps of the FP32 direct path")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-once", action="store_true",
+                    help="for counter runs: one warm-up and one timed FP16 map, then a 256 MiB "
+                         "elementwise copy (torch.neg) as the byte-count calibration; prints no JSON")
     ap.add_argument("--sections", default="adjoint,batched,kernels",
                     help="extra measured sections beside the headline: adjoint, batched, kernels (or none)")
     args = ap.parse_args()
@@ -212,30 +232,43 @@ def main() -> int:
     def run(prec):
         return lambda: kde.eval(pts, "gaussian", H_DEG, H_DEG, g, out=out, precision=prec)
 
+    if args.profile_once:
+        f = run("fp16")
+        f()
+        f()
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        log(f"profile run: 2 FP16 maps, then a copy of {src.numel() * 4} bytes read + written")
+        return 0
+
     results, maps = {}, {}
     for prec in ("fp16", "bf16", "fp16x3", "bf16x3", "fp32"):
         steps = args.steps if prec != "fp32" else args.direct_steps
         warm = args.warmup if prec != "fp32" else 1
-        total, per = timed_steps(torch, run(prec), steps, warm)
+        total, per, kern = timed_steps(torch, run(prec), steps, warm, kde)
         ms = total / steps
         results[prec] = {"ms_per_step": ms, "median_ms": statistics.median(per), "value": pairs / (ms * 1e-3),
-                         "steps": steps}
+                         "steps": steps, "main_kernel_ms": sum(kern) / len(kern)}
         maps[prec] = out.cpu().numpy().copy()
         log(f"{prec}: {ms:.3f} ms/step  {pairs / (ms * 1e-3):.3e} pairs/s")
 
     head = results["fp16"]
     mult = {"fp16": 1, "bf16": 1, "fp16x3": 3, "bf16x3": 3}
     for prec in mult:
-        tfl = 2.0 * mult[prec] * pairs / (results[prec]["ms_per_step"] * 1e-3) / 1e12
+        tfl = 2.0 * mult[prec] * pairs / (results[prec]["main_kernel_ms"] * 1e-3) / 1e12
         results[prec]["mfma_tflops"] = tfl
         results[prec]["mfma_frac"] = tfl / PEAK_MFMA_TFLOPS[prec]
     d = results["fp32"]
-    d["fp32_tflops"] = 2.0 * pairs / (d["ms_per_step"] * 1e-3) / 1e12
+    d["fp32_tflops"] = 2.0 * pairs / (d["main_kernel_ms"] * 1e-3) / 1e12
 
-    achieved = 2.0 * pairs / (head["ms_per_step"] * 1e-3) / 1e12
+    # Algorithmic work of one launch of the contraction kernel: 2 flop per
+    # pixel x point pair (one multiply-add of the rank-n product Gy Gx^T).
+    achieved = 2.0 * pairs / (head["main_kernel_ms"] * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_TFLOPS["fp16"], "unit": "TFLOP/s",
-                "frac": achieved / PEAK_MFMA_TFLOPS["fp16"], "traffic": None,
-                "kernel": "sep_mfma_kernel<gaussian, fp16> (+ split reduction)",
+                "frac": achieved / PEAK_MFMA_TFLOPS["fp16"], "traffic": TRAFFIC_FP16,
+                "kernel": "sep_mfma_kernel<gaussian, fp16>", "kernel_ms": head["main_kernel_ms"],
                 "flops_per_launch": 2.0 * pairs}
 
     line = {

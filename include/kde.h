@@ -174,6 +174,18 @@ int kde_backward(const float *points, int64_t n, int32_t kernel_id, double hx, d
 int kde_lscv(const float *points, int64_t n, int32_t kernel_id, double hx, double hy, const kde_grid *g,
              double *value, double *grad_h, void *stream);
 
+/* Measurement hook.  The next kde_eval call made by this thread records
+ * start_event on its stream right before it launches its main kernel (the
+ * separable contraction, the FP32 direct evaluation or the binned gather) and
+ * stop_event right after, so that the elapsed time between the two events is
+ * that kernel's duration alone, without the point padding, split reduction or
+ * binning passes.  Both are hipEvent_t handles owned by the caller, created on
+ * the device of that call with timing enabled; the request is consumed by that
+ * call (also by one that fails or has n = 0, which records nothing).  NULL,
+ * NULL cancels a pending request.  Returns KDE_OK, or KDE_EINVAL if exactly
+ * one event is NULL. */
+int kde_time_next_main_kernel(void *start_event, void *stop_event);
+
 /* Thread-local text of the last failure on this thread ("" if none). */
 const char *kde_last_error(void);
 

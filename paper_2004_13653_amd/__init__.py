@@ -71,6 +71,7 @@ def lib() -> ctypes.CDLL:
             "kde_eval_batched": (ctypes.c_int, [p, i32, u32, p]),
             "kde_backward": (ctypes.c_int, [p, i64, i32, d, d, p, p, p, p, u32, p]),
             "kde_lscv": (ctypes.c_int, [p, i64, i32, d, d, p, p, p, p]),
+            "kde_time_next_main_kernel": (ctypes.c_int, [p, p]),
             "kde_last_error": (ctypes.c_char_p, []),
             "kde_shutdown": (None, []),
         }
@@ -163,6 +164,20 @@ def eval(points, kernel, hx: float, hy: float, grid: Grid, out=None, precision: 
                               hx, hy, grid.handle, out.data_ptr(), PRECISIONS[precision],
                               RAW_SUM if raw else 0, _stream(torch, points.device)))
     return out
+
+
+def time_next_main_kernel(start, stop) -> None:
+    """Arms kde_time_next_main_kernel with two torch.cuda.Event objects (created
+    with enable_timing=True): the next `eval` on this thread records them around
+    its main kernel, so start.elapsed_time(stop) is that kernel's duration."""
+    import torch
+    if start is None and stop is None:
+        _check(lib().kde_time_next_main_kernel(None, None))
+        return
+    for e in (start, stop):
+        if e.cuda_event == 0:  # torch creates the HIP event on its first record
+            e.record(torch.cuda.current_stream())
+    _check(lib().kde_time_next_main_kernel(start.cuda_event, stop.cuda_event))
 
 
 GRID_UNIT_GRADS = 2

@@ -32,6 +32,12 @@ constexpr int64_t kMaxPoints = (int64_t)1 << 31;
 
 thread_local std::string g_err;
 
+// Events armed by kde_time_next_main_kernel for this thread's next kde_eval.
+struct MainTimer {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+thread_local MainTimer g_timer;
+
 int fail(int code, const char *fmt, ...) {
     char buf[512];
     va_list ap;
@@ -186,6 +192,9 @@ int kde_bandwidth_units(const kde_grid *g, double hx, double hy, float *Hx, floa
 
 int kde_eval(const float *points, int64_t n, int32_t kernel_id, double hx, double hy, const kde_grid *g, float *out,
              int32_t precision, uint32_t flags, void *stream) {
+    struct ConsumeTimer {
+        ~ConsumeTimer() { g_timer = MainTimer{}; }
+    } consume_timer;
     try {
         int st = check_map(points, n, kernel_id, hx, hy, g, "kde_eval");
         if (st != KDE_OK) return st;
@@ -346,6 +355,14 @@ int kde_lscv(const float *points, int64_t n, int32_t kernel_id, double hx, doubl
     }
 }
 
+int kde_time_next_main_kernel(void *start_event, void *stop_event) {
+    if ((start_event == nullptr) != (stop_event == nullptr))
+        return fail(KDE_EINVAL, "kde_time_next_main_kernel: give both events or neither");
+    g_timer.start = static_cast<hipEvent_t>(start_event);
+    g_timer.stop = static_cast<hipEvent_t>(stop_event);
+    return KDE_OK;
+}
+
 const char *kde_last_error(void) { return g_err.c_str(); }
 
 void kde_shutdown(void) {
@@ -364,3 +381,15 @@ void kde_shutdown(void) {
 }
 
 }  // extern "C"
+
+namespace kde {
+
+void main_kernel_begin(hipStream_t stream) {
+    if (g_timer.start) (void)hipEventRecord(g_timer.start, stream);
+}
+
+void main_kernel_end(hipStream_t stream) {
+    if (g_timer.stop) (void)hipEventRecord(g_timer.stop, stream);
+}
+
+}  // namespace kde

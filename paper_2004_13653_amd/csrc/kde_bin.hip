@@ -229,7 +229,9 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 template <int K>
 hipError_t launch_gather(const GatherLaunch &p, int tiles, int splits, hipStream_t s) {
+    main_kernel_begin(s);
     hipLaunchKernelGGL(bin_gather_kernel<K>, dim3(tiles, splits), dim3(tile::kThreads), 0, s, p);
+    main_kernel_end(s);
     return hipGetLastError();
 }
 

@@ -117,7 +117,9 @@ hipError_t launch_k(const MapArgs &a, const Plan &pl, float *dst, hipStream_t st
     DirectLaunch p{a.pts, a.n, pl.per_split, a.Hx, a.Hy, a.ax, a.ay, a.nx, a.ny, pl.tiles_x, dst, a.scale,
                    (int64_t)a.nx * a.ny};
     dim3 grid(pl.tiles, pl.splits);
+    main_kernel_begin(stream);
     hipLaunchKernelGGL((direct_fp32_kernel<K>), grid, dim3(kThreads), 0, stream, p);
+    main_kernel_end(stream);
     return hipGetLastError();
 }
 

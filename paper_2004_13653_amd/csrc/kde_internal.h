@@ -90,4 +90,10 @@ hipError_t launch_reduce_splits(const float *part, int splits, int64_t plane, fl
 // Zero-fill kernel (used for empty inputs; no memset nodes in captured graphs).
 hipError_t launch_fill_zero(float *out, int64_t count, hipStream_t stream);
 
+// Measurement hook: the launchers call these right before and after the launch of
+// their main kernel; they record the events a caller armed with
+// kde_time_next_main_kernel on this thread (and do nothing otherwise).
+void main_kernel_begin(hipStream_t stream);
+void main_kernel_end(hipStream_t stream);
+
 }  // namespace kde

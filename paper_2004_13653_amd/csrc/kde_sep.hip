@@ -582,12 +582,16 @@ hipError_t launch_sep_kp(const MapArgs &a, const SepPlan &pl, const float2 *padd
     if constexpr (K == kGaussian) recur = p.ax <= kMaxRecurScale && p.ay <= kMaxRecurScale;
     if constexpr (K == kGaussian) {
         if (recur) {
+            main_kernel_begin(stream);
             hipLaunchKernelGGL((sep_mfma_kernel<K, P, true>), dim3(pl.tiles, pl.splits), dim3(kThreadsSep), 0,
                                stream, p);
+            main_kernel_end(stream);
             return hipGetLastError();
         }
     }
+    main_kernel_begin(stream);
     hipLaunchKernelGGL((sep_mfma_kernel<K, P, false>), dim3(pl.tiles, pl.splits), dim3(kThreadsSep), 0, stream, p);
+    main_kernel_end(stream);
     return hipGetLastError();
 }
 

@@ -93,6 +93,14 @@ def test_other_entry_points_validate():
     assert "kernel" in L.kde_last_error().decode()
 
 
+def test_main_kernel_timer_arguments():
+    L = kde.lib()
+    assert L.kde_time_next_main_kernel(FAKE, None) == kde.KDE_EINVAL
+    assert "both events" in L.kde_last_error().decode()
+    assert L.kde_time_next_main_kernel(None, FAKE) == kde.KDE_EINVAL
+    assert L.kde_time_next_main_kernel(None, None) == kde.KDE_OK
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(kde, "_lib", None)
     monkeypatch.setattr(kde, "LIB_PATH", str(tmp_path / "libkde.so"))

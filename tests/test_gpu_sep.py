@@ -92,3 +92,29 @@ def test_split_is_more_accurate_and_deterministic():
     kt.log(str(errs))
     assert errs["bf16x3"] < errs["bf16"] / 10
     assert errs["fp16x3"] < errs["fp16"] / 10
+
+
+def test_main_kernel_timer_brackets_the_contraction():
+    """kde_time_next_main_kernel: the armed events bracket the contraction kernel
+    alone, inside the whole call, and the request is consumed by that call."""
+    import torch
+    t = kt.lanes(200, 500)
+    g, _ = kt.grids(synth.BOX_C2, 512, 512)
+    pts = kt.to_device(kde.to_grid_units(t.xy, g))
+    out = torch.empty((512, 512), device=kt.device())
+    stream = torch.cuda.current_stream()
+    w0, w1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    kde.eval(pts, 6, 0.004, 0.004, g, out=out, precision="fp16")
+    w0.record(stream)
+    kde.time_next_main_kernel(k0, k1)
+    kde.eval(pts, 6, 0.004, 0.004, g, out=out, precision="fp16")
+    w1.record(stream)
+    torch.cuda.synchronize()
+    whole, main = w0.elapsed_time(w1), k0.elapsed_time(k1)
+    kt.log(f"whole call {whole:.3f} ms, contraction kernel {main:.3f} ms")
+    assert 0.0 < main <= whole
+    # consumed: a further call leaves the events where they were
+    kde.eval(pts, 6, 0.004, 0.004, g, out=out, precision="fp16")
+    torch.cuda.synchronize()
+    assert k0.elapsed_time(k1) == main
