@@ -44,6 +44,7 @@
 #ifndef KDE_H
 #define KDE_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -173,6 +174,42 @@ int kde_backward(const float *points, int64_t n, int32_t kernel_id, double hx, d
  * value (host, FP64) and grad_h (host FP64 [2], or NULL); synchronises stream. */
 int kde_lscv(const float *points, int64_t n, int32_t kernel_id, double hx, double hy, const kde_grid *g,
              double *value, double *grad_h, void *stream);
+
+/* Tile-shape autotuner (FP32 direct path, kde_eval and kde_eval_batched).
+ * The direct kernels exist for register blocks of 2 x 2, 4 x 4 and 8 x 8 pixels
+ * per thread (pixel tiles of 32, 64 and 128 nodes per side).  The first call in
+ * a shape bucket (single maps: kernel class, bandwidth in pixels, point count
+ * and pixel count in log2 buckets; batches: every map's kernel class, point
+ * count and grid) times the candidates on the caller's own data and stream
+ * (each candidate computes the whole map or batch, so outputs stay valid) and
+ * caches the fastest per device architecture; later calls reuse it.  No tuning
+ * runs while `stream` is being captured (the cached or default shape is used).
+ * Untuned defaults: 8 x 8 for the Gaussian, 2 x 2 for compact single maps,
+ * 4 x 4 for compact maps in a batch.  Results of different shapes agree to
+ * FP32 rounding (the split count over points follows the tile count).
+ * Environment, read at first use: KDE_AUTOTUNE=0 disables tuning, KDE_TILE=2|4|8
+ * forces a shape, KDE_AUTOTUNE_CACHE=<path> loads that JSON cache and rewrites
+ * it after each new entry.  The cache is process-wide and thread-safe. */
+
+/* on = 1 (default) tunes on a cache miss; on = 0 uses cached or default
+ * shapes only.  KDE_EINVAL for other values. */
+int kde_autotune_enable(int32_t on);
+/* rc = 2, 4 or 8 makes every FP32 direct map use that register block; 0 ends
+ * the forcing.  KDE_EINVAL for other values. */
+int kde_autotune_force(int32_t rc);
+/* Merges the entries of a JSON cache file ({"format": "kde-autotune-1",
+ * "entries": {key: {"choice": ..., "ms": {...}}}}).  A file that cannot be read,
+ * does not parse or holds an invalid choice is rejected as a whole with
+ * KDE_EINVAL, leaving the cache unchanged. */
+int kde_autotune_load(const char *path);
+/* Writes the cache as JSON to path (via a temporary file and a rename). */
+int kde_autotune_save(const char *path);
+/* Copies the cache's JSON text (NUL-terminated) into buf and sets *needed to
+ * its size including the NUL; with buf NULL only *needed is set.  KDE_EINVAL
+ * if cap is too small (nothing written). */
+int kde_autotune_dump(char *buf, size_t cap, size_t *needed);
+/* Empties the in-memory cache. */
+int kde_autotune_clear(void);
 
 /* Measurement hook.  The next kde_eval call made by this thread records
  * start_event on its stream right before it launches its main kernel (the

@@ -72,6 +72,12 @@ def lib() -> ctypes.CDLL:
             "kde_backward": (ctypes.c_int, [p, i64, i32, d, d, p, p, p, p, u32, p]),
             "kde_lscv": (ctypes.c_int, [p, i64, i32, d, d, p, p, p, p]),
             "kde_time_next_main_kernel": (ctypes.c_int, [p, p]),
+            "kde_autotune_enable": (ctypes.c_int, [i32]),
+            "kde_autotune_force": (ctypes.c_int, [i32]),
+            "kde_autotune_load": (ctypes.c_int, [ctypes.c_char_p]),
+            "kde_autotune_save": (ctypes.c_int, [ctypes.c_char_p]),
+            "kde_autotune_dump": (ctypes.c_int, [p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
+            "kde_autotune_clear": (ctypes.c_int, []),
             "kde_last_error": (ctypes.c_char_p, []),
             "kde_shutdown": (None, []),
         }
@@ -164,6 +170,31 @@ def eval(points, kernel, hx: float, hy: float, grid: Grid, out=None, precision: 
                               hx, hy, grid.handle, out.data_ptr(), PRECISIONS[precision],
                               RAW_SUM if raw else 0, _stream(torch, points.device)))
     return out
+
+
+def autotune(enabled: bool | None = None, force: int | None = None, load: str | None = None,
+             save: str | None = None, clear: bool = False) -> dict:
+    """Tile-shape autotuner of the FP32 direct path (kde_autotune_*): switch
+    tuning on or off, force a register block (2, 4, 8; 0 ends forcing), merge or
+    write a JSON cache file, empty the cache.  Returns the cache's entries
+    {key: {"choice": ..., "ms": {...}}}."""
+    L = lib()
+    if clear:
+        _check(L.kde_autotune_clear())
+    if enabled is not None:
+        _check(L.kde_autotune_enable(1 if enabled else 0))
+    if force is not None:
+        _check(L.kde_autotune_force(int(force)))
+    if load is not None:
+        _check(L.kde_autotune_load(os.fsencode(load)))
+    if save is not None:
+        _check(L.kde_autotune_save(os.fsencode(save)))
+    need = ctypes.c_size_t()
+    _check(L.kde_autotune_dump(None, 0, ctypes.byref(need)))
+    buf = ctypes.create_string_buffer(need.value)
+    _check(L.kde_autotune_dump(buf, need.value, ctypes.byref(need)))
+    import json
+    return json.loads(buf.value.decode())["entries"]
 
 
 def time_next_main_kernel(start, stop) -> None:

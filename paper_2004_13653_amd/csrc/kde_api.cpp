@@ -3,6 +3,7 @@
 // before it touches the GPU and never lets a C++ exception escape.
 #include "kde.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -124,6 +125,207 @@ kde::MapArgs make_args(const float *points, int64_t n, int32_t kernel_id, double
     return a;
 }
 
+// ------------------------------------------------------------ tile-shape tuning
+// The FP32 direct kernels exist for register blocks of 2, 4 and 8 (tiles of 32,
+// 64 and 128 nodes).  The first call in a shape bucket times the candidates on
+// the caller's data and stream (each candidate computes the full map, so the
+// output is valid whichever runs last) and caches the fastest; see
+// kde_autotune.cpp for the buckets.  No tuning while the stream is capturing.
+
+constexpr int kRcGauss = 8;          // defaults: Gaussian maps amortise exp over 8 x 8 blocks,
+constexpr int kRcCompact = 2;        // single compact maps gain most from small tiles,
+constexpr int kRcCompactBatch = 4;   // batched compact tiles each scan all of the map's points
+constexpr float kTuneStopMs = 25.0f; // a default run this long is not tuned further
+
+std::string device_arch() {
+    static std::mutex mu;
+    static std::map<int, std::string> names;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return "unknown";
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = names.find(dev);
+    if (it != names.end()) return it->second;
+    hipDeviceProp_t prop;
+    std::string a = "unknown";
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        a = prop.gcnArchName;
+        const size_t c = a.find(':');
+        if (c != std::string::npos) a.resize(c);
+    }
+    names[dev] = a;
+    return a;
+}
+
+int log2_floor(double v) { return v > 0.0 ? (int)std::floor(std::log2(v)) : -1; }
+
+std::string eval_key(const kde::MapArgs &a) {
+    char buf[192];
+    const double H = std::max(a.Hx, a.Hy);
+    std::snprintf(buf, sizeof buf, "eval/%s/%s/H%d/n%d/px%d", device_arch().c_str(),
+                  a.kernel_id == KDE_GAUSSIAN ? "gauss" : "compact", (int)std::floor(2.0 * std::log2(H)),
+                  log2_floor((double)a.n), log2_floor((double)a.nx * a.ny));
+    return buf;
+}
+
+std::string batch_key(const std::vector<kde::MapArgs> &args) {
+    uint64_t h = 1469598103934665603ull;  // FNV-1a
+    auto mix = [&](int64_t v) {
+        for (int k = 0; k < 8; ++k) {
+            h ^= (uint64_t)((v >> (8 * k)) & 0xff);
+            h *= 1099511628211ull;
+        }
+    };
+    for (const kde::MapArgs &a : args) {
+        mix(a.kernel_id == KDE_GAUSSIAN);
+        mix(a.n);
+        mix(a.nx);
+        mix(a.ny);
+    }
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "batch/%s/%016llx", device_arch().c_str(), (unsigned long long)h);
+    return buf;
+}
+
+bool capturing(hipStream_t s) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &st) != hipSuccess || st != hipStreamCaptureStatusNone;
+}
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t init() {
+        hipError_t e = hipEventCreate(&a);
+        return e == hipSuccess ? hipEventCreate(&b) : e;
+    }
+    ~EventPair() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+// Runs f() twice (the first run warms up) and times the second on stream s.
+template <class F>
+hipError_t time_twice(F f, hipStream_t s, const EventPair &ev, float *ms) {
+    hipError_t e = f();
+    if (e == hipSuccess) e = hipEventRecord(ev.a, s);
+    if (e == hipSuccess) e = f();
+    if (e == hipSuccess) e = hipEventRecord(ev.b, s);
+    if (e == hipSuccess) e = hipEventSynchronize(ev.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, ev.a, ev.b);
+    return e;
+}
+
+// Register-block side for one FP32 direct map: forced, cached, tuned now or default.
+int pick_rc(kde::MapArgs a, hipStream_t s, int *rc_out) {
+    const int forced = kde::tune::forced();
+    const int def = a.kernel_id == KDE_GAUSSIAN ? kRcGauss : kRcCompact;
+    *rc_out = forced ? forced : def;
+    if (forced || !kde::tune::enabled()) return KDE_OK;
+    const std::string key = eval_key(a);
+    std::string choice;
+    if (kde::tune::lookup(key, &choice)) {
+        *rc_out = choice[0] - '0';
+        return KDE_OK;
+    }
+    if (capturing(s)) return KDE_OK;
+    EventPair ev;
+    hipError_t e = ev.init();
+    if (e != hipSuccess) return hip_fail(e, "kde_eval (tile-shape tuning)");
+    kde::tune::Entry entry;
+    float best = INFINITY;
+    int best_rc = def;
+    std::vector<int> order{def};
+    for (int rc : kde::kTileShapes)
+        if (rc != def) order.push_back(rc);
+    for (int rc : order) {
+        a.rc = rc;
+        void *ws = nullptr;
+        int st = get_workspace(s, kde::direct_workspace_bytes(a), &ws);
+        if (st != KDE_OK) return st;
+        float ms = 0.0f;
+        e = time_twice([&] { return kde::launch_direct(a, ws, s); }, s, ev, &ms);
+        if (e != hipSuccess) return hip_fail(e, "kde_eval (tile-shape tuning)");
+        entry.ms.emplace_back(std::to_string(rc), (double)ms);
+        if (ms < best) {
+            best = ms;
+            best_rc = rc;
+        }
+        if (rc == def && ms > kTuneStopMs) break;
+    }
+    entry.choice = std::to_string(best_rc);
+    kde::tune::store(key, entry);
+    *rc_out = best_rc;
+    return KDE_OK;
+}
+
+void set_batch_rc(std::vector<kde::MapArgs> &args, int rc_gauss, int rc_compact) {
+    for (kde::MapArgs &a : args) a.rc = a.kernel_id == KDE_GAUSSIAN ? rc_gauss : rc_compact;
+}
+
+// Register-block sides for a batch (one for its Gaussian maps, one for its
+// compact maps): forced, cached, tuned now (eager runs of the whole batch) or default.
+int pick_batch_rc(std::vector<kde::MapArgs> &args, hipStream_t s) {
+    const int forced = kde::tune::forced();
+    if (forced) {
+        set_batch_rc(args, forced, forced);
+        return KDE_OK;
+    }
+    set_batch_rc(args, kRcGauss, kRcCompactBatch);
+    if (!kde::tune::enabled()) return KDE_OK;
+    const std::string key = batch_key(args);
+    std::string choice;
+    if (kde::tune::lookup(key, &choice)) {
+        set_batch_rc(args, choice[0] - '0', choice[2] - '0');
+        return KDE_OK;
+    }
+    if (capturing(s)) return KDE_OK;
+    bool has_g = false, has_c = false;
+    for (const kde::MapArgs &a : args) (a.kernel_id == KDE_GAUSSIAN ? has_g : has_c) = true;
+    std::vector<int> gs{kRcGauss}, cs{kRcCompactBatch};
+    if (has_g) gs.push_back(4);
+    if (has_c) {
+        cs.push_back(2);
+        cs.push_back(8);
+    }
+    EventPair ev;
+    hipError_t e = ev.init();
+    if (e != hipSuccess) return hip_fail(e, "kde_eval_batched (tile-shape tuning)");
+    kde::tune::Entry entry;
+    float best = INFINITY;
+    int bg = kRcGauss, bc = kRcCompactBatch;
+    bool stop = false;
+    for (int g : gs) {
+        for (int c : cs) {
+            set_batch_rc(args, g, c);
+            const size_t bytes = kde::batched_workspace_bytes(args.data(), (int)args.size());
+            void *ws = nullptr;
+            int st = get_workspace(s, bytes, &ws);
+            if (st != KDE_OK) return st;
+            float ms = 0.0f;
+            e = time_twice([&] { return kde::run_batched(args.data(), (int)args.size(), false, ws, bytes, s); }, s,
+                           ev, &ms);
+            if (e != hipSuccess) return hip_fail(e, "kde_eval_batched (tile-shape tuning)");
+            char name[8];
+            std::snprintf(name, sizeof name, "%d,%d", g, c);
+            entry.ms.emplace_back(name, (double)ms);
+            if (ms < best) {
+                best = ms;
+                bg = g;
+                bc = c;
+            }
+            if (g == kRcGauss && c == kRcCompactBatch && ms > 4.0f * kTuneStopMs) stop = true;
+            if (stop) break;
+        }
+        if (stop) break;
+    }
+    char name[8];
+    std::snprintf(name, sizeof name, "%d,%d", bg, bc);
+    entry.choice = name;
+    kde::tune::store(key, entry);
+    set_batch_rc(args, bg, bc);
+    return KDE_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -210,6 +412,10 @@ int kde_eval(const float *points, int64_t n, int32_t kernel_id, double hx, doubl
         }
         kde::MapArgs a = make_args(points, n, kernel_id, hx, hy, g, out, flags);
         const bool direct = precision == KDE_FP32_DIRECT;
+        if (direct) {
+            st = pick_rc(a, s, &a.rc);
+            if (st != KDE_OK) return st;
+        }
         void *ws = nullptr;
         st = get_workspace(s, direct ? kde::direct_workspace_bytes(a) : kde::sep_workspace_bytes(a, precision), &ws);
         if (st != KDE_OK) return st;
@@ -241,11 +447,13 @@ int kde_eval_batched(const kde_map *maps, int32_t n_maps, uint32_t flags, void *
         }
         hipStream_t s = static_cast<hipStream_t>(stream);
         const bool eager = (flags & KDE_BATCH_EAGER) != 0;
+        int st = pick_batch_rc(args, s);
+        if (st != KDE_OK) return st;
         void *ws = nullptr;
         size_t bytes = 0;
         if (eager) {
             bytes = kde::batched_workspace_bytes(args.data(), n_maps);
-            int st = get_workspace(s, bytes, &ws);
+            st = get_workspace(s, bytes, &ws);
             if (st != KDE_OK) return st;
         }
         hipError_t e = kde::run_batched(args.data(), n_maps, !eager, ws, bytes, s);
@@ -353,6 +561,60 @@ int kde_lscv(const float *points, int64_t n, int32_t kernel_id, double hx, doubl
     } catch (...) {
         return fail(KDE_EHIP, "kde_lscv: internal error");
     }
+}
+
+int kde_autotune_enable(int32_t on) {
+    if (on != 0 && on != 1) return fail(KDE_EINVAL, "kde_autotune_enable: on must be 0 or 1");
+    kde::tune::set_enabled(on == 1);
+    return KDE_OK;
+}
+
+int kde_autotune_force(int32_t rc) {
+    if (rc != 0 && !kde::valid_rc(rc)) return fail(KDE_EINVAL, "kde_autotune_force: rc must be 0, 2, 4 or 8");
+    kde::tune::set_forced(rc);
+    return KDE_OK;
+}
+
+int kde_autotune_load(const char *path) {
+    try {
+        if (path == nullptr) return fail(KDE_EINVAL, "kde_autotune_load: path is NULL");
+        std::string err;
+        if (!kde::tune::load(path, &err)) return fail(KDE_EINVAL, "kde_autotune_load: %s", err.c_str());
+        return KDE_OK;
+    } catch (...) {
+        return fail(KDE_ENOMEM, "kde_autotune_load: out of host memory");
+    }
+}
+
+int kde_autotune_save(const char *path) {
+    try {
+        if (path == nullptr) return fail(KDE_EINVAL, "kde_autotune_save: path is NULL");
+        std::string err;
+        if (!kde::tune::save(path, &err)) return fail(KDE_EINVAL, "kde_autotune_save: %s", err.c_str());
+        return KDE_OK;
+    } catch (...) {
+        return fail(KDE_ENOMEM, "kde_autotune_save: out of host memory");
+    }
+}
+
+int kde_autotune_dump(char *buf, size_t cap, size_t *needed) {
+    try {
+        if (needed == nullptr) return fail(KDE_EINVAL, "kde_autotune_dump: needed is NULL");
+        const std::string text = kde::tune::dump();
+        *needed = text.size() + 1;
+        if (buf == nullptr) return KDE_OK;
+        if (cap < text.size() + 1) return fail(KDE_EINVAL, "kde_autotune_dump: buffer of %zu bytes, need %zu", cap,
+                                                text.size() + 1);
+        std::memcpy(buf, text.c_str(), text.size() + 1);
+        return KDE_OK;
+    } catch (...) {
+        return fail(KDE_ENOMEM, "kde_autotune_dump: out of host memory");
+    }
+}
+
+int kde_autotune_clear(void) {
+    kde::tune::clear();
+    return KDE_OK;
 }
 
 int kde_time_next_main_kernel(void *start_event, void *stop_event) {

@@ -42,7 +42,7 @@ struct BMap {
     const float2 *pts;
     float *out;
     int64_t n;
-    int kernel;
+    int kernel, rc;   // kernel id, register-block side (tile side 16 rc)
     int nx, ny, tiles_x;
     float Hx, Hy, ax, ay, scale;
 };
@@ -50,7 +50,7 @@ struct BMap {
 struct BItem {
     int map, tile, split, nsplit;
     int64_t p0, p1;
-    int64_t slot;      // index of this split's partial tile (split items only)
+    int64_t slot;      // first float of this split's partial tile (split items only)
     int tile_global;   // index of the tile's finish counter (split items only)
     int pad;
 };
@@ -63,10 +63,10 @@ struct BatchLaunch {
     float *partials;
 };
 
-template <int K>
+template <int K, int RC>
 __device__ __forceinline__ void run_item(const BMap &m, const BItem &w, const BatchLaunch &b, float2 *sp,
                                          int *swave, int *s_last) {
-    using S = tile::Shape<K>;
+    using S = tile::Shape<K, RC>;
     const int tid = threadIdx.x;
     const int tx = w.tile % m.tiles_x, ty = w.tile / m.tiles_x;
     const int x0 = tx * S::TW, y0 = ty * S::TH;
@@ -82,7 +82,7 @@ __device__ __forceinline__ void run_item(const BMap &m, const BItem &w, const Ba
     }
     // Partial tile, row-major TW x TH.
     constexpr int kTileElems = S::TW * S::TH;
-    float *mine = b.partials + w.slot * kTileElems;
+    float *mine = b.partials + w.slot;
 #pragma unroll
     for (int r = 0; r < S::R; ++r)
 #pragma unroll
@@ -93,7 +93,7 @@ __device__ __forceinline__ void run_item(const BMap &m, const BItem &w, const Ba
     __syncthreads();
     if (!*s_last) return;
     __threadfence();  // acquire the other splits' partials
-    const float *first = b.partials + (w.slot - w.split) * kTileElems;
+    const float *first = b.partials + (w.slot - (int64_t)w.split * kTileElems);
 #pragma unroll
     for (int r = 0; r < S::R; ++r)
 #pragma unroll
@@ -103,6 +103,17 @@ __device__ __forceinline__ void run_item(const BMap &m, const BItem &w, const Ba
             tot[r][c] = v;
         }
     tile::store_block<S::R, S::C>(tot, m.out, m.nx, m.ny, ib, jb, m.scale);
+}
+
+template <int K>
+__device__ __forceinline__ void run_shape(const BMap &m, const BItem &w, const BatchLaunch &b, float2 *sp,
+                                          int *swave, int *s_last) {
+    if (m.rc == 2)
+        run_item<K, 2>(m, w, b, sp, swave, s_last);
+    else if (m.rc == 4)
+        run_item<K, 4>(m, w, b, sp, swave, s_last);
+    else
+        run_item<K, 8>(m, w, b, sp, swave, s_last);
 }
 
 __global__ __launch_bounds__(kThreads) void batched_kernel(BatchLaunch b) {
@@ -118,14 +129,14 @@ __global__ __launch_bounds__(kThreads) void batched_kernel(BatchLaunch b) {
         const BItem w = b.items[it];
         const BMap m = b.maps[w.map];
         switch (m.kernel) {
-        case kUniform: run_item<kUniform>(m, w, b, sp, swave, &s_last); break;
-        case kTriangular: run_item<kTriangular>(m, w, b, sp, swave, &s_last); break;
-        case kEpanechnikov: run_item<kEpanechnikov>(m, w, b, sp, swave, &s_last); break;
-        case kQuartic: run_item<kQuartic>(m, w, b, sp, swave, &s_last); break;
-        case kTriweight: run_item<kTriweight>(m, w, b, sp, swave, &s_last); break;
-        case kTricube: run_item<kTricube>(m, w, b, sp, swave, &s_last); break;
-        case kGaussian: run_item<kGaussian>(m, w, b, sp, swave, &s_last); break;
-        default: run_item<kCosine>(m, w, b, sp, swave, &s_last); break;
+        case kUniform: run_shape<kUniform>(m, w, b, sp, swave, &s_last); break;
+        case kTriangular: run_shape<kTriangular>(m, w, b, sp, swave, &s_last); break;
+        case kEpanechnikov: run_shape<kEpanechnikov>(m, w, b, sp, swave, &s_last); break;
+        case kQuartic: run_shape<kQuartic>(m, w, b, sp, swave, &s_last); break;
+        case kTriweight: run_shape<kTriweight>(m, w, b, sp, swave, &s_last); break;
+        case kTricube: run_shape<kTricube>(m, w, b, sp, swave, &s_last); break;
+        case kGaussian: run_shape<kGaussian>(m, w, b, sp, swave, &s_last); break;
+        default: run_shape<kCosine>(m, w, b, sp, swave, &s_last); break;
         }
     }
 }
@@ -137,14 +148,11 @@ __global__ void zero_ints_kernel(int *p, int count) {
 
 // ------------------------------------------------------------------ host side
 
-int tile_w(int kernel) { return kernel == kGaussian ? tile::Shape<kGaussian>::TW : tile::Shape<kUniform>::TW; }
-int tile_h(int kernel) { return kernel == kGaussian ? tile::Shape<kGaussian>::TH : tile::Shape<kUniform>::TH; }
-
 struct Plan {
     std::vector<BMap> maps;
     std::vector<BItem> items;
     int n_split_tiles = 0;
-    int64_t n_slots = 0;
+    int64_t n_slots = 0;  // floats of partial tiles
     std::string signature;  // item list and static map fields
 };
 
@@ -159,12 +167,13 @@ Plan make_plan(const MapArgs *args, int n_maps) {
     std::vector<Costed> cs;
     for (int m = 0; m < n_maps; ++m) {
         const MapArgs &a = args[m];
-        const int TW = tile_w(a.kernel_id), TH = tile_h(a.kernel_id);
+        const int TW = 16 * a.rc, TH = 16 * a.rc;
         BMap &bm = pl.maps[m];
         bm.pts = a.pts;
         bm.out = a.out;
         bm.n = a.n;
         bm.kernel = a.kernel_id;
+        bm.rc = a.rc;
         bm.nx = a.nx;
         bm.ny = a.ny;
         bm.tiles_x = (a.nx + TW - 1) / TW;
@@ -191,7 +200,11 @@ Plan make_plan(const MapArgs *args, int n_maps) {
                 it.nsplit = nsplit;
                 it.p0 = std::min<int64_t>(a.n, s * per);
                 it.p1 = std::min<int64_t>(a.n, (s + 1) * per);
-                it.slot = nsplit > 1 ? pl.n_slots++ : -1;
+                it.slot = -1;
+                if (nsplit > 1) {
+                    it.slot = pl.n_slots;
+                    pl.n_slots += (int64_t)TW * TH;
+                }
                 it.tile_global = tg;
                 // Dense tiles cost pairs; culled tiles cost the scan plus a small
                 // share of in-support work.
@@ -208,7 +221,7 @@ Plan make_plan(const MapArgs *args, int n_maps) {
     // re-uploaded each call (pointers, bandwidth-dependent scalars).
     pl.signature.assign(reinterpret_cast<const char *>(pl.items.data()), pl.items.size() * sizeof(BItem));
     for (const BMap &bm : pl.maps) {
-        const int32_t st[5] = {bm.kernel, bm.nx, bm.ny, bm.tiles_x, (int32_t)(bm.n & 0x7fffffff)};
+        const int32_t st[6] = {bm.kernel, bm.rc, bm.nx, bm.ny, bm.tiles_x, (int32_t)(bm.n & 0x7fffffff)};
         pl.signature.append(reinterpret_cast<const char *>(st), sizeof st);
     }
     return pl;
@@ -230,8 +243,7 @@ Layout layout_of(const Plan &pl) {
     L.counters_off = L.stage_bytes;
     L.n_counters = 1 + pl.n_split_tiles;
     L.partials_off = align256(L.counters_off + (size_t)L.n_counters * sizeof(int));
-    const size_t tile_elems = (size_t)tile::Shape<kGaussian>::TW * tile::Shape<kGaussian>::TH;
-    L.total = align256(L.partials_off + (size_t)pl.n_slots * tile_elems * sizeof(float));
+    L.total = align256(L.partials_off + (size_t)pl.n_slots * sizeof(float));
     return L;
 }
 
@@ -292,6 +304,8 @@ std::map<std::pair<int, std::string>, std::unique_ptr<Captured>> g_graphs;  // (
 
 hipError_t run_batched(const MapArgs *args, int n_maps, bool use_graph, void *ws_eager, size_t ws_bytes,
                        hipStream_t stream) {
+    for (int m = 0; m < n_maps; ++m)
+        if (!valid_rc(args[m].rc)) return hipErrorInvalidValue;
     const Plan pl = make_plan(args, n_maps);
     if (pl.items.empty()) return hipSuccess;
     const Layout L = layout_of(pl);

@@ -1,7 +1,7 @@
 // Support binning for the compact kernels (FP32 direct path).
 //
-// A point contributes only to nodes within H of it, so each 64 x 64 output tile
-// needs only the points whose support square [X +- Hx] x [Y +- Hy] reaches one
+// A point contributes only to nodes within H of it, so each T x T output tile
+// (T = 16 rc, the map's register-block tile) needs only the points whose support square [X +- Hx] x [Y +- Hy] reaches one
 // of its nodes.  Instead of every tile scanning all points, the points are
 // counting-sorted into per-tile bins:
 //
@@ -28,11 +28,11 @@ namespace kde {
 
 namespace {
 
-constexpr int kBinTile = tile::Shape<kUniform>::TW;  // 64, the compact kernels' tile side
 constexpr int kScanBlock = 1024;
 
 struct BinGeom {
     int nx, ny, tiles_x, tiles_y;
+    int tile;  // tile side in nodes
     float Hx, Hy;
     int64_t n, wblocks;  // points, 64-point wave blocks
 };
@@ -46,10 +46,10 @@ __device__ __forceinline__ void reach(const BinGeom &g, float2 v, int &tx0, int 
         tx1 = ty1 = 0;
         return;
     }
-    tx0 = (int)i0 / kBinTile;
-    tx1 = (int)i1 / kBinTile;
-    ty0 = (int)j0 / kBinTile;
-    ty1 = (int)j1 / kBinTile;
+    tx0 = (int)i0 / g.tile;
+    tx1 = (int)i1 / g.tile;
+    ty0 = (int)j0 / g.tile;
+    ty1 = (int)j1 / g.tile;
 }
 
 __global__ __launch_bounds__(256) void bin_count_kernel(BinGeom g, const float2 *__restrict__ pts,
@@ -174,9 +174,9 @@ struct GatherLaunch {
     int64_t plane;
 };
 
-template <int K>
+template <int K, int RC>
 __global__ __launch_bounds__(tile::kThreads) void bin_gather_kernel(GatherLaunch p) {
-    using S = tile::Shape<K>;
+    using S = tile::Shape<K, RC>;
     __shared__ float2 sp[tile::kPointTile];
     __shared__ int swave[tile::kThreads / 64];
     const int t = blockIdx.x, tid = threadIdx.x;
@@ -204,8 +204,10 @@ BinPlan bin_plan(const MapArgs &a) {
     BinPlan pl;
     pl.g.nx = a.nx;
     pl.g.ny = a.ny;
-    pl.g.tiles_x = (a.nx + kBinTile - 1) / kBinTile;
-    pl.g.tiles_y = (a.ny + kBinTile - 1) / kBinTile;
+    const int T = 16 * a.rc;
+    pl.g.tile = T;
+    pl.g.tiles_x = (a.nx + T - 1) / T;
+    pl.g.tiles_y = (a.ny + T - 1) / T;
     pl.g.Hx = a.Hx;
     pl.g.Hy = a.Hy;
     pl.g.n = a.n;
@@ -213,8 +215,8 @@ BinPlan bin_plan(const MapArgs &a) {
     pl.cnt_len = (int64_t)pl.g.tiles_x * pl.g.tiles_y * pl.g.wblocks;
     pl.scan_blocks = (pl.cnt_len + kScanBlock - 1) / kScanBlock;
     // Tiles a point can reach per axis: its support spans at most 2H + 1 nodes.
-    const int64_t rx = std::min<int64_t>(pl.g.tiles_x, (int64_t)(2.0f * a.Hx) / kBinTile + 2);
-    const int64_t ry = std::min<int64_t>(pl.g.tiles_y, (int64_t)(2.0f * a.Hy) / kBinTile + 2);
+    const int64_t rx = std::min<int64_t>(pl.g.tiles_x, (int64_t)(2.0f * a.Hx) / T + 2);
+    const int64_t ry = std::min<int64_t>(pl.g.tiles_y, (int64_t)(2.0f * a.Hy) / T + 2);
     pl.max_entries = a.n * rx * ry;
     const int64_t tiles = (int64_t)pl.g.tiles_x * pl.g.tiles_y;
     pl.splits = (int)std::max<int64_t>(1, std::min<int64_t>(8, 2048 / std::max<int64_t>(1, tiles)));
@@ -227,19 +229,30 @@ BinPlan bin_plan(const MapArgs &a) {
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-template <int K>
-hipError_t launch_gather(const GatherLaunch &p, int tiles, int splits, hipStream_t s) {
+template <int K, int RC>
+hipError_t launch_gather_r(const GatherLaunch &p, int tiles, int splits, hipStream_t s) {
     main_kernel_begin(s);
-    hipLaunchKernelGGL(bin_gather_kernel<K>, dim3(tiles, splits), dim3(tile::kThreads), 0, s, p);
+    hipLaunchKernelGGL((bin_gather_kernel<K, RC>), dim3(tiles, splits), dim3(tile::kThreads), 0, s, p);
     main_kernel_end(s);
     return hipGetLastError();
+}
+
+template <int K>
+hipError_t launch_gather(const GatherLaunch &p, int rc, int tiles, int splits, hipStream_t s) {
+    switch (rc) {
+    case 2: return launch_gather_r<K, 2>(p, tiles, splits, s);
+    case 4: return launch_gather_r<K, 4>(p, tiles, splits, s);
+    case 8: return launch_gather_r<K, 8>(p, tiles, splits, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
 
 bool binning_applies(const MapArgs &a) {
-    if (a.kernel_id == kGaussian || a.n < 4096) return false;
-    if (a.Hx > (float)kBinTile || a.Hy > (float)kBinTile) return false;  // at most 3 x 3 tiles per point
+    if (a.kernel_id == kGaussian || a.n < 4096 || !valid_rc(a.rc)) return false;
+    const float T = (float)(16 * a.rc);
+    if (a.Hx > T || a.Hy > T) return false;  // at most 3 x 3 tiles per point
     const BinPlan pl = bin_plan(a);
     return pl.cnt_len <= (int64_t(1) << 26) && pl.max_entries <= (int64_t(1) << 30);
 }
@@ -283,13 +296,13 @@ hipError_t launch_binned(const MapArgs &a, void *ws, hipStream_t s) {
     p.plane = (int64_t)a.nx * a.ny;
     const int tiles = pl.g.tiles_x * pl.g.tiles_y;
     switch (a.kernel_id) {
-    case kUniform: e = launch_gather<kUniform>(p, tiles, pl.splits, s); break;
-    case kTriangular: e = launch_gather<kTriangular>(p, tiles, pl.splits, s); break;
-    case kEpanechnikov: e = launch_gather<kEpanechnikov>(p, tiles, pl.splits, s); break;
-    case kQuartic: e = launch_gather<kQuartic>(p, tiles, pl.splits, s); break;
-    case kTriweight: e = launch_gather<kTriweight>(p, tiles, pl.splits, s); break;
-    case kTricube: e = launch_gather<kTricube>(p, tiles, pl.splits, s); break;
-    case kCosine: e = launch_gather<kCosine>(p, tiles, pl.splits, s); break;
+    case kUniform: e = launch_gather<kUniform>(p, a.rc, tiles, pl.splits, s); break;
+    case kTriangular: e = launch_gather<kTriangular>(p, a.rc, tiles, pl.splits, s); break;
+    case kEpanechnikov: e = launch_gather<kEpanechnikov>(p, a.rc, tiles, pl.splits, s); break;
+    case kQuartic: e = launch_gather<kQuartic>(p, a.rc, tiles, pl.splits, s); break;
+    case kTriweight: e = launch_gather<kTriweight>(p, a.rc, tiles, pl.splits, s); break;
+    case kTricube: e = launch_gather<kTricube>(p, a.rc, tiles, pl.splits, s); break;
+    case kCosine: e = launch_gather<kCosine>(p, a.rc, tiles, pl.splits, s); break;
     default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess || pl.splits == 1) return e;

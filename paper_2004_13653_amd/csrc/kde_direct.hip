@@ -6,7 +6,8 @@
 // whole point tiles outside a workgroup's reach are skipped).
 //
 // Layout.  A workgroup of 256 threads (16 x 16) owns a TW x TH pixel tile, each
-// thread an R x C register block of R consecutive rows and C consecutive columns,
+// thread an R x C register block (R = C = 2, 4 or 8, chosen per map) of R
+// consecutive rows and C consecutive columns,
 // so the 16 threads of a row of the thread grid store 16*C contiguous floats.
 // Points stream through LDS 256 at a time and are read back as wave-wide
 // broadcasts.  Per point a thread evaluates C + R one-dimensional factors and
@@ -43,9 +44,9 @@ struct DirectLaunch {
 };
 
 // One workgroup: pixel tile blockIdx.x, point split blockIdx.y.
-template <int K>
+template <int K, int RC>
 __global__ __launch_bounds__(tile::kThreads) void direct_fp32_kernel(DirectLaunch p) {
-    using S = tile::Shape<K>;
+    using S = tile::Shape<K, RC>;
     __shared__ float2 sp[tile::kPointTile];
     __shared__ int swave[tile::kThreads / 64];
     const int tid = threadIdx.x;
@@ -78,16 +79,6 @@ __global__ __launch_bounds__(256) void fill_zero_kernel(float *out, int64_t coun
     if (i < count) out[i] = 0.0f;
 }
 
-struct ShapeInfo {
-    int R, C;
-    bool cull;
-};
-
-ShapeInfo shape_for(int kernel_id) {
-    if (kernel_id == kGaussian) return {tile::Shape<kGaussian>::R, tile::Shape<kGaussian>::C, false};
-    return {tile::Shape<kUniform>::R, tile::Shape<kUniform>::C, true};
-}
-
 struct Plan {
     int tiles_x, tiles;
     int splits;
@@ -95,8 +86,7 @@ struct Plan {
 };
 
 Plan plan_for(const MapArgs &a) {
-    const ShapeInfo s = shape_for(a.kernel_id);
-    const int TW = 16 * s.C, TH = 16 * s.R;
+    const int TW = 16 * a.rc, TH = 16 * a.rc;
     Plan pl;
     pl.tiles_x = (a.nx + TW - 1) / TW;
     pl.tiles = pl.tiles_x * ((a.ny + TH - 1) / TH);
@@ -112,15 +102,25 @@ Plan plan_for(const MapArgs &a) {
     return pl;
 }
 
-template <int K>
-hipError_t launch_k(const MapArgs &a, const Plan &pl, float *dst, hipStream_t stream) {
+template <int K, int RC>
+hipError_t launch_kr(const MapArgs &a, const Plan &pl, float *dst, hipStream_t stream) {
     DirectLaunch p{a.pts, a.n, pl.per_split, a.Hx, a.Hy, a.ax, a.ay, a.nx, a.ny, pl.tiles_x, dst, a.scale,
                    (int64_t)a.nx * a.ny};
     dim3 grid(pl.tiles, pl.splits);
     main_kernel_begin(stream);
-    hipLaunchKernelGGL((direct_fp32_kernel<K>), grid, dim3(kThreads), 0, stream, p);
+    hipLaunchKernelGGL((direct_fp32_kernel<K, RC>), grid, dim3(kThreads), 0, stream, p);
     main_kernel_end(stream);
     return hipGetLastError();
+}
+
+template <int K>
+hipError_t launch_k(const MapArgs &a, const Plan &pl, float *dst, hipStream_t stream) {
+    switch (a.rc) {
+    case 2: return launch_kr<K, 2>(a, pl, dst, stream);
+    case 4: return launch_kr<K, 4>(a, pl, dst, stream);
+    case 8: return launch_kr<K, 8>(a, pl, dst, stream);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
@@ -146,6 +146,7 @@ float arg_scale(int kernel_id, float H) {
 }
 
 size_t direct_workspace_bytes(const MapArgs &a) {
+    if (!valid_rc(a.rc)) return 0;
     if (binning_applies(a)) return binned_workspace_bytes(a);
     const Plan pl = plan_for(a);
     return pl.splits > 1 ? (size_t)pl.splits * a.nx * a.ny * sizeof(float) : 0;
@@ -158,6 +159,7 @@ hipError_t launch_fill_zero(float *out, int64_t count, hipStream_t stream) {
 }
 
 hipError_t launch_direct(const MapArgs &a, void *ws, hipStream_t stream) {
+    if (!valid_rc(a.rc)) return hipErrorInvalidValue;
     if (binning_applies(a)) return launch_binned(a, ws, stream);
     const Plan pl = plan_for(a);
     float *dst = pl.splits > 1 ? static_cast<float *>(ws) : a.out;

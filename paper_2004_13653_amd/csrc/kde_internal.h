@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
 
 namespace kde {
 
@@ -46,7 +49,12 @@ struct MapArgs {
     int nx, ny;
     float scale;        // c^2 / (n hx hy), or c^2 for raw sums
     float *out;         // [ny][nx]
+    int rc = 0;         // FP32 direct: register block side (2, 4 or 8; tile side 16 rc)
 };
+
+// Register-block sides the FP32 direct kernels are built for.
+constexpr int kTileShapes[3] = {2, 4, 8};
+inline bool valid_rc(int rc) { return rc == 2 || rc == 4 || rc == 8; }
 
 // FP32 direct path: enqueues the map on `stream`; ws holds
 // direct_workspace_bytes(a) bytes of device scratch.  Returns the launch status.
@@ -56,7 +64,8 @@ hipError_t launch_direct(const MapArgs &a, void *ws, hipStream_t stream);
 size_t direct_workspace_bytes(const MapArgs &a);
 
 // Support binning for the compact kernels (FP32 direct path): used when the
-// support reaches at most 3 x 3 tiles per point and the count table stays small.
+// support reaches at most 3 x 3 tiles (of side 16 a.rc) per point and the count
+// table stays small.
 bool binning_applies(const MapArgs &a);
 size_t binned_workspace_bytes(const MapArgs &a);
 hipError_t launch_binned(const MapArgs &a, void *ws, hipStream_t stream);
@@ -89,6 +98,26 @@ hipError_t launch_reduce_splits(const float *part, int splits, int64_t plane, fl
 
 // Zero-fill kernel (used for empty inputs; no memset nodes in captured graphs).
 hipError_t launch_fill_zero(float *out, int64_t count, hipStream_t stream);
+
+// Tile-shape autotuner cache (kde_autotune.cpp).  Keys and choices are
+// described there; the timing runs live in kde_api.cpp.
+namespace tune {
+struct Entry {
+    std::string choice;
+    std::vector<std::pair<std::string, double>> ms;  // candidate -> measured ms
+};
+bool valid_choice(const std::string &key, const std::string &choice);
+bool enabled();
+void set_enabled(bool on);
+int forced();  // 0, or the register-block side every FP32 direct map uses
+void set_forced(int rc);
+bool lookup(const std::string &key, std::string *choice);
+void store(const std::string &key, const Entry &e);
+bool load(const char *path, std::string *err);
+bool save(const char *path, std::string *err);
+std::string dump();
+void clear();
+}  // namespace tune
 
 // Measurement hook: the launchers call these right before and after the launch of
 // their main kernel; they record the events a caller armed with

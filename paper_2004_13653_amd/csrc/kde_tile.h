@@ -136,13 +136,15 @@ __device__ __forceinline__ void tile_sums(const float2 *__restrict__ pts, int64_
     }
 }
 
-// Register-block shape per kernel: the Gaussian counts every pair and amortises
-// its factors over 8 x 8 blocks (128 x 128 tiles); compact kernels use 4 x 4
-// blocks (64 x 64 tiles) so that culling skips more.
-template <int K>
+// Register-block shape: R x C = RC x RC per thread, so a workgroup covers a
+// 16 RC x 16 RC pixel tile.  Larger blocks amortise each factor over more FMAs;
+// smaller tiles waste fewer evaluations on pixels outside a compact kernel's
+// support and give more workgroups.  The shape is chosen per map (autotuned or
+// by default), among kTileShapes.
+template <int K, int RC>
 struct Shape {
-    static constexpr int R = K == kGaussian ? 8 : 4;
-    static constexpr int C = R;
+    static constexpr int R = RC;
+    static constexpr int C = RC;
     static constexpr bool kCull = K != kGaussian;
     static constexpr int TW = 16 * C, TH = 16 * R;
 };

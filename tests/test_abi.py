@@ -101,6 +101,44 @@ def test_main_kernel_timer_arguments():
     assert L.kde_time_next_main_kernel(None, None) == kde.KDE_OK
 
 
+def test_autotune_cache_roundtrip_and_rejection(tmp_path):
+    """The autotuner's JSON cache: entries load, dump and save; a corrupt file,
+    a foreign format tag or an invalid choice is rejected whole (cache unchanged);
+    bad switches are refused."""
+    import json
+    L = kde.lib()
+    kde.autotune(clear=True)
+    good = {"format": "kde-autotune-1", "entries": {
+        "eval/gfx950/compact/H2/n20/px20": {"choice": "2", "ms": {"2": 1.25, "4": 2.5, "8": 3.75}},
+        "batch/gfx950/00112233aabbccdd": {"choice": "8,4", "ms": {"8,4": 36.0, "8,2": 44.5}}}}
+    f = tmp_path / "good.json"
+    f.write_text(json.dumps(good))
+    ent = kde.autotune(load=str(f))
+    assert ent == good["entries"]
+    out = tmp_path / "saved.json"
+    kde.autotune(save=str(out))
+    assert json.loads(out.read_text()) == good
+    for bad in ('{"format": "kde-autotune-1", "entries": {', "not json",
+                '{"format": "kde-autotune-0", "entries": {}}',
+                '{"format": "kde-autotune-1", "entries": {"eval/x": {"choice": "3", "ms": {}}}}',
+                '{"format": "kde-autotune-1", "entries": {"batch/x": {"choice": "8,5", "ms": {}}}}',
+                '{"format": "kde-autotune-1", "entries": {"other/x": {"choice": "2", "ms": {}}}}',
+                '{"format": "kde-autotune-1", "entries": {"eval/x": {"ms": {}}}}'):
+        b = tmp_path / "bad.json"
+        b.write_text(bad)
+        assert L.kde_autotune_load(os.fsencode(str(b))) == kde.KDE_EINVAL, bad
+        assert L.kde_last_error().decode()
+        assert kde.autotune() == good["entries"]
+    assert L.kde_autotune_load(os.fsencode(str(tmp_path / "missing.json"))) == kde.KDE_EINVAL
+    assert L.kde_autotune_force(3) == kde.KDE_EINVAL and L.kde_autotune_force(16) == kde.KDE_EINVAL
+    assert L.kde_autotune_enable(2) == kde.KDE_EINVAL
+    need = ctypes.c_size_t()
+    assert L.kde_autotune_dump(None, 0, ctypes.byref(need)) == kde.KDE_OK and need.value > 10
+    small = ctypes.create_string_buffer(4)
+    assert L.kde_autotune_dump(small, 4, ctypes.byref(need)) == kde.KDE_EINVAL
+    assert kde.autotune(clear=True) == {}
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(kde, "_lib", None)
     monkeypatch.setattr(kde, "LIB_PATH", str(tmp_path / "libkde.so"))

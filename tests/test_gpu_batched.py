@@ -110,3 +110,51 @@ def test_batch_of_256_time_windows():
             r = kt.oracle_density_at(units[s.side][s.start:s.start + s.count], kernel, hx, hy, og, ij)
             assert kt.peak_error(y[ij[:, 1], ij[:, 0]], r) <= kt.FP32_GATE, (k, s)
     kt.log(f"256 maps: worst peak-normalised difference to separate calls {worst:.2e}")
+
+
+@pytest.mark.parametrize("rc", [2, 4, 8])
+def test_forced_tile_shapes_match_oracle(rc):
+    """The persistent kernel with every register-block shape forced (Gaussian
+    maps then also split into point ranges of other sizes)."""
+    import torch
+    t, grids, units = _pool(100)
+    specs = [synth.MapSpec(100, 20000, 256, 0.004, 6), synth.MapSpec(3000, 7000, 100, 0.015, 6)]
+    specs += [synth.MapSpec(1000 * k, 4000 + 500 * k, (64, 100, 256)[k % 3], 0.003 + 0.002 * k, k) for k in range(8)]
+    try:
+        kde.autotune(force=rc)
+        maps = _batch(specs, units, grids)
+        kde.eval_batched(maps)
+        torch.cuda.synchronize()
+    finally:
+        kde.autotune(force=0)
+    for s, (pts, kernel, hx, hy, g, out) in zip(specs, maps):
+        y = out.cpu().numpy().astype(np.float64)
+        og = oracle.Grid(*g.bounds, g.nx, g.ny)
+        ro = kt.oracle_density_window(units[s.side][s.start:s.start + s.count], kernel, hx, hy, og,
+                                      (0, g.nx, 0, g.ny), separable=True)
+        assert kt.peak_error(y, ro) <= kt.FP32_GATE, (rc, s)
+
+
+def test_batch_shapes_are_tuned_once():
+    """A new batch composition is tuned (whole-batch runs per shape pair), the
+    choice cached under a batch key and reused by the next call."""
+    import torch
+    t, grids, units = _pool(100)
+    specs = [synth.MapSpec(0, 9000, 256, 0.004, 6), synth.MapSpec(0, 15000, 100, 0.01, 3),
+             synth.MapSpec(500, 12000, 64, 0.02, 7), synth.MapSpec(900, 30000, 256, 0.003, 0)]
+    kde.autotune(clear=True, enabled=True, force=0)
+    maps = _batch(specs, units, grids)
+    kde.eval_batched(maps)
+    torch.cuda.synchronize()
+    ent = kde.autotune()
+    keys = [k for k in ent if k.startswith("batch/")]
+    assert len(keys) == 1, ent
+    e = ent[keys[0]]
+    kt.log(f"{keys[0]}: {e}")
+    assert e["choice"] in e["ms"] and e["ms"][e["choice"]] == min(e["ms"].values())
+    first = [m[5].cpu().numpy() for m in maps]
+    kde.eval_batched(maps)
+    torch.cuda.synchronize()
+    assert kde.autotune() == ent
+    for a, m in zip(first, maps):
+        np.testing.assert_array_equal(a, m[5].cpu().numpy())

@@ -152,9 +152,10 @@ def test_raw_sum_and_determinism():
 @pytest.mark.parametrize("kernel", [0, 1, 5, 7])
 @pytest.mark.parametrize("H", [1.3, 60.0, 70.0])
 def test_binned_and_scanned_compact_paths(kernel, H):
-    """Compact kernels with n >= 4096 go through support binning when H <= 64 px
-    and through per-tile culling scans otherwise; points also lie outside the
-    grid on every side."""
+    """Compact kernels with n >= 4096 go through support binning when H is at
+    most the tile side and through per-tile culling scans otherwise (the tile
+    side follows the tuned shape); points also lie outside the grid on every
+    side."""
     rng = np.random.default_rng(int(H) + 10 * kernel)
     XY = np.column_stack([rng.uniform(-90, 290, 50000), rng.uniform(-90, 240, 50000)]).astype(np.float32)
     g, og = kde.Grid(0.0, 199.0, 0.0, 149.0, 200, 150), oracle.Grid(0.0, 199.0, 0.0, 149.0, 200, 150)
@@ -163,3 +164,53 @@ def test_binned_and_scanned_compact_paths(kernel, H):
     assert kt.peak_error(y, r) <= kt.FP32_GATE
     y2 = kt.gpu_map(XY, kernel, H, 0.9 * H, g)
     np.testing.assert_array_equal(y, y2)
+
+
+@pytest.fixture
+def restore_autotune():
+    yield
+    kde.autotune(force=0, enabled=True)
+
+
+@pytest.mark.parametrize("rc", [2, 4, 8])
+@pytest.mark.parametrize("kernel", [0, 2, 5, 6, 7])
+@pytest.mark.parametrize("H", [1.3, 40.0])
+def test_every_tile_shape_matches_oracle(rc, kernel, H, restore_autotune):
+    """Each register-block shape forced (tiles of 32, 64 and 128 nodes) on a
+    ragged 200 x 150 grid: compact kernels binned (H <= tile side) or scanned
+    (H = 40 with 32-node tiles), the Gaussian dense."""
+    kde.autotune(force=rc)
+    rng = np.random.default_rng(100 * rc + 10 * kernel + int(H))
+    XY = np.column_stack([rng.uniform(-50, 250, 20000), rng.uniform(-50, 200, 20000)]).astype(np.float32)
+    g, og = kde.Grid(0.0, 199.0, 0.0, 149.0, 200, 150), oracle.Grid(0.0, 199.0, 0.0, 149.0, 200, 150)
+    kt.log(f"rc={rc} kernel={kernel} H={H}")
+    y = kt.gpu_map(XY, kernel, H, 0.8 * H, g)
+    r = kt.oracle_density_window(XY, kernel, H, 0.8 * H, og, (0, 200, 0, 150))
+    assert kt.peak_error(y, r) <= kt.FP32_GATE
+
+
+def test_autotune_times_candidates_once_and_reuses_the_choice(restore_autotune):
+    """A new bucket is tuned on the caller's data (all three shapes timed unless
+    the default run is long), the fastest is cached, later calls in the bucket
+    reuse it bit for bit; with tuning off no entry is added."""
+    kde.autotune(clear=True, enabled=True, force=0)
+    t = kt.lanes(400, 500)
+    g, og = kt.grids(synth.BOX_C2, 1024, 1024)
+    XY = kde.to_grid_units(t.xy, g)
+    y = kt.gpu_map(XY, 2, 0.002, 0.002, g)
+    ent = kde.autotune()
+    keys = [k for k in ent if k.startswith("eval/") and "/compact/" in k]
+    assert len(keys) == 1, ent
+    e = ent[keys[0]]
+    kt.log(f"{keys[0]}: {e}")
+    assert e["choice"] in e["ms"] and set(e["ms"]) <= {"2", "4", "8"}
+    assert e["ms"][e["choice"]] == min(e["ms"].values())
+    y2 = kt.gpu_map(XY, 2, 0.002, 0.002, g)
+    np.testing.assert_array_equal(y, y2)
+    assert kde.autotune() == ent
+    ij = kt.sample_pixels(y, 32, seed=5)
+    r = kt.oracle_density_at(XY, 2, 0.002, 0.002, og, ij)
+    assert kt.peak_error(y[ij[:, 1], ij[:, 0]], r) <= kt.FP32_GATE
+    kde.autotune(enabled=False)
+    kt.gpu_map(XY[:5000], 7, 0.02, 0.02, g)
+    assert kde.autotune() == ent
