@@ -27,6 +27,9 @@ METRIC = "pixel×point evals/s: MFMA separable vs FP32 direct KDE at stated erro
 UNIT = "pixel×point evals/s"
 PEAK_MFMA_TFLOPS = {"fp16": 2500.0, "bf16": 2500.0, "fp16x3": 2500.0, "bf16x3": 2500.0}
 PEAK_FP32_VECTOR_TFLOPS = 157.3
+# The library is built without packed FP32 instructions, so its FP32 kernels
+# issue one FMA per lane per cycle: 256 CUs x 64 lanes x 2 flop x 2.4 GHz.
+PEAK_FP32_UNPACKED_TFLOPS = 78.6
 N_TRACKS, PTS_PER_TRACK, SIDE, H_DEG = 8000, 500, 2048, 0.002
 # HBM-side bytes per launch of the FP16 contraction kernel at this workload, from
 # two rocprofv3 counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors a
@@ -283,7 +286,9 @@ def main() -> int:
         "speedup_vs_fp32_direct": head["value"] / d["value"],
         "fp32_direct": {"value": d["value"], "ms_per_step": d["ms_per_step"], "steps": d["steps"],
                         "roofline": {"bound": "alu", "achieved": d["fp32_tflops"], "peak": PEAK_FP32_VECTOR_TFLOPS,
-                                     "unit": "TFLOP/s", "frac": d["fp32_tflops"] / PEAK_FP32_VECTOR_TFLOPS}},
+                                     "unit": "TFLOP/s", "frac": d["fp32_tflops"] / PEAK_FP32_VECTOR_TFLOPS,
+                                     "peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,
+                                     "frac_unpacked": d["fp32_tflops"] / PEAK_FP32_UNPACKED_TFLOPS}},
         "paths": results,
     }
     extra = [x for x in args.sections.split(",") if x and x != "none"]

@@ -63,7 +63,7 @@ struct BatchLaunch {
     float *partials;
 };
 
-template <int K, int RC>
+template <int K, int RC, bool kRuns>
 __device__ __forceinline__ void run_item(const BMap &m, const BItem &w, const BatchLaunch &b, float2 *sp,
                                          int *swave, int *s_last) {
     using S = tile::Shape<K, RC>;
@@ -73,9 +73,10 @@ __device__ __forceinline__ void run_item(const BMap &m, const BItem &w, const Ba
     const int lib = (tid & 15) * S::C, ljb = (tid >> 4) * S::R;  // tile-local block origin
     const int ib = x0 + lib, jb = y0 + ljb;
     float tot[S::R][S::C];
-    tile::tile_sums<K, S::R, S::C, S::kCull>(m.pts, w.p0, w.p1, m.Hx, m.Hy, m.ax, m.ay, ib, jb, (float)x0,
-                                             (float)(min(x0 + S::TW, m.nx) - 1), (float)y0,
-                                             (float)(min(y0 + S::TH, m.ny) - 1), sp, swave, tot);
+    tile::tile_sums<K, S::R, S::C, S::kCull, kRuns>(m.pts, w.p0, w.p1, m.Hx, m.Hy, m.ax, m.ay, ib, jb, (float)x0,
+                                                    (float)(min(x0 + S::TW, m.nx) - 1), (float)y0,
+                                                    (float)(min(y0 + S::TH, m.ny) - 1), sp, swave, tot);
+    if constexpr (kRuns) tile::apply_run_q<S::R, S::C>(tot, m.ax, m.ay);
     if (w.nsplit == 1) {
         tile::store_block<S::R, S::C>(tot, m.out, m.nx, m.ny, ib, jb, m.scale);
         return;
@@ -108,12 +109,23 @@ __device__ __forceinline__ void run_item(const BMap &m, const BItem &w, const Ba
 template <int K>
 __device__ __forceinline__ void run_shape(const BMap &m, const BItem &w, const BatchLaunch &b, float2 *sp,
                                           int *swave, int *s_last) {
+    if constexpr (K == kGaussian) {
+        if (m.ax <= kMaxRunScale && m.ay <= kMaxRunScale) {
+            if (m.rc == 2)
+                run_item<K, 2, true>(m, w, b, sp, swave, s_last);
+            else if (m.rc == 4)
+                run_item<K, 4, true>(m, w, b, sp, swave, s_last);
+            else
+                run_item<K, 8, true>(m, w, b, sp, swave, s_last);
+            return;
+        }
+    }
     if (m.rc == 2)
-        run_item<K, 2>(m, w, b, sp, swave, s_last);
+        run_item<K, 2, false>(m, w, b, sp, swave, s_last);
     else if (m.rc == 4)
-        run_item<K, 4>(m, w, b, sp, swave, s_last);
+        run_item<K, 4, false>(m, w, b, sp, swave, s_last);
     else
-        run_item<K, 8>(m, w, b, sp, swave, s_last);
+        run_item<K, 8, false>(m, w, b, sp, swave, s_last);
 }
 
 __global__ __launch_bounds__(kThreads) void batched_kernel(BatchLaunch b) {

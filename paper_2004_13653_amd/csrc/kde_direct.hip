@@ -44,7 +44,7 @@ struct DirectLaunch {
 };
 
 // One workgroup: pixel tile blockIdx.x, point split blockIdx.y.
-template <int K, int RC>
+template <int K, int RC, bool kRuns>
 __global__ __launch_bounds__(tile::kThreads) void direct_fp32_kernel(DirectLaunch p) {
     using S = tile::Shape<K, RC>;
     __shared__ float2 sp[tile::kPointTile];
@@ -56,9 +56,10 @@ __global__ __launch_bounds__(tile::kThreads) void direct_fp32_kernel(DirectLaunc
     const int64_t beg = (int64_t)blockIdx.y * p.per_split;
     const int64_t end = min(p.n, beg + p.per_split);
     float tot[S::R][S::C];
-    tile::tile_sums<K, S::R, S::C, S::kCull>(p.pts, beg, end, p.Hx, p.Hy, p.ax, p.ay, ib, jb, (float)x0,
-                                             (float)(min(x0 + S::TW, p.nx) - 1), (float)y0,
-                                             (float)(min(y0 + S::TH, p.ny) - 1), sp, swave, tot);
+    tile::tile_sums<K, S::R, S::C, S::kCull, kRuns>(p.pts, beg, end, p.Hx, p.Hy, p.ax, p.ay, ib, jb, (float)x0,
+                                                    (float)(min(x0 + S::TW, p.nx) - 1), (float)y0,
+                                                    (float)(min(y0 + S::TH, p.ny) - 1), sp, swave, tot);
+    if constexpr (kRuns) tile::apply_run_q<S::R, S::C>(tot, p.ax, p.ay);
     float *dst = p.dst + (int64_t)blockIdx.y * p.plane;
     tile::store_block<S::R, S::C>(tot, dst, p.nx, p.ny, ib, jb, gridDim.y == 1 ? p.scale : 1.0f);
 }
@@ -108,7 +109,10 @@ hipError_t launch_kr(const MapArgs &a, const Plan &pl, float *dst, hipStream_t s
                    (int64_t)a.nx * a.ny};
     dim3 grid(pl.tiles, pl.splits);
     main_kernel_begin(stream);
-    hipLaunchKernelGGL((direct_fp32_kernel<K, RC>), grid, dim3(kThreads), 0, stream, p);
+    if (K == kGaussian && a.ax <= kMaxRunScale && a.ay <= kMaxRunScale)
+        hipLaunchKernelGGL((direct_fp32_kernel<K, RC, K == kGaussian>), grid, dim3(kThreads), 0, stream, p);
+    else
+        hipLaunchKernelGGL((direct_fp32_kernel<K, RC, false>), grid, dim3(kThreads), 0, stream, p);
     main_kernel_end(stream);
     return hipGetLastError();
 }

@@ -52,6 +52,12 @@ struct MapArgs {
     int rc = 0;         // FP32 direct: register block side (2, 4 or 8; tile side 16 rc)
 };
 
+// Gaussian runs (consecutive nodes' factors as P_0 B^r times a per-position
+// constant, see kde_tile.h and kde_sep.hip) are used when the argument scale
+// a = sqrt(log2(e) / 2) / H is at most this (H >= 1.05 grid units), which keeps
+// the run's intermediate values within a factor 2^8 of the factors.
+constexpr float kMaxRunScale = 0.8f;
+
 // Register-block sides the FP32 direct kernels are built for.
 constexpr int kTileShapes[3] = {2, 4, 8};
 inline bool valid_rc(int rc) { return rc == 2 || rc == 4 || rc == 8; }

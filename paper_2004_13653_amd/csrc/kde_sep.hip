@@ -39,7 +39,6 @@ namespace {
 constexpr int kTile = 256;     // output tile side (rows and columns)
 constexpr int kThreadsSep = 256;
 constexpr float kFar = 1.0e30f;
-constexpr float kMaxRecurScale = 0.8f;
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -579,7 +578,7 @@ hipError_t launch_sep_kp(const MapArgs &a, const SepPlan &pl, const float2 *padd
     // The Gaussian's multiplicative runs need a <= 0.8 (H >= 1.05 px); narrower
     // bandwidths evaluate every factor with its own exp2.
     bool recur = false;
-    if constexpr (K == kGaussian) recur = p.ax <= kMaxRecurScale && p.ay <= kMaxRecurScale;
+    if constexpr (K == kGaussian) recur = p.ax <= kMaxRunScale && p.ay <= kMaxRunScale;
     if constexpr (K == kGaussian) {
         if (recur) {
             main_kernel_begin(stream);

@@ -41,6 +41,45 @@ __device__ __forceinline__ float factor(float d, float a, float H) {
     }
 }
 
+// Gaussian run of N consecutive nodes c0 .. c0+N-1 against one point: with the
+// centre node c = c0 + (N-1)/2, t = (c - X) a and rho_r = r - (N-1)/2,
+//     g(c0 + r) = exp2(-(t + rho_r a)^2) = P_r q_r,
+//     P_r = exp2(-t^2 - 2 t a rho_r) = P_0 B^r,  B = exp2(-2 a t),  q_r = exp2(-(rho_r a)^2).
+// v receives P_0 .. P_{N-1}: two exp2 and N-1 multiplies instead of N exp2.
+// q_r depends only on r, so it multiplies the finished sums (run_q).  With
+// a <= kMaxRunScale, P_r <= g / q_r <= 2^7.9 g; a P_0 that underflows means
+// every factor of the run is negligible, and B is clamped to stay finite, so a
+// run never produces NaN or turns a zero into a non-zero.
+template <int N>
+__device__ __forceinline__ void gauss_run(float t, float a, float (&v)[N]) {
+    const float span = (float)(N - 1) * a;
+    v[0] = __builtin_amdgcn_exp2f(t * (span - t));  // -t^2 + (N-1) a t
+    const float ratio = __builtin_amdgcn_exp2f(fminf(-2.0f * a * t, 126.0f));
+#pragma unroll
+    for (int r = 1; r < N; ++r) v[r] = v[r - 1] * ratio;
+}
+
+template <int N>
+__device__ __forceinline__ void run_q(float a, float (&q)[N]) {
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        const float rho = ((float)r - 0.5f * (float)(N - 1)) * a;
+        q[r] = __builtin_amdgcn_exp2f(-rho * rho);
+    }
+}
+
+// tot[r][c] *= q_y[r] q_x[c]: the position factors of Gaussian runs.
+template <int R, int C>
+__device__ __forceinline__ void apply_run_q(float (&tot)[R][C], float ax, float ay) {
+    float qx[C], qy[R];
+    run_q<C>(ax, qx);
+    run_q<R>(ay, qy);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < C; ++c) tot[r][c] *= qy[r] * qx[c];
+}
+
 template <int R, int C>
 __device__ __forceinline__ void store_block(float (&v)[R][C], float *dst, int nx, int ny, int ib, int jb,
                                             float scale) {
@@ -69,7 +108,8 @@ __device__ __forceinline__ void store_block(float (&v)[R][C], float *dst, int nx
 // columns starting at (jb, ib); tile reach x0..x1, y0..y1 (nodes) for culling.
 // Each LDS tile of points is summed into a fresh block before joining the total.
 // sp: LDS [kPointTile] float2; swave: LDS [kThreads / 64] int.
-template <int K, int R, int C, bool kCull>
+// kRuns (Gaussian): factors as Gaussian runs; the caller applies apply_run_q.
+template <int K, int R, int C, bool kCull, bool kRuns = false>
 __device__ __forceinline__ void tile_sums(const float2 *__restrict__ pts, int64_t beg, int64_t end, float Hx,
                                           float Hy, float ax, float ay, int ib, int jb, float bx0, float bx1,
                                           float by0, float by1, float2 *sp, int *swave, float (&tot)[R][C]) {
@@ -118,12 +158,18 @@ __device__ __forceinline__ void tile_sums(const float2 *__restrict__ pts, int64_
 
         for (int k = 0; k < cnt; ++k) {
             const float2 pt = sp[k];
-            const float dx0 = fib - pt.x, dy0 = fjb - pt.y;
             float kx[C], ky[R];
+            if constexpr (kRuns) {
+                // run centres: half-integer nodes, so (centre - X) is exact like dx0 below
+                gauss_run<C>((fib + 0.5f * (float)(C - 1) - pt.x) * ax, ax, kx);
+                gauss_run<R>((fjb + 0.5f * (float)(R - 1) - pt.y) * ay, ay, ky);
+            } else {
+                const float dx0 = fib - pt.x, dy0 = fjb - pt.y;
 #pragma unroll
-            for (int c = 0; c < C; ++c) kx[c] = factor<K>(dx0 + (float)c, ax, Hx);
+                for (int c = 0; c < C; ++c) kx[c] = factor<K>(dx0 + (float)c, ax, Hx);
 #pragma unroll
-            for (int r = 0; r < R; ++r) ky[r] = factor<K>(dy0 + (float)r, ay, Hy);
+                for (int r = 0; r < R; ++r) ky[r] = factor<K>(dy0 + (float)r, ay, Hy);
+            }
 #pragma unroll
             for (int r = 0; r < R; ++r)
 #pragma unroll
