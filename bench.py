@@ -27,9 +27,6 @@ METRIC = "pixel×point evals/s: MFMA separable vs FP32 direct KDE at stated erro
 UNIT = "pixel×point evals/s"
 PEAK_MFMA_TFLOPS = {"fp16": 2500.0, "bf16": 2500.0, "fp16x3": 2500.0, "bf16x3": 2500.0}
 PEAK_FP32_VECTOR_TFLOPS = 157.3
-# The library is built without packed FP32 instructions, so its FP32 kernels
-# issue one FMA per lane per cycle: 256 CUs x 64 lanes x 2 flop x 2.4 GHz.
-PEAK_FP32_UNPACKED_TFLOPS = 78.6
 N_TRACKS, PTS_PER_TRACK, SIDE, H_DEG = 8000, 500, 2048, 0.002
 # HBM-side bytes per launch of the FP16 contraction kernel at this workload, from
 # two rocprofv3 counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors a
@@ -205,7 +202,7 @@ def main() -> int:
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-once", action="store_true",
-                    help="for counter runs: one warm-up and one timed FP16 map, then a 256 MiB "
+                    help="for counter runs: two FP16 maps and one FP32 direct map, then a 256 MiB "
                          "elementwise copy (torch.neg) as the byte-count calibration; prints no JSON")
     ap.add_argument("--sections", default="adjoint,batched,kernels",
                     help="extra measured sections beside the headline: adjoint, batched, kernels (or none)")
@@ -239,11 +236,12 @@ def main() -> int:
         f = run("fp16")
         f()
         f()
+        run("fp32")()
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         torch.neg(src, out=dst)
         torch.cuda.synchronize()
-        log(f"profile run: 2 FP16 maps, then a copy of {src.numel() * 4} bytes read + written")
+        log(f"profile run: 2 FP16 maps, 1 FP32 direct map, then a copy of {src.numel() * 4} bytes read + written")
         return 0
 
     results, maps = {}, {}
@@ -286,9 +284,7 @@ def main() -> int:
         "speedup_vs_fp32_direct": head["value"] / d["value"],
         "fp32_direct": {"value": d["value"], "ms_per_step": d["ms_per_step"], "steps": d["steps"],
                         "roofline": {"bound": "alu", "achieved": d["fp32_tflops"], "peak": PEAK_FP32_VECTOR_TFLOPS,
-                                     "unit": "TFLOP/s", "frac": d["fp32_tflops"] / PEAK_FP32_VECTOR_TFLOPS,
-                                     "peak_unpacked": PEAK_FP32_UNPACKED_TFLOPS,
-                                     "frac_unpacked": d["fp32_tflops"] / PEAK_FP32_UNPACKED_TFLOPS}},
+                                     "unit": "TFLOP/s", "frac": d["fp32_tflops"] / PEAK_FP32_VECTOR_TFLOPS}},
         "paths": results,
     }
     extra = [x for x in args.sections.split(",") if x and x != "none"]
