@@ -68,8 +68,10 @@ def lib():
         L.ko_vjp_units.argtypes = [p, i64, i, f, f, i, i, p, p, i64, p, p]
         L.ko_lscv_world.argtypes = [p, i64, i, d, d, p, p]
         L.ko_lscv_units.argtypes = [p, i64, i, f, f, p, p]
+        L.ko_bin_counts.argtypes = [p, i64, p, i, i, p, p]
+        L.ko_conv_counts.argtypes = [p, i, i, i, f, f, i, i, i, i, i, i, p]
         for name in ("ko_map_world", "ko_map_units", "ko_map_units_at", "ko_vjp_units", "ko_lscv_world",
-                     "ko_lscv_units"):
+                     "ko_lscv_units", "ko_bin_counts", "ko_conv_counts"):
             getattr(L, name).restype = None
         _lib = L
     return _lib
@@ -283,6 +285,34 @@ def lscv_units(XY, kernel: int, Hx, Hy):
 
 
 # --------------------------------------------------------------------------- errors
+def bin_counts(XY, labels, nx: int, ny: int):
+    """The paper's count matrix (Eq. (5)-(6) ceil projection, Eq. (12)-(13) gap
+    filling between consecutive points with equal labels; labels None: no
+    filling): (counts uint32 [ny, nx], number of counted cells)."""
+    XY = _f32(XY).reshape(-1, 2)
+    counts = np.zeros((ny, nx), dtype=np.uint32)
+    total = ctypes.c_int64()
+    lab = None
+    if labels is not None:
+        lab = np.ascontiguousarray(labels, dtype=np.int32)
+        assert lab.shape == (XY.shape[0],)
+    lib().ko_bin_counts(_ptr(XY), XY.shape[0], _ptr(lab) if lab is not None else None, nx, ny, _ptr(counts),
+                        ctypes.byref(total))
+    return counts, int(total.value)
+
+
+def conv_counts(counts, kernel: int, Hx, Hy, a: int, b: int, window=None) -> np.ndarray:
+    """Eq. (7): raw convolution of a count matrix with the taps k(s/Hx) k(t/Hy),
+    |s| <= a, |t| <= b, over window (i0, i1, j0, j1) (default: whole grid)."""
+    counts = np.ascontiguousarray(counts, dtype=np.uint32)
+    ny, nx = counts.shape
+    i0, i1, j0, j1 = window if window is not None else (0, nx, 0, ny)
+    out = np.empty((j1 - j0, i1 - i0), dtype=np.float64)
+    lib().ko_conv_counts(_ptr(counts), nx, ny, kernel, float(np.float32(Hx)), float(np.float32(Hy)), int(a),
+                         int(b), i0, i1, j0, j1, _ptr(out))
+    return out
+
+
 def errors(y, r) -> dict:
     """Peak-normalised max error e_inf = max|y - r| / max|r|, relative L2 error
     e_2 = ||y - r|| / ||r||, and the max per-pixel relative error over pixels

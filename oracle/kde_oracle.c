@@ -324,3 +324,94 @@ void ko_lscv_units(const float *XY, int64_t n, int kernel, float Hx, float Hy,
     ko_lscv_world(xy, n, kernel, (double)Hx, (double)Hy, value, grad);
     free(xy);
 }
+
+/* ---------------------------------------------------------------------------
+ * The paper's own binned visualisation (Sec. III-C and IV-B): a count matrix
+ * from the ceil projection of Eq. (5)-(6), gap filling between consecutive
+ * points of one trajectory by the linear interpolation of Eq. (12)-(13), then
+ * the convolution of Eq. (7) with a table of Table I kernel values.
+ *
+ * Readings (the paper leaves these open):
+ *  - Grid units X = (x - xmin)/dx.  Eq. (5) with 1-based indices is
+ *    ceil(X) + 1, so the 0-based cell is i = ceil(X) (likewise j = ceil(Y)).
+ *    The box is given (it is not the data's extremes), so a point counts only
+ *    when 0 <= i < nx and 0 <= j < ny.
+ *  - Interpolation joins consecutive points p, p+1 with equal labels when both
+ *    cells lie in the grid.  With di = i' - i, dj = j' - j and
+ *    cmax = max(|di|, |dj|) > 1, cells c = 1 .. cmax-1 are added at the rounded
+ *    positions of Eq. (12)-(13).  The rounded quantity is the positive 1-based
+ *    coordinate, so rounding half away from zero is rounding half up; it is done
+ *    exactly, in integers: i_c = floor((2 i cmax + 2 c di + cmax) / (2 cmax)).
+ *  - Convolution taps are f(s, t) = k(s/Hx) k(t/Hy) at integer offsets
+ *    |s| <= a, |t| <= b (support test |s| <= Hx on the offset for compact
+ *    kernels); cells outside the grid count zero.
+ * -------------------------------------------------------------------------*/
+
+/* 0-based cell of one FP32 coordinate, or -1 when it falls outside [0, n). */
+static int64_t bin_cell(float X, int n)
+{
+    double c = ceil((double)X);
+    if (!(c >= 0.0 && c <= (double)(n - 1))) return -1; /* also rejects NaN */
+    return (int64_t)c;
+}
+
+/* Count matrix counts[ny][nx] (zeroed here) of the points XY[n][2] (FP32 grid
+ * units) plus, when labels is not NULL, the interpolated cells of Eq. (12)-(13)
+ * between consecutive points with equal labels.  *total receives the number of
+ * counted cells (points plus interpolated cells).  Sequential, point order. */
+void ko_bin_counts(const float *XY, int64_t n, const int32_t *labels, int nx, int ny, uint32_t *counts,
+                   int64_t *total)
+{
+    int64_t tot = 0;
+    for (int64_t k = 0; k < (int64_t)nx * ny; ++k) counts[k] = 0;
+    for (int64_t p = 0; p < n; ++p) {
+        int64_t i = bin_cell(XY[2 * p], nx), j = bin_cell(XY[2 * p + 1], ny);
+        if (i < 0 || j < 0) continue;
+        counts[j * nx + i] += 1;
+        tot += 1;
+        if (labels == NULL || p + 1 >= n || labels[p] != labels[p + 1]) continue;
+        int64_t i2 = bin_cell(XY[2 * p + 2], nx), j2 = bin_cell(XY[2 * p + 3], ny);
+        if (i2 < 0 || j2 < 0) continue;
+        int64_t di = i2 - i, dj = j2 - j;
+        int64_t cmax = llabs(di) > llabs(dj) ? llabs(di) : llabs(dj);
+        for (int64_t c = 1; c < cmax; ++c) {
+            int64_t ic = (2 * i * cmax + 2 * c * di + cmax) / (2 * cmax);
+            int64_t jc = (2 * j * cmax + 2 * c * dj + cmax) / (2 * cmax);
+            counts[jc * nx + ic] += 1;
+            tot += 1;
+        }
+    }
+    *total = tot;
+}
+
+/* One convolution tap: k(s/H) at integer offset s (0 outside a compact support). */
+static double tap(int kernel, int s, float H)
+{
+    double d = (double)s;
+    if (kernel != KO_GAUSSIAN && fabs(d) > (double)H) return 0.0;
+    return ko_k(kernel, d / (double)H);
+}
+
+/* Eq. (7) over the window [i0, i1) x [j0, j1):
+ *   out[r] = sum_{t=-b..b} sum_{s=-a..a} f(s, t) counts[j - t][i - s]
+ * with f(s, t) = tap(s; Hx) tap(t; Hy), raw (no normalisation). */
+void ko_conv_counts(const uint32_t *counts, int nx, int ny, int kernel, float Hx, float Hy, int a, int b,
+                    int i0, int i1, int j0, int j1, double *out)
+{
+    int w = i1 - i0, h = j1 - j0;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int r = 0; r < h * w; ++r) {
+        int j = j0 + r / w, i = i0 + r % w;
+        double sum = 0.0;
+        for (int t = -b; t <= b; ++t) {
+            int jj = j - t;
+            if (jj < 0 || jj >= ny) continue;
+            for (int s = -a; s <= a; ++s) {
+                int ii = i - s;
+                if (ii < 0 || ii >= nx) continue;
+                sum += tap(kernel, s, Hx) * tap(kernel, t, Hy) * (double)counts[(int64_t)jj * nx + ii];
+            }
+        }
+        out[r] = sum;
+    }
+}

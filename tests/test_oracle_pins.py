@@ -8,6 +8,7 @@ function.  A dropped term, a wrong sign, exponent or index, or transposed x/y
 in the oracle fails at least one of them.
 """
 import math
+from fractions import Fraction
 import os
 
 import numpy as np
@@ -395,3 +396,138 @@ def test_errors_measure():
     assert e["e_inf"] == pytest.approx(0.1)
     assert e["e_2"] == pytest.approx(0.4 / math.sqrt(21))
     assert e["e_rel"] == pytest.approx(0.1)
+
+
+# ---------------------------------------------------------------------------
+# The paper's binned visualisation: count matrix (Eq. (5)-(6), (12)-(13)) and
+# the convolution of Eq. (7).
+
+def _golden_binned():
+    pts, rows, total, mode = [], [], None, None
+    with open(os.path.join(HERE, "golden", "binned_counts_small.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            if line.startswith("points"):
+                mode = "p"
+            elif line.startswith("counts"):
+                mode = "c"
+            elif line.startswith("total"):
+                total = int(line.split()[1])
+            elif mode == "p":
+                x, y, lab = line.split()
+                pts.append((float(x), float(y), int(lab)))
+            else:
+                rows.append([int(v) for v in line.split()])
+    XY = np.array([(x, y) for x, y, _ in pts], dtype=np.float32)
+    labels = np.array([lab for _, _, lab in pts], dtype=np.int32)
+    return XY, labels, np.array(rows, dtype=np.uint32), total
+
+
+def test_binned_counts_hand_worked_example():
+    XY, labels, want, total = _golden_binned()
+    counts, tot = oracle.bin_counts(XY, labels, 8, 6)
+    np.testing.assert_array_equal(counts, want)
+    assert tot == total == int(want.sum())
+    # without labels: points only (9 of the 10 lie in the grid)
+    counts0, tot0 = oracle.bin_counts(XY, None, 8, 6)
+    assert tot0 == 9 and int(counts0.sum()) == 9
+    assert counts0[3, 6] == 2 and counts0[2, 2] == 1 and counts0[0, 0] == 1
+
+
+def _round_half_up(q: Fraction) -> int:
+    return math.floor(q + Fraction(1, 2))
+
+
+def test_binned_gap_cells_match_exact_rational_rounding():
+    """Random segments inside a 40 x 30 grid: the filled cells equal Eq. (12)-(13)
+    evaluated in exact rational arithmetic (1-based coordinates rounded half
+    up), form an 8-connected monotone path, and number cmax - 1."""
+    rng = np.random.default_rng(1213)
+    for trial in range(300):
+        a = rng.integers(0, [40, 30])
+        b = rng.integers(0, [40, 30])
+        XY = np.array([a, b], dtype=np.float32) - np.float32(0.25)  # ceil gives back a, b
+        counts, tot = oracle.bin_counts(XY, np.zeros(2, np.int32), 40, 30)
+        di, dj = int(b[0] - a[0]), int(b[1] - a[1])
+        cmax = max(abs(di), abs(dj))
+        want = np.zeros((30, 40), dtype=np.uint32)
+        want[a[1], a[0]] += 1
+        want[b[1], b[0]] += 1
+        path = []
+        for c in range(1, cmax):
+            i1 = _round_half_up(Fraction(int(a[0]) + 1) + Fraction(c, cmax) * di) - 1
+            j1 = _round_half_up(Fraction(int(a[1]) + 1) + Fraction(c, cmax) * dj) - 1
+            want[j1, i1] += 1
+            path.append((i1, j1))
+        np.testing.assert_array_equal(counts, want)
+        assert tot == 2 + max(cmax - 1, 0)
+        full = [(int(a[0]), int(a[1]))] + path + [(int(b[0]), int(b[1]))]
+        if cmax > 0:
+            for (x0, y0), (x1, y1) in zip(full, full[1:]):
+                assert abs(x1 - x0) <= 1 and abs(y1 - y0) <= 1
+
+
+def test_binned_projection_edges():
+    """ceil projection at the edges: X in (-1, 0] -> cell 0, X = nx-1 -> last cell,
+    just above nx-1 or at -1 -> outside; NaN -> outside."""
+    XY = np.array([[-0.999, 0.0], [0.0, -0.5], [4.0, 0.0], [np.nextafter(np.float32(4), np.float32(5)), 0.0],
+                   [-1.0, 0.0], [np.nan, 1.0], [1.0, 3.0]], dtype=np.float32)
+    counts, tot = oracle.bin_counts(XY, None, 5, 4)
+    assert tot == 4
+    assert counts[0, 0] == 2 and counts[0, 4] == 1 and counts[3, 1] == 1
+
+
+def test_conv_impulse_response_closed_forms():
+    """A single count: the map is the tap table itself (uniform: 1/4 on a 5 x 5
+    square for H = 2; Epanechnikov H = 2: 0.75, 0.5625, 0 along an axis), cut
+    at the grid edge."""
+    counts = np.zeros((9, 11), dtype=np.uint32)
+    counts[4, 5] = 1
+    u = oracle.conv_counts(counts, 0, 2.0, 2.0, 3, 3)
+    want = np.zeros((9, 11))
+    want[2:7, 3:8] = 0.25
+    np.testing.assert_allclose(u, want, rtol=0, atol=1e-15)
+    e = oracle.conv_counts(counts, 2, 2.0, 2.0, 2, 2)
+    ax = {0: 0.75, 1: 0.5625, 2: 0.0}
+    for j in range(9):
+        for i in range(11):
+            di, dj = abs(i - 5), abs(j - 4)
+            w = ax.get(di, 0.0) * ax.get(dj, 0.0) if di <= 2 and dj <= 2 else 0.0
+            assert e[j, i] == pytest.approx(w, abs=1e-15)
+    corner = np.zeros((9, 11), dtype=np.uint32)
+    corner[0, 0] = 4
+    c = oracle.conv_counts(corner, 0, 2.0, 2.0, 2, 2)
+    assert c[0:3, 0:3].sum() == pytest.approx(4 * 9 * 0.25) and c.sum() == pytest.approx(4 * 9 * 0.25)
+
+
+def test_conv_gaussian_tap_mass_poisson_summation():
+    """Sum over a wide grid of the Gaussian taps of one count at H = 1 (sigma one
+    cell, the paper's Gaussian): by Poisson summation sum_s phi(s) = 1 + 2
+    sum_m exp(-2 pi^2 m^2), so the 2-D mass is (1 + 2 e^(-2 pi^2))^2 to 1e-15."""
+    counts = np.zeros((41, 41), dtype=np.uint32)
+    counts[20, 20] = 1
+    g = oracle.conv_counts(counts, 6, 1.0, 1.0, 20, 20)
+    one_d = 1.0 + 2.0 * sum(math.exp(-2.0 * math.pi ** 2 * m * m) for m in range(1, 4))
+    assert g.sum() == pytest.approx(one_d ** 2, rel=1e-13)
+
+
+def test_conv_shift_transpose_and_linearity():
+    """Shifting the counts shifts the map; transposing counts with Hx, a and Hy,
+    b swapped transposes it; the map is linear in the counts."""
+    rng = np.random.default_rng(77)
+    A = rng.integers(0, 5, (23, 31)).astype(np.uint32)
+    A[:, -3:] = 0
+    A[-2:, :] = 0
+    B = rng.integers(0, 3, (23, 31)).astype(np.uint32)
+    for kernel in (1, 5, 6, 7):
+        m = oracle.conv_counts(A, kernel, 2.5, 1.5, 3, 2)
+        sh = np.zeros_like(A)
+        sh[2:, 3:] = A[:-2, :-3]
+        ms = oracle.conv_counts(sh, kernel, 2.5, 1.5, 3, 2)
+        np.testing.assert_allclose(ms[2 + 4:, 3 + 4:], m[4:-2, 4:-3], rtol=1e-13, atol=1e-13)
+        mt = oracle.conv_counts(np.ascontiguousarray(A.T), kernel, 1.5, 2.5, 2, 3)
+        np.testing.assert_allclose(mt, m.T, rtol=1e-13, atol=1e-13)
+        mab = oracle.conv_counts(A + B, kernel, 2.5, 1.5, 3, 2)
+        np.testing.assert_allclose(mab, m + oracle.conv_counts(B, kernel, 2.5, 1.5, 3, 2), rtol=1e-12, atol=1e-12)
