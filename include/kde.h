@@ -175,6 +175,41 @@ int kde_backward(const float *points, int64_t n, int32_t kernel_id, double hx, d
 int kde_lscv(const float *points, int64_t n, int32_t kernel_id, double hx, double hy, const kde_grid *g,
              double *value, double *grad_h, void *stream);
 
+/* The paper's own binned visualisation (Sec. III-C and IV-B): a count matrix
+ * of the points, optionally with the gaps between consecutive points of one
+ * trajectory filled, then the convolution of Eq. (7) with a table of Table I
+ * kernel values.  It approximates the kde_eval map (each point moved to the
+ * cell above it, taps truncated at the radii) at a cost independent of the
+ * bandwidth's reach over points.
+ *
+ * kde_bin_counts: counts[j*nx + i] = number of points with ceil(X) = i and
+ * ceil(Y) = j (Eq. (5)-(6) with 0-based cells; points outside the grid are
+ * dropped), plus, when labels is not NULL, the cells of Eq. (12)-(13) between
+ * consecutive points p, p+1 with labels[p] == labels[p+1] whose cells are both
+ * in the grid and more than one cell apart: c = 1 .. cmax-1,
+ * cmax = max(|di|, |dj|), at the 1-based coordinate rounded half up.
+ *   points  device FP32 [n][2] grid units (as kde_eval); n >= 0
+ *   labels  device int32 [n] trajectory labels, or NULL (no gap filling)
+ *   counts  device uint32 [ny][nx], overwritten
+ *   total   device uint64 [1] receiving the number of counted cells, or NULL
+ * Integer atomics: the result does not depend on thread order.  Asynchronous. */
+int kde_bin_counts(const float *points, int64_t n, const int32_t *labels, const kde_grid *g, uint32_t *counts,
+                   uint64_t *total, void *stream);
+
+/* Eq. (7): out[j*nx + i] = scale * sum_{t=-b..b} sum_{s=-a..a} k(s/Hx) k(t/Hy)
+ * counts[(j-t)*nx + (i-s)], cells outside the grid counting zero, Hx = hx/dx,
+ * Hy = hy/dy, compact kernels 0 for |s| > Hx.  scale = 1/(N hx hy) with
+ * N = *total (device uint64, the number of counted cells), or 1 with
+ * KDE_RAW_SUM (total may then be NULL); N = 0 gives a zero map.  a, b in
+ * [0, 128] (the paper's odd table size is 2a + 1).  FP32 taps and sums, a row
+ * pass then a column pass.  Asynchronous. */
+int kde_conv_counts(const uint32_t *counts, const uint64_t *total, const kde_grid *g, int32_t kernel_id, double hx,
+                    double hy, int32_t a, int32_t b, float *out, uint32_t flags, void *stream);
+
+/* kde_bin_counts then kde_conv_counts, the counts kept in library workspace. */
+int kde_eval_binned(const float *points, int64_t n, const int32_t *labels, int32_t kernel_id, double hx, double hy,
+                    int32_t a, int32_t b, const kde_grid *g, float *out, uint32_t flags, void *stream);
+
 /* Tile-shape autotuner (FP32 direct path, kde_eval and kde_eval_batched).
  * The direct kernels exist for register blocks of 2 x 2, 4 x 4 and 8 x 8 pixels
  * per thread (pixel tiles of 32, 64 and 128 nodes per side).  The first call in

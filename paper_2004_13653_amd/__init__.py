@@ -71,6 +71,9 @@ def lib() -> ctypes.CDLL:
             "kde_eval_batched": (ctypes.c_int, [p, i32, u32, p]),
             "kde_backward": (ctypes.c_int, [p, i64, i32, d, d, p, p, p, p, u32, p]),
             "kde_lscv": (ctypes.c_int, [p, i64, i32, d, d, p, p, p, p]),
+            "kde_bin_counts": (ctypes.c_int, [p, i64, p, p, p, p, p]),
+            "kde_conv_counts": (ctypes.c_int, [p, p, p, i32, d, d, i32, i32, p, u32, p]),
+            "kde_eval_binned": (ctypes.c_int, [p, i64, p, i32, d, d, i32, i32, p, p, u32, p]),
             "kde_time_next_main_kernel": (ctypes.c_int, [p, p]),
             "kde_autotune_enable": (ctypes.c_int, [i32]),
             "kde_autotune_force": (ctypes.c_int, [i32]),
@@ -170,6 +173,74 @@ def eval(points, kernel, hx: float, hy: float, grid: Grid, out=None, precision: 
                               hx, hy, grid.handle, out.data_ptr(), PRECISIONS[precision],
                               RAW_SUM if raw else 0, _stream(torch, points.device)))
     return out
+
+
+def _check_labels(labels, n, torch):
+    if labels is None:
+        return None
+    if not (labels.is_cuda and labels.dtype == torch.int32 and labels.dim() == 1 and labels.shape[0] == n
+            and labels.is_contiguous()):
+        raise ValueError("labels must be a contiguous CUDA int32 tensor of shape [n]")
+    return labels.data_ptr()
+
+
+def bin_counts(points, labels, grid: Grid, counts=None, total=None):
+    """The paper's count matrix (kde_bin_counts): ceil projection of the points
+    and, with trajectory labels ([n] int32 CUDA tensor), the gap cells between
+    consecutive points.  Returns (counts [ny, nx] int32 tensor holding the
+    uint32 counts, total [1] int64 tensor holding the number of counted cells)."""
+    import torch
+    _check_points(points, torch)
+    dev = points.device
+    if counts is None:
+        counts = torch.empty((grid.ny, grid.nx), dtype=torch.int32, device=dev)
+    if total is None:
+        total = torch.empty(1, dtype=torch.int64, device=dev)
+    lab = _check_labels(labels, points.shape[0], torch)
+    with torch.cuda.device(dev):
+        _check(lib().kde_bin_counts(points.data_ptr() if points.numel() else None, points.shape[0], lab, grid.handle,
+                                    counts.data_ptr(), total.data_ptr(), _stream(torch, dev)))
+    return counts, total
+
+
+def conv_counts(counts, total, kernel, hx: float, hy: float, a: int, b: int, grid: Grid, out=None,
+                raw: bool = False):
+    """Eq. (7) convolution of a count matrix (kde_conv_counts); density scaled
+    by the number of counted cells in `total` unless raw."""
+    import torch
+    if out is None:
+        out = torch.empty((grid.ny, grid.nx), dtype=torch.float32, device=counts.device)
+    with torch.cuda.device(counts.device):
+        _check(lib().kde_conv_counts(counts.data_ptr(), total.data_ptr() if total is not None else None,
+                                     grid.handle, _kernel_id(kernel), hx, hy, int(a), int(b), out.data_ptr(),
+                                     RAW_SUM if raw else 0, _stream(torch, counts.device)))
+    return out
+
+
+def eval_binned(points, labels, kernel, hx: float, hy: float, a: int, b: int, grid: Grid, out=None,
+                raw: bool = False):
+    """The paper's binned heat map in one call (kde_eval_binned)."""
+    import torch
+    _check_points(points, torch)
+    if out is None:
+        out = torch.empty((grid.ny, grid.nx), dtype=torch.float32, device=points.device)
+    lab = _check_labels(labels, points.shape[0], torch)
+    with torch.cuda.device(points.device):
+        _check(lib().kde_eval_binned(points.data_ptr() if points.numel() else None, points.shape[0], lab,
+                                     _kernel_id(kernel), hx, hy, int(a), int(b), grid.handle, out.data_ptr(),
+                                     RAW_SUM if raw else 0, _stream(torch, points.device)))
+    return out
+
+
+def paper_taps(kernel, varpi: int, grid: Grid) -> tuple[float, float, int, int]:
+    """The paper's table of odd size varpi (Eq. (7)-(8)) in this library's terms:
+    (hx, hy, a, b) with a = b = (varpi - 1) / 2 cells; compact kernels reach
+    exactly a cells (H = a), the Gaussian has sigma = one cell (H = 1)."""
+    if varpi < 1 or varpi % 2 == 0:
+        raise ValueError("varpi must be a positive odd integer")
+    r = (varpi - 1) // 2
+    H = 1.0 if _kernel_id(kernel) == KERNELS["gaussian"] else float(max(r, 1))
+    return H * grid.dx, H * grid.dy, r, r
 
 
 def autotune(enabled: bool | None = None, force: int | None = None, load: str | None = None,

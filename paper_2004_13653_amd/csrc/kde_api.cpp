@@ -465,6 +465,106 @@ int kde_eval_batched(const kde_map *maps, int32_t n_maps, uint32_t flags, void *
     }
 }
 
+// ------------------------------------------------------------ binned visualisation
+
+namespace {
+
+int check_taps(int32_t kernel_id, double hx, double hy, int32_t a, int32_t b, const kde_grid *g, const char *who) {
+    int st = check_map(nullptr, 0, kernel_id, hx, hy, g, who);
+    if (st != KDE_OK) return st;
+    if (a < 0 || b < 0 || a > kde::kMaxTapRadius || b > kde::kMaxTapRadius)
+        return fail(KDE_EINVAL, "%s: tap radii (%d, %d) outside [0, %d]", who, (int)a, (int)b, kde::kMaxTapRadius);
+    return KDE_OK;
+}
+
+kde::BinnedConvArgs conv_args(const uint32_t *counts, const uint64_t *total, const kde_grid *g, int32_t kernel_id,
+                              double hx, double hy, int32_t a, int32_t b, float *out, uint32_t flags) {
+    kde::BinnedConvArgs c;
+    c.counts = counts;
+    c.nx = g->nx;
+    c.ny = g->ny;
+    c.kernel_id = kernel_id;
+    c.Hx = (float)(hx / g->dx);
+    c.Hy = (float)(hy / g->dy);
+    c.a = a;
+    c.b = b;
+    const double k0 = kde::kernel_norm(kernel_id);
+    c.raw = (flags & KDE_RAW_SUM) != 0;
+    c.c2_over_hxhy = c.raw ? k0 * k0 : k0 * k0 / (hx * hy);
+    c.total = reinterpret_cast<const unsigned long long *>(total);
+    c.out = out;
+    return c;
+}
+
+size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
+
+}  // namespace
+
+int kde_bin_counts(const float *points, int64_t n, const int32_t *labels, const kde_grid *g, uint32_t *counts,
+                   uint64_t *total, void *stream) {
+    try {
+        if (!grid_ok(g)) return fail(KDE_EINVAL, "kde_bin_counts: invalid grid handle");
+        if (n < 0 || n >= kMaxPoints) return fail(KDE_EINVAL, "kde_bin_counts: n = %lld out of range", (long long)n);
+        if (n > 0 && points == nullptr) return fail(KDE_EINVAL, "kde_bin_counts: points is NULL with n > 0");
+        if (counts == nullptr) return fail(KDE_EINVAL, "kde_bin_counts: counts is NULL");
+        hipError_t e = kde::launch_bin_counts(reinterpret_cast<const float2 *>(points), n, labels, g->nx, g->ny,
+                                              counts, reinterpret_cast<unsigned long long *>(total),
+                                              static_cast<hipStream_t>(stream));
+        return e == hipSuccess ? KDE_OK : hip_fail(e, "kde_bin_counts");
+    } catch (...) {
+        return fail(KDE_EHIP, "kde_bin_counts: internal error");
+    }
+}
+
+int kde_conv_counts(const uint32_t *counts, const uint64_t *total, const kde_grid *g, int32_t kernel_id, double hx,
+                    double hy, int32_t a, int32_t b, float *out, uint32_t flags, void *stream) {
+    try {
+        int st = check_taps(kernel_id, hx, hy, a, b, g, "kde_conv_counts");
+        if (st != KDE_OK) return st;
+        if (counts == nullptr || out == nullptr) return fail(KDE_EINVAL, "kde_conv_counts: counts or out is NULL");
+        if (flags & ~KDE_RAW_SUM) return fail(KDE_EINVAL, "kde_conv_counts: unknown flags 0x%x", flags);
+        if (!(flags & KDE_RAW_SUM) && total == nullptr)
+            return fail(KDE_EINVAL, "kde_conv_counts: a density needs total (or KDE_RAW_SUM)");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        void *ws = nullptr;
+        st = get_workspace(s, kde::conv_workspace_bytes(g->nx, g->ny), &ws);
+        if (st != KDE_OK) return st;
+        hipError_t e = kde::launch_conv_counts(conv_args(counts, total, g, kernel_id, hx, hy, a, b, out, flags), ws, s);
+        return e == hipSuccess ? KDE_OK : hip_fail(e, "kde_conv_counts");
+    } catch (...) {
+        return fail(KDE_EHIP, "kde_conv_counts: internal error");
+    }
+}
+
+int kde_eval_binned(const float *points, int64_t n, const int32_t *labels, int32_t kernel_id, double hx, double hy,
+                    int32_t a, int32_t b, const kde_grid *g, float *out, uint32_t flags, void *stream) {
+    try {
+        int st = check_taps(kernel_id, hx, hy, a, b, g, "kde_eval_binned");
+        if (st != KDE_OK) return st;
+        if (n < 0 || n >= kMaxPoints) return fail(KDE_EINVAL, "kde_eval_binned: n = %lld out of range", (long long)n);
+        if (n > 0 && points == nullptr) return fail(KDE_EINVAL, "kde_eval_binned: points is NULL with n > 0");
+        if (out == nullptr) return fail(KDE_EINVAL, "kde_eval_binned: out is NULL");
+        if (flags & ~KDE_RAW_SUM) return fail(KDE_EINVAL, "kde_eval_binned: unknown flags 0x%x", flags);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const size_t cells = (size_t)g->nx * g->ny;
+        const size_t counts_bytes = align_up(cells * sizeof(uint32_t)), total_bytes = 256;
+        void *ws = nullptr;
+        st = get_workspace(s, counts_bytes + total_bytes + kde::conv_workspace_bytes(g->nx, g->ny), &ws);
+        if (st != KDE_OK) return st;
+        char *w = static_cast<char *>(ws);
+        uint32_t *counts = reinterpret_cast<uint32_t *>(w);
+        uint64_t *total = reinterpret_cast<uint64_t *>(w + counts_bytes);
+        hipError_t e = kde::launch_bin_counts(reinterpret_cast<const float2 *>(points), n, labels, g->nx, g->ny,
+                                              counts, reinterpret_cast<unsigned long long *>(total), s);
+        if (e == hipSuccess)
+            e = kde::launch_conv_counts(conv_args(counts, total, g, kernel_id, hx, hy, a, b, out, flags),
+                                        w + counts_bytes + total_bytes, s);
+        return e == hipSuccess ? KDE_OK : hip_fail(e, "kde_eval_binned");
+    } catch (...) {
+        return fail(KDE_EHIP, "kde_eval_binned: internal error");
+    }
+}
+
 int kde_backward(const float *points, int64_t n, int32_t kernel_id, double hx, double hy, const kde_grid *g,
                  const float *grad_out, float *grad_points, double *grad_h, uint32_t flags, void *stream) {
     try {

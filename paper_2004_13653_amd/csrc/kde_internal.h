@@ -105,6 +105,24 @@ hipError_t launch_reduce_splits(const float *part, int splits, int64_t plane, fl
 // Zero-fill kernel (used for empty inputs; no memset nodes in captured graphs).
 hipError_t launch_fill_zero(float *out, int64_t count, hipStream_t stream);
 
+// The paper's binned visualisation (kde_binned.hip): count matrix with gap
+// filling, then the separable convolution of the counts.
+constexpr int kMaxTapRadius = 128;  // taps |s| <= a, |t| <= b with a, b <= this
+struct BinnedConvArgs {
+    const uint32_t *counts;               // [ny][nx]
+    int nx, ny, kernel_id;
+    float Hx, Hy;                         // bandwidths in cells
+    int a, b;                             // tap radii in cells
+    double c2_over_hxhy;                  // c^2 / (hx hy), or c^2 for raw sums
+    bool raw;                             // true: no division by the number of counted cells
+    const unsigned long long *total;      // device: number of counted cells (density only)
+    float *out;                           // [ny][nx]
+};
+hipError_t launch_bin_counts(const float2 *pts, int64_t n, const int32_t *labels, int nx, int ny, uint32_t *counts,
+                             unsigned long long *total, hipStream_t s);
+size_t conv_workspace_bytes(int nx, int ny);
+hipError_t launch_conv_counts(const BinnedConvArgs &c, void *ws, hipStream_t s);
+
 // Tile-shape autotuner cache (kde_autotune.cpp).  Keys and choices are
 // described there; the timing runs live in kde_api.cpp.
 namespace tune {

@@ -139,6 +139,26 @@ def test_autotune_cache_roundtrip_and_rejection(tmp_path):
     assert kde.autotune(clear=True) == {}
 
 
+def test_binned_entry_points_validate():
+    L = kde.lib()
+    g = kde.Grid(0.0, 1.0, 0.0, 1.0, 16, 16)
+    assert L.kde_bin_counts(FAKE, 10, None, None, FAKE, None, None) == kde.KDE_EINVAL
+    assert L.kde_bin_counts(None, 10, None, g.handle, FAKE, None, None) == kde.KDE_EINVAL
+    assert L.kde_bin_counts(FAKE, 10, None, g.handle, None, None, None) == kde.KDE_EINVAL
+    assert L.kde_conv_counts(FAKE, FAKE, g.handle, 6, 0.1, 0.1, 129, 3, FAKE, 0, None) == kde.KDE_EINVAL
+    assert "tap radii" in L.kde_last_error().decode()
+    assert L.kde_conv_counts(FAKE, FAKE, g.handle, 6, 0.1, 0.1, 3, -1, FAKE, 0, None) == kde.KDE_EINVAL
+    assert L.kde_conv_counts(FAKE, None, g.handle, 6, 0.1, 0.1, 3, 3, FAKE, 0, None) == kde.KDE_EINVAL
+    assert L.kde_conv_counts(FAKE, FAKE, g.handle, 8, 0.1, 0.1, 3, 3, FAKE, 0, None) == kde.KDE_EINVAL
+    assert L.kde_conv_counts(FAKE, FAKE, g.handle, 6, 0.1, 0.1, 3, 3, FAKE, 8, None) == kde.KDE_EINVAL
+    assert L.kde_eval_binned(FAKE, 10, None, 6, 0.1, 0.1, 3, 3, g.handle, None, 0, None) == kde.KDE_EINVAL
+    assert L.kde_eval_binned(FAKE, 10, None, 6, -0.1, 0.1, 3, 3, g.handle, FAKE, 0, None) == kde.KDE_EINVAL
+    assert kde.paper_taps("gaussian", 7, g) == (g.dx, g.dy, 3, 3)
+    assert kde.paper_taps("epanechnikov", 7, g) == (3 * g.dx, 3 * g.dy, 3, 3)
+    with pytest.raises(ValueError):
+        kde.paper_taps(2, 8, g)
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(kde, "_lib", None)
     monkeypatch.setattr(kde, "LIB_PATH", str(tmp_path / "libkde.so"))
