@@ -176,6 +176,47 @@ def bench_batched(torch, kde, synth, steps: int):
             "separate_pairs_per_s": pairs / (ms_s * 1e-3), "speedup": ms_s / ms_b}
 
 
+def bench_binned(torch, kde, pts, labels, g, ref_map, steps: int):
+    """The paper's binned visualisation on the bench workload: count matrix with
+    gap filling (one label per track), then the Eq. (7) convolution, (a) with the
+    paper's 15 x 15 Gaussian table (sigma one cell) and (b) with the bench's
+    bandwidth (h = 0.002 deg, taps to 6 sigma), whose map without gap filling is
+    compared with the FP32 direct map (the error of the ceil binning itself)."""
+    import numpy as np
+    n, side = pts.shape[0], g.nx
+    res = {"points": n, "grid": [side, side]}
+    counts, total = kde.bin_counts(pts, labels, g)
+    tot, _, _ = timed_steps(torch, lambda: kde.bin_counts(pts, labels, g, counts, total), steps, 1)
+    res["counts_ms"] = tot / steps
+    res["counted_cells"] = int(total.cpu().item())
+    out = torch.empty((side, side), dtype=torch.float32, device=pts.device)
+    H = H_DEG / g.dx
+    r6 = int(np.ceil(6.0 * H))
+    for name, (hx, hy, a, b) in (("paper_gauss_15x15", kde.paper_taps("gaussian", 15, g)),
+                                 ("gauss_h0.002_6sigma", (H_DEG, H_DEG, r6, r6))):
+        tot, _, kern = timed_steps(torch, lambda: kde.conv_counts(counts, total, "gaussian", hx, hy, a, b, g, out=out),
+                                   steps, 1, kde)
+        conv_ms = sum(kern) / len(kern)
+        ms_full, _, _ = timed_steps(torch, lambda: kde.eval_binned(pts, labels, "gaussian", hx, hy, a, b, g, out=out),
+                                    steps, 1)
+        ent = {"taps": [2 * a + 1, 2 * b + 1], "conv_ms": conv_ms, "eval_binned_ms": ms_full / steps,
+               "conv_hbm_gbs": 16.0 * side * side / (conv_ms * 1e-3) / 1e9,
+               "logical_pairs_per_s": n * side * side / (ms_full / steps * 1e-3)}
+        if name.startswith("gauss_h"):
+            # without gap filling both maps are normalised by the same point count
+            kde.eval_binned(pts, None, "gaussian", hx, hy, a, b, g, out=out)
+            y = out.cpu().numpy().astype(np.float64)
+            r = ref_map.astype(np.float64)
+            peak = np.abs(r).max()
+            ent["vs_fp32_direct"] = {"e_inf": float(np.abs(y - r).max() / peak),
+                                     "e_2": float(np.linalg.norm(y - r) / np.linalg.norm(r))}
+        res[name] = ent
+    log("binned: counts %.3f ms, " % res["counts_ms"] + ", ".join(
+        f"{k} conv {v['conv_ms']:.3f} ms / map {v['eval_binned_ms']:.3f} ms" for k, v in res.items()
+        if isinstance(v, dict)))
+    return res
+
+
 def bench_compact(torch, kde, synth, steps: int):
     """The eight kernels on the FP32 direct path: 1,000,000 points (2,000 tracks x
     500) on 1024 x 1024, h = 0.002 degrees."""
@@ -204,8 +245,9 @@ def main() -> int:
     ap.add_argument("--profile-once", action="store_true",
                     help="for counter runs: two FP16 maps and one FP32 direct map, then a 256 MiB "
                          "elementwise copy (torch.neg) as the byte-count calibration; prints no JSON")
-    ap.add_argument("--sections", default="adjoint,batched,kernels",
-                    help="extra measured sections beside the headline: adjoint, batched, kernels (or none)")
+    ap.add_argument("--sections", default="adjoint,batched,kernels,binned",
+                    help="extra measured sections beside the headline: adjoint, batched, kernels, binned "
+                         "(or none)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the KDE map runs on a single MI355X here "
@@ -294,6 +336,9 @@ def main() -> int:
         line["batched"] = bench_batched(torch, kde, synth, 6)
     if "kernels" in extra:
         line["fp32_direct_kernels"] = bench_compact(torch, kde, synth, 5)
+    if "binned" in extra:
+        lab = torch.from_numpy(np.repeat(np.arange(len(t.lengths), dtype=np.int32), t.lengths)).to(dev)
+        line["binned"] = bench_binned(torch, kde, pts, lab, g, maps["fp32"], 10)
     if not args.no_cpu_baseline:
         og_mod = __import__("oracle")
         og = og_mod.Grid(b.lon0, b.lon1, b.lat0, b.lat1, SIDE, SIDE)

@@ -246,12 +246,13 @@ int kde_autotune_dump(char *buf, size_t cap, size_t *needed);
 /* Empties the in-memory cache. */
 int kde_autotune_clear(void);
 
-/* Measurement hook.  The next kde_eval call made by this thread records
- * start_event on its stream right before it launches its main kernel (the
- * separable contraction, the FP32 direct evaluation or the binned gather) and
+/* Measurement hook.  The next kde_eval, kde_conv_counts or kde_eval_binned
+ * call made by this thread records start_event on its stream right before it
+ * launches its main kernel (the separable contraction, the FP32 direct
+ * evaluation, the support-binned gather, or the two convolution passes) and
  * stop_event right after, so that the elapsed time between the two events is
- * that kernel's duration alone, without the point padding, split reduction or
- * binning passes.  Both are hipEvent_t handles owned by the caller, created on
+ * that work alone, without the point padding, split reduction, support-binning
+ * or counting passes.  Both are hipEvent_t handles owned by the caller, created on
  * the device of that call with timing enabled; the request is consumed by that
  * call (also by one that fails or has n = 0, which records nothing).  NULL,
  * NULL cancels a pending request.  Returns KDE_OK, or KDE_EINVAL if exactly

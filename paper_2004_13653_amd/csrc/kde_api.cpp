@@ -33,11 +33,16 @@ constexpr int64_t kMaxPoints = (int64_t)1 << 31;
 
 thread_local std::string g_err;
 
-// Events armed by kde_time_next_main_kernel for this thread's next kde_eval.
+// Events armed by kde_time_next_main_kernel for this thread's next map call.
 struct MainTimer {
     hipEvent_t start = nullptr, stop = nullptr;
 };
 thread_local MainTimer g_timer;
+
+// Disarms the events when a map call returns (whether or not it launched).
+struct ConsumeTimer {
+    ~ConsumeTimer() { g_timer = MainTimer{}; }
+};
 
 int fail(int code, const char *fmt, ...) {
     char buf[512];
@@ -394,9 +399,7 @@ int kde_bandwidth_units(const kde_grid *g, double hx, double hy, float *Hx, floa
 
 int kde_eval(const float *points, int64_t n, int32_t kernel_id, double hx, double hy, const kde_grid *g, float *out,
              int32_t precision, uint32_t flags, void *stream) {
-    struct ConsumeTimer {
-        ~ConsumeTimer() { g_timer = MainTimer{}; }
-    } consume_timer;
+    ConsumeTimer consume_timer;
     try {
         int st = check_map(points, n, kernel_id, hx, hy, g, "kde_eval");
         if (st != KDE_OK) return st;
@@ -518,6 +521,7 @@ int kde_bin_counts(const float *points, int64_t n, const int32_t *labels, const 
 
 int kde_conv_counts(const uint32_t *counts, const uint64_t *total, const kde_grid *g, int32_t kernel_id, double hx,
                     double hy, int32_t a, int32_t b, float *out, uint32_t flags, void *stream) {
+    ConsumeTimer consume_timer;
     try {
         int st = check_taps(kernel_id, hx, hy, a, b, g, "kde_conv_counts");
         if (st != KDE_OK) return st;
@@ -538,6 +542,7 @@ int kde_conv_counts(const uint32_t *counts, const uint64_t *total, const kde_gri
 
 int kde_eval_binned(const float *points, int64_t n, const int32_t *labels, int32_t kernel_id, double hx, double hy,
                     int32_t a, int32_t b, const kde_grid *g, float *out, uint32_t flags, void *stream) {
+    ConsumeTimer consume_timer;
     try {
         int st = check_taps(kernel_id, hx, hy, a, b, g, "kde_eval_binned");
         if (st != KDE_OK) return st;

@@ -42,33 +42,48 @@ __global__ __launch_bounds__(256) void zero_counts_kernel(uint32_t *counts, int6
 }
 
 // One thread per point: its own cell, then the gap cells towards the next point.
+// Consecutive points of a track often share a cell, so the point cells of a
+// wave are combined first: one atomic per distinct cell, adding its
+// multiplicity (integer sums, so the result is the same).
 __global__ __launch_bounds__(256) void bin_points_kernel(const float2 *__restrict__ pts, int64_t n,
                                                          const int32_t *__restrict__ labels, int nx, int ny,
                                                          uint32_t *__restrict__ counts,
                                                          unsigned long long *__restrict__ total) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
     unsigned mine = 0;
+    int64_t key = -1;  // this point's cell, -1 if none
+    int i = -1, j = -1;
     if (p < n) {
         const float2 v = pts[p];
-        const int i = cell_of(v.x, nx), j = cell_of(v.y, ny);
-        if (i >= 0 && j >= 0) {
-            atomicAdd(counts + (int64_t)j * nx + i, 1u);
-            mine = 1;
-            if (labels != nullptr && p + 1 < n && labels[p] == labels[p + 1]) {
-                const float2 w = pts[p + 1];
-                const int i2 = cell_of(w.x, nx), j2 = cell_of(w.y, ny);
-                if (i2 >= 0 && j2 >= 0) {
-                    const int64_t di = i2 - i, dj = j2 - j;
-                    const int64_t cmax = max(di < 0 ? -di : di, dj < 0 ? -dj : dj);
-                    const int64_t bx = 2 * (int64_t)i * cmax + cmax, by = 2 * (int64_t)j * cmax + cmax;
-                    for (int64_t c = 1; c < cmax; ++c) {
-                        // both numerators are positive: the cells lie between the end points
-                        const int64_t ic = (bx + 2 * c * di) / (2 * cmax);
-                        const int64_t jc = (by + 2 * c * dj) / (2 * cmax);
-                        atomicAdd(counts + jc * nx + ic, 1u);
-                    }
-                    mine += (unsigned)(cmax > 1 ? cmax - 1 : 0);
+        i = cell_of(v.x, nx);
+        j = cell_of(v.y, ny);
+        if (i >= 0 && j >= 0) key = (int64_t)j * nx + i;
+    }
+    uint64_t pending = __ballot(key >= 0);
+    while (pending != 0ull) {  // uniform: every lane sees the same masks
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int64_t lkey = __shfl(key, leader);
+        const uint64_t same = __ballot(key == lkey);
+        if (lane == leader) atomicAdd(counts + lkey, (unsigned)__popcll(same));
+        pending &= ~same;
+    }
+    if (key >= 0) {
+        mine = 1;
+        if (labels != nullptr && p + 1 < n && labels[p] == labels[p + 1]) {
+            const float2 w = pts[p + 1];
+            const int i2 = cell_of(w.x, nx), j2 = cell_of(w.y, ny);
+            if (i2 >= 0 && j2 >= 0) {
+                const int64_t di = i2 - i, dj = j2 - j;
+                const int64_t cmax = max(di < 0 ? -di : di, dj < 0 ? -dj : dj);
+                const int64_t bx = 2 * (int64_t)i * cmax + cmax, by = 2 * (int64_t)j * cmax + cmax;
+                for (int64_t c = 1; c < cmax; ++c) {
+                    // both numerators are positive: the cells lie between the end points
+                    const int64_t ic = (bx + 2 * c * di) / (2 * cmax);
+                    const int64_t jc = (by + 2 * c * dj) / (2 * cmax);
+                    atomicAdd(counts + jc * nx + ic, 1u);
                 }
+                mine += (unsigned)(cmax > 1 ? cmax - 1 : 0);
             }
         }
     }
@@ -76,7 +91,7 @@ __global__ __launch_bounds__(256) void bin_points_kernel(const float2 *__restric
     unsigned long long s = mine;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off);
-    if ((threadIdx.x & 63) == 0 && s != 0ull) atomicAdd(total, s);
+    if (lane == 0 && s != 0ull) atomicAdd(total, s);
 }
 
 // One tap g(s / H) at integer offset s (g without the Table I constant).
