@@ -174,7 +174,7 @@ struct SepConfig {
 #if defined(KDE_SEP_HINT_SINGLE) && defined(KDE_SEP_HINT_SPLIT)
     static constexpr int kHintValu = kSplit ? KDE_SEP_HINT_SPLIT : KDE_SEP_HINT_SINGLE;
 #else
-    static constexpr int kHintValu = !kSplit ? 0 : PrecTraits<P>::kBf16 ? 6 : 3;
+    static constexpr int kHintValu = !kSplit ? 0 : PrecTraits<P>::kBf16 ? 4 : 3;
 #endif
 };
 
@@ -375,14 +375,26 @@ __global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p) {
     // factor rows; scheduling barriers keep the phases apart so that every
     // MFMA group has generation work to overlap with.
     auto step_phased = [&](int64_t c, uint4 *gen, const uint4 *use) {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) pts[k] = nxt[k];
-        load_points(qg + (c + 2) * Cfg::KC, nxt);  // consumed one chunk later
+        // The points of chunk c + 1 (in nxt), scaled; nxt then takes chunk c + 2.
+        // The two orders below leave the register allocator different room: for
+        // the splits, scaling first keeps the chunk loop free of spills.
         float px[8], py[8];
+        if constexpr (Cfg::kSplit) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            px[k] = (pts[k].x - x0) * p.ax;
-            py[k] = (pts[k].y - y0) * p.ay;
+            for (int k = 0; k < 8; ++k) {
+                px[k] = (nxt[k].x - x0) * p.ax;
+                py[k] = (nxt[k].y - y0) * p.ay;
+            }
+            load_points(qg + (c + 2) * Cfg::KC, nxt);  // consumed one chunk later
+        } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) pts[k] = nxt[k];
+            load_points(qg + (c + 2) * Cfg::KC, nxt);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                px[k] = (pts[k].x - x0) * p.ax;
+                py[k] = (pts[k].y - y0) * p.ay;
+            }
         }
         const int g8 = tid % Cfg::G, mrun = Cfg::R * (tid / Cfg::G);
         const int word0 = mrun * Cfg::kRowWords + g8;
