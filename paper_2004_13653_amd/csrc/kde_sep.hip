@@ -68,7 +68,7 @@ struct SepLaunch {
     const float2 *pts;  // padded copy: split s owns [s * pad_stride, (s + 1) * pad_stride)
     int64_t n;
     int64_t per_split;  // points per split, multiple of the chunk size
-    int64_t pad_stride; // per_split + 2 chunks of far-away points
+    int64_t pad_stride; // per_split + 3 chunks of far-away points
     float ax, ay;       // Gaussian argument scales sqrt(log2(e)/2)/H
     float Hx, Hy;       // compact kernels: support half-widths
     float ix, iy;       // compact kernels: 1/H
@@ -354,7 +354,9 @@ __global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p) {
 
     const int64_t beg = (int64_t)blockIdx.y * p.per_split;
     const int64_t end = min(p.n, beg + p.per_split);
-    const int64_t nch = (end - beg + Cfg::KC - 1) / Cfg::KC;
+    // Chunks of this split, rounded up to even so that the loop below runs whole
+    // pairs of steps (the padded copy holds far-away points past the end).
+    const int64_t nch = ((end - beg + Cfg::KC - 1) / Cfg::KC + 1) & ~int64_t(1);
     const float2 *qg = p.pts + blockIdx.y * p.pad_stride + 8 * (tid % Cfg::G);  // this thread's group, chunk 0
     const int ta0 = 4 * (wave >> 1), tb0 = 4 * (wave & 1);  // first MFMA row / column tile of this wave
     // Fragment word of lane `lane` for MFMA tile t (32 rows) and k-step kk: row
@@ -490,10 +492,10 @@ __global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p) {
     for (int64_t c = 0; c < nch; c += 2) {
         if constexpr (kPhased) {
             step_phased(c, lds1, lds0);
-            if (c + 1 < nch) step_phased(c + 1, lds0, lds1);
+            step_phased(c + 1, lds0, lds1);
         } else {
             step(c, lds1, lds0);
-            if (c + 1 < nch) step(c + 1, lds0, lds1);
+            step(c + 1, lds0, lds1);
         }
     }
 
@@ -545,8 +547,9 @@ SepPlan sep_plan(const MapArgs &a, int kc) {
     per = (per + kc - 1) / kc * kc;
     pl.splits = (int)std::max<int64_t>(1, (a.n + per - 1) / per);
     pl.per_split = per;
-    // Two extra chunks: the point loads run two chunks ahead of the MFMAs.
-    pl.pad_stride = per + 2 * kc;
+    // Three extra chunks: the chunk count is rounded up to even and the point
+    // loads run two chunks ahead of the MFMAs.
+    pl.pad_stride = per + 3 * kc;
     pl.partial_bytes = pl.splits > 1 ? ((size_t)pl.splits * a.nx * a.ny * sizeof(float) + 255) / 256 * 256 : 0;
     return pl;
 }
