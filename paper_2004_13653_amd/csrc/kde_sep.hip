@@ -171,11 +171,15 @@ struct SepConfig {
     static constexpr int R = G;                            // consecutive rows (and columns) per thread
     // VALU instructions the scheduler places after each MFMA in the Gaussian
     // runs' phases (0: no placement hints).
-#if defined(KDE_SEP_HINT_SINGLE) && defined(KDE_SEP_HINT_SPLIT)
-    static constexpr int kHintValu = kSplit ? KDE_SEP_HINT_SPLIT : KDE_SEP_HINT_SINGLE;
-#else
-    static constexpr int kHintValu = !kSplit ? 0 : PrecTraits<P>::kBf16 ? 4 : 3;
+#ifndef KDE_SEP_HINT_SINGLE
+#define KDE_SEP_HINT_SINGLE 0
 #endif
+#ifndef KDE_SEP_HINT_SPLIT
+    static constexpr int kHintSplit = PrecTraits<P>::kBf16 ? 4 : 2;
+#else
+    static constexpr int kHintSplit = KDE_SEP_HINT_SPLIT;
+#endif
+    static constexpr int kHintValu = kSplit ? kHintSplit : KDE_SEP_HINT_SINGLE;
 };
 
 // The 8 points of one group: 64 contiguous bytes of the padded copy (points
