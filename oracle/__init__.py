@@ -28,6 +28,7 @@ import numpy as np
 
 KERNELS = ("uniform", "triangular", "epanechnikov", "quartic", "triweight", "tricube", "gaussian", "cosine")
 GAUSSIAN = 6
+GAUSS_TRUNC = 8  # the Gaussian truncated at |u| <= 8 (not in Table I)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "kde_oracle.c")
@@ -198,7 +199,9 @@ def _factors(kernel: int, nodes: np.ndarray, coord: np.ndarray, H: np.float32, d
     d = nodes[:, None].astype(np.float64) - coord[None, :].astype(np.float64)
     u = d / np.float64(H)
     val = (dk if deriv else k)(kernel, u)
-    if kernel != GAUSSIAN:
+    if kernel == GAUSS_TRUNC:
+        val = np.where(np.abs(d) <= 8.0 * np.float64(H), val, 0.0)
+    elif kernel != GAUSSIAN:
         val = np.where(np.abs(d) <= np.float64(H), val, 0.0)
     return val
 

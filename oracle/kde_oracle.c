@@ -46,6 +46,11 @@
 #define KO_TRICUBE 5
 #define KO_GAUSSIAN 6
 #define KO_COSINE 7
+/* Not in Table I: the Gaussian truncated at |u| <= KO_TRUNC_SIGMAS (inclusive),
+ * same constant 1/sqrt(2 pi); every pair it drops is below e^-32 of the peak
+ * pair value. */
+#define KO_GAUSS_TRUNC 8
+#define KO_TRUNC_SIGMAS 8.0
 
 static const double PI = 3.14159265358979323846;
 
@@ -65,6 +70,7 @@ double ko_k(int kernel, double u)
 {
     double a = fabs(u);
     if (kernel == KO_GAUSSIAN) return exp(-0.5 * u * u) / sqrt(2.0 * PI);
+    if (kernel == KO_GAUSS_TRUNC) return a <= KO_TRUNC_SIGMAS ? exp(-0.5 * u * u) / sqrt(2.0 * PI) : 0.0;
     if (a > 1.0) return 0.0;
     switch (kernel) {
     case KO_UNIFORM: return 0.5;
@@ -177,6 +183,8 @@ void ko_map_world(const double *xy, int64_t n, int kernel, double hx, double hy,
 static double unit_factor(int kernel, int i, float X, float H)
 {
     double d = (double)i - (double)X;
+    if (kernel == KO_GAUSS_TRUNC) /* support |d| <= 8 H on the exact difference */
+        return fabs(d) <= KO_TRUNC_SIGMAS * (double)H ? ko_k(KO_GAUSSIAN, d / (double)H) : 0.0;
     if (kernel != KO_GAUSSIAN && fabs(d) > (double)H) return 0.0;
     return ko_k(kernel, d / (double)H); /* |d| <= H implies |d/H| <= 1 */
 }

@@ -531,3 +531,36 @@ def test_conv_shift_transpose_and_linearity():
         np.testing.assert_allclose(mt, m.T, rtol=1e-13, atol=1e-13)
         mab = oracle.conv_counts(A + B, kernel, 2.5, 1.5, 3, 2)
         np.testing.assert_allclose(mab, m + oracle.conv_counts(B, kernel, 2.5, 1.5, 3, 2), rtol=1e-12, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# The Gaussian truncated at |u| <= 8 (a banded variant of the Gaussian map).
+
+def test_truncated_gaussian_factor_and_mass():
+    """k_T(u) = phi(u) for |u| <= 8 (inclusive), 0 beyond; its mass is
+    erf(8 / sqrt 2) = 1 - 1.2e-15."""
+    u = np.array([0.0, 1.5, -7.999, 8.0, -8.0, 8.0001, 20.0])
+    want = np.where(np.abs(u) <= 8.0, stats.norm.pdf(u), 0.0)
+    np.testing.assert_array_equal(oracle.k(oracle.GAUSS_TRUNC, u) == 0.0, want == 0.0)
+    np.testing.assert_allclose(oracle.k(oracle.GAUSS_TRUNC, u), want, rtol=1e-14, atol=0)
+    m, _ = integrate.quad(lambda x: oracle.k(oracle.GAUSS_TRUNC, [x])[0], -8.0, 8.0, points=[0.0], limit=200)
+    assert m == pytest.approx(math.erf(8.0 / math.sqrt(2.0)), abs=1e-13)
+
+
+def test_truncated_gaussian_map_bound_and_boundary():
+    """The truncated map never exceeds the full one and differs by at most the
+    dropped tails: each pair loses less than phi(0)^2 e^-32.  On the grid, the
+    support is |i - X| <= 8 H on the exact difference (inclusive)."""
+    rng = np.random.default_rng(8)
+    XY = np.column_stack([rng.uniform(-20, 60, 3000), rng.uniform(-20, 50, 3000)]).astype(np.float32)
+    for H in (0.7, 2.0, 5.0):
+        full = oracle.map_units(XY, oracle.GAUSSIAN, H, 0.8 * H, (0, 40, 0, 30))
+        trunc = oracle.map_units(XY, oracle.GAUSS_TRUNC, H, 0.8 * H, (0, 40, 0, 30))
+        assert np.all(trunc <= full + 1e-300)
+        bound = XY.shape[0] * stats.norm.pdf(0.0) ** 2 * math.exp(-32.0)
+        assert np.max(full - trunc) <= bound
+        assert np.max(full - trunc) > 0.0 or H == 5.0
+    one = np.array([[0.0, 0.0]], dtype=np.float32)
+    m = oracle.map_units(one, oracle.GAUSS_TRUNC, 0.5, 0.5, (0, 6, 0, 1))[0]
+    assert m[4] == pytest.approx(stats.norm.pdf(8.0) * stats.norm.pdf(0.0), rel=1e-13)  # d = 4 = 8 H: kept
+    assert m[5] == 0.0                                                                   # d = 5 > 8 H
