@@ -217,6 +217,26 @@ def bench_binned(torch, kde, pts, labels, g, ref_map, steps: int):
     return res
 
 
+def bench_truncated(torch, kde, pts, g, ref_map, steps: int):
+    """The Gaussian truncated at 8 bandwidths (KDE_TRUNCATE, FP32 direct path
+    with support binning) on the bench workload, against the full FP32 map."""
+    import numpy as np
+    n, side = pts.shape[0], g.nx
+    out = torch.empty((side, side), dtype=torch.float32, device=pts.device)
+    f = lambda: kde.eval(pts, "gaussian", H_DEG, H_DEG, g, out=out, truncate=True)  # noqa: E731
+    tot, _, kern = timed_steps(torch, f, steps, 2, kde)
+    ms = tot / steps
+    y = out.cpu().numpy().astype(np.float64)
+    r = ref_map.astype(np.float64)
+    res = {"ms_per_map": ms, "gather_kernel_ms": sum(kern) / len(kern),
+           "logical_pairs_per_s": n * side * side / (ms * 1e-3),
+           "vs_fp32_direct": {"e_inf": float(np.abs(y - r).max() / np.abs(r).max()),
+                              "e_2": float(np.linalg.norm(y - r) / np.linalg.norm(r))},
+           "shape": {k: v["choice"] for k, v in kde.autotune().items() if "/gtrunc/" in k}}
+    log(f"truncated Gaussian (8 h): {ms:.3f} ms per map, e_inf vs full FP32 {res['vs_fp32_direct']['e_inf']:.1e}")
+    return res
+
+
 def bench_compact(torch, kde, synth, steps: int):
     """The eight kernels on the FP32 direct path: 1,000,000 points (2,000 tracks x
     500) on 1024 x 1024, h = 0.002 degrees."""
@@ -245,9 +265,9 @@ def main() -> int:
     ap.add_argument("--profile-once", action="store_true",
                     help="for counter runs: two FP16 maps and one FP32 direct map, then a 256 MiB "
                          "elementwise copy (torch.neg) as the byte-count calibration; prints no JSON")
-    ap.add_argument("--sections", default="adjoint,batched,kernels,binned",
-                    help="extra measured sections beside the headline: adjoint, batched, kernels, binned "
-                         "(or none)")
+    ap.add_argument("--sections", default="adjoint,batched,kernels,binned,truncated",
+                    help="extra measured sections beside the headline: adjoint, batched, kernels, binned, "
+                         "truncated (or none)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the KDE map runs on a single MI355X here "
@@ -336,6 +356,8 @@ def main() -> int:
         line["batched"] = bench_batched(torch, kde, synth, 6)
     if "kernels" in extra:
         line["fp32_direct_kernels"] = bench_compact(torch, kde, synth, 5)
+    if "truncated" in extra:
+        line["truncated"] = bench_truncated(torch, kde, pts, g, maps["fp32"], 10)
     if "binned" in extra:
         lab = torch.from_numpy(np.repeat(np.arange(len(t.lengths), dtype=np.int32), t.lengths)).to(dev)
         line["binned"] = bench_binned(torch, kde, pts, lab, g, maps["fp32"], 10)

@@ -88,6 +88,7 @@ enum {
 #define KDE_RAW_SUM 1u          /* the map is S instead of S/(n hx hy) */
 #define KDE_GRID_UNIT_GRADS 2u  /* kde_backward: grad_points as dL/dX_p, dL/dY_p in grid units */
 #define KDE_BATCH_EAGER 4u      /* kde_eval_batched: launch directly instead of replaying a graph */
+#define KDE_TRUNCATE 8u         /* kde_eval, Gaussian, KDE_FP32_DIRECT: drop pairs beyond 8 bandwidths */
 
 typedef struct kde_grid kde_grid; /* opaque, immutable, library-owned */
 
@@ -121,8 +122,17 @@ int kde_bandwidth_units(const kde_grid *g, double hx, double hy, float *Hx, floa
  *   g         grid handle
  *   out       device, FP32 [ny][nx], fully overwritten
  *   precision KDE_FP32_DIRECT or one of the *_SEP matrix-core paths
- *   flags     0 or KDE_RAW_SUM
- *   stream    hipStream_t or NULL */
+ *   flags     0, KDE_RAW_SUM, KDE_TRUNCATE (or both)
+ *   stream    hipStream_t or NULL
+ * KDE_TRUNCATE (not in the paper; Gaussian only, else KDE_EINVAL): pairs with
+ * |i - X| > 8 Hx or |j - Y| > 8 Hy are dropped, so the Gaussian gets the compact
+ * kernels' treatment: support binning on the FP32 path, banded (block-sparse)
+ * products on the matrix-core paths.  Each dropped pair is below
+ * e^-32 = 1.3e-14 of the largest pair value, so the map is below the full one by
+ * at most n * 1.3e-14 of the peak pair value.
+ * Matrix-core paths with a compact kernel (or KDE_TRUNCATE) whose support is at
+ * most 256 grid units run banded: points are binned by 256 x 256 tile and only
+ * the tiles a point reaches multiply it. */
 int kde_eval(const float *points, int64_t n, int32_t kernel_id, double hx, double hy, const kde_grid *g,
              float *out, int32_t precision, uint32_t flags, void *stream);
 

@@ -158,10 +158,15 @@ def _check_points(points, torch):
         raise ValueError("points must be contiguous")
 
 
+TRUNCATE = 8
+
+
 def eval(points, kernel, hx: float, hy: float, grid: Grid, out=None, precision: str = "fp32",
-         raw: bool = False):
+         raw: bool = False, truncate: bool = False):
     """The heat map of `points` ([n, 2] FP32 grid units on the GPU) on `grid`:
-    returns (or fills) an [ny, nx] FP32 tensor (kde_eval)."""
+    returns (or fills) an [ny, nx] FP32 tensor (kde_eval).  truncate: the
+    Gaussian cut at 8 bandwidths (binned on the FP32 path, banded on the
+    matrix-core paths)."""
     import torch
     _check_points(points, torch)
     if out is None:
@@ -171,7 +176,8 @@ def eval(points, kernel, hx: float, hy: float, grid: Grid, out=None, precision: 
     with torch.cuda.device(points.device):
         _check(lib().kde_eval(points.data_ptr() if points.numel() else None, points.shape[0], _kernel_id(kernel),
                               hx, hy, grid.handle, out.data_ptr(), PRECISIONS[precision],
-                              RAW_SUM if raw else 0, _stream(torch, points.device)))
+                              (RAW_SUM if raw else 0) | (TRUNCATE if truncate else 0),
+                              _stream(torch, points.device)))
     return out
 
 

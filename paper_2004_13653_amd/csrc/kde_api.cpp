@@ -167,7 +167,8 @@ std::string eval_key(const kde::MapArgs &a) {
     char buf[192];
     const double H = std::max(a.Hx, a.Hy);
     std::snprintf(buf, sizeof buf, "eval/%s/%s/H%d/n%d/px%d", device_arch().c_str(),
-                  a.kernel_id == KDE_GAUSSIAN ? "gauss" : "compact", (int)std::floor(2.0 * std::log2(H)),
+                  a.kernel_id == KDE_GAUSSIAN ? "gauss" : a.kernel_id == kde::kGaussTrunc ? "gtrunc" : "compact",
+                  (int)std::floor(2.0 * std::log2(H)),
                   log2_floor((double)a.n), log2_floor((double)a.nx * a.ny));
     return buf;
 }
@@ -223,7 +224,11 @@ hipError_t time_twice(F f, hipStream_t s, const EventPair &ev, float *ms) {
 // Register-block side for one FP32 direct map: forced, cached, tuned now or default.
 int pick_rc(kde::MapArgs a, hipStream_t s, int *rc_out) {
     const int forced = kde::tune::forced();
-    const int def = a.kernel_id == KDE_GAUSSIAN ? kRcGauss : kRcCompact;
+    int def = a.kernel_id == KDE_GAUSSIAN ? kRcGauss : kRcCompact;
+    if (a.kernel_id == kde::kGaussTrunc) {  // the smallest tile that still bins the support
+        const float reach = std::max(a.Hx, a.Hy);
+        def = reach <= 32.0f ? 2 : reach <= 64.0f ? 4 : 8;
+    }
     *rc_out = forced ? forced : def;
     if (forced || !kde::tune::enabled()) return KDE_OK;
     const std::string key = eval_key(a);
@@ -404,9 +409,12 @@ int kde_eval(const float *points, int64_t n, int32_t kernel_id, double hx, doubl
         int st = check_map(points, n, kernel_id, hx, hy, g, "kde_eval");
         if (st != KDE_OK) return st;
         if (out == nullptr) return fail(KDE_EINVAL, "kde_eval: out is NULL");
-        if (flags & ~KDE_RAW_SUM) return fail(KDE_EINVAL, "kde_eval: unknown flags 0x%x", flags);
+        if (flags & ~(KDE_RAW_SUM | KDE_TRUNCATE)) return fail(KDE_EINVAL, "kde_eval: unknown flags 0x%x", flags);
         if (precision < KDE_FP32_DIRECT || precision > KDE_BF16X3_SEP)
             return fail(KDE_EINVAL, "kde_eval: unknown precision %d", (int)precision);
+        const bool truncate = (flags & KDE_TRUNCATE) != 0;
+        if (truncate && kernel_id != KDE_GAUSSIAN)
+            return fail(KDE_EINVAL, "kde_eval: KDE_TRUNCATE applies to the Gaussian kernel only");
         hipStream_t s = static_cast<hipStream_t>(stream);
         const int64_t plane = (int64_t)g->nx * g->ny;
         if (n == 0) {
@@ -414,6 +422,11 @@ int kde_eval(const float *points, int64_t n, int32_t kernel_id, double hx, doubl
             return e == hipSuccess ? KDE_OK : hip_fail(e, "kde_eval");
         }
         kde::MapArgs a = make_args(points, n, kernel_id, hx, hy, g, out, flags);
+        if (truncate) {  // support 8 bandwidths, Gaussian argument scale and constant
+            a.kernel_id = kde::kGaussTrunc;
+            a.Hx *= kde::kTruncSigmas;
+            a.Hy *= kde::kTruncSigmas;
+        }
         const bool direct = precision == KDE_FP32_DIRECT;
         if (direct) {
             st = pick_rc(a, s, &a.rc);

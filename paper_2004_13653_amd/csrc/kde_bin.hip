@@ -200,11 +200,10 @@ struct BinPlan {
     size_t off_bytes, totals_bytes, bins_bytes, part_bytes;
 };
 
-BinPlan bin_plan(const MapArgs &a) {
+BinPlan bin_plan(const MapArgs &a, int T) {
     BinPlan pl;
     pl.g.nx = a.nx;
     pl.g.ny = a.ny;
-    const int T = 16 * a.rc;
     pl.g.tile = T;
     pl.g.tiles_x = (a.nx + T - 1) / T;
     pl.g.tiles_y = (a.ny + T - 1) / T;
@@ -247,29 +246,13 @@ hipError_t launch_gather(const GatherLaunch &p, int rc, int tiles, int splits, h
     }
 }
 
-}  // namespace
-
-bool binning_applies(const MapArgs &a) {
-    if (a.kernel_id == kGaussian || a.n < 4096 || !valid_rc(a.rc)) return false;
-    const float T = (float)(16 * a.rc);
-    if (a.Hx > T || a.Hy > T) return false;  // at most 3 x 3 tiles per point
-    const BinPlan pl = bin_plan(a);
-    return pl.cnt_len <= (int64_t(1) << 26) && pl.max_entries <= (int64_t(1) << 30);
-}
-
-size_t binned_workspace_bytes(const MapArgs &a) {
-    const BinPlan pl = bin_plan(a);
-    return align256(pl.off_bytes) + align256(pl.totals_bytes) + align256(pl.bins_bytes) + pl.part_bytes;
-}
-
-hipError_t launch_binned(const MapArgs &a, void *ws, hipStream_t s) {
-    const BinPlan pl = bin_plan(a);
-    char *w = static_cast<char *>(ws);
+// Count, scan and scatter into workspace ws (layout: counts/ends, scan totals,
+// bins); the bins then hold each tile's points contiguously, in tile order.
+hipError_t scatter_bins(const MapArgs &a, const BinPlan &pl, char *w, unsigned **off_out, float2 **bins_out,
+                        hipStream_t s) {
     unsigned *off = reinterpret_cast<unsigned *>(w);
     unsigned *totals = reinterpret_cast<unsigned *>(w + align256(pl.off_bytes));
     float2 *bins = reinterpret_cast<float2 *>(w + align256(pl.off_bytes) + align256(pl.totals_bytes));
-    float *part = reinterpret_cast<float *>(w + align256(pl.off_bytes) + align256(pl.totals_bytes) +
-                                            align256(pl.bins_bytes));
     hipError_t e = launch_fill_zero(reinterpret_cast<float *>(off), pl.cnt_len, s);  // 0.0f is all-zero bits
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(bin_count_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, pl.g, a.pts, off);
@@ -279,7 +262,60 @@ hipError_t launch_binned(const MapArgs &a, void *ws, hipStream_t s) {
                        pl.cnt_len, static_cast<const unsigned *>(totals));
     hipLaunchKernelGGL(bin_scatter_kernel, dim3((unsigned)((pl.g.wblocks + 3) / 4)), dim3(256), 0, s, pl.g, a.pts,
                        off, bins);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    *off_out = off;
+    *bins_out = bins;
+    return hipGetLastError();
+}
+
+size_t scatter_bytes(const BinPlan &pl) {
+    return align256(pl.off_bytes) + align256(pl.totals_bytes) + align256(pl.bins_bytes);
+}
+
+}  // namespace
+
+bool binning_applies(const MapArgs &a) {
+    if (a.kernel_id == kGaussian || a.n < 4096 || !valid_rc(a.rc)) return false;
+    const float T = (float)(16 * a.rc);
+    if (a.Hx > T || a.Hy > T) return false;  // at most 3 x 3 tiles per point
+    const BinPlan pl = bin_plan(a, 16 * a.rc);
+    return pl.cnt_len <= (int64_t(1) << 26) && pl.max_entries <= (int64_t(1) << 30);
+}
+
+size_t binned_workspace_bytes(const MapArgs &a) {
+    const BinPlan pl = bin_plan(a, 16 * a.rc);
+    return scatter_bytes(pl) + pl.part_bytes;
+}
+
+bool tile_bins_fit(const MapArgs &a, int tile) {
+    if (a.n < 1 || a.Hx > (float)tile || a.Hy > (float)tile) return false;
+    const BinPlan pl = bin_plan(a, tile);
+    return pl.cnt_len <= (int64_t(1) << 26) && pl.max_entries <= (int64_t(1) << 30);
+}
+
+size_t tile_bins_bytes(const MapArgs &a, int tile) { return scatter_bytes(bin_plan(a, tile)); }
+
+hipError_t launch_tile_bins(const MapArgs &a, int tile, void *ws, hipStream_t s, TileBins *out) {
+    const BinPlan pl = bin_plan(a, tile);
+    unsigned *off = nullptr;
+    float2 *bins = nullptr;
+    hipError_t e = scatter_bins(a, pl, static_cast<char *>(ws), &off, &bins, s);
+    out->bins = bins;
+    out->end = off;
+    out->wblocks = pl.g.wblocks;
+    out->tiles_x = pl.g.tiles_x;
+    out->tiles_y = pl.g.tiles_y;
+    out->max_entries = pl.max_entries;
+    return e;
+}
+
+hipError_t launch_binned(const MapArgs &a, void *ws, hipStream_t s) {
+    const BinPlan pl = bin_plan(a, 16 * a.rc);
+    char *w = static_cast<char *>(ws);
+    float *part = reinterpret_cast<float *>(w + scatter_bytes(pl));
+    unsigned *off = nullptr;
+    float2 *bins = nullptr;
+    hipError_t e = scatter_bins(a, pl, w, &off, &bins, s);
+    if (e != hipSuccess) return e;
     GatherLaunch p;
     p.bins = bins;
     p.end = off;
@@ -303,6 +339,7 @@ hipError_t launch_binned(const MapArgs &a, void *ws, hipStream_t s) {
     case kTriweight: e = launch_gather<kTriweight>(p, a.rc, tiles, pl.splits, s); break;
     case kTricube: e = launch_gather<kTricube>(p, a.rc, tiles, pl.splits, s); break;
     case kCosine: e = launch_gather<kCosine>(p, a.rc, tiles, pl.splits, s); break;
+    case kGaussTrunc: e = launch_gather<kGaussTrunc>(p, a.rc, tiles, pl.splits, s); break;
     default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess || pl.splits == 1) return e;

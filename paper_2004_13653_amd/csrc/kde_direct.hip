@@ -140,12 +140,14 @@ double kernel_norm(int kernel_id) {
     case kTricube: return 70.0 / 81.0;
     case kGaussian: return 1.0 / std::sqrt(2.0 * pi);
     case kCosine: return pi / 4.0;
+    case kGaussTrunc: return 1.0 / std::sqrt(2.0 * pi);
     default: return 0.0;
     }
 }
 
 float arg_scale(int kernel_id, float H) {
     if (kernel_id == kGaussian) return (float)(std::sqrt(0.5 / std::log(2.0)) / (double)H);
+    if (kernel_id == kGaussTrunc) return arg_scale(kGaussian, H / kTruncSigmas);  // H: the support
     return (float)(1.0 / (double)H);
 }
 
@@ -177,6 +179,7 @@ hipError_t launch_direct(const MapArgs &a, void *ws, hipStream_t stream) {
     case kTricube: e = launch_k<kTricube>(a, pl, dst, stream); break;
     case kGaussian: e = launch_k<kGaussian>(a, pl, dst, stream); break;
     case kCosine: e = launch_k<kCosine>(a, pl, dst, stream); break;
+    case kGaussTrunc: e = launch_k<kGaussTrunc>(a, pl, dst, stream); break;
     default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess || pl.splits == 1) return e;

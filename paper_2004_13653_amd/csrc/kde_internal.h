@@ -29,7 +29,13 @@ enum KernelId : int {
     kTricube = 5,
     kGaussian = 6,
     kCosine = 7,
+    kGaussTrunc = 8,  // internal: the Gaussian truncated at |u| <= kTruncSigmas (KDE_TRUNCATE)
 };
+
+// KDE_TRUNCATE: support half-width of the truncated Gaussian in bandwidths.  The
+// map arguments then carry H = kTruncSigmas * (h / spacing) as the support and
+// a = arg_scale(kGaussian, h / spacing) as the argument scale.
+constexpr float kTruncSigmas = 8.0f;
 
 // Normalising constant c of the 1-D factor k(u) = c g(u) (Table I); the kernels
 // accumulate products of g and the epilogue multiplies by c^2.
@@ -76,7 +82,25 @@ bool binning_applies(const MapArgs &a);
 size_t binned_workspace_bytes(const MapArgs &a);
 hipError_t launch_binned(const MapArgs &a, void *ws, hipStream_t stream);
 
-// Matrix-core separable path (precision kPrecFp16 .. kPrecBf16x3).
+// Points binned by square tiles of side `tile` (each point registered in every
+// tile its support rectangle [X +- Hx] x [Y +- Hy] reaches; needs Hx, Hy <= tile):
+// bins holds each tile's points contiguously in tile order, point order kept;
+// tile t's points are bins[end[t*wblocks - 1] .. end[t*wblocks + wblocks - 1])
+// (begin 0 for t = 0).  max_entries bounds the number of registrations.
+struct TileBins {
+    const float2 *bins;
+    const unsigned *end;
+    int64_t wblocks;
+    int tiles_x, tiles_y;
+    int64_t max_entries;
+};
+bool tile_bins_fit(const MapArgs &a, int tile);
+size_t tile_bins_bytes(const MapArgs &a, int tile);
+hipError_t launch_tile_bins(const MapArgs &a, int tile, void *ws, hipStream_t s, TileBins *out);
+
+// Matrix-core separable path (precision kPrecFp16 .. kPrecBf16x3).  Compact
+// kernels (and the truncated Gaussian) whose support fits a 256-node tile run
+// banded: only the (tile, point) pairs the support reaches are multiplied.
 hipError_t launch_sep(const MapArgs &a, int precision, void *ws, hipStream_t stream);
 size_t sep_workspace_bytes(const MapArgs &a, int precision);
 

@@ -64,7 +64,19 @@ struct PrecTraits<kPrecBf16x3> {
     static constexpr bool kSplit = true, kBf16 = true;
 };
 
+// Banded work item: the points of one 256 x 256 tile's bin (or a share of
+// them), copied padded to pts[pad_off ..]; its partial tile goes to slot
+// (the item's index).
+struct SepItem {
+    int tile, pad_;
+    int64_t begin;    // first point in the tile bins
+    int64_t len;      // points
+    int64_t pad_off;  // first point of the padded copy
+};
+
 struct SepLaunch {
+    const SepItem *items;  // banded: the work item of each workgroup; nullptr: dense splits
+    const int *n_items;    // banded: number of valid items (device)
     const float2 *pts;  // padded copy: split s owns [s * pad_stride, (s + 1) * pad_stride)
     int64_t n;
     int64_t per_split;  // points per split, multiple of the chunk size
@@ -85,6 +97,9 @@ __device__ __forceinline__ float sep_factor(float m, float pr, float H, float in
     if constexpr (K == kGaussian) {
         const float t = m - pr;
         return __builtin_amdgcn_exp2f(-t * t);
+    } else if constexpr (K == kGaussTrunc) {  // H: support 8 h; inv: the Gaussian argument scale
+        const float d = m - pr, t = d * inv;
+        return fabsf(d) <= H ? __builtin_amdgcn_exp2f(-t * t) : 0.0f;
     } else {
         const float d = m - pr;
         const float u = fminf(fabsf(d) * inv, 1.0f);
@@ -338,7 +353,24 @@ __global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p) {
     __shared__ uint4 lds1[kOps * W];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int tx = blockIdx.x % p.tiles_x, ty = blockIdx.x / p.tiles_x;
+    // Dense: tile blockIdx.x, point split blockIdx.y.  Banded: the item's tile
+    // and points (workgroups past the last item leave at once).
+    const bool banded = p.items != nullptr;
+    int tile_idx = blockIdx.x;
+    int64_t count;
+    const float2 *qbase;
+    if (banded) {
+        if ((int)blockIdx.x >= *p.n_items) return;
+        const SepItem it = p.items[blockIdx.x];
+        tile_idx = it.tile;
+        count = it.len;
+        qbase = p.pts + it.pad_off;
+    } else {
+        const int64_t beg = (int64_t)blockIdx.y * p.per_split;
+        count = min(p.n, beg + p.per_split) - beg;
+        qbase = p.pts + blockIdx.y * p.pad_stride;
+    }
+    const int tx = tile_idx % p.tiles_x, ty = tile_idx / p.tiles_x;
     const int col0 = tx * kTile, row0 = ty * kTile;
     const float x0 = (float)col0, y0 = (float)row0;
 
@@ -356,12 +388,10 @@ __global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
 
-    const int64_t beg = (int64_t)blockIdx.y * p.per_split;
-    const int64_t end = min(p.n, beg + p.per_split);
     // Chunks of this split, rounded up to even so that the loop below runs whole
     // pairs of steps (the padded copy holds far-away points past the end).
-    const int64_t nch = ((end - beg + Cfg::KC - 1) / Cfg::KC + 1) & ~int64_t(1);
-    const float2 *qg = p.pts + blockIdx.y * p.pad_stride + 8 * (tid % Cfg::G);  // this thread's group, chunk 0
+    const int64_t nch = ((count + Cfg::KC - 1) / Cfg::KC + 1) & ~int64_t(1);
+    const float2 *qg = qbase + 8 * (tid % Cfg::G);  // this thread's group, chunk 0
     const int ta0 = 4 * (wave >> 1), tb0 = 4 * (wave & 1);  // first MFMA row / column tile of this wave
     // Fragment word of lane `lane` for MFMA tile t (32 rows) and k-step kk: row
     // 32 t + lane % 32, point group 2 kk + lane / 32.
@@ -505,6 +535,18 @@ __global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p) {
 
     // Epilogue: register r of lane l in a 32 x 32 tile holds row 8 (r / 4) + 4 (l / 32) + r % 4,
     // column l % 32.  Gaussian runs: multiply by q(row mod R) q(column mod R).
+    if (banded) {  // raw partial tile, row-major 256 x 256, in the item's slot
+        float *slot = p.dst + (int64_t)blockIdx.x * (kTile * kTile);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    slot[(32 * (ta0 + a) + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)) * kTile + 32 * (tb0 + b) +
+                         (lane & 31)] = acc[a][b][r];
+        return;
+    }
     float *dst = p.dst + (int64_t)blockIdx.y * p.plane;
     const float sc = gridDim.y == 1 ? p.scale : 1.0f;
     float qcol = 1.0f, qrow[4] = {1.0f, 1.0f, 1.0f, 1.0f};
@@ -574,20 +616,34 @@ int chunk_for(int precision) {
     }
 }
 
+// Banded launch: one workgroup per possible item.
+struct BandedItems {
+    const SepItem *items;
+    const int *n_items;
+    int max_items;
+};
+
 template <int K, int P>
 hipError_t launch_sep_kp(const MapArgs &a, const SepPlan &pl, const float2 *padded, float *dst,
-                         hipStream_t stream) {
+                         hipStream_t stream, const BandedItems *bi = nullptr) {
     SepLaunch p;
     p.pts = padded;
     p.n = a.n;
     p.per_split = pl.per_split;
     p.pad_stride = pl.pad_stride;
+    p.items = bi ? bi->items : nullptr;
+    p.n_items = bi ? bi->n_items : nullptr;
+    const dim3 grid = bi ? dim3((unsigned)bi->max_items, 1) : dim3(pl.tiles, pl.splits);
     p.ax = arg_scale(kGaussian, a.Hx);
     p.ay = arg_scale(kGaussian, a.Hy);
     p.Hx = a.Hx;
     p.Hy = a.Hy;
     p.ix = (float)(1.0 / (double)a.Hx);
     p.iy = (float)(1.0 / (double)a.Hy);
+    if constexpr (K == kGaussTrunc) {  // support in H, Gaussian argument scale in ix, iy
+        p.ix = a.ax;
+        p.iy = a.ay;
+    }
     p.nx = a.nx;
     p.ny = a.ny;
     p.tiles_x = pl.tiles_x;
@@ -601,43 +657,244 @@ hipError_t launch_sep_kp(const MapArgs &a, const SepPlan &pl, const float2 *padd
     if constexpr (K == kGaussian) {
         if (recur) {
             main_kernel_begin(stream);
-            hipLaunchKernelGGL((sep_mfma_kernel<K, P, true>), dim3(pl.tiles, pl.splits), dim3(kThreadsSep), 0,
-                               stream, p);
+            hipLaunchKernelGGL((sep_mfma_kernel<K, P, true>), grid, dim3(kThreadsSep), 0, stream, p);
             main_kernel_end(stream);
             return hipGetLastError();
         }
     }
     main_kernel_begin(stream);
-    hipLaunchKernelGGL((sep_mfma_kernel<K, P, false>), dim3(pl.tiles, pl.splits), dim3(kThreadsSep), 0, stream, p);
+    hipLaunchKernelGGL((sep_mfma_kernel<K, P, false>), grid, dim3(kThreadsSep), 0, stream, p);
     main_kernel_end(stream);
     return hipGetLastError();
 }
 
 template <int P>
 hipError_t launch_sep_p(const MapArgs &a, const SepPlan &pl, const float2 *padded, float *dst,
-                        hipStream_t stream) {
+                        hipStream_t stream, const BandedItems *bi = nullptr) {
     switch (a.kernel_id) {
-    case kUniform: return launch_sep_kp<kUniform, P>(a, pl, padded, dst, stream);
-    case kTriangular: return launch_sep_kp<kTriangular, P>(a, pl, padded, dst, stream);
-    case kEpanechnikov: return launch_sep_kp<kEpanechnikov, P>(a, pl, padded, dst, stream);
-    case kQuartic: return launch_sep_kp<kQuartic, P>(a, pl, padded, dst, stream);
-    case kTriweight: return launch_sep_kp<kTriweight, P>(a, pl, padded, dst, stream);
-    case kTricube: return launch_sep_kp<kTricube, P>(a, pl, padded, dst, stream);
-    case kGaussian: return launch_sep_kp<kGaussian, P>(a, pl, padded, dst, stream);
-    case kCosine: return launch_sep_kp<kCosine, P>(a, pl, padded, dst, stream);
+    case kUniform: return launch_sep_kp<kUniform, P>(a, pl, padded, dst, stream, bi);
+    case kTriangular: return launch_sep_kp<kTriangular, P>(a, pl, padded, dst, stream, bi);
+    case kEpanechnikov: return launch_sep_kp<kEpanechnikov, P>(a, pl, padded, dst, stream, bi);
+    case kQuartic: return launch_sep_kp<kQuartic, P>(a, pl, padded, dst, stream, bi);
+    case kTriweight: return launch_sep_kp<kTriweight, P>(a, pl, padded, dst, stream, bi);
+    case kTricube: return launch_sep_kp<kTricube, P>(a, pl, padded, dst, stream, bi);
+    case kGaussian: return launch_sep_kp<kGaussian, P>(a, pl, padded, dst, stream, bi);
+    case kCosine: return launch_sep_kp<kCosine, P>(a, pl, padded, dst, stream, bi);
+    case kGaussTrunc: return launch_sep_kp<kGaussTrunc, P>(a, pl, padded, dst, stream, bi);
     default: return hipErrorInvalidValue;
     }
+}
+
+template <int P>
+hipError_t launch_sep_prec(int precision, const MapArgs &a, const SepPlan &pl, const float2 *padded, float *dst,
+                           hipStream_t stream, const BandedItems *bi) {
+    (void)precision;
+    return launch_sep_p<P>(a, pl, padded, dst, stream, bi);
+}
+
+hipError_t launch_sep_any(int precision, const MapArgs &a, const SepPlan &pl, const float2 *padded, float *dst,
+                          hipStream_t stream, const BandedItems *bi = nullptr) {
+    switch (precision) {
+    case kPrecFp16: return launch_sep_p<kPrecFp16>(a, pl, padded, dst, stream, bi);
+    case kPrecBf16: return launch_sep_p<kPrecBf16>(a, pl, padded, dst, stream, bi);
+    case kPrecFp16x3: return launch_sep_p<kPrecFp16x3>(a, pl, padded, dst, stream, bi);
+    case kPrecBf16x3: return launch_sep_p<kPrecBf16x3>(a, pl, padded, dst, stream, bi);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// ------------------------------------------------------------------ banded path
+// Compact supports (and the truncated Gaussian) reach few 256 x 256 tiles, so
+// instead of every tile streaming every point, the points are binned by tile
+// (support binning at tile side 256), each tile's bin is cut into items of
+// about equal length (so that about kBandTarget workgroups share the work) and
+// padded like a dense split, the contraction kernel runs one workgroup per item
+// writing a raw partial tile, and a last pass adds each tile's partials in item
+// order and applies the scale.  Every sum keeps a fixed order: deterministic.
+
+constexpr int kBandTarget = 256;  // items aimed at (one workgroup per CU)
+
+__host__ __device__ inline int64_t band_padded_len(int64_t len, int kc) {
+    return ((((len + kc - 1) / kc) + 1) & ~int64_t(1)) * kc + 2 * kc;
+}
+
+// One workgroup: tile counts from the bin ends, the points per item, the items
+// (tile-major), each tile's first item and item count, the padded offsets.
+__global__ __launch_bounds__(256) void band_assign_kernel(const unsigned *__restrict__ end, int64_t wblocks, int tiles,
+                                                          int kc, SepItem *__restrict__ items,
+                                                          int *__restrict__ first_item, int *__restrict__ nsplit,
+                                                          int *__restrict__ n_items) {
+    __shared__ long long sh[256];
+    __shared__ long long s_total, s_per;
+    const int tid = threadIdx.x;
+    const int t0 = (int)((int64_t)tiles * tid / 256), t1 = (int)((int64_t)tiles * (tid + 1) / 256);
+    auto bin_begin = [&](int t) -> int64_t { return t > 0 ? (int64_t)end[(int64_t)t * wblocks - 1] : 0; };
+    auto bin_end = [&](int t) -> int64_t { return (int64_t)end[(int64_t)t * wblocks + wblocks - 1]; };
+    long long local = 0;
+    for (int t = t0; t < t1; ++t) local += bin_end(t) - bin_begin(t);
+    sh[tid] = local;
+    __syncthreads();
+    if (tid == 0) {
+        long long tot = 0;
+        for (int k = 0; k < 256; ++k) tot += sh[k];
+        s_total = tot;
+        long long per = (tot + kBandTarget - 1) / kBandTarget;
+        per = (per + kc - 1) / kc * kc;
+        s_per = per < 4 * kc ? 4 * kc : per;
+    }
+    __syncthreads();
+    const long long per = s_per;
+    auto splits_of = [&](int64_t c) -> int64_t { return c == 0 ? 0 : (c + per - 1) / per; };
+    local = 0;
+    for (int t = t0; t < t1; ++t) local += splits_of(bin_end(t) - bin_begin(t));
+    __syncthreads();
+    sh[tid] = local;
+    __syncthreads();
+    if (tid == 0) {  // exclusive scan of the item counts
+        long long run = 0;
+        for (int k = 0; k < 256; ++k) {
+            const long long v = sh[k];
+            sh[k] = run;
+            run += v;
+        }
+        *n_items = (int)run;
+    }
+    __syncthreads();
+    int64_t item = sh[tid];
+    long long padded = 0;
+    for (int t = t0; t < t1; ++t) {
+        const int64_t b = bin_begin(t), c = bin_end(t) - b, ns = splits_of(c);
+        first_item[t] = (int)item;
+        nsplit[t] = (int)ns;
+        for (int64_t q = 0; q < ns; ++q) {
+            SepItem it;
+            it.tile = t;
+            it.pad_ = 0;
+            it.begin = b + c * q / ns;
+            it.len = b + c * (q + 1) / ns - it.begin;
+            it.pad_off = padded;  // local for now
+            items[item + q] = it;
+            padded += band_padded_len(it.len, kc);
+        }
+        item += ns;
+    }
+    __syncthreads();
+    sh[tid] = padded;
+    __syncthreads();
+    if (tid == 0) {
+        long long run = 0;
+        for (int k = 0; k < 256; ++k) {
+            const long long v = sh[k];
+            sh[k] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    const long long base = sh[tid];
+    for (int64_t i = (t0 < t1 ? first_item[t0] : 0), e = item; t0 < t1 && i < e; ++i) items[i].pad_off += base;
+}
+
+// One workgroup per item slot: the item's points then far-away points.
+__global__ __launch_bounds__(256) void band_pad_kernel(const SepItem *__restrict__ items, const int *__restrict__ n_items,
+                                                       const float2 *__restrict__ bins, int kc,
+                                                       float2 *__restrict__ out) {
+    if ((int)blockIdx.x >= *n_items) return;
+    const SepItem it = items[blockIdx.x];
+    const int64_t plen = band_padded_len(it.len, kc);
+    for (int64_t k = threadIdx.x; k < plen; k += blockDim.x)
+        out[it.pad_off + k] = k < it.len ? bins[it.begin + k] : make_float2(kFar, kFar);
+}
+
+// out[j][i] = scale * sum of the tile's partials (items in order), 0 for tiles without points.
+__global__ __launch_bounds__(256) void band_reduce_kernel(const float *__restrict__ part,
+                                                          const int *__restrict__ first_item,
+                                                          const int *__restrict__ nsplit, int nx, int ny, int tiles_x,
+                                                          float scale, float *__restrict__ out) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)nx * ny) return;
+    const int j = (int)(idx / nx), i = (int)(idx % nx);
+    const int t = (j / kTile) * tiles_x + i / kTile;
+    const int64_t loc = (int64_t)(j % kTile) * kTile + i % kTile;
+    const int f = first_item[t], ns = nsplit[t];
+    float s = 0.0f;
+    for (int k = 0; k < ns; ++k) s += part[(int64_t)(f + k) * (kTile * kTile) + loc];
+    out[idx] = s * scale;
+}
+
+struct BandPlan {
+    int tiles, tiles_x, max_items, kc;
+    size_t bins_bytes, items_off, first_off, nsplit_off, nitems_off, padded_off, part_off, total;
+};
+
+size_t align256z(size_t x) { return (x + 255) / 256 * 256; }
+
+BandPlan band_plan(const MapArgs &a, int kc) {
+    BandPlan b;
+    b.kc = kc;
+    b.tiles_x = (a.nx + kTile - 1) / kTile;
+    b.tiles = b.tiles_x * ((a.ny + kTile - 1) / kTile);
+    b.max_items = b.tiles + kBandTarget;
+    b.bins_bytes = align256z(tile_bins_bytes(a, kTile));
+    // registrations per point: at most 3 x 3 tiles (support <= tile side)
+    const int64_t entries = std::min<int64_t>(a.n * 9, a.n * (int64_t)b.tiles);
+    b.items_off = b.bins_bytes;
+    b.first_off = b.items_off + align256z((size_t)b.max_items * sizeof(SepItem));
+    b.nsplit_off = b.first_off + align256z((size_t)b.tiles * sizeof(int));
+    b.nitems_off = b.nsplit_off + align256z((size_t)b.tiles * sizeof(int));
+    b.padded_off = b.nitems_off + 256;
+    b.part_off = b.padded_off + align256z((size_t)(entries + (int64_t)b.max_items * 4 * kc) * sizeof(float2));
+    b.total = b.part_off + (size_t)b.max_items * kTile * kTile * sizeof(float);
+    return b;
+}
+
+bool banded_applies(const MapArgs &a) {
+    if (a.kernel_id == kGaussian || a.n < 1) return false;  // the full Gaussian reaches every tile
+    return a.Hx <= (float)kTile && a.Hy <= (float)kTile && tile_bins_fit(a, kTile);
+}
+
+hipError_t launch_sep_banded(const MapArgs &a, int precision, void *ws, hipStream_t s) {
+    const int kc = chunk_for(precision);
+    const BandPlan b = band_plan(a, kc);
+    char *w = static_cast<char *>(ws);
+    TileBins tb;
+    hipError_t e = launch_tile_bins(a, kTile, w, s, &tb);
+    if (e != hipSuccess) return e;
+    SepItem *items = reinterpret_cast<SepItem *>(w + b.items_off);
+    int *first_item = reinterpret_cast<int *>(w + b.first_off);
+    int *nsplit = reinterpret_cast<int *>(w + b.nsplit_off);
+    int *n_items = reinterpret_cast<int *>(w + b.nitems_off);
+    float2 *padded = reinterpret_cast<float2 *>(w + b.padded_off);
+    float *part = reinterpret_cast<float *>(w + b.part_off);
+    hipLaunchKernelGGL(band_assign_kernel, dim3(1), dim3(256), 0, s, tb.end, tb.wblocks, b.tiles, kc, items,
+                       first_item, nsplit, n_items);
+    hipLaunchKernelGGL(band_pad_kernel, dim3((unsigned)b.max_items), dim3(256), 0, s, items,
+                       static_cast<const int *>(n_items), tb.bins, kc, padded);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    SepPlan pl{};
+    pl.tiles_x = b.tiles_x;
+    pl.tiles = b.tiles;
+    pl.splits = 1;
+    const BandedItems bi{items, n_items, b.max_items};
+    e = launch_sep_any(precision, a, pl, padded, part, s, &bi);
+    if (e != hipSuccess) return e;
+    const int64_t cells = (int64_t)a.nx * a.ny;
+    hipLaunchKernelGGL(band_reduce_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s,
+                       static_cast<const float *>(part), static_cast<const int *>(first_item),
+                       static_cast<const int *>(nsplit), a.nx, a.ny, b.tiles_x, a.scale, a.out);
+    return hipGetLastError();
 }
 
 }  // namespace
 
 size_t sep_workspace_bytes(const MapArgs &a, int precision) {
+    if (banded_applies(a)) return band_plan(a, chunk_for(precision)).total;
     const SepPlan pl = sep_plan(a, chunk_for(precision));
     return pl.partial_bytes + padded_bytes(pl);
 }
 
-// Workspace: [split partial planes][padded points].
+// Workspace: [split partial planes][padded points] (dense) or the banded layout.
 hipError_t launch_sep(const MapArgs &a, int precision, void *ws, hipStream_t stream) {
+    if (banded_applies(a)) return launch_sep_banded(a, precision, ws, stream);
     const SepPlan pl = sep_plan(a, chunk_for(precision));
     float *dst = pl.splits > 1 ? static_cast<float *>(ws) : a.out;
     float2 *padded = reinterpret_cast<float2 *>(static_cast<char *>(ws) + pl.partial_bytes);

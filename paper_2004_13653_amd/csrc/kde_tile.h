@@ -16,6 +16,9 @@ __device__ __forceinline__ float factor(float d, float a, float H) {
     if constexpr (K == kGaussian) {
         const float t = d * a;
         return __builtin_amdgcn_exp2f(-t * t);
+    } else if constexpr (K == kGaussTrunc) {  // H is the support half-width here
+        const float t = d * a;
+        return fabsf(d) <= H ? __builtin_amdgcn_exp2f(-t * t) : 0.0f;
     } else {
         const float u = fminf(fabsf(d) * a, 1.0f);  // |u|, clamped against rounding past 1
         float v;

@@ -139,6 +139,14 @@ def test_autotune_cache_roundtrip_and_rejection(tmp_path):
     assert kde.autotune(clear=True) == {}
 
 
+def test_truncate_flag_validation():
+    L = kde.lib()
+    g = kde.Grid(0.0, 1.0, 0.0, 1.0, 16, 16)
+    assert L.kde_eval(FAKE, 10, 2, 0.1, 0.1, g.handle, FAKE, 0, 8, None) == kde.KDE_EINVAL  # not Gaussian
+    assert "KDE_TRUNCATE" in L.kde_last_error().decode()
+    assert L.kde_eval(FAKE, 10, 6, 0.1, 0.1, g.handle, FAKE, 0, 16, None) == kde.KDE_EINVAL  # unknown flag
+
+
 def test_binned_entry_points_validate():
     L = kde.lib()
     g = kde.Grid(0.0, 1.0, 0.0, 1.0, 16, 16)
