@@ -41,7 +41,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_SO):
         tmp = _SO + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-Wall",
-                               _SRC, "-o", tmp, "-lm"])
+                               "-ffp-contract=off", _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _SO)
     return _SO
 
@@ -71,6 +71,8 @@ def lib():
         L.ko_lscv_units.argtypes = [p, i64, i, f, f, p, p]
         L.ko_bin_counts.argtypes = [p, i64, p, i, i, p, p]
         L.ko_conv_counts.argtypes = [p, i, i, i, f, f, i, i, i, i, i, i, p]
+        L.ko_dp_keep.argtypes = [p, i64, p, i64, d, p]
+        L.ko_dp_keep.restype = i64
         for name in ("ko_map_world", "ko_map_units", "ko_map_units_at", "ko_vjp_units", "ko_lscv_world",
                      "ko_lscv_units", "ko_bin_counts", "ko_conv_counts"):
             getattr(L, name).restype = None
@@ -314,6 +316,17 @@ def conv_counts(counts, kernel: int, Hx, Hy, a: int, b: int, window=None) -> np.
     lib().ko_conv_counts(_ptr(counts), nx, ny, kernel, float(np.float32(Hx)), float(np.float32(Hy)), int(a),
                          int(b), i0, i1, j0, j1, _ptr(out))
     return out
+
+
+def dp_keep(xy_m, lengths, eps: float):
+    """Douglas-Peucker keep mask (uint8 [n]) of tracks given by their lengths,
+    points in metres (FP64 [n, 2]); see ko_dp_keep for the decision rule."""
+    xy = _f64(xy_m).reshape(-1, 2)
+    start = np.concatenate([[0], np.cumsum(np.asarray(lengths, dtype=np.int64))]).astype(np.int64)
+    assert start[-1] == xy.shape[0]
+    keep = np.zeros(xy.shape[0], dtype=np.uint8)
+    lib().ko_dp_keep(_ptr(xy), xy.shape[0], _ptr(start), len(start) - 1, float(eps), _ptr(keep))
+    return keep
 
 
 def errors(y, r) -> dict:

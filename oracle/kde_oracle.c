@@ -423,3 +423,79 @@ void ko_conv_counts(const uint32_t *counts, int nx, int ny, int kernel, float Hx
         out[r] = sum;
     }
 }
+
+/* ---------------------------------------------------------------------------
+ * Douglas-Peucker compression of every trajectory (Sec. III-B, its GPU form in
+ * Sec. IV-A): keep both end points of a track; for the chord between two kept
+ * points, the interior point farthest from the chord's line (Eq. (9), the
+ * vertical Euclidean distance) is kept when that distance is larger than eps,
+ * which splits the chord in two; repeat until no chord has such a point.
+ *
+ * Readings: the lowest index wins a tie for the largest distance; a chord with
+ * coinciding end points uses the distance to that point; the test
+ * D > eps is taken as cross^2 > eps^2 |chord|^2 (cross = the 2-D cross product
+ * of Eq. (9)'s numerator), or |P - Ps|^2 > eps^2 for a zero chord, so that no
+ * square root or division enters the decision.  FP64, no fused multiply-add.
+ * -------------------------------------------------------------------------*/
+
+/* Score of point i against chord (s, e): |cross| (or the squared distance to
+ * P_s when the chord has zero length).  *zero tells which. */
+static double dp_score(const double *xy, int64_t s, int64_t e, int64_t i, int *zero)
+{
+    double cx = xy[2 * e] - xy[2 * s], cy = xy[2 * e + 1] - xy[2 * s + 1];
+    double px = xy[2 * i] - xy[2 * s], py = xy[2 * i + 1] - xy[2 * s + 1];
+    double c2 = cx * cx + cy * cy;
+    *zero = c2 == 0.0;
+    if (*zero) return px * px + py * py;
+    double a = px * cy, b = py * cx;
+    return fabs(a - b);
+}
+
+/* keep[n] (0/1) for points xy[n][2] (metres, FP64) in tracks
+ * [start[t], start[t+1]), t < n_tracks.  Returns the number kept. */
+int64_t ko_dp_keep(const double *xy, int64_t n, const int64_t *start, int64_t n_tracks, double eps, uint8_t *keep)
+{
+    (void)n;
+    int64_t kept = 0;
+    double eps2 = eps * eps;
+    for (int64_t t = 0; t < n_tracks; ++t) {
+        int64_t a = start[t], z = start[t + 1];
+        for (int64_t i = a; i < z; ++i) keep[i] = 0;
+        if (z <= a) continue;
+        keep[a] = 1;
+        keep[z - 1] = 1;
+        /* explicit stack of chords (s, e) */
+        int64_t cap = 64, top = 0;
+        int64_t *st = (int64_t *)malloc((size_t)cap * 2 * sizeof(int64_t));
+        st[0] = a;
+        st[1] = z - 1;
+        top = 1;
+        while (top > 0) {
+            --top;
+            int64_t s = st[2 * top], e = st[2 * top + 1];
+            if (e - s < 2) continue;
+            int64_t best = -1;
+            double bs = -1.0;
+            int zero = 0;
+            for (int64_t i = s + 1; i < e; ++i) {
+                double sc = dp_score(xy, s, e, i, &zero);
+                if (sc > bs) { bs = sc; best = i; } /* strict: the lowest index wins ties */
+            }
+            double cx = xy[2 * e] - xy[2 * s], cy = xy[2 * e + 1] - xy[2 * s + 1];
+            double c2 = cx * cx + cy * cy;
+            int split = zero ? (bs > eps2) : (bs * bs > eps2 * c2);
+            if (!split) continue;
+            keep[best] = 1;
+            if (top + 2 > cap) {
+                cap *= 2;
+                st = (int64_t *)realloc(st, (size_t)cap * 2 * sizeof(int64_t));
+            }
+            st[2 * top] = best; st[2 * top + 1] = e; ++top;
+            st[2 * top] = s; st[2 * top + 1] = best; ++top;
+        }
+        free(st);
+    }
+    for (int64_t t = 0; t < n_tracks; ++t)
+        for (int64_t i = start[t]; i < start[t + 1]; ++i) kept += keep[i];
+    return kept;
+}

@@ -16,6 +16,8 @@ import pytest
 from scipy import integrate, stats
 
 import oracle
+import synth
+from synth import ais
 from oracle import GAUSSIAN, Grid
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -564,3 +566,66 @@ def test_truncated_gaussian_map_bound_and_boundary():
     m = oracle.map_units(one, oracle.GAUSS_TRUNC, 0.5, 0.5, (0, 6, 0, 1))[0]
     assert m[4] == pytest.approx(stats.norm.pdf(8.0) * stats.norm.pdf(0.0), rel=1e-13)  # d = 4 = 8 H: kept
     assert m[5] == 0.0                                                                   # d = 5 > 8 H
+
+
+# ---------------------------------------------------------------------------
+# Douglas-Peucker (Sec. III-B; Eq. (9)).
+
+def _dp1(x, y, eps):
+    xy = np.column_stack([np.asarray(x, float), np.asarray(y, float)])
+    return list(np.flatnonzero(oracle.dp_keep(xy, [len(x)], eps)))
+
+
+def test_dp_oracle_textbook_cases():
+    assert _dp1(np.arange(10.0), 2 * np.arange(10.0), 0.0) == [0, 9]       # collinear
+    y = np.zeros(9)
+    y[4] = 5.0
+    assert _dp1(np.arange(9.0), y, 4.999) == [0, 4, 8]                        # spike of height 5
+    assert _dp1(np.arange(9.0), y, 5.0) == [0, 8]                             # strictly larger only
+    assert _dp1([0.0, 1.0, 2.0, 3.0, 4.0], [0.0, 1.0, 0.0, 1.0, 0.0], 0.7) == [0, 1, 4]  # lowest index on ties
+    assert _dp1([0.0, 10.0, 5.0], [0.0, 0.0, 0.0], 0.0) == [0, 2]            # distance to the line
+    assert _dp1([0.0, 3.0, 0.0], [0.0, 4.0, 0.0], 4.9) == [0, 1, 2]          # zero chord: point distance 5
+    assert _dp1([0.0, 3.0, 0.0], [0.0, 4.0, 0.0], 5.0) == [0, 2]
+
+
+def test_dp_oracle_track_boundaries():
+    """Tracks of 1, 2 and 3 points and a zig-zag: each track on its own."""
+    xy = np.array([[0, 0], [5, 5], [6, 6], [0, 0], [1, 9], [2, 0],
+                   [0, 0], [1, 1], [2, 0], [3, 1], [4, 0]], dtype=float)
+    keep = oracle.dp_keep(xy, [1, 2, 3, 5], 0.5)
+    assert list(keep) == [1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1]
+    keep = oracle.dp_keep(xy, [1, 2, 3, 5], 100.0)
+    assert list(keep) == [1, 1, 1, 1, 0, 1, 1, 0, 0, 0, 1]
+
+
+def test_dp_oracle_matches_independent_python_dp():
+    """The recursive Python compressor of the input generator (distance by
+    hypot and division) gives the same mask on lane tracks at several eps: the
+    two decision forms differ only at exact ties."""
+    t = synth.generate(17, 40, 300, synth.BOX_C2, n_lanes=3)
+    mx, my = synth.mercator(t.xy[:, 0], t.xy[:, 1], t.box.center_lat)
+    xy = np.column_stack([mx, my])
+    for eps in (0.0, 10.0, 50.0, 200.0):
+        keep = oracle.dp_keep(xy, t.lengths, eps)
+        ref = np.concatenate([ais._dp_keep(mx[k * 300:(k + 1) * 300], my[k * 300:(k + 1) * 300], eps)
+                              for k in range(40)])
+        np.testing.assert_array_equal(keep.astype(bool), ref)
+
+
+def test_dp_oracle_dropped_points_within_eps():
+    """Brute force on random walks: every dropped point lies within eps of the
+    line through the kept points that enclose it, and the end points are kept."""
+    rng = np.random.default_rng(99)
+    for trial in range(20):
+        n = 60
+        xy = np.cumsum(rng.normal(0, 1, (n, 2)), axis=0)
+        eps = float(rng.uniform(0.2, 3.0))
+        keep = oracle.dp_keep(xy, [n], eps).astype(bool)
+        assert keep[0] and keep[-1]
+        idx = np.flatnonzero(keep)
+        for s, e in zip(idx, idx[1:]):
+            c = xy[e] - xy[s]
+            for i in range(s + 1, e):
+                p = xy[i] - xy[s]
+                d = abs(p[0] * c[1] - p[1] * c[0]) / max(np.hypot(*c), 1e-300) if np.hypot(*c) > 0 else np.hypot(*p)
+                assert d <= eps * (1 + 1e-12)
