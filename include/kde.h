@@ -220,6 +220,27 @@ int kde_conv_counts(const uint32_t *counts, const uint64_t *total, const kde_gri
 int kde_eval_binned(const float *points, int64_t n, const int32_t *labels, int32_t kernel_id, double hx, double hy,
                     int32_t a, int32_t b, const kde_grid *g, float *out, uint32_t flags, void *stream);
 
+/* Douglas-Peucker compression of many trajectories at once (Sec. III-B; the
+ * GPU framework of Sec. IV-A: every chord of every track handled in the same
+ * level-synchronous pass).  Each track keeps its end points; within a chord
+ * between kept points, the interior point farthest from the chord's line
+ * (Eq. (9)) is kept when that distance is larger than eps, splitting the chord;
+ * until no chord splits.  The farthest point is the lowest index among equal
+ * distances; a chord with coinciding end points uses the distance to that
+ * point; the test is cross^2 > eps^2 |chord|^2 in FP64 (no square root, no
+ * fused multiply-add), so the mask is exact and order-independent.
+ *   xy           device FP64 [n][2], planar coordinates (e.g. Mercator metres), finite
+ *   track_start  device int64 [n_tracks + 1]: track t is [track_start[t], track_start[t+1]),
+ *                rising from 0 to n (else KDE_EINVAL)
+ *   eps          finite, >= 0, in the units of xy
+ *   keep         device uint8 [n]: 1 for kept points
+ *   out_xy       device FP64 [n][2] receiving the kept points in order, or NULL
+ *   out_lengths  device int64 [n_tracks] receiving kept points per track, or NULL
+ *   n_kept       host, number of kept points, or NULL
+ * Synchronises `stream` (once per few levels of the recursion and at the end). */
+int kde_dp_compress(const double *xy, int64_t n, const int64_t *track_start, int64_t n_tracks, double eps,
+                    uint8_t *keep, double *out_xy, int64_t *out_lengths, int64_t *n_kept, void *stream);
+
 /* Tile-shape autotuner (FP32 direct path, kde_eval and kde_eval_batched).
  * The direct kernels exist for register blocks of 2 x 2, 4 x 4 and 8 x 8 pixels
  * per thread (pixel tiles of 32, 64 and 128 nodes per side).  The first call in

@@ -74,6 +74,7 @@ def lib() -> ctypes.CDLL:
             "kde_bin_counts": (ctypes.c_int, [p, i64, p, p, p, p, p]),
             "kde_conv_counts": (ctypes.c_int, [p, p, p, i32, d, d, i32, i32, p, u32, p]),
             "kde_eval_binned": (ctypes.c_int, [p, i64, p, i32, d, d, i32, i32, p, p, u32, p]),
+            "kde_dp_compress": (ctypes.c_int, [p, i64, p, i64, d, p, p, p, p, p]),
             "kde_time_next_main_kernel": (ctypes.c_int, [p, p]),
             "kde_autotune_enable": (ctypes.c_int, [i32]),
             "kde_autotune_force": (ctypes.c_int, [i32]),
@@ -247,6 +248,32 @@ def paper_taps(kernel, varpi: int, grid: Grid) -> tuple[float, float, int, int]:
     r = (varpi - 1) // 2
     H = 1.0 if _kernel_id(kernel) == KERNELS["gaussian"] else float(max(r, 1))
     return H * grid.dx, H * grid.dy, r, r
+
+
+def dp_compress(xy, track_start, eps: float, compact: bool = True):
+    """Douglas-Peucker compression of merged tracks on the GPU (kde_dp_compress).
+    xy: [n, 2] float64 CUDA tensor (planar, e.g. Mercator metres); track_start:
+    [n_tracks + 1] int64 CUDA tensor of offsets.  Returns (keep [n] uint8,
+    kept points [n_kept, 2] or None, kept per track [n_tracks] or None)."""
+    import torch
+    if not (xy.is_cuda and xy.dtype == torch.float64 and xy.dim() == 2 and xy.shape[1] == 2 and xy.is_contiguous()):
+        raise ValueError("xy must be a contiguous CUDA float64 tensor of shape [n, 2]")
+    if not (track_start.is_cuda and track_start.dtype == torch.int64 and track_start.dim() == 1
+            and track_start.is_contiguous()):
+        raise ValueError("track_start must be a contiguous CUDA int64 tensor")
+    n, nt = xy.shape[0], track_start.shape[0] - 1
+    keep = torch.empty(n, dtype=torch.uint8, device=xy.device)
+    out = torch.empty_like(xy) if compact else None
+    lens = torch.empty(max(nt, 0), dtype=torch.int64, device=xy.device) if compact else None
+    kept = ctypes.c_int64()
+    with torch.cuda.device(xy.device):
+        _check(lib().kde_dp_compress(xy.data_ptr() if n else None, n, track_start.data_ptr(), nt, float(eps),
+                                     keep.data_ptr() if n else None, out.data_ptr() if compact and n else None,
+                                     lens.data_ptr() if compact and nt > 0 else None, ctypes.byref(kept),
+                                     _stream(torch, xy.device)))
+    if compact:
+        out = out[:kept.value]
+    return keep, out, lens
 
 
 def autotune(enabled: bool | None = None, force: int | None = None, load: str | None = None,

@@ -583,6 +583,38 @@ int kde_eval_binned(const float *points, int64_t n, const int32_t *labels, int32
     }
 }
 
+int kde_dp_compress(const double *xy, int64_t n, const int64_t *track_start, int64_t n_tracks, double eps,
+                    uint8_t *keep, double *out_xy, int64_t *out_lengths, int64_t *n_kept, void *stream) {
+    try {
+        if (n < 0 || n >= kMaxPoints) return fail(KDE_EINVAL, "kde_dp_compress: n = %lld out of range", (long long)n);
+        if (n_tracks < 0 || (n_tracks == 0 && n > 0) || n_tracks > n)
+            return fail(KDE_EINVAL, "kde_dp_compress: n_tracks = %lld invalid for n = %lld", (long long)n_tracks,
+                        (long long)n);
+        if (!(std::isfinite(eps) && eps >= 0.0)) return fail(KDE_EINVAL, "kde_dp_compress: eps must be finite and >= 0");
+        if (n > 0 && (xy == nullptr || track_start == nullptr || keep == nullptr))
+            return fail(KDE_EINVAL, "kde_dp_compress: xy, track_start and keep are required");
+        if (n == 0) {
+            if (n_kept) *n_kept = 0;
+            return KDE_OK;
+        }
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        void *ws = nullptr;
+        int st = get_workspace(s, kde::dp_workspace_bytes(n), &ws);
+        if (st != KDE_OK) return st;
+        kde::DpArgs a{reinterpret_cast<const double2 *>(xy), n, track_start, n_tracks, eps, keep,
+                      reinterpret_cast<double2 *>(out_xy), out_lengths};
+        int64_t kept = 0;
+        hipError_t e = kde::run_dp(a, ws, s, &kept);
+        if (e == hipErrorInvalidValue && kept < 0)
+            return fail(KDE_EINVAL, "kde_dp_compress: track offsets must rise from 0 to n without decreasing");
+        if (e != hipSuccess) return hip_fail(e, "kde_dp_compress");
+        if (n_kept) *n_kept = kept;
+        return KDE_OK;
+    } catch (...) {
+        return fail(KDE_EHIP, "kde_dp_compress: internal error");
+    }
+}
+
 int kde_backward(const float *points, int64_t n, int32_t kernel_id, double hx, double hy, const kde_grid *g,
                  const float *grad_out, float *grad_points, double *grad_h, uint32_t flags, void *stream) {
     try {

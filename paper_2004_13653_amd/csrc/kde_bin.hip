@@ -273,6 +273,18 @@ size_t scatter_bytes(const BinPlan &pl) {
 
 }  // namespace
 
+size_t scan_u32_totals_bytes(int64_t len) { return (size_t)((len + kScanBlock - 1) / kScanBlock + 1) * sizeof(unsigned); }
+
+hipError_t launch_scan_u32(unsigned *a, int64_t len, unsigned *totals, hipStream_t s) {
+    const int64_t blocks = (len + kScanBlock - 1) / kScanBlock;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(scan_blocks_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a, len, totals);
+    hipLaunchKernelGGL(scan_totals_kernel, dim3(1), dim3(256), 0, s, totals, blocks);
+    hipLaunchKernelGGL(scan_add_kernel, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, a, len,
+                       static_cast<const unsigned *>(totals));
+    return hipGetLastError();
+}
+
 bool binning_applies(const MapArgs &a) {
     if (a.kernel_id == kGaussian || a.n < 4096 || !valid_rc(a.rc)) return false;
     const float T = (float)(16 * a.rc);

@@ -1,0 +1,283 @@
+// Douglas-Peucker compression of many trajectories at once (Sec. III-B, its
+// GPU form in Sec. IV-A), level-synchronous: every chord of every track is
+// processed in the same pass, as the paper's label sets do.
+//
+// State per point i: the kept points lo[i] < i < hi[i] that enclose it (its
+// chord), and whether it is still undecided (active).  One level:
+//   1. reset the slot of every active chord (slots are indexed by the chord's
+//      first point, unique among the chords of one level);
+//   2. score: |cross| of Eq. (9)'s numerator (squared distance to P_s for a
+//      chord of zero length), integer atomic max of its bits into the slot;
+//   3. argmax: points whose score equals the slot's maximum take an integer
+//      atomic min of their index (the lowest index wins ties);
+//   4. decide: the chord's argmax keeps itself when cross^2 > eps^2 |chord|^2
+//      (or dist^2 > eps^2), marking the chord split or final;
+//   5. update: points of final chords are dropped, the others move to the half
+//      chord on their side of the new kept point.
+// Scores are FP64 with no fused multiply-add (the decision is taken exactly as
+// the reference does), and all cross-thread combination is integer atomics:
+// the keep mask does not depend on thread order.  The host checks after each
+// group of levels whether any chord still split (the paper synchronises with
+// the host every level).
+#include "kde_internal.h"
+
+#include <algorithm>
+#include <climits>
+
+namespace kde {
+
+namespace {
+
+constexpr unsigned long long kNoIndex = ULLONG_MAX;
+constexpr int kLevelsPerCheck = 8;
+
+__device__ __forceinline__ double dp_score(const double2 *__restrict__ xy, int64_t s, int64_t e, int64_t i,
+                                           bool &zero) {
+#pragma clang fp contract(off)
+    const double2 ps = xy[s], pe = xy[e], pi = xy[i];
+    const double cx = pe.x - ps.x, cy = pe.y - ps.y;
+    const double px = pi.x - ps.x, py = pi.y - ps.y;
+    const double c2 = cx * cx + cy * cy;
+    zero = c2 == 0.0;
+    if (zero) return px * px + py * py;
+    const double a = px * cy, b = py * cx;
+    return fabs(a - b);
+}
+
+__device__ __forceinline__ bool dp_split(const double2 *__restrict__ xy, int64_t s, int64_t e, double score,
+                                         bool zero, double eps2) {
+#pragma clang fp contract(off)
+    if (zero) return score > eps2;
+    const double2 ps = xy[s], pe = xy[e];
+    const double cx = pe.x - ps.x, cy = pe.y - ps.y;
+    const double c2 = cx * cx + cy * cy;
+    return score * score > eps2 * c2;
+}
+
+// bad = 1 unless start[0] = 0, start[n_tracks] = n and the offsets never decrease.
+__global__ __launch_bounds__(256) void dp_check_kernel(const int64_t *__restrict__ start, int64_t n_tracks, int64_t n,
+                                                       unsigned *__restrict__ bad) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > n_tracks) return;
+    bool ok = true;
+    if (t == 0) ok = start[0] == 0;
+    if (t == n_tracks) ok = ok && start[n_tracks] == n;
+    if (t < n_tracks) ok = ok && start[t] <= start[t + 1];
+    if (!ok) atomicOr(bad, 1u);
+}
+
+// Track of point i (binary search in the offsets), its end points kept.
+__global__ __launch_bounds__(256) void dp_init_kernel(const int64_t *__restrict__ start, int64_t n_tracks, int64_t n,
+                                                      int64_t *__restrict__ lo, int64_t *__restrict__ hi,
+                                                      uint8_t *__restrict__ keep, uint8_t *__restrict__ active) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int64_t a = 0, b = n_tracks;  // find t with start[t] <= i < start[t + 1]
+    while (b - a > 1) {
+        const int64_t m = (a + b) / 2;
+        if (start[m] <= i) a = m;
+        else b = m;
+    }
+    const int64_t s = start[a], e = start[a + 1] - 1;
+    lo[i] = s;
+    hi[i] = e;
+    const bool end_point = i == s || i == e;
+    keep[i] = end_point ? 1 : 0;
+    active[i] = end_point ? 0 : 1;
+}
+
+__global__ __launch_bounds__(256) void dp_reset_kernel(int64_t n, const int64_t *__restrict__ lo,
+                                                       const uint8_t *__restrict__ active,
+                                                       unsigned long long *__restrict__ segmax,
+                                                       unsigned long long *__restrict__ segarg) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !active[i]) return;
+    const int64_t s = lo[i];
+    segmax[s] = 0ull;  // every point of the chord writes the same values
+    segarg[s] = kNoIndex;
+}
+
+__global__ __launch_bounds__(256) void dp_score_kernel(const double2 *__restrict__ xy, int64_t n,
+                                                       const int64_t *__restrict__ lo, const int64_t *__restrict__ hi,
+                                                       const uint8_t *__restrict__ active,
+                                                       unsigned long long *__restrict__ segmax) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !active[i]) return;
+    bool zero;
+    const double sc = dp_score(xy, lo[i], hi[i], i, zero);
+    // non-negative doubles order like their bit patterns
+    atomicMax(segmax + lo[i], (unsigned long long)__double_as_longlong(sc));
+}
+
+__global__ __launch_bounds__(256) void dp_argmax_kernel(const double2 *__restrict__ xy, int64_t n,
+                                                        const int64_t *__restrict__ lo, const int64_t *__restrict__ hi,
+                                                        const uint8_t *__restrict__ active,
+                                                        const unsigned long long *__restrict__ segmax,
+                                                        unsigned long long *__restrict__ segarg) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !active[i]) return;
+    bool zero;
+    const double sc = dp_score(xy, lo[i], hi[i], i, zero);
+    if ((unsigned long long)__double_as_longlong(sc) == segmax[lo[i]]) atomicMin(segarg + lo[i], (unsigned long long)i);
+}
+
+// The chord's argmax decides: 1 = split at it (kept), 2 = final.
+__global__ __launch_bounds__(256) void dp_decide_kernel(const double2 *__restrict__ xy, int64_t n, double eps2,
+                                                        const int64_t *__restrict__ lo, const int64_t *__restrict__ hi,
+                                                        const uint8_t *__restrict__ active,
+                                                        const unsigned long long *__restrict__ segarg,
+                                                        uint8_t *__restrict__ segdec, uint8_t *__restrict__ keep,
+                                                        unsigned *__restrict__ splits) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool split = false;
+    if (i < n && active[i] && segarg[lo[i]] == (unsigned long long)i) {
+        bool zero;
+        const double sc = dp_score(xy, lo[i], hi[i], i, zero);
+        split = dp_split(xy, lo[i], hi[i], sc, zero, eps2);
+        segdec[lo[i]] = split ? 1 : 2;
+        if (split) keep[i] = 1;
+    }
+    const unsigned long long m = __ballot(split);
+    if ((threadIdx.x & 63) == 0 && m != 0ull) atomicAdd(splits, (unsigned)__popcll(m));
+}
+
+__global__ __launch_bounds__(256) void dp_update_kernel(int64_t n, int64_t *__restrict__ lo, int64_t *__restrict__ hi,
+                                                        uint8_t *__restrict__ active,
+                                                        const unsigned long long *__restrict__ segarg,
+                                                        const uint8_t *__restrict__ segdec) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !active[i]) return;
+    const int64_t s = lo[i];
+    if (segdec[s] == 2) {
+        active[i] = 0;  // within eps of its final chord: dropped
+        return;
+    }
+    const int64_t k = (int64_t)segarg[s];
+    if (k == i) active[i] = 0;  // kept
+    else if (i < k) hi[i] = k;
+    else lo[i] = k;
+}
+
+__global__ __launch_bounds__(256) void zero_u32_kernel(unsigned *p, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0u;
+}
+
+__global__ __launch_bounds__(256) void keep_to_u32_kernel(const uint8_t *__restrict__ keep, int64_t n,
+                                                          unsigned *__restrict__ pos) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) pos[i] = keep[i];
+}
+
+// Compaction (pos = exclusive scan of keep) and kept points per track.
+__global__ __launch_bounds__(256) void dp_compact_kernel(const double2 *__restrict__ xy, int64_t n,
+                                                         const uint8_t *__restrict__ keep,
+                                                         const unsigned *__restrict__ pos, double2 *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && keep[i]) out[pos[i]] = xy[i];
+}
+
+__global__ __launch_bounds__(256) void dp_lengths_kernel(const int64_t *__restrict__ start, int64_t n_tracks,
+                                                         const unsigned *__restrict__ pos, unsigned total,
+                                                         int64_t n, int64_t *__restrict__ lengths) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tracks) return;
+    const int64_t a = start[t], b = start[t + 1];
+    const unsigned pa = a < n ? pos[a] : total, pb = b < n ? pos[b] : total;
+    lengths[t] = (int64_t)pb - (int64_t)pa;
+}
+
+struct DpLayout {
+    size_t lo, hi, active, segmax, segarg, segdec, counters, pos, totals, total;
+};
+
+size_t al(size_t x) { return (x + 255) / 256 * 256; }
+
+DpLayout dp_layout(int64_t n) {
+    DpLayout L;
+    size_t o = 0;
+    L.lo = o; o += al((size_t)n * 8);
+    L.hi = o; o += al((size_t)n * 8);
+    L.active = o; o += al((size_t)n);
+    L.segmax = o; o += al((size_t)n * 8);
+    L.segarg = o; o += al((size_t)n * 8);
+    L.segdec = o; o += al((size_t)n);
+    L.counters = o; o += 256;
+    L.pos = o; o += al((size_t)n * 4);
+    L.totals = o; o += al(scan_u32_totals_bytes(n));
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+size_t dp_workspace_bytes(int64_t n) { return dp_layout(n).total; }
+
+hipError_t run_dp(const DpArgs &a, void *ws, hipStream_t s, int64_t *n_kept) {
+    const DpLayout L = dp_layout(a.n);
+    char *w = static_cast<char *>(ws);
+    int64_t *lo = reinterpret_cast<int64_t *>(w + L.lo);
+    int64_t *hi = reinterpret_cast<int64_t *>(w + L.hi);
+    uint8_t *active = reinterpret_cast<uint8_t *>(w + L.active);
+    unsigned long long *segmax = reinterpret_cast<unsigned long long *>(w + L.segmax);
+    unsigned long long *segarg = reinterpret_cast<unsigned long long *>(w + L.segarg);
+    uint8_t *segdec = reinterpret_cast<uint8_t *>(w + L.segdec);
+    unsigned *splits = reinterpret_cast<unsigned *>(w + L.counters);
+    unsigned *pos = reinterpret_cast<unsigned *>(w + L.pos);
+    unsigned *totals = reinterpret_cast<unsigned *>(w + L.totals);
+    const dim3 grid((unsigned)((a.n + 255) / 256)), block(256);
+    const double eps2 = a.eps * a.eps;
+    *n_kept = -1;
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), block, 0, s, splits, (int64_t)1);
+    hipLaunchKernelGGL(dp_check_kernel, dim3((unsigned)((a.n_tracks + 1 + 255) / 256)), block, 0, s, a.start,
+                       a.n_tracks, a.n, splits);
+    unsigned bad = 0;
+    hipError_t e0 = hipMemcpyAsync(&bad, splits, sizeof bad, hipMemcpyDeviceToHost, s);
+    if (e0 == hipSuccess) e0 = hipStreamSynchronize(s);
+    if (e0 != hipSuccess) return e0;
+    if (bad) return hipErrorInvalidValue;  // *n_kept stays -1: invalid offsets
+    hipLaunchKernelGGL(dp_init_kernel, grid, block, 0, s, a.start, a.n_tracks, a.n, lo, hi, a.keep, active);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // Every level either splits a chord or leaves all remaining ones final, so
+    // no track needs more levels than it has points.
+    for (int64_t level = 0; level <= a.n; level += kLevelsPerCheck) {
+        hipLaunchKernelGGL(zero_u32_kernel, dim3(1), block, 0, s, splits, (int64_t)1);
+        for (int l = 0; l < kLevelsPerCheck; ++l) {
+            hipLaunchKernelGGL(dp_reset_kernel, grid, block, 0, s, a.n, static_cast<const int64_t *>(lo),
+                               static_cast<const uint8_t *>(active), segmax, segarg);
+            hipLaunchKernelGGL(dp_score_kernel, grid, block, 0, s, a.xy, a.n, static_cast<const int64_t *>(lo),
+                               static_cast<const int64_t *>(hi), static_cast<const uint8_t *>(active), segmax);
+            hipLaunchKernelGGL(dp_argmax_kernel, grid, block, 0, s, a.xy, a.n, static_cast<const int64_t *>(lo),
+                               static_cast<const int64_t *>(hi), static_cast<const uint8_t *>(active),
+                               static_cast<const unsigned long long *>(segmax), segarg);
+            hipLaunchKernelGGL(dp_decide_kernel, grid, block, 0, s, a.xy, a.n, eps2, static_cast<const int64_t *>(lo),
+                               static_cast<const int64_t *>(hi), static_cast<const uint8_t *>(active),
+                               static_cast<const unsigned long long *>(segarg), segdec, a.keep, splits);
+            hipLaunchKernelGGL(dp_update_kernel, grid, block, 0, s, a.n, lo, hi, active,
+                               static_cast<const unsigned long long *>(segarg), static_cast<const uint8_t *>(segdec));
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        unsigned got = 0;
+        if ((e = hipMemcpyAsync(&got, splits, sizeof got, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+        if (got == 0) break;  // the group's last level split nothing: every chord is final
+    }
+    // Kept count (and compaction) from the exclusive scan of the mask.
+    hipLaunchKernelGGL(keep_to_u32_kernel, grid, block, 0, s, static_cast<const uint8_t *>(a.keep), a.n, pos);
+    if ((e = launch_scan_u32(pos, a.n, totals, s)) != hipSuccess) return e;
+    const int64_t blocks = (a.n + 1023) / 1024;
+    unsigned total = 0;
+    if ((e = hipMemcpyAsync(&total, totals + blocks, sizeof total, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    *n_kept = total;
+    if (a.out_xy)
+        hipLaunchKernelGGL(dp_compact_kernel, grid, block, 0, s, a.xy, a.n, static_cast<const uint8_t *>(a.keep),
+                           static_cast<const unsigned *>(pos), a.out_xy);
+    if (a.out_lengths)
+        hipLaunchKernelGGL(dp_lengths_kernel, dim3((unsigned)((a.n_tracks + 255) / 256)), block, 0, s, a.start,
+                           a.n_tracks, static_cast<const unsigned *>(pos), total, a.n, a.out_lengths);
+    return hipGetLastError();
+}
+
+}  // namespace kde

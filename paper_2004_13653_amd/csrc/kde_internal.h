@@ -98,6 +98,28 @@ bool tile_bins_fit(const MapArgs &a, int tile);
 size_t tile_bins_bytes(const MapArgs &a, int tile);
 hipError_t launch_tile_bins(const MapArgs &a, int tile, void *ws, hipStream_t s, TileBins *out);
 
+// In-place exclusive scan of a[len] (uint32, sums below 2^32); totals holds
+// scan_u32_totals_bytes(len) bytes and receives the grand total at
+// totals[ceil(len / 1024)].
+size_t scan_u32_totals_bytes(int64_t len);
+hipError_t launch_scan_u32(unsigned *a, int64_t len, unsigned *totals, hipStream_t s);
+
+// Douglas-Peucker compression of merged tracks (kde_dp.hip).
+struct DpArgs {
+    const double2 *xy;      // [n] metres
+    int64_t n;
+    const int64_t *start;   // [n_tracks + 1] track offsets (device)
+    int64_t n_tracks;
+    double eps;
+    uint8_t *keep;          // [n] output
+    double2 *out_xy;        // [n] compacted kept points, or nullptr
+    int64_t *out_lengths;   // [n_tracks] kept points per track, or nullptr
+};
+size_t dp_workspace_bytes(int64_t n);
+// Runs the level loop (synchronising `stream` once per group of levels) and
+// returns the number of kept points in *n_kept.
+hipError_t run_dp(const DpArgs &a, void *ws, hipStream_t stream, int64_t *n_kept);
+
 // Matrix-core separable path (precision kPrecFp16 .. kPrecBf16x3).  Compact
 // kernels (and the truncated Gaussian) whose support fits a 256-node tile run
 // banded: only the (tile, point) pairs the support reaches are multiplied.

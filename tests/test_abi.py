@@ -147,6 +147,19 @@ def test_truncate_flag_validation():
     assert L.kde_eval(FAKE, 10, 6, 0.1, 0.1, g.handle, FAKE, 0, 16, None) == kde.KDE_EINVAL  # unknown flag
 
 
+def test_dp_entry_point_validates():
+    L = kde.lib()
+    n = ctypes.c_int64()
+    assert L.kde_dp_compress(FAKE, -1, FAKE, 1, 1.0, FAKE, None, None, None, None) == kde.KDE_EINVAL
+    assert L.kde_dp_compress(FAKE, 10, FAKE, 0, 1.0, FAKE, None, None, None, None) == kde.KDE_EINVAL
+    assert L.kde_dp_compress(FAKE, 10, FAKE, 11, 1.0, FAKE, None, None, None, None) == kde.KDE_EINVAL
+    assert L.kde_dp_compress(FAKE, 10, FAKE, 2, -1.0, FAKE, None, None, None, None) == kde.KDE_EINVAL
+    assert L.kde_dp_compress(FAKE, 10, FAKE, 2, float("nan"), FAKE, None, None, None, None) == kde.KDE_EINVAL
+    assert L.kde_dp_compress(None, 10, FAKE, 2, 1.0, FAKE, None, None, None, None) == kde.KDE_EINVAL
+    assert L.kde_dp_compress(None, 0, None, 0, 1.0, None, None, None, ctypes.byref(n), None) == kde.KDE_OK
+    assert n.value == 0
+
+
 def test_binned_entry_points_validate():
     L = kde.lib()
     g = kde.Grid(0.0, 1.0, 0.0, 1.0, 16, 16)
