@@ -241,6 +241,40 @@ def bench_truncated(torch, kde, pts, g, ref_maps, steps: int):
     return res
 
 
+def bench_dp(torch, kde, synth, t, steps: int):
+    """Douglas-Peucker compression of the bench's 8,000 tracks (4,000,000 points,
+    Mercator metres resident on the GPU) at eps = 10, 50, 100 m: GPU time per
+    compression (mask, compaction and per-track counts), kept points, CR."""
+    import numpy as np
+    mx, my = synth.mercator(t.xy[:, 0], t.xy[:, 1], t.box.center_lat)
+    xy = torch.from_numpy(np.column_stack([mx, my])).cuda()
+    start = torch.from_numpy(np.concatenate([[0], np.cumsum(t.lengths)]).astype(np.int64)).cuda()
+    res = {"points": int(t.n), "tracks": int(len(t.lengths))}
+    for eps in (10.0, 50.0, 100.0):
+        tot, _, _ = timed_steps(torch, lambda: kde.dp_compress(xy, start, eps), steps, 1)
+        keep, out, _ = kde.dp_compress(xy, start, eps)
+        kept = int(out.shape[0])
+        res[f"eps_{eps:g}m"] = {"ms": tot / steps, "points_per_s": t.n / (tot / steps * 1e-3), "kept": kept,
+                                "cr_percent": (1.0 - kept / t.n) * 100.0}
+    log("dp: " + ", ".join(f"{k} {v['ms']:.2f} ms (CR {v['cr_percent']:.1f} %)" for k, v in res.items()
+                           if isinstance(v, dict)))
+    return res
+
+
+def dp_cpu_baseline(synth, t, eps: float = 50.0):
+    """The oracle's sequential Douglas-Peucker on the same tracks (one core)."""
+    import numpy as np
+
+    import oracle
+    mx, my = synth.mercator(t.xy[:, 0], t.xy[:, 1], t.box.center_lat)
+    xy = np.column_stack([mx, my])
+    t0 = time.perf_counter()
+    keep = oracle.dp_keep(xy, t.lengths, eps)
+    dt = time.perf_counter() - t0
+    return {"eps_m": eps, "ms": dt * 1e3, "points_per_s": t.n / dt, "cores": 1, "kind": "oracle",
+            "kept": int(keep.sum())}
+
+
 def bench_compact(torch, kde, synth, steps: int):
     """The eight kernels on the FP32 direct path: 1,000,000 points (2,000 tracks x
     500) on 1024 x 1024, h = 0.002 degrees."""
@@ -269,9 +303,9 @@ def main() -> int:
     ap.add_argument("--profile-once", action="store_true",
                     help="for counter runs: two FP16 maps and one FP32 direct map, then a 256 MiB "
                          "elementwise copy (torch.neg) as the byte-count calibration; prints no JSON")
-    ap.add_argument("--sections", default="adjoint,batched,kernels,binned,truncated",
+    ap.add_argument("--sections", default="adjoint,batched,kernels,binned,truncated,dp",
                     help="extra measured sections beside the headline: adjoint, batched, kernels, binned, "
-                         "truncated (or none)")
+                         "truncated, dp (or none)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the KDE map runs on a single MI355X here "
@@ -360,6 +394,8 @@ def main() -> int:
         line["batched"] = bench_batched(torch, kde, synth, 6)
     if "kernels" in extra:
         line["fp32_direct_kernels"] = bench_compact(torch, kde, synth, 5)
+    if "dp" in extra:
+        line["dp"] = bench_dp(torch, kde, synth, t, 5)
     if "truncated" in extra:
         line["truncated"] = bench_truncated(torch, kde, pts, g, maps, 10)
     if "binned" in extra:
@@ -370,6 +406,9 @@ def main() -> int:
         og = og_mod.Grid(b.lon0, b.lon1, b.lat0, b.lat1, SIDE, SIDE)
         base, errs, crop, win = cpu_baseline(XY, maps, og, args.cpu_budget)
         line["cpu_baseline"] = base
+        if "dp" in extra:
+            line["dp"]["cpu_baseline"] = dp_cpu_baseline(synth, t)
+            line["dp"]["speedup_vs_cpu_eps_50m"] = line["dp"]["cpu_baseline"]["ms"] / line["dp"]["eps_50m"]["ms"]
         line["error_vs_fp64"] = {"sampled_e_inf": errs, "peak_crop": {"window": list(win), **crop}}
     print(json.dumps(line), flush=True)
     return 0

@@ -66,10 +66,13 @@ __global__ __launch_bounds__(256) void dp_check_kernel(const int64_t *__restrict
     if (!ok) atomicOr(bad, 1u);
 }
 
-// Track of point i (binary search in the offsets), its end points kept.
+// Track of point i (binary search in the offsets), its end points kept; the
+// slots of the first chords (at the track starts) are reset for level 0.
 __global__ __launch_bounds__(256) void dp_init_kernel(const int64_t *__restrict__ start, int64_t n_tracks, int64_t n,
-                                                      int64_t *__restrict__ lo, int64_t *__restrict__ hi,
-                                                      uint8_t *__restrict__ keep, uint8_t *__restrict__ active) {
+                                                      int *__restrict__ lo, int *__restrict__ hi,
+                                                      uint8_t *__restrict__ keep, uint8_t *__restrict__ active,
+                                                      unsigned long long *__restrict__ segmax,
+                                                      unsigned long long *__restrict__ segarg) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int64_t a = 0, b = n_tracks;  // find t with start[t] <= i < start[t + 1]
@@ -79,80 +82,106 @@ __global__ __launch_bounds__(256) void dp_init_kernel(const int64_t *__restrict_
         else b = m;
     }
     const int64_t s = start[a], e = start[a + 1] - 1;
-    lo[i] = s;
-    hi[i] = e;
+    lo[i] = (int)s;
+    hi[i] = (int)e;
     const bool end_point = i == s || i == e;
     keep[i] = end_point ? 1 : 0;
     active[i] = end_point ? 0 : 1;
+    if (i == s) {
+        segmax[i] = 0ull;
+        segarg[i] = kNoIndex;
+    }
 }
 
-__global__ __launch_bounds__(256) void dp_reset_kernel(int64_t n, const int64_t *__restrict__ lo,
-                                                       const uint8_t *__restrict__ active,
-                                                       unsigned long long *__restrict__ segmax,
-                                                       unsigned long long *__restrict__ segarg) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || !active[i]) return;
-    const int64_t s = lo[i];
-    segmax[s] = 0ull;  // every point of the chord writes the same values
-    segarg[s] = kNoIndex;
-}
-
+// Slots of level L live in buffer L % 2: the kept point of a split chord resets
+// the next level's slots of both halves while this level's are still read.
 __global__ __launch_bounds__(256) void dp_score_kernel(const double2 *__restrict__ xy, int64_t n,
-                                                       const int64_t *__restrict__ lo, const int64_t *__restrict__ hi,
+                                                       const int *__restrict__ lo, const int *__restrict__ hi,
                                                        const uint8_t *__restrict__ active,
+                                                       double *__restrict__ score,
                                                        unsigned long long *__restrict__ segmax) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || !active[i]) return;
-    bool zero;
-    const double sc = dp_score(xy, lo[i], hi[i], i, zero);
-    // non-negative doubles order like their bit patterns
-    atomicMax(segmax + lo[i], (unsigned long long)__double_as_longlong(sc));
+    const bool act = i < n && active[i];
+    unsigned long long bits = 0ull;
+    int s = -1;
+    if (act) {
+        bool zero;
+        s = lo[i];
+        const double sc = dp_score(xy, s, hi[i], i, zero);
+        score[i] = sc;
+        bits = (unsigned long long)__double_as_longlong(sc);  // non-negative doubles order like their bits
+    }
+    // Chords are index ranges, so the lanes of a wave mostly share one: then one
+    // atomic per wave carries the wave's maximum (an integer max, order-free).
+    const unsigned long long am = __ballot(act);
+    if (am == 0ull) return;
+    const int first = __ffsll(am) - 1;
+    const int s0 = __shfl(s, first);
+    if (__ballot(act && s == s0) == am) {
+        unsigned long long m = bits;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned long long o = __shfl_xor(m, off);
+            m = o > m ? o : m;
+        }
+        if ((int)(threadIdx.x & 63) == first) atomicMax(segmax + s0, m);
+    } else if (act) {
+        atomicMax(segmax + s, bits);
+    }
 }
 
-__global__ __launch_bounds__(256) void dp_argmax_kernel(const double2 *__restrict__ xy, int64_t n,
-                                                        const int64_t *__restrict__ lo, const int64_t *__restrict__ hi,
+__global__ __launch_bounds__(256) void dp_argmax_kernel(int64_t n, const int *__restrict__ lo,
                                                         const uint8_t *__restrict__ active,
+                                                        const double *__restrict__ score,
                                                         const unsigned long long *__restrict__ segmax,
                                                         unsigned long long *__restrict__ segarg) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || !active[i]) return;
-    bool zero;
-    const double sc = dp_score(xy, lo[i], hi[i], i, zero);
-    if ((unsigned long long)__double_as_longlong(sc) == segmax[lo[i]]) atomicMin(segarg + lo[i], (unsigned long long)i);
+    if ((unsigned long long)__double_as_longlong(score[i]) == segmax[lo[i]])
+        atomicMin(segarg + lo[i], (unsigned long long)i);
 }
 
 // The chord's argmax decides: 1 = split at it (kept), 2 = final.
 __global__ __launch_bounds__(256) void dp_decide_kernel(const double2 *__restrict__ xy, int64_t n, double eps2,
-                                                        const int64_t *__restrict__ lo, const int64_t *__restrict__ hi,
+                                                        const int *__restrict__ lo, const int *__restrict__ hi,
                                                         const uint8_t *__restrict__ active,
+                                                        const double *__restrict__ score,
                                                         const unsigned long long *__restrict__ segarg,
                                                         uint8_t *__restrict__ segdec, uint8_t *__restrict__ keep,
+                                                        unsigned long long *__restrict__ next_max,
+                                                        unsigned long long *__restrict__ next_arg,
                                                         unsigned *__restrict__ splits) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool split = false;
     if (i < n && active[i] && segarg[lo[i]] == (unsigned long long)i) {
+        const int s = lo[i];
         bool zero;
-        const double sc = dp_score(xy, lo[i], hi[i], i, zero);
-        split = dp_split(xy, lo[i], hi[i], sc, zero, eps2);
-        segdec[lo[i]] = split ? 1 : 2;
-        if (split) keep[i] = 1;
+        (void)dp_score(xy, s, hi[i], i, zero);  // the zero-chord case, decided as the score was
+        split = dp_split(xy, s, hi[i], score[i], zero, eps2);
+        segdec[s] = split ? 1 : 2;
+        if (split) {
+            keep[i] = 1;
+            next_max[s] = 0ull;
+            next_arg[s] = kNoIndex;
+            next_max[i] = 0ull;
+            next_arg[i] = kNoIndex;
+        }
     }
-    const unsigned long long m = __ballot(split);
-    if ((threadIdx.x & 63) == 0 && m != 0ull) atomicAdd(splits, (unsigned)__popcll(m));
+    if (split) *splits = 1u;  // only "some chord split" is needed: same value from every writer
 }
 
-__global__ __launch_bounds__(256) void dp_update_kernel(int64_t n, int64_t *__restrict__ lo, int64_t *__restrict__ hi,
+__global__ __launch_bounds__(256) void dp_update_kernel(int64_t n, int *__restrict__ lo, int *__restrict__ hi,
                                                         uint8_t *__restrict__ active,
                                                         const unsigned long long *__restrict__ segarg,
                                                         const uint8_t *__restrict__ segdec) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || !active[i]) return;
-    const int64_t s = lo[i];
+    const int s = lo[i];
     if (segdec[s] == 2) {
         active[i] = 0;  // within eps of its final chord: dropped
         return;
     }
-    const int64_t k = (int64_t)segarg[s];
+    const int k = (int)segarg[s];
     if (k == i) active[i] = 0;  // kept
     else if (i < k) hi[i] = k;
     else lo[i] = k;
@@ -188,7 +217,7 @@ __global__ __launch_bounds__(256) void dp_lengths_kernel(const int64_t *__restri
 }
 
 struct DpLayout {
-    size_t lo, hi, active, segmax, segarg, segdec, counters, pos, totals, total;
+    size_t lo, hi, active, score, segmax, segarg, segdec, counters, pos, totals, total;
 };
 
 size_t al(size_t x) { return (x + 255) / 256 * 256; }
@@ -196,11 +225,12 @@ size_t al(size_t x) { return (x + 255) / 256 * 256; }
 DpLayout dp_layout(int64_t n) {
     DpLayout L;
     size_t o = 0;
-    L.lo = o; o += al((size_t)n * 8);
-    L.hi = o; o += al((size_t)n * 8);
+    L.lo = o; o += al((size_t)n * 4);
+    L.hi = o; o += al((size_t)n * 4);
     L.active = o; o += al((size_t)n);
-    L.segmax = o; o += al((size_t)n * 8);
-    L.segarg = o; o += al((size_t)n * 8);
+    L.score = o; o += al((size_t)n * 8);
+    L.segmax = o; o += al((size_t)n * 16);  // two parity buffers
+    L.segarg = o; o += al((size_t)n * 16);
     L.segdec = o; o += al((size_t)n);
     L.counters = o; o += 256;
     L.pos = o; o += al((size_t)n * 4);
@@ -216,9 +246,10 @@ size_t dp_workspace_bytes(int64_t n) { return dp_layout(n).total; }
 hipError_t run_dp(const DpArgs &a, void *ws, hipStream_t s, int64_t *n_kept) {
     const DpLayout L = dp_layout(a.n);
     char *w = static_cast<char *>(ws);
-    int64_t *lo = reinterpret_cast<int64_t *>(w + L.lo);
-    int64_t *hi = reinterpret_cast<int64_t *>(w + L.hi);
+    int *lo = reinterpret_cast<int *>(w + L.lo);
+    int *hi = reinterpret_cast<int *>(w + L.hi);
     uint8_t *active = reinterpret_cast<uint8_t *>(w + L.active);
+    double *score = reinterpret_cast<double *>(w + L.score);
     unsigned long long *segmax = reinterpret_cast<unsigned long long *>(w + L.segmax);
     unsigned long long *segarg = reinterpret_cast<unsigned long long *>(w + L.segarg);
     uint8_t *segdec = reinterpret_cast<uint8_t *>(w + L.segdec);
@@ -232,36 +263,40 @@ hipError_t run_dp(const DpArgs &a, void *ws, hipStream_t s, int64_t *n_kept) {
     hipLaunchKernelGGL(dp_check_kernel, dim3((unsigned)((a.n_tracks + 1 + 255) / 256)), block, 0, s, a.start,
                        a.n_tracks, a.n, splits);
     unsigned bad = 0;
-    hipError_t e0 = hipMemcpyAsync(&bad, splits, sizeof bad, hipMemcpyDeviceToHost, s);
-    if (e0 == hipSuccess) e0 = hipStreamSynchronize(s);
-    if (e0 != hipSuccess) return e0;
-    if (bad) return hipErrorInvalidValue;  // *n_kept stays -1: invalid offsets
-    hipLaunchKernelGGL(dp_init_kernel, grid, block, 0, s, a.start, a.n_tracks, a.n, lo, hi, a.keep, active);
-    hipError_t e = hipGetLastError();
+    hipError_t e = hipMemcpyAsync(&bad, splits, sizeof bad, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return e;
+    if (bad) return hipErrorInvalidValue;  // *n_kept stays -1: invalid offsets
+    hipLaunchKernelGGL(dp_init_kernel, grid, block, 0, s, a.start, a.n_tracks, a.n, lo, hi, a.keep, active, segmax,
+                       segarg);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     // Every level either splits a chord or leaves all remaining ones final, so
     // no track needs more levels than it has points.
-    for (int64_t level = 0; level <= a.n; level += kLevelsPerCheck) {
+    int64_t level = 0;
+    for (int64_t group = 0; group <= a.n / kLevelsPerCheck + 1; ++group) {
         hipLaunchKernelGGL(zero_u32_kernel, dim3(1), block, 0, s, splits, (int64_t)1);
-        for (int l = 0; l < kLevelsPerCheck; ++l) {
-            hipLaunchKernelGGL(dp_reset_kernel, grid, block, 0, s, a.n, static_cast<const int64_t *>(lo),
-                               static_cast<const uint8_t *>(active), segmax, segarg);
-            hipLaunchKernelGGL(dp_score_kernel, grid, block, 0, s, a.xy, a.n, static_cast<const int64_t *>(lo),
-                               static_cast<const int64_t *>(hi), static_cast<const uint8_t *>(active), segmax);
-            hipLaunchKernelGGL(dp_argmax_kernel, grid, block, 0, s, a.xy, a.n, static_cast<const int64_t *>(lo),
-                               static_cast<const int64_t *>(hi), static_cast<const uint8_t *>(active),
-                               static_cast<const unsigned long long *>(segmax), segarg);
-            hipLaunchKernelGGL(dp_decide_kernel, grid, block, 0, s, a.xy, a.n, eps2, static_cast<const int64_t *>(lo),
-                               static_cast<const int64_t *>(hi), static_cast<const uint8_t *>(active),
-                               static_cast<const unsigned long long *>(segarg), segdec, a.keep, splits);
+        for (int l = 0; l < kLevelsPerCheck; ++l, ++level) {
+            const int64_t cur = (level & 1) * a.n, nxt = ((level + 1) & 1) * a.n;
+            hipLaunchKernelGGL(dp_score_kernel, grid, block, 0, s, a.xy, a.n, static_cast<const int *>(lo),
+                               static_cast<const int *>(hi), static_cast<const uint8_t *>(active), score,
+                               segmax + cur);
+            hipLaunchKernelGGL(dp_argmax_kernel, grid, block, 0, s, a.n, static_cast<const int *>(lo),
+                               static_cast<const uint8_t *>(active), static_cast<const double *>(score),
+                               static_cast<const unsigned long long *>(segmax + cur), segarg + cur);
+            hipLaunchKernelGGL(dp_decide_kernel, grid, block, 0, s, a.xy, a.n, eps2, static_cast<const int *>(lo),
+                               static_cast<const int *>(hi), static_cast<const uint8_t *>(active),
+                               static_cast<const double *>(score),
+                               static_cast<const unsigned long long *>(segarg + cur), segdec, a.keep, segmax + nxt,
+                               segarg + nxt, splits);
             hipLaunchKernelGGL(dp_update_kernel, grid, block, 0, s, a.n, lo, hi, active,
-                               static_cast<const unsigned long long *>(segarg), static_cast<const uint8_t *>(segdec));
+                               static_cast<const unsigned long long *>(segarg + cur),
+                               static_cast<const uint8_t *>(segdec));
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
         unsigned got = 0;
         if ((e = hipMemcpyAsync(&got, splits, sizeof got, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
         if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-        if (got == 0) break;  // the group's last level split nothing: every chord is final
+        if (got == 0) break;  // no chord split in the whole group: every chord is final
     }
     // Kept count (and compaction) from the exclusive scan of the mask.
     hipLaunchKernelGGL(keep_to_u32_kernel, grid, block, 0, s, static_cast<const uint8_t *>(a.keep), a.n, pos);
