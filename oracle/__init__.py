@@ -73,6 +73,12 @@ def lib():
         L.ko_conv_counts.argtypes = [p, i, i, i, f, f, i, i, i, i, i, i, p]
         L.ko_dp_keep.argtypes = [p, i64, p, i64, d, p]
         L.ko_dp_keep.restype = i64
+        L.ko_track_length.argtypes = [p, i64]
+        L.ko_track_length.restype = d
+        L.ko_dtw.argtypes = [p, i64, p, i64]
+        L.ko_dtw.restype = d
+        L.ko_track_metrics.argtypes = [p, p, p, p, i64, p, p, p]
+        L.ko_track_metrics.restype = None
         for name in ("ko_map_world", "ko_map_units", "ko_map_units_at", "ko_vjp_units", "ko_lscv_world",
                      "ko_lscv_units", "ko_bin_counts", "ko_conv_counts"):
             getattr(L, name).restype = None
@@ -327,6 +333,50 @@ def dp_keep(xy_m, lengths, eps: float):
     keep = np.zeros(xy.shape[0], dtype=np.uint8)
     lib().ko_dp_keep(_ptr(xy), xy.shape[0], _ptr(start), len(start) - 1, float(eps), _ptr(keep))
     return keep
+
+
+def track_length(xy) -> float:
+    """|T| = sum of |P_n P_{n+1}| over consecutive points (Eq. (15))."""
+    xy = _f64(xy).reshape(-1, 2)
+    return float(lib().ko_track_length(_ptr(xy), xy.shape[0]))
+
+
+def dtw(a, b) -> float:
+    """Squared-Euclidean DTW distance sqrt(D[N_o, N_c]) of Eq. (16)-(18)."""
+    a = _f64(a).reshape(-1, 2)
+    b = _f64(b).reshape(-1, 2)
+    return float(lib().ko_dtw(_ptr(a), a.shape[0], _ptr(b), b.shape[0]))
+
+
+def _starts(lengths):
+    return np.concatenate([[0], np.cumsum(np.asarray(lengths, dtype=np.int64))]).astype(np.int64)
+
+
+def track_metrics(xy_o, lengths_o, xy_c, lengths_c) -> dict:
+    """Compression quality of M tracks against their compressed versions
+    (Sec. V-B): per track |T_m|, |T'_m| and DTW(T_m, T'_m); over the set
+    N_o, N_c, CR = (1 - N_c / N_o) * 100 (Eq. (14)), RLL = (sum |T| - sum |T'|)
+    / sum |T| (Eq. (15), a fraction), the mean mu and population standard
+    deviation delta of the DTW distances (Eq. (19)-(20)).  The sums over tracks
+    are exactly rounded (math.fsum); delta is taken about the computed mu."""
+    import math
+    xo = _f64(xy_o).reshape(-1, 2)
+    xc = _f64(xy_c).reshape(-1, 2)
+    so, sc = _starts(lengths_o), _starts(lengths_c)
+    m = len(so) - 1
+    assert len(sc) - 1 == m and so[-1] == xo.shape[0] and sc[-1] == xc.shape[0]
+    lo, lc, dw = (np.zeros(m) for _ in range(3))
+    lib().ko_track_metrics(_ptr(xo), _ptr(so), _ptr(xc), _ptr(sc), m, _ptr(lo), _ptr(lc), _ptr(dw))
+    n_o, n_c = int(xo.shape[0]), int(xc.shape[0])
+    tot_o, tot_c = math.fsum(lo), math.fsum(lc)
+    nan = float("nan")
+    mu = math.fsum(dw) / m if m else nan
+    delta = math.sqrt(math.fsum((v - mu) ** 2 for v in dw) / m) if m else nan
+    return {"len_o": lo, "len_c": lc, "dtw": dw, "n_original": n_o, "n_compressed": n_c,
+            "cr_percent": (1.0 - n_c / n_o) * 100.0 if n_o else nan,
+            "length_original": tot_o, "length_compressed": tot_c,
+            "rll": (tot_o - tot_c) / tot_o if tot_o != 0.0 else nan,
+            "dtw_mean": mu, "dtw_std": delta}
 
 
 def errors(y, r) -> dict:

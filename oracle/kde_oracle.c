@@ -30,6 +30,11 @@
  * Differentiation (not in the paper): the vector-Jacobian product of the map and
  * the least-squares cross-validation (LSCV) bandwidth objective of Rudemo (1982)
  * and Bowman (1984), both written from their definitions below.
+ *
+ * The trajectory side (Sec. III-B, V-B): the binned count matrix, recursive
+ * Douglas-Peucker, and the compression-quality measures (track lengths for the
+ * rate of length loss, squared-Euclidean DTW), each a plain loop over its
+ * definition.
  */
 #include <math.h>
 #include <stdint.h>
@@ -498,4 +503,71 @@ int64_t ko_dp_keep(const double *xy, int64_t n, const int64_t *start, int64_t n_
     for (int64_t t = 0; t < n_tracks; ++t)
         for (int64_t i = start[t]; i < start[t + 1]; ++i) kept += keep[i];
     return kept;
+}
+
+/* ------------------------------------------------------------------------
+ * Compression quality (Sec. V-B).  Points are planar FP64 pairs (x, y).
+ * ------------------------------------------------------------------------ */
+
+/* Track length: sum over consecutive points of the Euclidean distance
+ * |P_n P_{n+1}| (the |T| inside the RLL definition, Eq. (15)).  Index order. */
+double ko_track_length(const double *xy, int64_t n)
+{
+    double len = 0.0;
+    for (int64_t i = 0; i + 1 < n; ++i) {
+        double dx = xy[2 * (i + 1)] - xy[2 * i];
+        double dy = xy[2 * (i + 1) + 1] - xy[2 * i + 1];
+        len += sqrt(dx * dx + dy * dy);
+    }
+    return len;
+}
+
+/* DTW distance of Eq. (16)-(18): the accumulated cost matrix
+ *   D[i][j] = d(P_i, P'_j) + min(D[i-1][j-1], D[i-1][j], D[i][j-1]),
+ * d the squared Euclidean distance, with D[-1][-1] = 0 and every other border
+ * entry +inf, filled row by row (two rows kept); returns sqrt(D[na-1][nb-1]).
+ * No warping path joins an empty series to a non-empty one (+inf); two empty
+ * series are at distance 0. */
+double ko_dtw(const double *a, int64_t na, const double *b, int64_t nb)
+{
+    if (na == 0 || nb == 0) return (na == 0 && nb == 0) ? 0.0 : INFINITY;
+    double *prev = (double *)malloc((size_t)(nb + 1) * sizeof(double));
+    double *cur = (double *)malloc((size_t)(nb + 1) * sizeof(double));
+    /* column 0 of these rows is the border j = -1 */
+    prev[0] = 0.0;
+    for (int64_t j = 1; j <= nb; ++j) prev[j] = INFINITY;
+    for (int64_t i = 0; i < na; ++i) {
+        cur[0] = INFINITY;
+        for (int64_t j = 0; j < nb; ++j) {
+            double dx = a[2 * i] - b[2 * j], dy = a[2 * i + 1] - b[2 * j + 1];
+            double d = dx * dx + dy * dy;
+            double m = prev[j];                    /* D[i-1][j-1] */
+            if (prev[j + 1] < m) m = prev[j + 1];  /* D[i-1][j] */
+            if (cur[j] < m) m = cur[j];            /* D[i][j-1] */
+            cur[j + 1] = d + m;
+        }
+        double *t = prev;
+        prev = cur;
+        cur = t;
+    }
+    double r = sqrt(prev[nb]);
+    free(prev);
+    free(cur);
+    return r;
+}
+
+/* Per-track lengths and DTW distances of a track set and its compressed
+ * version, tracks [start_o[m], start_o[m+1]) and [start_c[m], start_c[m+1]).
+ * Tracks are independent: one OpenMP task each. */
+void ko_track_metrics(const double *xy_o, const int64_t *start_o, const double *xy_c, const int64_t *start_c,
+                      int64_t n_tracks, double *len_o, double *len_c, double *dtw)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t m = 0; m < n_tracks; ++m) {
+        const double *o = xy_o + 2 * start_o[m], *c = xy_c + 2 * start_c[m];
+        int64_t no = start_o[m + 1] - start_o[m], nc = start_c[m + 1] - start_c[m];
+        len_o[m] = ko_track_length(o, no);
+        len_c[m] = ko_track_length(c, nc);
+        dtw[m] = ko_dtw(o, no, c, nc);
+    }
 }

@@ -629,3 +629,133 @@ def test_dp_oracle_dropped_points_within_eps():
                 p = xy[i] - xy[s]
                 d = abs(p[0] * c[1] - p[1] * c[0]) / max(np.hypot(*c), 1e-300) if np.hypot(*c) > 0 else np.hypot(*p)
                 assert d <= eps * (1 + 1e-12)
+
+
+# ------------------------------------------------------- compression quality (Sec. V-B)
+def _golden_metrics():
+    vals = {}
+    with open(os.path.join(HERE, "golden", "compression_metrics_small.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            key, val = line.split()
+            if key.startswith(("points", "lengths")):
+                rows = [[float(v) for v in r.split(",")] for r in val.split(";")]
+                vals[key] = np.array(rows) if key.startswith("points") else [int(v) for v in rows[0]]
+            else:
+                vals[key] = eval(val, {"__builtins__": {}, "sqrt": math.sqrt})
+    return vals
+
+
+def test_metrics_hand_worked_example():
+    g = _golden_metrics()
+    r = oracle.track_metrics(g["points_o"], g["lengths_o"], g["points_c"], g["lengths_c"])
+    for m in (1, 2):
+        assert r["dtw"][m - 1] == pytest.approx(g[f"dtw_{m}"], rel=1e-15)
+        assert r["len_o"][m - 1] == pytest.approx(g[f"len_o_{m}"], rel=1e-15)
+        assert r["len_c"][m - 1] == pytest.approx(g[f"len_c_{m}"], rel=1e-15, abs=0)
+    for key in ("cr_percent", "rll", "dtw_mean", "dtw_std"):
+        assert r[key] == pytest.approx(g[key], rel=1e-14), key
+    assert (r["n_original"], r["n_compressed"]) == (6, 3)
+
+
+def _dtw_brute(a, b):
+    """Minimum over every warping path from (0, 0) to (na-1, nb-1) with steps
+    (1, 0), (0, 1), (1, 1) of the summed squared distances, square-rooted."""
+    na, nb = len(a), len(b)
+    best = math.inf
+
+    def walk(i, j, cost):
+        nonlocal best
+        cost += float(np.sum((a[i] - b[j]) ** 2))
+        if (i, j) == (na - 1, nb - 1):
+            best = min(best, cost)
+            return
+        if i + 1 < na:
+            walk(i + 1, j, cost)
+        if j + 1 < nb:
+            walk(i, j + 1, cost)
+        if i + 1 < na and j + 1 < nb:
+            walk(i + 1, j + 1, cost)
+
+    walk(0, 0, 0.0)
+    return math.sqrt(best)
+
+
+def test_dtw_matches_brute_force_over_warping_paths():
+    rng = np.random.default_rng(5)
+    for na in range(1, 6):
+        for nb in range(1, 6):
+            a = rng.normal(0, 3, (na, 2))
+            b = rng.normal(0, 3, (nb, 2))
+            assert oracle.dtw(a, b) == pytest.approx(_dtw_brute(a, b), rel=1e-13)
+
+
+def test_dtw_closed_forms_and_symmetries():
+    rng = np.random.default_rng(6)
+    a = rng.normal(0, 10, (37, 2))
+    p = rng.normal(0, 10, (1, 2))
+    # one point on either side: every cell of the single row or column is on the path
+    want = math.sqrt(float(np.sum((a - p) ** 2)))
+    assert oracle.dtw(a, p) == pytest.approx(want, rel=1e-13)
+    assert oracle.dtw(p, a) == pytest.approx(want, rel=1e-13)
+    b = rng.normal(0, 10, (23, 2))
+    assert oracle.dtw(a, a) == 0.0
+    assert oracle.dtw(a, b) == oracle.dtw(b, a)  # the recurrence is symmetric under transposition
+    assert oracle.dtw(a + 1000.0, b + 1000.0) == pytest.approx(oracle.dtw(a, b), rel=1e-9)  # translation
+    assert oracle.dtw(2.0 * a, 2.0 * b) == pytest.approx(2.0 * oracle.dtw(a, b), rel=1e-13)  # degree-1 scaling
+    assert oracle.dtw(a[:0], b[:0]) == 0.0
+    assert oracle.dtw(a, b[:0]) == math.inf
+
+
+def test_track_length_forms():
+    rng = np.random.default_rng(7)
+    xy = rng.normal(0, 50, (101, 2))
+    assert oracle.track_length(xy) == pytest.approx(float(np.sum(np.hypot(*np.diff(xy, axis=0).T))), rel=1e-13)
+    assert oracle.track_length(xy[::-1]) == pytest.approx(oracle.track_length(xy), rel=1e-13)
+    line = np.column_stack([np.arange(11.0) * 3.0, np.arange(11.0) * 4.0])
+    assert oracle.track_length(line) == 50.0
+    assert oracle.track_length(xy[:1]) == 0.0 and oracle.track_length(xy[:0]) == 0.0
+
+
+def _dp_pair(t, eps):
+    mx, my = synth.mercator(t.xy[:, 0], t.xy[:, 1], t.box.center_lat)
+    xy = np.column_stack([mx, my])
+    keep = oracle.dp_keep(xy, t.lengths, eps).astype(bool)
+    starts = np.concatenate([[0], np.cumsum(t.lengths)])
+    lc = np.array([int(keep[a:b].sum()) for a, b in zip(starts[:-1], starts[1:])])
+    return xy, xy[keep], lc
+
+
+def test_metrics_threshold_zero_row_and_nesting():
+    """Eps 0 keeps every point off its chord, which on noisy tracks is all of
+    them: CR, RLL and DTW are 0 (the first row of Table IV).  Larger eps keeps a
+    subset of the points of smaller eps, so CR grows; a kept subsequence with
+    the end points is never longer (triangle inequality), so 0 <= RLL < 1."""
+    t = synth.generate(23, 30, 200, synth.BOX_C2, n_lanes=2)
+    xy, xc, lc = _dp_pair(t, 0.0)
+    r = oracle.track_metrics(xy, t.lengths, xc, lc)
+    assert r["cr_percent"] == 0.0 and r["rll"] == 0.0 and r["dtw_mean"] == 0.0 and r["dtw_std"] == 0.0
+    prev = None
+    for eps in (1.0, 10.0, 50.0):
+        xy, xc, lc = _dp_pair(t, eps)
+        r = oracle.track_metrics(xy, t.lengths, xc, lc)
+        assert 0.0 <= r["rll"] < 1.0
+        assert np.all(r["len_c"] <= r["len_o"] * (1 + 1e-12))
+        assert np.all(r["dtw"] >= 0.0)
+        if prev is not None:
+            assert r["cr_percent"] >= prev["cr_percent"]
+        prev = r
+
+
+def test_metrics_population_std_and_empty_tracks():
+    # DTW values 1 and 3 from one-column tracks: mu 2, population delta 1
+    xo = np.array([[0.0, 0.0], [0.0, 1.0], [5.0, 5.0], [5.0, 8.0]])
+    xc = np.array([[0.0, 0.0], [5.0, 5.0]])
+    r = oracle.track_metrics(xo, [2, 2], xc, [1, 1])
+    assert list(r["dtw"]) == [1.0, 3.0]
+    assert r["dtw_mean"] == 2.0 and r["dtw_std"] == 1.0
+    # an empty pair is at distance 0 and counts in M
+    r = oracle.track_metrics(xo, [2, 0, 2], xc, [1, 0, 1])
+    assert list(r["dtw"]) == [1.0, 0.0, 3.0]
+    assert r["dtw_mean"] == pytest.approx(4.0 / 3.0, rel=1e-15)
