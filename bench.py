@@ -252,7 +252,7 @@ def bench_dp(torch, kde, synth, t, steps: int):
     res = {"points": int(t.n), "tracks": int(len(t.lengths))}
     for eps in (10.0, 50.0, 100.0):
         tot, _, _ = timed_steps(torch, lambda: kde.dp_compress(xy, start, eps), steps, 1)
-        keep, out, _ = kde.dp_compress(xy, start, eps)
+        keep, out, _, _ = kde.dp_compress(xy, start, eps)
         kept = int(out.shape[0])
         res[f"eps_{eps:g}m"] = {"ms": tot / steps, "points_per_s": t.n / (tot / steps * 1e-3), "kept": kept,
                                 "cr_percent": (1.0 - kept / t.n) * 100.0}

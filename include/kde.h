@@ -236,10 +236,51 @@ int kde_eval_binned(const float *points, int64_t n, const int32_t *labels, int32
  *   keep         device uint8 [n]: 1 for kept points
  *   out_xy       device FP64 [n][2] receiving the kept points in order, or NULL
  *   out_lengths  device int64 [n_tracks] receiving kept points per track, or NULL
+ *   out_start    device int64 [n_tracks + 1] receiving the offsets of the compressed
+ *                tracks in out_xy (0, ..., n_kept), or NULL
  *   n_kept       host, number of kept points, or NULL
  * Synchronises `stream` (once per few levels of the recursion and at the end). */
 int kde_dp_compress(const double *xy, int64_t n, const int64_t *track_start, int64_t n_tracks, double eps,
-                    uint8_t *keep, double *out_xy, int64_t *out_lengths, int64_t *n_kept, void *stream);
+                    uint8_t *keep, double *out_xy, int64_t *out_lengths, int64_t *out_start, int64_t *n_kept,
+                    void *stream);
+
+/* Compression quality of a track set against its compressed version
+ * (Sec. V-B), over M tracks given by offsets: original track m is
+ * xy_o[start_o[m] .. start_o[m+1]), its compressed version xy_c[start_c[m] ..
+ * start_c[m+1]) (e.g. out_xy and out_start of kde_dp_compress; any series
+ * works, a subsequence is not required).
+ *   per track   len_o[m] = |T_m|, len_c[m] = |T'_m| (sum of Euclidean distances
+ *               between consecutive points); dtw[m] = DTW(T_m, T'_m) of
+ *               Eq. (16)-(18): sqrt of the last entry of the accumulated cost
+ *               matrix D[i][j] = d(P_i, P'_j) + min(D[i-1][j-1], D[i-1][j],
+ *               D[i][j-1]), d the squared Euclidean distance.  Two empty
+ *               series are at distance 0, an empty and a non-empty one at +inf.
+ *   totals      N_o, N_c, CR = (1 - N_c/N_o) * 100 (Eq. (14)), the summed
+ *               lengths, RLL = (sum |T| - sum |T'|) / sum |T| (Eq. (15), a
+ *               fraction), mu and delta = the mean and population standard
+ *               deviation of the M DTW distances (Eq. (19)-(20)).  NaN where a
+ *               denominator is 0.
+ * FP64 throughout.  Each D entry is exact to the plain row-by-row recurrence
+ * (no fused multiply-add); lengths and totals are fixed-order tree sums, so
+ * results are bitwise reproducible.
+ *   xy_o, xy_c        device FP64 [n][2] planar points (e.g. Mercator metres)
+ *   start_o, start_c  device int64 [n_tracks + 1], rising from 0 to n_o (n_c);
+ *                     tracks under 2^30 points (else KDE_EINVAL)
+ *   len_o, len_c, dtw device FP64 [n_tracks] each, or NULL (not returned)
+ *   out               host, the totals, or NULL
+ * Synchronises `stream` once to validate the offsets, and again at the end
+ * when out is given. */
+typedef struct kde_track_metrics {
+    int64_t n_original, n_compressed;
+    double cr_percent;
+    double length_original, length_compressed;
+    double rll;
+    double dtw_mean, dtw_std;
+} kde_track_metrics;
+
+int kde_compression_metrics(const double *xy_o, int64_t n_o, const int64_t *start_o, const double *xy_c, int64_t n_c,
+                            const int64_t *start_c, int64_t n_tracks, double *len_o, double *len_c, double *dtw,
+                            kde_track_metrics *out, void *stream);
 
 /* Tile-shape autotuner (FP32 direct path, kde_eval and kde_eval_batched).
  * The direct kernels exist for register blocks of 2 x 2, 4 x 4 and 8 x 8 pixels
@@ -277,10 +318,11 @@ int kde_autotune_dump(char *buf, size_t cap, size_t *needed);
 /* Empties the in-memory cache. */
 int kde_autotune_clear(void);
 
-/* Measurement hook.  The next kde_eval, kde_conv_counts or kde_eval_binned
- * call made by this thread records start_event on its stream right before it
- * launches its main kernel (the separable contraction, the FP32 direct
- * evaluation, the support-binned gather, or the two convolution passes) and
+/* Measurement hook.  The next kde_eval, kde_conv_counts, kde_eval_binned or
+ * kde_compression_metrics call made by this thread records start_event on its
+ * stream right before it launches its main kernel (the separable contraction,
+ * the FP32 direct evaluation, the support-binned gather, the two convolution
+ * passes, or the per-track length and DTW pass) and
  * stop_event right after, so that the elapsed time between the two events is
  * that work alone, without the point padding, split reduction, support-binning
  * or counting passes.  Both are hipEvent_t handles owned by the caller, created on

@@ -11,6 +11,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+from typing import NamedTuple
 
 import numpy as np
 
@@ -74,7 +75,9 @@ def lib() -> ctypes.CDLL:
             "kde_bin_counts": (ctypes.c_int, [p, i64, p, p, p, p, p]),
             "kde_conv_counts": (ctypes.c_int, [p, p, p, i32, d, d, i32, i32, p, u32, p]),
             "kde_eval_binned": (ctypes.c_int, [p, i64, p, i32, d, d, i32, i32, p, p, u32, p]),
-            "kde_dp_compress": (ctypes.c_int, [p, i64, p, i64, d, p, p, p, p, p]),
+            "kde_dp_compress": (ctypes.c_int, [p, i64, p, i64, d, p, p, p, p, p, p]),
+            "kde_compression_metrics": (ctypes.c_int, [p, i64, p, p, i64, p, i64, p, p, p,
+                                                       ctypes.POINTER(TrackMetrics), p]),
             "kde_time_next_main_kernel": (ctypes.c_int, [p, p]),
             "kde_autotune_enable": (ctypes.c_int, [i32]),
             "kde_autotune_force": (ctypes.c_int, [i32]),
@@ -250,11 +253,18 @@ def paper_taps(kernel, varpi: int, grid: Grid) -> tuple[float, float, int, int]:
     return H * grid.dx, H * grid.dy, r, r
 
 
-def dp_compress(xy, track_start, eps: float, compact: bool = True):
+class DpResult(NamedTuple):
+    keep: object     # [n] uint8, 1 for kept points
+    xy: object       # [n_kept, 2] kept points in order, or None
+    lengths: object  # [n_tracks] kept points per track, or None
+    start: object    # [n_tracks + 1] offsets of the compressed tracks, or None
+
+
+def dp_compress(xy, track_start, eps: float, compact: bool = True) -> DpResult:
     """Douglas-Peucker compression of merged tracks on the GPU (kde_dp_compress).
     xy: [n, 2] float64 CUDA tensor (planar, e.g. Mercator metres); track_start:
-    [n_tracks + 1] int64 CUDA tensor of offsets.  Returns (keep [n] uint8,
-    kept points [n_kept, 2] or None, kept per track [n_tracks] or None)."""
+    [n_tracks + 1] int64 CUDA tensor of offsets.  With compact=False only the
+    keep mask is produced."""
     import torch
     if not (xy.is_cuda and xy.dtype == torch.float64 and xy.dim() == 2 and xy.shape[1] == 2 and xy.is_contiguous()):
         raise ValueError("xy must be a contiguous CUDA float64 tensor of shape [n, 2]")
@@ -265,15 +275,65 @@ def dp_compress(xy, track_start, eps: float, compact: bool = True):
     keep = torch.empty(n, dtype=torch.uint8, device=xy.device)
     out = torch.empty_like(xy) if compact else None
     lens = torch.empty(max(nt, 0), dtype=torch.int64, device=xy.device) if compact else None
+    starts = torch.empty(max(nt, 0) + 1, dtype=torch.int64, device=xy.device) if compact else None
     kept = ctypes.c_int64()
     with torch.cuda.device(xy.device):
         _check(lib().kde_dp_compress(xy.data_ptr() if n else None, n, track_start.data_ptr(), nt, float(eps),
                                      keep.data_ptr() if n else None, out.data_ptr() if compact and n else None,
-                                     lens.data_ptr() if compact and nt > 0 else None, ctypes.byref(kept),
+                                     lens.data_ptr() if compact and nt > 0 else None,
+                                     starts.data_ptr() if compact else None, ctypes.byref(kept),
                                      _stream(torch, xy.device)))
     if compact:
         out = out[:kept.value]
-    return keep, out, lens
+    return DpResult(keep, out, lens, starts)
+
+
+class TrackMetrics(ctypes.Structure):
+    """kde_track_metrics: totals of the compression-quality measures."""
+    _fields_ = [("n_original", ctypes.c_int64), ("n_compressed", ctypes.c_int64), ("cr_percent", ctypes.c_double),
+                ("length_original", ctypes.c_double), ("length_compressed", ctypes.c_double),
+                ("rll", ctypes.c_double), ("dtw_mean", ctypes.c_double), ("dtw_std", ctypes.c_double)]
+
+
+def _track_set(xy, start, what):
+    import torch
+    if not (xy.is_cuda and xy.dtype == torch.float64 and xy.dim() == 2 and xy.shape[1] == 2 and xy.is_contiguous()):
+        raise ValueError(f"{what} points must be a contiguous CUDA float64 tensor of shape [n, 2]")
+    if not (start.is_cuda and start.dtype == torch.int64 and start.dim() == 1 and start.shape[0] >= 1
+            and start.is_contiguous()):
+        raise ValueError(f"{what} offsets must be a contiguous CUDA int64 tensor of length n_tracks + 1")
+
+
+def compression_metrics(xy_o, start_o, xy_c, start_c, per_track: bool = True) -> dict:
+    """Compression quality of tracks against their compressed versions on the
+    GPU (kde_compression_metrics, Sec. V-B): CR, RLL, and the mean and
+    population standard deviation of the per-track DTW distances.  xy_*: [n, 2]
+    float64 CUDA tensors; start_*: [n_tracks + 1] int64 CUDA offsets (e.g. the
+    xy and start of dp_compress).  With per_track the dict also holds the
+    per-track tensors len_o, len_c and dtw."""
+    import torch
+    _track_set(xy_o, start_o, "original")
+    _track_set(xy_c, start_c, "compressed")
+    nt = start_o.shape[0] - 1
+    if start_c.shape[0] - 1 != nt:
+        raise ValueError("both track sets must hold the same number of tracks")
+    dev = xy_o.device
+    lo = lc = dt = None
+    if per_track:
+        lo, lc, dt = (torch.empty(nt, dtype=torch.float64, device=dev) for _ in range(3))
+    tot = TrackMetrics()
+    with torch.cuda.device(dev):
+        _check(lib().kde_compression_metrics(xy_o.data_ptr() if xy_o.shape[0] else None, xy_o.shape[0],
+                                             start_o.data_ptr(), xy_c.data_ptr() if xy_c.shape[0] else None,
+                                             xy_c.shape[0], start_c.data_ptr(), nt,
+                                             lo.data_ptr() if per_track and nt else None,
+                                             lc.data_ptr() if per_track and nt else None,
+                                             dt.data_ptr() if per_track and nt else None, ctypes.byref(tot),
+                                             _stream(torch, dev)))
+    out = {name: getattr(tot, name) for name, _ in TrackMetrics._fields_}
+    if per_track:
+        out.update(len_o=lo, len_c=lc, dtw=dt)
+    return out
 
 
 def autotune(enabled: bool | None = None, force: int | None = None, load: str | None = None,

@@ -584,7 +584,8 @@ int kde_eval_binned(const float *points, int64_t n, const int32_t *labels, int32
 }
 
 int kde_dp_compress(const double *xy, int64_t n, const int64_t *track_start, int64_t n_tracks, double eps,
-                    uint8_t *keep, double *out_xy, int64_t *out_lengths, int64_t *n_kept, void *stream) {
+                    uint8_t *keep, double *out_xy, int64_t *out_lengths, int64_t *out_start, int64_t *n_kept,
+                    void *stream) {
     try {
         if (n < 0 || n >= kMaxPoints) return fail(KDE_EINVAL, "kde_dp_compress: n = %lld out of range", (long long)n);
         if (n_tracks < 0 || (n_tracks == 0 && n > 0) || n_tracks > n)
@@ -593,16 +594,21 @@ int kde_dp_compress(const double *xy, int64_t n, const int64_t *track_start, int
         if (!(std::isfinite(eps) && eps >= 0.0)) return fail(KDE_EINVAL, "kde_dp_compress: eps must be finite and >= 0");
         if (n > 0 && (xy == nullptr || track_start == nullptr || keep == nullptr))
             return fail(KDE_EINVAL, "kde_dp_compress: xy, track_start and keep are required");
-        if (n == 0) {
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (n == 0) {  // no tracks either
+            if (out_start != nullptr) {
+                hipError_t e = hipMemsetAsync(out_start, 0, sizeof(int64_t), s);
+                if (e == hipSuccess) e = hipStreamSynchronize(s);
+                if (e != hipSuccess) return hip_fail(e, "kde_dp_compress");
+            }
             if (n_kept) *n_kept = 0;
             return KDE_OK;
         }
-        hipStream_t s = static_cast<hipStream_t>(stream);
         void *ws = nullptr;
         int st = get_workspace(s, kde::dp_workspace_bytes(n), &ws);
         if (st != KDE_OK) return st;
         kde::DpArgs a{reinterpret_cast<const double2 *>(xy), n, track_start, n_tracks, eps, keep,
-                      reinterpret_cast<double2 *>(out_xy), out_lengths};
+                      reinterpret_cast<double2 *>(out_xy), out_lengths, out_start};
         int64_t kept = 0;
         hipError_t e = kde::run_dp(a, ws, s, &kept);
         if (e == hipErrorInvalidValue && kept < 0)
@@ -612,6 +618,51 @@ int kde_dp_compress(const double *xy, int64_t n, const int64_t *track_start, int
         return KDE_OK;
     } catch (...) {
         return fail(KDE_EHIP, "kde_dp_compress: internal error");
+    }
+}
+
+static_assert(sizeof(kde_track_metrics) == sizeof(kde::MetricsTotals), "kde_track_metrics layout");
+
+int kde_compression_metrics(const double *xy_o, int64_t n_o, const int64_t *start_o, const double *xy_c, int64_t n_c,
+                            const int64_t *start_c, int64_t n_tracks, double *len_o, double *len_c, double *dtw,
+                            kde_track_metrics *out, void *stream) {
+    ConsumeTimer consume_timer;
+    try {
+        if (n_o < 0 || n_o >= kMaxPoints || n_c < 0 || n_c >= kMaxPoints)
+            return fail(KDE_EINVAL, "kde_compression_metrics: n_o = %lld, n_c = %lld out of range", (long long)n_o,
+                        (long long)n_c);
+        if (n_tracks < 0 || n_tracks >= kMaxPoints)
+            return fail(KDE_EINVAL, "kde_compression_metrics: n_tracks = %lld out of range", (long long)n_tracks);
+        if (start_o == nullptr || start_c == nullptr)
+            return fail(KDE_EINVAL, "kde_compression_metrics: start_o and start_c are required");
+        if ((n_o > 0 && xy_o == nullptr) || (n_c > 0 && xy_c == nullptr))
+            return fail(KDE_EINVAL, "kde_compression_metrics: points are required");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const bool given = len_o != nullptr && len_c != nullptr && dtw != nullptr;
+        void *ws = nullptr;
+        int st = get_workspace(s, kde::metrics_workspace_bytes(n_o, n_c, n_tracks, given), &ws);
+        if (st != KDE_OK) return st;
+        kde::MetricsArgs a{reinterpret_cast<const double2 *>(xy_o), n_o, start_o, reinterpret_cast<const double2 *>(xy_c),
+                           n_c, start_c, n_tracks, len_o, len_c, dtw};
+        kde::MetricsTotals t{};
+        hipError_t e = kde::run_metrics(a, ws, s, out != nullptr ? &t : nullptr);
+        if (e == hipErrorInvalidValue)
+            return fail(KDE_EINVAL, "kde_compression_metrics: track offsets must rise from 0 to the point counts "
+                                    "without decreasing, tracks under 2^30 points");
+        if (e != hipSuccess) return hip_fail(e, "kde_compression_metrics");
+        if (out != nullptr) {
+            out->n_original = t.n_original;
+            out->n_compressed = t.n_compressed;
+            out->cr_percent = t.cr_percent;
+            out->length_original = t.length_original;
+            out->length_compressed = t.length_compressed;
+            out->rll = t.rll;
+            out->dtw_mean = t.dtw_mean;
+            out->dtw_std = t.dtw_std;
+        }
+        return KDE_OK;
+    } catch (...) {
+        return fail(KDE_EHIP, "kde_compression_metrics: internal error");
     }
 }
 

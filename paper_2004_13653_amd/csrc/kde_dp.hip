@@ -206,14 +206,22 @@ __global__ __launch_bounds__(256) void dp_compact_kernel(const double2 *__restri
     if (i < n && keep[i]) out[pos[i]] = xy[i];
 }
 
+// Kept points per track and the compressed tracks' offsets (pos of each track's
+// first point; the last offset is the total).
 __global__ __launch_bounds__(256) void dp_lengths_kernel(const int64_t *__restrict__ start, int64_t n_tracks,
                                                          const unsigned *__restrict__ pos, unsigned total,
-                                                         int64_t n, int64_t *__restrict__ lengths) {
+                                                         int64_t n, int64_t *__restrict__ lengths,
+                                                         int64_t *__restrict__ out_start) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_tracks) return;
+    if (t > n_tracks) return;
+    if (t == n_tracks) {
+        if (out_start != nullptr) out_start[t] = total;
+        return;
+    }
     const int64_t a = start[t], b = start[t + 1];
     const unsigned pa = a < n ? pos[a] : total, pb = b < n ? pos[b] : total;
-    lengths[t] = (int64_t)pb - (int64_t)pa;
+    if (lengths != nullptr) lengths[t] = (int64_t)pb - (int64_t)pa;
+    if (out_start != nullptr) out_start[t] = pa;
 }
 
 struct DpLayout {
@@ -309,9 +317,9 @@ hipError_t run_dp(const DpArgs &a, void *ws, hipStream_t s, int64_t *n_kept) {
     if (a.out_xy)
         hipLaunchKernelGGL(dp_compact_kernel, grid, block, 0, s, a.xy, a.n, static_cast<const uint8_t *>(a.keep),
                            static_cast<const unsigned *>(pos), a.out_xy);
-    if (a.out_lengths)
-        hipLaunchKernelGGL(dp_lengths_kernel, dim3((unsigned)((a.n_tracks + 255) / 256)), block, 0, s, a.start,
-                           a.n_tracks, static_cast<const unsigned *>(pos), total, a.n, a.out_lengths);
+    if (a.out_lengths || a.out_start)
+        hipLaunchKernelGGL(dp_lengths_kernel, dim3((unsigned)((a.n_tracks + 1 + 255) / 256)), block, 0, s, a.start,
+                           a.n_tracks, static_cast<const unsigned *>(pos), total, a.n, a.out_lengths, a.out_start);
     return hipGetLastError();
 }
 

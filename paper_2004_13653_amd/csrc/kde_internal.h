@@ -114,11 +114,36 @@ struct DpArgs {
     uint8_t *keep;          // [n] output
     double2 *out_xy;        // [n] compacted kept points, or nullptr
     int64_t *out_lengths;   // [n_tracks] kept points per track, or nullptr
+    int64_t *out_start;     // [n_tracks + 1] offsets of the compressed tracks, or nullptr
 };
 size_t dp_workspace_bytes(int64_t n);
 // Runs the level loop (synchronising `stream` once per group of levels) and
 // returns the number of kept points in *n_kept.
 hipError_t run_dp(const DpArgs &a, void *ws, hipStream_t stream, int64_t *n_kept);
+
+// Compression-quality measures (kde_metrics.hip): per track |T|, |T'| and the
+// DTW distance; totals over the set.  Same layout as the C ABI's
+// kde_track_metrics.
+struct MetricsTotals {
+    int64_t n_original, n_compressed;
+    double cr_percent, length_original, length_compressed, rll, dtw_mean, dtw_std;
+};
+constexpr int64_t kMaxTrackPoints = (int64_t)1 << 30;  // per track, either set
+struct MetricsArgs {
+    const double2 *xo;   // [n_o] original points
+    int64_t n_o;
+    const int64_t *so;   // [n_tracks + 1] original offsets (device)
+    const double2 *xc;   // [n_c] compressed points
+    int64_t n_c;
+    const int64_t *sc;   // [n_tracks + 1] compressed offsets (device)
+    int64_t n_tracks;
+    double *len_o, *len_c, *dtw;  // [n_tracks] each, or nullptr (then workspace)
+};
+size_t metrics_workspace_bytes(int64_t n_o, int64_t n_c, int64_t n_tracks, bool per_track_given);
+// Validates the offsets (one stream synchronisation; hipErrorInvalidValue if
+// they do not rise from 0 to n_o and n_c with tracks under kMaxTrackPoints),
+// then computes; with host_out the totals are copied back (synchronising).
+hipError_t run_metrics(const MetricsArgs &a, void *ws, hipStream_t stream, MetricsTotals *host_out);
 
 // Matrix-core separable path (precision kPrecFp16 .. kPrecBf16x3).  Compact
 // kernels (and the truncated Gaussian) whose support fits a 256-node tile run

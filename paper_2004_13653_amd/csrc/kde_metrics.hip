@@ -1,0 +1,292 @@
+// Compression quality of a track set against its compressed version (Sec. V-B)
+// on gfx950: per track the lengths |T| and |T'| (RLL, Eq. (15)) and the DTW
+// distance of Eq. (16)-(18); over the set CR (Eq. (14)), RLL, and the mean and
+// population standard deviation of the DTW distances (Eq. (19)-(20)).
+//
+// One wave per track.  DTW fills the accumulated cost matrix as an
+// anti-diagonal wavefront inside the wave: the shorter of the two series is
+// "owned" (lane l holds R consecutive entries of it, a strip of 64 R), the
+// longer one is swept; at step s lane l updates its R cells of swept column
+// j = s - l, so every cell's left neighbours are in the lane's own registers
+// and its upper neighbours come from lane l - 1's last row of the step before
+// (one cross-lane shift per step).  Swept points are staged 64 at a time into
+// an LDS ring of two chunks, each chunk loaded a whole chunk ahead.  Series
+// longer than one strip run several strips; the last row of each is handed to
+// the next through a per-track global buffer (two of them, by strip parity).
+//
+// The recurrence is symmetric under transposing the matrix (d is symmetric and
+// min is exact), so owning either series gives the same cells.  Squared
+// distances and sums are FP64 without fused multiply-add, so every D entry, and
+// the DTW distance before its square root, is bit-identical to a plain row-by-row
+// fill.  Per-track lengths are wave tree sums; set totals a fixed-order block
+// reduction: both deterministic.
+#include "kde_internal.h"
+
+#include <cmath>
+
+namespace kde {
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kReduceThreads = 1024;
+
+__device__ __forceinline__ double kInfD() { return __builtin_huge_val(); }
+
+// Butterfly sum over the wave; every lane ends with the same bits (each
+// pairwise add is commutative).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+__device__ __forceinline__ double sq_dist(double ax, double ay, double2 b) {
+#pragma clang fp contract(off)
+    const double dx = ax - b.x, dy = ay - b.y;
+    return dx * dx + dy * dy;
+}
+
+// Sum of |P_i P_{i+1}|: lane l takes i = l, l + 64, ... in order, then a wave sum.
+__device__ double polyline_length(const double2 *__restrict__ p, int n, int lane) {
+#pragma clang fp contract(off)
+    double s = 0.0;
+    for (int i = lane; i + 1 < n; i += kWave) {
+        const double2 a = p[i], b = p[i + 1];
+        const double dx = b.x - a.x, dy = b.y - a.y;
+        s += sqrt(dx * dx + dy * dy);
+    }
+    return wave_sum(s);
+}
+
+// D[na-1][nb-1] of the accumulated cost matrix between A (owned, na entries)
+// and B (swept, nb entries), both non-empty.  bound: 2 * nb doubles.  Returns
+// the value on every lane.
+template <int R>
+__device__ double dtw_wave(const double2 *__restrict__ A, int na, const double2 *__restrict__ B, int nb,
+                           double *__restrict__ bound, double2 *ring_b, double *ring_t, int lane) {
+#pragma clang fp contract(off)
+    constexpr int kStrip = kWave * R;
+    const double inf = kInfD();
+    const int strips = (na + kStrip - 1) / kStrip;
+    double result = 0.0;
+    for (int k = 0; k < strips; ++k) {
+        const int base = k * kStrip;
+        double ax[R], ay[R], left[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int idx = base + lane * R + r;
+            const double2 a = idx < na ? A[idx] : make_double2(0.0, 0.0);  // rows past na feed no valid cell
+            ax[r] = a.x;
+            ay[r] = a.y;
+            left[r] = inf;  // column -1
+        }
+        const bool last = k + 1 == strips;
+        const double *tin = k > 0 ? bound + ((k - 1) & 1) * (size_t)nb : nullptr;  // row base - 1
+        double *tout = last ? nullptr : bound + (k & 1) * (size_t)nb;             // row base + kStrip - 1
+        const int lanes_used = last ? (na - base + R - 1) / R : kWave;
+        const int owner = (na - 1 - base) / R, owner_r = (na - 1 - base) - owner * R;  // meaningful in the last strip
+        const int steps = nb + lanes_used - 1;
+        double bottom = inf;                                // last row of the previous step (inf before the start)
+        double diag = (k == 0 && lane == 0) ? 0.0 : inf;   // D[row0 - 1][j - 1]; D[-1][-1] = 0
+        // chunk c of the swept series (and of the row above the strip), one a lane
+        double2 nxt_b = lane < nb ? B[lane] : make_double2(0.0, 0.0);
+        double nxt_t = (tin != nullptr && lane < nb) ? tin[lane] : inf;
+        for (int s = 0; s < steps; ++s) {
+            if ((s & (kWave - 1)) == 0) {  // uniform
+                const int c = s / kWave;
+                __syncthreads();  // the slot's previous chunk (c - 2) is no longer read
+                ring_b[(c & 1) * kWave + lane] = nxt_b;
+                ring_t[(c & 1) * kWave + lane] = nxt_t;
+                __syncthreads();
+                const int jn = (c + 1) * kWave + lane;
+                nxt_b = jn < nb ? B[jn] : make_double2(0.0, 0.0);
+                nxt_t = (tin != nullptr && jn < nb) ? tin[jn] : inf;
+            }
+            // D[row0 - 1][j]: lane l - 1's last row of the previous step, or the row above the strip
+            const double from_above = __shfl_up(bottom, 1);
+            const double top = ring_t[s & (2 * kWave - 1)];  // used by lane 0 only (its column is s)
+            const double up_in = lane == 0 ? (s < nb ? top : inf) : from_above;
+            const int j = s - lane;
+            if (j >= 0 && j < nb) {
+                const double2 b = ring_b[j & (2 * kWave - 1)];
+                double up = up_in, dg = diag;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const double m = fmin(fmin(dg, up), left[r]);
+                    const double v = sq_dist(ax[r], ay[r], b) + m;
+                    dg = left[r];
+                    left[r] = v;
+                    up = v;
+                }
+                bottom = up;
+                if (tout != nullptr && lane == kWave - 1) tout[j] = bottom;
+                if (last && j == nb - 1 && lane == owner) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        if (r == owner_r) result = left[r];
+                }
+            }
+            diag = up_in;
+        }
+        __syncthreads();  // the strip's last row is visible to the next strip's loads
+    }
+    return __shfl(result, (na - 1 - (strips - 1) * kStrip) / R);
+}
+
+__global__ __launch_bounds__(kWave) void track_metrics_kernel(const double2 *__restrict__ xo,
+                                                              const int64_t *__restrict__ so,
+                                                              const double2 *__restrict__ xc,
+                                                              const int64_t *__restrict__ sc,
+                                                              double *__restrict__ bound, double *__restrict__ len_o,
+                                                              double *__restrict__ len_c, double *__restrict__ dtw) {
+    __shared__ double2 ring_b[2 * kWave];
+    __shared__ double ring_t[2 * kWave];
+    const int64_t m = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t o0 = so[m], c0 = sc[m];
+    const int no = (int)(so[m + 1] - o0), nc = (int)(sc[m + 1] - c0);
+    const double2 *O = xo + o0, *C = xc + c0;
+    const double lo = polyline_length(O, no, lane);
+    const double lc = polyline_length(C, nc, lane);
+    double d;
+    if (no == 0 || nc == 0) {
+        d = (no == 0 && nc == 0) ? 0.0 : kInfD();  // no warping path joins an empty series to a non-empty one
+    } else {
+        const bool own_c = nc <= no;
+        const double2 *A = own_c ? C : O, *B = own_c ? O : C;
+        const int na = own_c ? nc : no, nb = own_c ? no : nc;
+        double *bd = bound + 2 * (o0 + c0);  // 2 (no + nc) >= 2 nb doubles of this track
+        double D;
+        if (na <= kWave)
+            D = dtw_wave<1>(A, na, B, nb, bd, ring_b, ring_t, lane);
+        else if (na <= 2 * kWave)
+            D = dtw_wave<2>(A, na, B, nb, bd, ring_b, ring_t, lane);
+        else if (na <= 4 * kWave)
+            D = dtw_wave<4>(A, na, B, nb, bd, ring_b, ring_t, lane);
+        else
+            D = dtw_wave<8>(A, na, B, nb, bd, ring_b, ring_t, lane);
+        d = sqrt(D);
+    }
+    if (lane == 0) {
+        len_o[m] = lo;
+        len_c[m] = lc;
+        dtw[m] = d;
+    }
+}
+
+// Fixed-order block sum: strided per-thread partials, wave sums, then the 16
+// wave results added in wave order.  Every thread returns the total.
+__device__ double block_sum(double v, double *red) {
+    v = wave_sum(v);
+    const int w = threadIdx.x / kWave;
+    __syncthreads();  // red free from any previous use
+    if ((threadIdx.x & (kWave - 1)) == 0) red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < kReduceThreads / kWave; ++i) t += red[i];
+    return t;
+}
+
+__global__ __launch_bounds__(kReduceThreads) void metrics_reduce_kernel(const double *__restrict__ len_o,
+                                                                        const double *__restrict__ len_c,
+                                                                        const double *__restrict__ dtw, int64_t m,
+                                                                        const int64_t *__restrict__ so,
+                                                                        const int64_t *__restrict__ sc,
+                                                                        MetricsTotals *__restrict__ out) {
+#pragma clang fp contract(off)
+    __shared__ double red[kReduceThreads / kWave];
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int64_t i = threadIdx.x; i < m; i += kReduceThreads) {
+        a += len_o[i];
+        b += len_c[i];
+        c += dtw[i];
+    }
+    const double lo = block_sum(a, red), lc = block_sum(b, red), sd = block_sum(c, red);
+    const double nan = __builtin_nan("");
+    const double mu = m > 0 ? sd / (double)m : nan;
+    double q = 0.0;
+    for (int64_t i = threadIdx.x; i < m; i += kReduceThreads) {
+        const double e = dtw[i] - mu;
+        q += e * e;
+    }
+    const double sq = block_sum(q, red);
+    if (threadIdx.x == 0) {
+        const int64_t no = so[m], nc = sc[m];
+        out->n_original = no;
+        out->n_compressed = nc;
+        out->cr_percent = no > 0 ? (1.0 - (double)nc / (double)no) * 100.0 : nan;
+        out->length_original = lo;
+        out->length_compressed = lc;
+        out->rll = lo != 0.0 ? (lo - lc) / lo : nan;
+        out->dtw_mean = mu;
+        out->dtw_std = m > 0 ? sqrt(sq / (double)m) : nan;
+    }
+}
+
+// bad = 1 unless both offset arrays rise from 0 to their point counts.
+__global__ __launch_bounds__(256) void metrics_check_kernel(const int64_t *__restrict__ so, int64_t n_o,
+                                                            const int64_t *__restrict__ sc, int64_t n_c, int64_t m,
+                                                            unsigned *__restrict__ bad) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > m) return;
+    bool ok = true;
+    if (t == 0) ok = so[0] == 0 && sc[0] == 0;
+    if (t == m) ok = ok && so[m] == n_o && sc[m] == n_c;
+    if (t < m) ok = ok && so[t] <= so[t + 1] && sc[t] <= sc[t + 1] && so[t + 1] - so[t] < kMaxTrackPoints &&
+                    sc[t + 1] - sc[t] < kMaxTrackPoints;
+    if (!ok) atomicOr(bad, 1u);
+}
+
+__global__ void zero_flag_kernel(unsigned *flag) {
+    if (threadIdx.x == 0) *flag = 0u;
+}
+
+size_t al256(size_t x) { return (x + 255) / 256 * 256; }
+
+}  // namespace
+
+size_t metrics_workspace_bytes(int64_t n_o, int64_t n_c, int64_t n_tracks, bool per_track_given) {
+    size_t b = al256(sizeof(MetricsTotals)) + 256 + al256((size_t)2 * (n_o + n_c) * sizeof(double));
+    if (!per_track_given) b += 3 * al256((size_t)n_tracks * sizeof(double));
+    return b;
+}
+
+hipError_t run_metrics(const MetricsArgs &a, void *ws, hipStream_t s, MetricsTotals *host_out) {
+    char *w = static_cast<char *>(ws);
+    MetricsTotals *tot = reinterpret_cast<MetricsTotals *>(w);
+    w += al256(sizeof(MetricsTotals));
+    unsigned *bad = reinterpret_cast<unsigned *>(w);
+    w += 256;
+    double *bound = reinterpret_cast<double *>(w);
+    w += al256((size_t)2 * (a.n_o + a.n_c) * sizeof(double));
+    double *lo = a.len_o, *lc = a.len_c, *dt = a.dtw;
+    const size_t per = al256((size_t)a.n_tracks * sizeof(double));
+    if (lo == nullptr) { lo = reinterpret_cast<double *>(w); w += per; }
+    if (lc == nullptr) { lc = reinterpret_cast<double *>(w); w += per; }
+    if (dt == nullptr) { dt = reinterpret_cast<double *>(w); w += per; }
+    hipLaunchKernelGGL(zero_flag_kernel, dim3(1), dim3(64), 0, s, bad);
+    hipLaunchKernelGGL(metrics_check_kernel, dim3((unsigned)((a.n_tracks + 1 + 255) / 256)), dim3(256), 0, s, a.so,
+                       a.n_o, a.sc, a.n_c, a.n_tracks, bad);
+    unsigned flag = 0;
+    hipError_t e = hipMemcpyAsync(&flag, bad, sizeof flag, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    if (flag) return hipErrorInvalidValue;
+    if (a.n_tracks > 0) {
+        main_kernel_begin(s);
+        hipLaunchKernelGGL(track_metrics_kernel, dim3((unsigned)a.n_tracks), dim3(kWave), 0, s, a.xo, a.so, a.xc,
+                           a.sc, bound, lo, lc, dt);
+        main_kernel_end(s);
+    }
+    hipLaunchKernelGGL(metrics_reduce_kernel, dim3(1), dim3(kReduceThreads), 0, s, static_cast<const double *>(lo),
+                       static_cast<const double *>(lc), static_cast<const double *>(dt), a.n_tracks, a.so, a.sc, tot);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (host_out != nullptr) {
+        e = hipMemcpyAsync(host_out, tot, sizeof(MetricsTotals), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+    return e;
+}
+
+}  // namespace kde

@@ -150,14 +150,27 @@ def test_truncate_flag_validation():
 def test_dp_entry_point_validates():
     L = kde.lib()
     n = ctypes.c_int64()
-    assert L.kde_dp_compress(FAKE, -1, FAKE, 1, 1.0, FAKE, None, None, None, None) == kde.KDE_EINVAL
-    assert L.kde_dp_compress(FAKE, 10, FAKE, 0, 1.0, FAKE, None, None, None, None) == kde.KDE_EINVAL
-    assert L.kde_dp_compress(FAKE, 10, FAKE, 11, 1.0, FAKE, None, None, None, None) == kde.KDE_EINVAL
-    assert L.kde_dp_compress(FAKE, 10, FAKE, 2, -1.0, FAKE, None, None, None, None) == kde.KDE_EINVAL
-    assert L.kde_dp_compress(FAKE, 10, FAKE, 2, float("nan"), FAKE, None, None, None, None) == kde.KDE_EINVAL
-    assert L.kde_dp_compress(None, 10, FAKE, 2, 1.0, FAKE, None, None, None, None) == kde.KDE_EINVAL
-    assert L.kde_dp_compress(None, 0, None, 0, 1.0, None, None, None, ctypes.byref(n), None) == kde.KDE_OK
+    assert L.kde_dp_compress(FAKE, -1, FAKE, 1, 1.0, FAKE, None, None, None, None, None) == kde.KDE_EINVAL
+    assert L.kde_dp_compress(FAKE, 10, FAKE, 0, 1.0, FAKE, None, None, None, None, None) == kde.KDE_EINVAL
+    assert L.kde_dp_compress(FAKE, 10, FAKE, 11, 1.0, FAKE, None, None, None, None, None) == kde.KDE_EINVAL
+    assert L.kde_dp_compress(FAKE, 10, FAKE, 2, -1.0, FAKE, None, None, None, None, None) == kde.KDE_EINVAL
+    assert L.kde_dp_compress(FAKE, 10, FAKE, 2, float("nan"), FAKE, None, None, None, None, None) == kde.KDE_EINVAL
+    assert L.kde_dp_compress(None, 10, FAKE, 2, 1.0, FAKE, None, None, None, None, None) == kde.KDE_EINVAL
+    assert L.kde_dp_compress(None, 0, None, 0, 1.0, None, None, None, None, ctypes.byref(n), None) == kde.KDE_OK
     assert n.value == 0
+
+
+def test_metrics_entry_point_validates():
+    L = kde.lib()
+    f = L.kde_compression_metrics
+    assert f(FAKE, -1, FAKE, FAKE, 0, FAKE, 1, None, None, None, None, None) == kde.KDE_EINVAL
+    assert f(FAKE, 10, FAKE, FAKE, -1, FAKE, 1, None, None, None, None, None) == kde.KDE_EINVAL
+    assert f(FAKE, 10, FAKE, FAKE, 10, FAKE, -1, None, None, None, None, None) == kde.KDE_EINVAL
+    assert f(FAKE, 10, None, FAKE, 10, FAKE, 1, None, None, None, None, None) == kde.KDE_EINVAL
+    assert f(FAKE, 10, FAKE, FAKE, 10, None, 1, None, None, None, None, None) == kde.KDE_EINVAL
+    assert f(None, 10, FAKE, FAKE, 10, FAKE, 1, None, None, None, None, None) == kde.KDE_EINVAL
+    assert f(FAKE, 10, FAKE, None, 10, FAKE, 1, None, None, None, None, None) == kde.KDE_EINVAL
+    assert "kde_compression_metrics" in L.kde_last_error().decode()
 
 
 def test_binned_entry_points_validate():

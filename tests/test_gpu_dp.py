@@ -17,9 +17,12 @@ def _run(xy, lengths, eps):
     start = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
     x = torch.from_numpy(np.ascontiguousarray(xy, dtype=np.float64)).to(kt.device())
     st = torch.from_numpy(start).to(kt.device())
-    keep, out, lens = kde.dp_compress(x, st, eps)
+    keep, out, lens, cst = kde.dp_compress(x, st, eps)
     torch.cuda.synchronize()
-    return keep.cpu().numpy(), out.cpu().numpy(), lens.cpu().numpy()
+    lens = lens.cpu().numpy()
+    # the compressed tracks' offsets are the running sums of their lengths
+    np.testing.assert_array_equal(cst.cpu().numpy(), np.concatenate([[0], np.cumsum(lens)]))
+    return keep.cpu().numpy(), out.cpu().numpy(), lens
 
 
 def _check(xy, lengths, eps):
