@@ -275,6 +275,57 @@ def dp_cpu_baseline(synth, t, eps: float = 50.0):
             "kept": int(keep.sum())}
 
 
+DTW_OPS_PER_CELL = 8  # FP64: 2 differences, 2 squares, 1 add (the distance), 2 min, 1 add
+PEAK_FP64_OPS = 256 * 64 * 2.4e9  # FP64 VALU lane-operations per second (78.6 TFLOP/s counts an FMA twice)
+
+
+def bench_metrics(torch, kde, synth, t, steps: int):
+    """Compression quality of the bench's 8,000 tracks against their GPU
+    Douglas-Peucker output at eps = 10, 50, 100 m (the workflow of Table IV):
+    CR, RLL, DTW mean and population std.  Times the whole call and the
+    per-track length + DTW kernel alone; the DTW work is the sum over tracks of
+    N_o x N_c accumulated-cost cells, 8 FP64 operations each."""
+    import numpy as np
+    mx, my = synth.mercator(t.xy[:, 0], t.xy[:, 1], t.box.center_lat)
+    xy = torch.from_numpy(np.column_stack([mx, my])).cuda()
+    start = torch.from_numpy(np.concatenate([[0], np.cumsum(t.lengths)]).astype(np.int64)).cuda()
+    res = {"points": int(t.n), "tracks": int(len(t.lengths))}
+    for eps in (10.0, 50.0, 100.0):
+        _, out, lens, cst = kde.dp_compress(xy, start, eps)
+        cells = float(np.sum(t.lengths.astype(np.float64) * lens.cpu().numpy().astype(np.float64)))
+        tot, _, kern = timed_steps(torch, lambda: kde.compression_metrics(xy, start, out, cst, per_track=False),
+                                   steps, 1, kde)
+        r = kde.compression_metrics(xy, start, out, cst, per_track=False)
+        k_ms = sum(kern) / len(kern)
+        ops = cells * DTW_OPS_PER_CELL / (k_ms * 1e-3)
+        res[f"eps_{eps:g}m"] = {"ms": tot / steps, "kernel_ms": k_ms, "dtw_cells": cells,
+                                "cells_per_s": cells / (k_ms * 1e-3), "fp64_ops_per_s": ops,
+                                "alu_frac": ops / PEAK_FP64_OPS, "cr_percent": r["cr_percent"], "rll": r["rll"],
+                                "dtw_mean": r["dtw_mean"], "dtw_std": r["dtw_std"]}
+    log("metrics: " + ", ".join(f"{k} {v['ms']:.3f} ms (kernel {v['kernel_ms']:.3f} ms, "
+                                f"{v['alu_frac'] * 100:.1f} % of FP64 issue; DTW {v['dtw_mean']:.2f} +- "
+                                f"{v['dtw_std']:.2f} m)" for k, v in res.items() if isinstance(v, dict)))
+    return res
+
+
+def metrics_cpu_baseline(synth, t, eps: float = 50.0):
+    """The oracle's metrics (per-track lengths and DTW, OpenMP over tracks) on
+    the same tracks against the oracle's Douglas-Peucker output."""
+    import numpy as np
+
+    import oracle
+    mx, my = synth.mercator(t.xy[:, 0], t.xy[:, 1], t.box.center_lat)
+    xy = np.column_stack([mx, my])
+    keep = oracle.dp_keep(xy, t.lengths, eps).astype(bool)
+    lc = np.add.reduceat(keep.astype(np.int64), np.concatenate([[0], np.cumsum(t.lengths)[:-1]]))
+    t0 = time.perf_counter()
+    r = oracle.track_metrics(xy, t.lengths, xy[keep], lc)
+    dt = time.perf_counter() - t0
+    cells = float(np.sum(t.lengths.astype(np.float64) * lc))
+    return {"eps_m": eps, "ms": dt * 1e3, "cells_per_s": cells / dt, "cores": oracle.num_threads(),
+            "kind": "oracle", "dtw_mean": r["dtw_mean"]}
+
+
 def bench_compact(torch, kde, synth, steps: int):
     """The eight kernels on the FP32 direct path: 1,000,000 points (2,000 tracks x
     500) on 1024 x 1024, h = 0.002 degrees."""
@@ -303,9 +354,9 @@ def main() -> int:
     ap.add_argument("--profile-once", action="store_true",
                     help="for counter runs: two FP16 maps and one FP32 direct map, then a 256 MiB "
                          "elementwise copy (torch.neg) as the byte-count calibration; prints no JSON")
-    ap.add_argument("--sections", default="adjoint,batched,kernels,binned,truncated,dp",
+    ap.add_argument("--sections", default="adjoint,batched,kernels,binned,truncated,dp,metrics",
                     help="extra measured sections beside the headline: adjoint, batched, kernels, binned, "
-                         "truncated, dp (or none)")
+                         "truncated, dp, metrics (or none)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the KDE map runs on a single MI355X here "
@@ -396,6 +447,8 @@ def main() -> int:
         line["fp32_direct_kernels"] = bench_compact(torch, kde, synth, 5)
     if "dp" in extra:
         line["dp"] = bench_dp(torch, kde, synth, t, 5)
+    if "metrics" in extra:
+        line["metrics"] = bench_metrics(torch, kde, synth, t, 5)
     if "truncated" in extra:
         line["truncated"] = bench_truncated(torch, kde, pts, g, maps, 10)
     if "binned" in extra:
@@ -409,6 +462,10 @@ def main() -> int:
         if "dp" in extra:
             line["dp"]["cpu_baseline"] = dp_cpu_baseline(synth, t)
             line["dp"]["speedup_vs_cpu_eps_50m"] = line["dp"]["cpu_baseline"]["ms"] / line["dp"]["eps_50m"]["ms"]
+        if "metrics" in extra:
+            line["metrics"]["cpu_baseline"] = metrics_cpu_baseline(synth, t)
+            line["metrics"]["speedup_vs_cpu_eps_50m"] = (line["metrics"]["cpu_baseline"]["ms"]
+                                                        / line["metrics"]["eps_50m"]["ms"])
         line["error_vs_fp64"] = {"sampled_e_inf": errs, "peak_crop": {"window": list(win), **crop}}
     print(json.dumps(line), flush=True)
     return 0

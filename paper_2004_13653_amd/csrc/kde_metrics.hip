@@ -4,15 +4,16 @@
 // population standard deviation of the DTW distances (Eq. (19)-(20)).
 //
 // One wave per track.  DTW fills the accumulated cost matrix as an
-// anti-diagonal wavefront inside the wave: the shorter of the two series is
-// "owned" (lane l holds R consecutive entries of it, a strip of 64 R), the
-// longer one is swept; at step s lane l updates its R cells of swept column
-// j = s - l, so every cell's left neighbours are in the lane's own registers
-// and its upper neighbours come from lane l - 1's last row of the step before
-// (one cross-lane shift per step).  Swept points are staged 64 at a time into
-// an LDS ring of two chunks, each chunk loaded a whole chunk ahead.  Series
-// longer than one strip run several strips; the last row of each is handed to
-// the next through a per-track global buffer (two of them, by strip parity).
+// anti-diagonal wavefront inside the wave: one series is "owned" (lane l holds
+// R consecutive entries of it, a strip of 64 R), the other is swept; at step s
+// lane l updates its R cells of swept column j = s - l, so every cell's left
+// neighbours are in the lane's own registers and its upper neighbours come
+// from lane l - 1's last row of the step before (one DPP lane shift per
+// step).  Which series is owned, and R (1 to 8), are chosen per track to
+// minimise lane-steps.  Swept points are staged 64 at a time into an LDS ring
+// of two chunks, each chunk loaded a whole chunk ahead.  Series longer than
+// one strip run several strips; the last row of each is handed to the next
+// through a per-track global buffer (two of them, by strip parity).
 //
 // The recurrence is symmetric under transposing the matrix (d is symmetric and
 // min is exact), so owning either series gives the same cells.  Squared
@@ -30,6 +31,8 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kReduceThreads = 1024;
+constexpr int kMaxBlock = 8;     // register block (owned entries per lane) at most
+constexpr double kStepCost = 2.0; // per-step shifts, loads and bookkeeping, in cells (measured)
 
 __device__ __forceinline__ double kInfD() { return __builtin_huge_val(); }
 
@@ -59,9 +62,33 @@ __device__ double polyline_length(const double2 *__restrict__ p, int n, int lane
     return wave_sum(s);
 }
 
+// min of two FP64 values known to be non-NaN.  (The compiler's fmin quiets
+// signalling NaNs first, one extra v_max_f64 per operand it cannot prove
+// canonical; accumulated costs are sums of squares or +inf.)
+__device__ __forceinline__ double dmin(double a, double b) {
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+// Lane l receives lane l - 1's v, lane 0 receives fill (a DPP whole-wave shift
+// right by one lane: two 32-bit moves, no LDS traffic).
+__device__ __forceinline__ double shift_up_or(double v, double fill) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(fill), __double2loint(v), 0x138, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(fill), __double2hiint(v), 0x138, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
 // D[na-1][nb-1] of the accumulated cost matrix between A (owned, na entries)
 // and B (swept, nb entries), both non-empty.  bound: 2 * nb doubles.  Returns
 // the value on every lane.
+//
+// No lane is masked inside the sweep: before its first column a lane reads the
+// swept point (+inf, +inf) (the LDS slot of chunk -1), so every cell it
+// computes is +inf, the border value; past its last column it computes cells no
+// valid cell depends on.  The sweep of the last strip ends on the step where
+// the lane holding row na - 1 finishes column nb - 1, so that lane's register
+// then holds the result.
 template <int R>
 __device__ double dtw_wave(const double2 *__restrict__ A, int na, const double2 *__restrict__ B, int nb,
                            double *__restrict__ bound, double2 *ring_b, double *ring_t, int lane) {
@@ -85,53 +112,84 @@ __device__ double dtw_wave(const double2 *__restrict__ A, int na, const double2 
         const double *tin = k > 0 ? bound + ((k - 1) & 1) * (size_t)nb : nullptr;  // row base - 1
         double *tout = last ? nullptr : bound + (k & 1) * (size_t)nb;             // row base + kStrip - 1
         const int lanes_used = last ? (na - base + R - 1) / R : kWave;
-        const int owner = (na - 1 - base) / R, owner_r = (na - 1 - base) - owner * R;  // meaningful in the last strip
         const int steps = nb + lanes_used - 1;
         double bottom = inf;                                // last row of the previous step (inf before the start)
         double diag = (k == 0 && lane == 0) ? 0.0 : inf;   // D[row0 - 1][j - 1]; D[-1][-1] = 0
+        __syncthreads();  // the previous strip no longer reads the ring
+        ring_b[kWave + lane] = make_double2(inf, inf);  // chunk -1: columns before the first
         // chunk c of the swept series (and of the row above the strip), one a lane
         double2 nxt_b = lane < nb ? B[lane] : make_double2(0.0, 0.0);
         double nxt_t = (tin != nullptr && lane < nb) ? tin[lane] : inf;
-        for (int s = 0; s < steps; ++s) {
-            if ((s & (kWave - 1)) == 0) {  // uniform
-                const int c = s / kWave;
-                __syncthreads();  // the slot's previous chunk (c - 2) is no longer read
-                ring_b[(c & 1) * kWave + lane] = nxt_b;
-                ring_t[(c & 1) * kWave + lane] = nxt_t;
-                __syncthreads();
-                const int jn = (c + 1) * kWave + lane;
-                nxt_b = jn < nb ? B[jn] : make_double2(0.0, 0.0);
-                nxt_t = (tin != nullptr && jn < nb) ? tin[jn] : inf;
-            }
-            // D[row0 - 1][j]: lane l - 1's last row of the previous step, or the row above the strip
-            const double from_above = __shfl_up(bottom, 1);
-            const double top = ring_t[s & (2 * kWave - 1)];  // used by lane 0 only (its column is s)
-            const double up_in = lane == 0 ? (s < nb ? top : inf) : from_above;
-            const int j = s - lane;
-            if (j >= 0 && j < nb) {
+        for (int c = 0; c * kWave < steps; ++c) {  // chunk c: steps 64 c .. 64 c + 63
+            __syncthreads();  // the slot's previous chunk (c - 2) is no longer read
+            ring_b[(c & 1) * kWave + lane] = nxt_b;
+            ring_t[(c & 1) * kWave + lane] = nxt_t;
+            __syncthreads();
+            const int jn = (c + 1) * kWave + lane;
+            nxt_b = jn < nb ? B[jn] : make_double2(0.0, 0.0);
+            nxt_t = (tin != nullptr && jn < nb) ? tin[jn] : inf;
+            const int s_end = min(steps, (c + 1) * kWave);
+            for (int s = c * kWave; s < s_end; ++s) {
+                // D[row0 - 1][j]: lane l - 1's last row of the previous step; for
+                // lane 0 (column s) the row above the strip
+                const double up_in = shift_up_or(bottom, ring_t[s & (2 * kWave - 1)]);
+                const int j = s - lane;
                 const double2 b = ring_b[j & (2 * kWave - 1)];
-                double up = up_in, dg = diag;
+                // cell r takes min(D[r-1][j-1], D[r][j-1]) (old registers, off the
+                // dependency chain), then min with D[r-1][j] and the distance;
+                // each new value overwrites its row's register once the next
+                // row's first min has read the old one.
+                double t = dmin(diag, left[0]), up = up_in;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const double m = fmin(fmin(dg, up), left[r]);
-                    const double v = sq_dist(ax[r], ay[r], b) + m;
-                    dg = left[r];
-                    left[r] = v;
-                    up = v;
+                    const double t_next = r + 1 < R ? dmin(left[r], left[r + 1]) : 0.0;
+                    left[r] = sq_dist(ax[r], ay[r], b) + dmin(t, up);
+                    up = left[r];
+                    t = t_next;
                 }
                 bottom = up;
-                if (tout != nullptr && lane == kWave - 1) tout[j] = bottom;
-                if (last && j == nb - 1 && lane == owner) {
-#pragma unroll
-                    for (int r = 0; r < R; ++r)
-                        if (r == owner_r) result = left[r];
-                }
+                if (tout != nullptr && lane == kWave - 1 && j >= 0) tout[j] = bottom;  // j < nb: s < nb + 63
+                diag = up_in;
             }
-            diag = up_in;
+        }
+        if (last) {
+            const int owner_r = (na - 1 - base) - (lanes_used - 1) * R;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (r == owner_r) result = left[r];
         }
         __syncthreads();  // the strip's last row is visible to the next strip's loads
     }
     return __shfl(result, (na - 1 - (strips - 1) * kStrip) / R);
+}
+
+// Lane-steps of a sweep owning na entries with register block R, swept over
+// nb; each step costs R cells plus about kStepCost cells' worth of shifts,
+// loads and bookkeeping.
+__device__ __forceinline__ double sweep_cost(int na, int nb, int R) {
+    const int strip = kWave * R, strips = (na + strip - 1) / strip;
+    const int last_lanes = (na - (strips - 1) * strip + R - 1) / R;
+    const double steps = (double)(strips - 1) * (nb + kWave - 1) + (nb + last_lanes - 1);
+    return steps * (R + kStepCost);
+}
+
+// Cheapest orientation and register block for a pair of series of lengths
+// no and nc: returns R, and own_c = whether the compressed series is owned.
+__device__ __forceinline__ int pick_block(int no, int nc, bool *own_c) {
+    int best = 0;
+    double best_cost = 0.0;
+    for (int o = 0; o < 2; ++o) {
+        const int na = o ? nc : no, nb = o ? no : nc;
+        for (int R = 1; R <= kMaxBlock; ++R) {
+            const double cost = sweep_cost(na, nb, R);
+            if (best == 0 || cost < best_cost) {
+                best = R;
+                best_cost = cost;
+                *own_c = o != 0;
+            }
+        }
+    }
+    return best;
 }
 
 __global__ __launch_bounds__(kWave) void track_metrics_kernel(const double2 *__restrict__ xo,
@@ -153,19 +211,22 @@ __global__ __launch_bounds__(kWave) void track_metrics_kernel(const double2 *__r
     if (no == 0 || nc == 0) {
         d = (no == 0 && nc == 0) ? 0.0 : kInfD();  // no warping path joins an empty series to a non-empty one
     } else {
-        const bool own_c = nc <= no;
+        bool own_c = false;
+        const int R = pick_block(no, nc, &own_c);
         const double2 *A = own_c ? C : O, *B = own_c ? O : C;
         const int na = own_c ? nc : no, nb = own_c ? no : nc;
         double *bd = bound + 2 * (o0 + c0);  // 2 (no + nc) >= 2 nb doubles of this track
         double D;
-        if (na <= kWave)
-            D = dtw_wave<1>(A, na, B, nb, bd, ring_b, ring_t, lane);
-        else if (na <= 2 * kWave)
-            D = dtw_wave<2>(A, na, B, nb, bd, ring_b, ring_t, lane);
-        else if (na <= 4 * kWave)
-            D = dtw_wave<4>(A, na, B, nb, bd, ring_b, ring_t, lane);
-        else
-            D = dtw_wave<8>(A, na, B, nb, bd, ring_b, ring_t, lane);
+        switch (R) {
+        case 1: D = dtw_wave<1>(A, na, B, nb, bd, ring_b, ring_t, lane); break;
+        case 2: D = dtw_wave<2>(A, na, B, nb, bd, ring_b, ring_t, lane); break;
+        case 3: D = dtw_wave<3>(A, na, B, nb, bd, ring_b, ring_t, lane); break;
+        case 4: D = dtw_wave<4>(A, na, B, nb, bd, ring_b, ring_t, lane); break;
+        case 5: D = dtw_wave<5>(A, na, B, nb, bd, ring_b, ring_t, lane); break;
+        case 6: D = dtw_wave<6>(A, na, B, nb, bd, ring_b, ring_t, lane); break;
+        case 7: D = dtw_wave<7>(A, na, B, nb, bd, ring_b, ring_t, lane); break;
+        default: D = dtw_wave<8>(A, na, B, nb, bd, ring_b, ring_t, lane); break;
+        }
         d = sqrt(D);
     }
     if (lane == 0) {
