@@ -120,7 +120,7 @@ def dk(kernel: int, u) -> np.ndarray:
 
 
 def kbar(kernel: int, u) -> np.ndarray:
-    """Autoconvolution (k * k)(u); Gaussian and Epanechnikov only."""
+    """Autoconvolution (k * k)(u) of a Table I factor."""
     return _apply("ko_kbar_array", kernel, u)
 
 

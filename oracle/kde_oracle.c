@@ -108,10 +108,63 @@ double ko_dk(int kernel, double u)
     }
 }
 
+/* 16-point Gauss-Legendre rule on [-1, 1], computed once at load time by Newton
+ * iteration on the Legendre polynomial P_16 (three-term recurrence).  It
+ * integrates polynomials up to degree 31 exactly. */
+#define KO_GL 16
+static double gl_x[KO_GL], gl_w[KO_GL];
+
+__attribute__((constructor)) static void gl_init(void)
+{
+    for (int i = 0; i < KO_GL; ++i) {
+        double x = cos(PI * (i + 0.75) / (KO_GL + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = x;
+            for (int k = 2; k <= KO_GL; ++k) {
+                double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = KO_GL * (x * p1 - p0) / (x * x - 1.0);
+            double dx = p1 / dp;
+            x -= dx;
+            if (fabs(dx) < 1e-16) break;
+        }
+        gl_x[i] = x;
+        gl_w[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+    }
+}
+
+/* Integral over u in [lo, hi] of k(u) k(a - u) (deriv = 0) or k(u) k'(a - u). */
+static double conv_piece(int kernel, double a, double lo, double hi, int deriv)
+{
+    double c = 0.5 * (hi + lo), h = 0.5 * (hi - lo), s = 0.0;
+    for (int i = 0; i < KO_GL; ++i) {
+        double u = c + h * gl_x[i];
+        s += gl_w[i] * ko_k(kernel, u) * (deriv ? ko_dk(kernel, a - u) : ko_k(kernel, a - u));
+    }
+    return s * h;
+}
+
+/* For a compact kernel and 0 <= a < 2: the integral of k(u) k(a - u) over the
+ * overlap [a - 1, 1] of the two supports, split where |u| or |a - u| has a
+ * kink (u = 0, u = a), each piece by Gauss-Legendre.  The factors are
+ * polynomials of degree <= 9 on every piece (cosine: smooth), so the rule is
+ * exact up to rounding (cosine: to far below it). */
+static double conv_compact(int kernel, double a, int deriv)
+{
+    if (a >= 1.0) return conv_piece(kernel, a, a - 1.0, 1.0, deriv);
+    return conv_piece(kernel, a, a - 1.0, 0.0, deriv) + conv_piece(kernel, a, 0.0, a, deriv) +
+           conv_piece(kernel, a, a, 1.0, deriv);
+}
+
 /* Autoconvolution kbar = k * k (the integral of k(v) k(u - v) dv) and its
- * derivative, for the kernels whose LSCV the oracle supports: Gaussian
- * (kbar is the N(0, 2) density) and Epanechnikov (piecewise polynomial on
- * |u| <= 2).  Returns NAN for other kernels. */
+ * derivative.  Gaussian: kbar is the N(0, 2) density.  Epanechnikov: its
+ * piecewise polynomial on |u| <= 2.  The other Table I kernels: the defining
+ * integral itself, by the quadrature above (kbar is even, zero for |u| >= 2).
+ * The derivative of the integral over [u - 1, 1] is, by Leibniz's rule,
+ * -k(u - 1) k(1) (the moving lower end; non-zero only for the uniform kernel,
+ * whose factor jumps at the support's edge) plus the integral of k(v) k'(u - v). */
 double ko_kbar(int kernel, double u)
 {
     double a = fabs(u);
@@ -121,7 +174,9 @@ double ko_kbar(int kernel, double u)
         double b = 2.0 - a;
         return (3.0 / 160.0) * b * b * b * (a * a + 6.0 * a + 4.0);
     }
-    return NAN;
+    if (kernel < KO_UNIFORM || kernel > KO_COSINE) return NAN;
+    if (a >= 2.0) return 0.0;
+    return conv_compact(kernel, a, 0);
 }
 
 double ko_dkbar(int kernel, double u)
@@ -133,7 +188,10 @@ double ko_dkbar(int kernel, double u)
         double b = 2.0 - a;
         return -(3.0 / 32.0) * u * (a + 4.0) * b * b;
     }
-    return NAN;
+    if (kernel < KO_UNIFORM || kernel > KO_COSINE) return NAN;
+    if (a >= 2.0) return 0.0;
+    double d = -ko_k(kernel, a - 1.0) * ko_k(kernel, 1.0) + conv_compact(kernel, a, 1);
+    return u < 0.0 ? -d : d;
 }
 
 void ko_k_array(int kernel, const double *u, int64_t n, double *out)
@@ -277,8 +335,8 @@ void ko_vjp_units(const float *XY, int64_t n, int kernel, float Hx, float Hy,
  *   B = 2/(n (n-1) hx hy)    * sum_{p != q}  k(dx_pq/hx)    k(dy_pq/hy)      (leave-one-out term)
  * with dx_pq = x_p - x_q.  grad[2] = (dLSCV/dhx, dLSCV/dhy) uses
  *   d/dh [g(a/h)/h] = -(g(u) + u g'(u)) / h^2,  u = a/h.
- * The pair sums run q fastest inside p, p in order.  Supported kernels:
- * Gaussian and Epanechnikov; returns NAN otherwise. */
+ * The pair sums run q fastest inside p, p in order.  Every Table I kernel
+ * (kbar as above). */
 void ko_lscv_world(const double *xy, int64_t n, int kernel, double hx, double hy,
                    double *value, double *grad)
 {
