@@ -180,7 +180,11 @@ int kde_backward(const float *points, int64_t n, int32_t kernel_id, double hx, d
  *   LSCV = 1/(n^2 hx hy) sum_{p,q} kbar(dx_pq/hx) kbar(dy_pq/hy)
  *        - 2/(n(n-1) hx hy) sum_{p!=q} k(dx_pq/hx) k(dy_pq/hy),   kbar = k * k,
  * and its gradient with respect to (hx, hy).  points as for kde_eval (the grid
- * only fixes the units), n >= 2, kernel KDE_GAUSSIAN or KDE_EPANECHNIKOV.
+ * only fixes the units), n >= 2, any Table I kernel (kbar: the Gaussian's is the
+ * N(0, 2) density, the others' piecewise polynomials on |u| < 2, the cosine's
+ * a closed form).  The derivative of k is taken from its formula inside the
+ * support (the uniform kernel's jumps at the support edge contribute nothing).
+ * Per pair FP32; sums in FP64.
  * value (host, FP64) and grad_h (host FP64 [2], or NULL); synchronises stream. */
 int kde_lscv(const float *points, int64_t n, int32_t kernel_id, double hx, double hy, const kde_grid *g,
              double *value, double *grad_h, void *stream);

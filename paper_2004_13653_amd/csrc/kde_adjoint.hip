@@ -221,8 +221,24 @@ struct LscvLaunch {
     double *part;     // [gridDim.x][6]
 };
 
+// Horner evaluation with compile-time coefficients, highest power first.
+__device__ __forceinline__ float hp(float, float acc) { return acc; }
+template <typename... C>
+__device__ __forceinline__ float hp(float t, float acc, float c, C... rest) {
+    return hp(t, fmaf(acc, t, c), rest...);
+}
+
 // Per pair and axis: squared scaled distance w = (d/H)^2 and the four factors
-// kb, kb + u kb', g, g + u g' (without normalising constants).
+// kb, kb + u kb', g, g + u g' (without normalising constants).  g is the Table I
+// factor scaled to g(0) = 1 and kb its autoconvolution g * g (support |u| < 2)
+// up to a constant; the launch's host code applies the constants.
+//
+// The autoconvolutions of the polynomial factors are piecewise polynomials:
+// the integral over the overlap [a - 1, 1] (a = |u|) of g(v) g(a - v), one
+// polynomial on 0 <= a <= 1 and one on 1 <= a <= 2 (for the even polynomial
+// factors the two coincide).  They are evaluated in FP32 around each piece's
+// midpoint (t = a - 1/2 or a - 3/2), where the terms stay within a few times
+// the result; the coefficients below are those expansions, rounded to FP32.
 template <int K>
 __device__ __forceinline__ void lscv_axis(float d, float i2, float &kb, float &kbd, float &g, float &gd) {
     const float w = fminf(d * d * i2, 1.0e4f);  // u^2, capped: every factor is 0 there and stays finite
@@ -231,7 +247,7 @@ __device__ __forceinline__ void lscv_axis(float d, float i2, float &kb, float &k
         g = kb * kb;                                              // exp(-u^2/2)
         kbd = kb * fmaf(-0.5f, w, 1.0f);                          // (1 - u^2/2) kb
         gd = g * (1.0f - w);                                      // (1 - u^2) g
-    } else {  // Epanechnikov: kb ~ (2-a)^3 (a^2 + 6a + 4) on a <= 2, g = 1 - u^2 on a <= 1
+    } else if constexpr (K == kEpanechnikov) {  // kb ~ (2-a)^3 (a^2 + 6a + 4) on a <= 2, g = 1 - u^2 on a <= 1
         const float a = sqrtf(w);
         const float b = fmaxf(2.0f - a, 0.0f);
         const float b2 = b * b;
@@ -240,6 +256,84 @@ __device__ __forceinline__ void lscv_axis(float d, float i2, float &kb, float &k
         const bool in = w <= 1.0f;
         g = in ? 1.0f - w : 0.0f;
         gd = in ? 1.0f - 3.0f * w : 0.0f;
+    } else {
+        const float a = sqrtf(w);
+        const bool reach = a < 2.0f, lo = a <= 1.0f, in = w <= 1.0f;
+        float klo, khi, dlo, dhi;  // kb and kb + a kb' on each piece
+        if constexpr (K == kUniform) {  // kb = 2 - a
+            klo = khi = 2.0f - a;
+            dlo = dhi = 2.0f - 2.0f * a;
+            g = in ? 1.0f : 0.0f;
+            gd = g;
+        } else if constexpr (K == kTriangular) {  // the centred cubic B-spline
+            const float b = 2.0f - a;
+            klo = fmaf(w, fmaf(3.0f, a, -6.0f), 4.0f) * (1.0f / 6.0f);
+            khi = b * b * b * (1.0f / 6.0f);
+            dlo = fmaf(w, fmaf(12.0f, a, -18.0f), 4.0f) * (1.0f / 6.0f);
+            dhi = b * b * fmaf(-4.0f, a, 2.0f) * (1.0f / 6.0f);
+            g = in ? 1.0f - a : 0.0f;
+            gd = in ? fmaf(-2.0f, a, 1.0f) : 0.0f;
+        } else if constexpr (K == kQuartic) {
+            const float tl = a - 0.5f, th = a - 1.5f;
+            klo = hp(tl, -1.587301587e-03f, -7.142857143e-03f, 2.380952381e-02f, 1.166666667e-01f, -3.458333333e-01f,
+                     -1.062500000e-01f, 8.812500000e-01f, -2.611607143e-01f, -8.482700893e-01f, 5.582310268e-01f);
+            khi = hp(th, -1.587301587e-03f, -2.142857143e-02f, -9.047619048e-02f, -5.000000000e-02f, 2.541666667e-01f,
+                     4.791666667e-02f, -3.687500000e-01f, 2.796130952e-01f, -8.577008929e-02f, 9.712921627e-03f);
+            dlo = hp(tl, -1.587301587e-02f, -7.142857143e-02f, 1.619047619e-01f, 9.000000000e-01f, -1.725000000e+00f,
+                     -1.395833333e+00f, 3.312500000e+00f, 5.383928571e-01f, -1.957700893e+00f, 1.340959821e-01f);
+            dhi = hp(th, -1.587301587e-02f, -2.142857143e-01f, -9.809523810e-01f, -1.300000000e+00f, 1.075000000e+00f,
+                     2.145833333e+00f, -1.187500000e+00f, -8.205357143e-01f, 6.672991071e-01f, -1.189422123e-01f);
+            const float v = 1.0f - w;  // g = (1 - u^2)^2, u g' = -4 u^2 (1 - u^2)
+            g = in ? v * v : 0.0f;
+            gd = in ? v * fmaf(-5.0f, w, 1.0f) : 0.0f;
+        } else if constexpr (K == kTriweight) {
+            const float tl = a - 0.5f, th = a - 1.5f;
+            klo = hp(tl, -8.325008325e-05f, -5.411255411e-04f, 9.740259740e-04f, 1.130952381e-02f, -6.101190476e-03f,
+                     -1.212053571e-01f, 1.656250000e-01f, 3.220982143e-01f, -6.245256696e-01f, -3.529436384e-01f,
+                     1.104031808e+00f, -6.887999696e-02f, -8.430865399e-01f, 4.149201933e-01f);
+            khi = hp(th, -8.325008325e-05f, -1.623376623e-03f, -1.201298701e-02f, -3.750000000e-02f, -1.800595238e-02f,
+                     1.185267857e-01f, 8.348214286e-02f, -2.426339286e-01f, -5.775669643e-03f, 2.686988467e-01f,
+                     -2.391601563e-01f, 9.679446530e-02f, -1.950953100e-02f, 1.591997277e-03f);
+            dlo = hp(tl, -1.165501166e-03f, -7.575757576e-03f, 8.441558442e-03f, 1.297619048e-01f, -4.464285714e-03f,
+                     -1.118303571e+00f, 8.401785714e-01f, 2.834375000e+00f, -2.780859375e+00f, -3.326032366e+00f,
+                     3.710239955e+00f, 1.449407721e+00f, -1.755053077e+00f, -6.623076630e-03f);
+            dhi = hp(th, -1.165501166e-03f, -2.272727273e-02f, -1.733766234e-01f, -6.107142857e-01f, -7.425595238e-01f,
+                     8.236607143e-01f, 2.090178571e+00f, -8.218750000e-01f, -2.218359375e+00f, 1.300176711e+00f,
+                     6.555524554e-01f, -7.858373072e-01f, 2.513643339e-01f, -2.767229922e-02f);
+            const float v = 1.0f - w;  // g = (1 - u^2)^3, u g' = -6 u^2 (1 - u^2)^2
+            g = in ? v * v * v : 0.0f;
+            gd = in ? v * v * fmaf(-7.0f, w, 1.0f) : 0.0f;
+        } else if constexpr (K == kTricube) {
+            const float tl = a - 0.5f, th = a - 1.5f;
+            klo = hp(tl, 3.247526467e-06f, 3.085150144e-05f, 1.388317565e-04f, 3.184315684e-04f, 1.873126873e-04f,
+                     -1.067682318e-03f, 1.676448551e-03f, 2.879464286e-02f, 9.884841721e-02f, -3.200334821e-02f,
+                     2.913643973e-01f, -3.782207539e-01f, -6.789474685e-01f, 7.915561245e-01f, 1.970283257e-01f,
+                     -5.366161487e-01f, 7.719792895e-01f, -2.202373705e-01f, -9.418320762e-01f, 6.534530266e-01f);
+            khi = hp(th, -1.082508822e-06f, -3.085150144e-05f, -4.164952694e-04f, -3.465284715e-03f, -1.944305694e-02f,
+                     -7.535589411e-02f, -1.957885864e-01f, -2.971387987e-01f, -1.113585633e-01f, 4.632533482e-01f,
+                     7.370675223e-01f, -7.730379972e-02f, -9.847535765e-01f, -2.053903372e-01f, 8.611649215e-01f,
+                     6.489563293e-02f, -6.115566235e-01f, 3.679434487e-01f, -9.104161577e-02f, 8.480808063e-03f);
+            dlo = hp(tl, 6.495052935e-05f, 6.170300288e-04f, 2.776635130e-03f, 6.593406593e-03f, 5.544455544e-03f,
+                     -1.461038961e-02f, 1.599650350e-02f, 3.852272727e-01f, 1.358948864e+00f, 1.916294643e-01f,
+                     2.753627232e+00f, -2.092846997e+00f, -6.944462764e+00f, 3.164576732e+00f, 3.556838328e+00f,
+                     -2.190509930e+00f, 2.014684860e+00f, 4.972568226e-01f, -2.103901523e+00f, 1.825369885e-01f);
+            dhi = hp(th, -2.165017645e-05f, -6.170300288e-04f, -8.329905389e-03f, -6.953046953e-02f, -3.942557443e-01f,
+                     -1.567807193e+00f, -4.323513986e+00f, -7.680681818e+00f, -6.684801136e+00f, 3.258370536e+00f,
+                     1.431947545e+01f, 9.254677354e+00f, -8.805674209e+00f, -1.177764491e+01f, 3.318476494e+00f,
+                     6.783215076e+00f, -2.056852696e+00f, -1.648174460e+00f, 9.217471144e-01f, -1.280816156e-01f);
+            const float c3 = w * a, v = 1.0f - c3;  // g = (1 - a^3)^3, u g' = -9 a^3 (1 - a^3)^2
+            g = in ? v * v * v : 0.0f;
+            gd = in ? v * v * fmaf(-10.0f, c3, 1.0f) : 0.0f;
+        } else {  // cosine: kb = ((2/pi) sin(pi a/2) + (2 - a) cos(pi a/2)) / 2, kb' = -(pi/4)(2 - a) sin(pi a/2)
+            const float s = __builtin_amdgcn_sinf(a * 0.25f), c = __builtin_amdgcn_cosf(a * 0.25f);  // revolutions
+            const float b = 2.0f - a;
+            klo = khi = fmaf(0.5f * b, c, 0.31830988618379067f * s);
+            dlo = dhi = klo - 0.78539816339744831f * a * b * s;
+            g = in ? c : 0.0f;
+            gd = in ? fmaf(-1.5707963267948966f * a, s, c) : 0.0f;
+        }
+        kb = reach ? (lo ? klo : khi) : 0.0f;
+        kbd = reach ? (lo ? dlo : dhi) : 0.0f;
     }
 }
 
@@ -319,12 +413,17 @@ hipError_t launch_lscv(const float2 *pts, int64_t n, int kernel_id, float Hx, fl
                        hipStream_t stream) {
     LscvLaunch p{pts, n, (float)(1.0 / ((double)Hx * Hx)), (float)(1.0 / ((double)Hy * Hy)), part};
     const dim3 grid((unsigned)lscv_blocks(n));
-    if (kernel_id == kGaussian)
-        hipLaunchKernelGGL(lscv_kernel<kGaussian>, grid, dim3(kAdjThreads), 0, stream, p);
-    else if (kernel_id == kEpanechnikov)
-        hipLaunchKernelGGL(lscv_kernel<kEpanechnikov>, grid, dim3(kAdjThreads), 0, stream, p);
-    else
-        return hipErrorInvalidValue;
+    switch (kernel_id) {
+    case kUniform: hipLaunchKernelGGL(lscv_kernel<kUniform>, grid, dim3(kAdjThreads), 0, stream, p); break;
+    case kTriangular: hipLaunchKernelGGL(lscv_kernel<kTriangular>, grid, dim3(kAdjThreads), 0, stream, p); break;
+    case kEpanechnikov: hipLaunchKernelGGL(lscv_kernel<kEpanechnikov>, grid, dim3(kAdjThreads), 0, stream, p); break;
+    case kQuartic: hipLaunchKernelGGL(lscv_kernel<kQuartic>, grid, dim3(kAdjThreads), 0, stream, p); break;
+    case kTriweight: hipLaunchKernelGGL(lscv_kernel<kTriweight>, grid, dim3(kAdjThreads), 0, stream, p); break;
+    case kTricube: hipLaunchKernelGGL(lscv_kernel<kTricube>, grid, dim3(kAdjThreads), 0, stream, p); break;
+    case kGaussian: hipLaunchKernelGGL(lscv_kernel<kGaussian>, grid, dim3(kAdjThreads), 0, stream, p); break;
+    case kCosine: hipLaunchKernelGGL(lscv_kernel<kCosine>, grid, dim3(kAdjThreads), 0, stream, p); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

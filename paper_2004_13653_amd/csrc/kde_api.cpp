@@ -725,9 +725,6 @@ int kde_lscv(const float *points, int64_t n, int32_t kernel_id, double hx, doubl
         if (st != KDE_OK) return st;
         if (n < 2) return fail(KDE_EINVAL, "kde_lscv: need n >= 2");
         if (value == nullptr) return fail(KDE_EINVAL, "kde_lscv: value is NULL");
-        if (kernel_id != KDE_GAUSSIAN && kernel_id != KDE_EPANECHNIKOV)
-            return fail(KDE_EUNSUPPORTED, "kde_lscv: kernel %d not supported (Gaussian and Epanechnikov are)",
-                        (int)kernel_id);
         hipStream_t s = static_cast<hipStream_t>(stream);
         const float Hx = (float)(hx / g->dx), Hy = (float)(hy / g->dy);
         const int64_t blocks = kde::lscv_blocks(n);
@@ -751,7 +748,11 @@ int kde_lscv(const float *points, int64_t n, int32_t kernel_id, double hx, doubl
         S[5] -= nn;
         const double pi = 3.14159265358979323846;
         const double c = kde::kernel_norm(kernel_id);  // k = c g
-        const double cb = kernel_id == KDE_GAUSSIAN ? 1.0 / (2.0 * std::sqrt(pi)) : 3.0 / 160.0;  // kbar = cb kb
+        // kbar = cb kb: the Gaussian's kb is exp(-u^2/4), the Epanechnikov's (2-a)^3 (a^2+6a+4),
+        // the others' g * g with k = c g
+        const double cb = kernel_id == KDE_GAUSSIAN ? 1.0 / (2.0 * std::sqrt(pi))
+                          : kernel_id == KDE_EPANECHNIKOV ? 3.0 / 160.0
+                                                          : c * c;
         const double ca = cb * cb / (nn * nn), cbb = 2.0 * c * c / (nn * (nn - 1.0));
         *value = (ca * S[0] - cbb * S[3]) / (hx * hy);
         if (grad_h != nullptr) {
