@@ -725,7 +725,7 @@ __global__ __launch_bounds__(256) void band_assign_kernel(const unsigned *__rest
                                                           int *__restrict__ first_item, int *__restrict__ nsplit,
                                                           int *__restrict__ n_items) {
     __shared__ long long sh[256];
-    __shared__ long long s_total, s_per;
+    __shared__ long long s_per;
     const int tid = threadIdx.x;
     const int t0 = (int)((int64_t)tiles * tid / 256), t1 = (int)((int64_t)tiles * (tid + 1) / 256);
     auto bin_begin = [&](int t) -> int64_t { return t > 0 ? (int64_t)end[(int64_t)t * wblocks - 1] : 0; };
@@ -737,7 +737,6 @@ __global__ __launch_bounds__(256) void band_assign_kernel(const unsigned *__rest
     if (tid == 0) {
         long long tot = 0;
         for (int k = 0; k < 256; ++k) tot += sh[k];
-        s_total = tot;
         long long per = (tot + kBandTarget - 1) / kBandTarget;
         per = (per + kc - 1) / kc * kc;
         s_per = per < 4 * kc ? 4 * kc : per;
