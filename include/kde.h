@@ -272,8 +272,9 @@ int kde_dp_compress(const double *xy, int64_t n, const int64_t *track_start, int
  *                     tracks under 2^30 points (else KDE_EINVAL)
  *   len_o, len_c, dtw device FP64 [n_tracks] each, or NULL (not returned)
  *   out               host, the totals, or NULL
- * Synchronises `stream` once to validate the offsets, and again at the end
- * when out is given. */
+ * The offsets are checked on the device before any point is read; the call
+ * synchronises `stream` once, at the end (KDE_EINVAL for bad offsets, with the
+ * per-track outputs then unwritten). */
 typedef struct kde_track_metrics {
     int64_t n_original, n_compressed;
     double cr_percent;

@@ -140,9 +140,10 @@ struct MetricsArgs {
     double *len_o, *len_c, *dtw;  // [n_tracks] each, or nullptr (then workspace)
 };
 size_t metrics_workspace_bytes(int64_t n_o, int64_t n_c, int64_t n_tracks, bool per_track_given);
-// Validates the offsets (one stream synchronisation; hipErrorInvalidValue if
-// they do not rise from 0 to n_o and n_c with tracks under kMaxTrackPoints),
-// then computes; with host_out the totals are copied back (synchronising).
+// Checks the offsets on the device (the compute kernels skip all work when they
+// do not rise from 0 to n_o and n_c with tracks under kMaxTrackPoints), computes,
+// and synchronises once: hipErrorInvalidValue for bad offsets, else the totals
+// in *host_out (if given).
 hipError_t run_metrics(const MetricsArgs &a, void *ws, hipStream_t stream, MetricsTotals *host_out);
 
 // Matrix-core separable path (precision kPrecFp16 .. kPrecBf16x3).  Compact

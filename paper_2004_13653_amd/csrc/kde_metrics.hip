@@ -197,9 +197,11 @@ __global__ __launch_bounds__(kWave) void track_metrics_kernel(const double2 *__r
                                                               const double2 *__restrict__ xc,
                                                               const int64_t *__restrict__ sc,
                                                               double *__restrict__ bound, double *__restrict__ len_o,
-                                                              double *__restrict__ len_c, double *__restrict__ dtw) {
+                                                              double *__restrict__ len_c, double *__restrict__ dtw,
+                                                              const unsigned *__restrict__ bad) {
     __shared__ double2 ring_b[2 * kWave];
     __shared__ double ring_t[2 * kWave];
+    if (*bad != 0u) return;  // offsets rejected by the check: touch no point
     const int64_t m = blockIdx.x;
     const int lane = threadIdx.x;
     const int64_t o0 = so[m], c0 = sc[m];
@@ -254,9 +256,11 @@ __global__ __launch_bounds__(kReduceThreads) void metrics_reduce_kernel(const do
                                                                         const double *__restrict__ dtw, int64_t m,
                                                                         const int64_t *__restrict__ so,
                                                                         const int64_t *__restrict__ sc,
+                                                                        const unsigned *__restrict__ bad,
                                                                         MetricsTotals *__restrict__ out) {
 #pragma clang fp contract(off)
     __shared__ double red[kReduceThreads / kWave];
+    if (*bad != 0u) return;
     double a = 0.0, b = 0.0, c = 0.0;
     for (int64_t i = threadIdx.x; i < m; i += kReduceThreads) {
         a += len_o[i];
@@ -307,18 +311,24 @@ size_t al256(size_t x) { return (x + 255) / 256 * 256; }
 
 }  // namespace
 
+// Totals and the offsets check's flag, next to each other so that one copy
+// brings both back.
+struct MetricsResult {
+    MetricsTotals totals;
+    unsigned bad;
+    unsigned pad_;
+};
+
 size_t metrics_workspace_bytes(int64_t n_o, int64_t n_c, int64_t n_tracks, bool per_track_given) {
-    size_t b = al256(sizeof(MetricsTotals)) + 256 + al256((size_t)2 * (n_o + n_c) * sizeof(double));
+    size_t b = al256(sizeof(MetricsResult)) + al256((size_t)2 * (n_o + n_c) * sizeof(double));
     if (!per_track_given) b += 3 * al256((size_t)n_tracks * sizeof(double));
     return b;
 }
 
 hipError_t run_metrics(const MetricsArgs &a, void *ws, hipStream_t s, MetricsTotals *host_out) {
     char *w = static_cast<char *>(ws);
-    MetricsTotals *tot = reinterpret_cast<MetricsTotals *>(w);
-    w += al256(sizeof(MetricsTotals));
-    unsigned *bad = reinterpret_cast<unsigned *>(w);
-    w += 256;
+    MetricsResult *res = reinterpret_cast<MetricsResult *>(w);
+    w += al256(sizeof(MetricsResult));
     double *bound = reinterpret_cast<double *>(w);
     w += al256((size_t)2 * (a.n_o + a.n_c) * sizeof(double));
     double *lo = a.len_o, *lc = a.len_c, *dt = a.dtw;
@@ -326,28 +336,30 @@ hipError_t run_metrics(const MetricsArgs &a, void *ws, hipStream_t s, MetricsTot
     if (lo == nullptr) { lo = reinterpret_cast<double *>(w); w += per; }
     if (lc == nullptr) { lc = reinterpret_cast<double *>(w); w += per; }
     if (dt == nullptr) { dt = reinterpret_cast<double *>(w); w += per; }
+    unsigned *bad = &res->bad;
+    // The check runs first on the stream; the kernels after it read its flag
+    // and do nothing when it is set, so bad offsets never index the points.
     hipLaunchKernelGGL(zero_flag_kernel, dim3(1), dim3(64), 0, s, bad);
     hipLaunchKernelGGL(metrics_check_kernel, dim3((unsigned)((a.n_tracks + 1 + 255) / 256)), dim3(256), 0, s, a.so,
                        a.n_o, a.sc, a.n_c, a.n_tracks, bad);
-    unsigned flag = 0;
-    hipError_t e = hipMemcpyAsync(&flag, bad, sizeof flag, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return e;
-    if (flag) return hipErrorInvalidValue;
     if (a.n_tracks > 0) {
         main_kernel_begin(s);
         hipLaunchKernelGGL(track_metrics_kernel, dim3((unsigned)a.n_tracks), dim3(kWave), 0, s, a.xo, a.so, a.xc,
-                           a.sc, bound, lo, lc, dt);
+                           a.sc, bound, lo, lc, dt, static_cast<const unsigned *>(bad));
         main_kernel_end(s);
     }
     hipLaunchKernelGGL(metrics_reduce_kernel, dim3(1), dim3(kReduceThreads), 0, s, static_cast<const double *>(lo),
-                       static_cast<const double *>(lc), static_cast<const double *>(dt), a.n_tracks, a.so, a.sc, tot);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (host_out != nullptr) {
-        e = hipMemcpyAsync(host_out, tot, sizeof(MetricsTotals), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-    }
-    return e;
+                       static_cast<const double *>(lc), static_cast<const double *>(dt), a.n_tracks, a.so, a.sc,
+                       static_cast<const unsigned *>(bad), &res->totals);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    MetricsResult host;
+    e = hipMemcpyAsync(&host, res, sizeof host, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    if (host.bad) return hipErrorInvalidValue;
+    if (host_out != nullptr) *host_out = host.totals;
+    return hipSuccess;
 }
 
 }  // namespace kde
