@@ -328,18 +328,32 @@ def metrics_cpu_baseline(synth, t, eps: float = 50.0):
 
 def bench_compact(torch, kde, synth, steps: int):
     """The eight kernels on the FP32 direct path: 1,000,000 points (2,000 tracks x
-    500) on 1024 x 1024, h = 0.002 degrees."""
+    500) on 1024 x 1024, h = 0.002 degrees, raw and Douglas-Peucker-compressed at
+    eps = 10, 50, 100 m (compressed on the GPU, the kept points' grid units then
+    evaluated like the raw ones)."""
+    import numpy as np
     t = synth.workload_lanes(n_tracks=2000, pts=500, seed_index=1)
     b = synth.BOX_C2
     g = kde.Grid(b.lon0, b.lon1, b.lat0, b.lat1, 1024, 1024)
-    pts = torch.from_numpy(kde.to_grid_units(t.xy, g)).cuda()
     out = torch.empty((1024, 1024), device="cuda")
+    mx, my = synth.mercator(t.xy[:, 0], t.xy[:, 1], t.box.center_lat)
+    xy_m = torch.from_numpy(np.column_stack([mx, my])).cuda()
+    start = torch.from_numpy(np.concatenate([[0], np.cumsum(t.lengths)]).astype(np.int64)).cuda()
+    inputs = {"raw": t.xy}
+    for eps in (10.0, 50.0, 100.0):
+        keep = kde.dp_compress(xy_m, start, eps, compact=False).keep.cpu().numpy().astype(bool)
+        inputs[f"dp_{eps:g}m"] = t.xy[keep]
     res = {}
-    for kname, kid in kde.KERNELS.items():
-        tot, _, _ = timed_steps(torch, lambda: kde.eval(pts, kid, 0.002, 0.002, g, out=out), steps, 1)
-        ms = tot / steps
-        res[kname] = {"ms": ms, "logical_pairs_per_s": pts.shape[0] * 1024 * 1024 / (ms * 1e-3)}
-    log("compact kernels: " + ", ".join(f"{k} {v['ms']:.2f} ms" for k, v in res.items()))
+    for name, xy in inputs.items():
+        pts = torch.from_numpy(kde.to_grid_units(xy, g)).cuda()
+        ent = {"points": int(pts.shape[0])}
+        for kname, kid in kde.KERNELS.items():
+            tot, _, _ = timed_steps(torch, lambda: kde.eval(pts, kid, 0.002, 0.002, g, out=out), steps, 1)
+            ms = tot / steps
+            ent[kname] = {"ms": ms, "logical_pairs_per_s": pts.shape[0] * 1024 * 1024 / (ms * 1e-3)}
+        res[name] = ent
+        log(f"kernels ({name}, {ent['points']} points): " + ", ".join(
+            f"{k} {v['ms']:.2f} ms" for k, v in ent.items() if isinstance(v, dict)))
     return res
 
 
