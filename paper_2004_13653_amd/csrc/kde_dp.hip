@@ -4,16 +4,19 @@
 //
 // State per point i: the kept points lo[i] < i < hi[i] that enclose it (its
 // chord), and whether it is still undecided (active).  One level:
-//   1. reset the slot of every active chord (slots are indexed by the chord's
-//      first point, unique among the chords of one level);
-//   2. score: |cross| of Eq. (9)'s numerator (squared distance to P_s for a
-//      chord of zero length), integer atomic max of its bits into the slot;
-//   3. argmax: points whose score equals the slot's maximum take an integer
+//   1. score: |cross| of Eq. (9)'s numerator (squared distance to P_s for a
+//      chord of zero length), integer atomic max of its bits into the chord's
+//      slot (slots are indexed by the chord's first point, unique among the
+//      chords of one level, and double-buffered by level parity);
+//   2. argmax: points whose score equals the slot's maximum take an integer
 //      atomic min of their index (the lowest index wins ties);
-//   4. decide: the chord's argmax keeps itself when cross^2 > eps^2 |chord|^2
-//      (or dist^2 > eps^2), marking the chord split or final;
-//   5. update: points of final chords are dropped, the others move to the half
-//      chord on their side of the new kept point.
+//   3. decide: the chord's argmax keeps itself when cross^2 > eps^2 |chord|^2
+//      (or dist^2 > eps^2), marking the chord split or final, and resets the
+//      next level's slots of both halves;
+//   4. update: points of final chords are dropped, the others move to the half
+//      chord on their side of the new kept point, and are scored right away for
+//      the next level (the same kernel: a point's update needs only its own
+//      chord's decision).
 // Scores are FP64 with no fused multiply-add (the decision is taken exactly as
 // the reference does), and all cross-thread combination is integer atomics:
 // the keep mask does not depend on thread order.  The host checks after each
@@ -95,6 +98,38 @@ __global__ __launch_bounds__(256) void dp_init_kernel(const int64_t *__restrict_
 
 // Slots of level L live in buffer L % 2: the kept point of a split chord resets
 // the next level's slots of both halves while this level's are still read.
+// Scores an active point against its chord (s, e) and folds the chord maxima
+// of the wave into the chord slots.  Chords are index ranges, so the active
+// lanes of a wave fall into a few runs of equal chord: a segmented max-scan
+// over the wave (a lane takes the running max of lanes off = 1, 2, 4, ... below
+// it while they hold its chord) leaves each run's maximum in its last lane,
+// which alone issues the atomic.  Runs cut by inactive lanes (chord -1) give
+// one atomic per piece; integer max is order-free, so the slot ends the same.
+__device__ __forceinline__ void score_point(const double2 *__restrict__ xy, int64_t i, bool act, int s, int e,
+                                            double *__restrict__ score, unsigned long long *__restrict__ segmax) {
+    unsigned long long bits = 0ull;
+    if (act) {
+        bool zero;
+        const double sc = dp_score(xy, s, e, i, zero);
+        score[i] = sc;
+        bits = (unsigned long long)__double_as_longlong(sc);  // non-negative doubles order like their bits
+    } else {
+        s = -1;
+    }
+    if (__ballot(act) == 0ull) return;
+    const int lane = (int)(threadIdx.x & 63);
+    unsigned long long m = bits;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const unsigned long long o = __shfl_up(m, off);
+        const int so = __shfl_up(s, off);
+        if (lane >= off && so == s && o > m) m = o;
+    }
+    const int s_next = __shfl_down(s, 1);
+    if (act && (lane == 63 || s_next != s)) atomicMax(segmax + s, m);
+}
+
+// Level 0: every active point against its track's end-point chord.
 __global__ __launch_bounds__(256) void dp_score_kernel(const double2 *__restrict__ xy, int64_t n,
                                                        const int *__restrict__ lo, const int *__restrict__ hi,
                                                        const uint8_t *__restrict__ active,
@@ -102,32 +137,7 @@ __global__ __launch_bounds__(256) void dp_score_kernel(const double2 *__restrict
                                                        unsigned long long *__restrict__ segmax) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool act = i < n && active[i];
-    unsigned long long bits = 0ull;
-    int s = -1;
-    if (act) {
-        bool zero;
-        s = lo[i];
-        const double sc = dp_score(xy, s, hi[i], i, zero);
-        score[i] = sc;
-        bits = (unsigned long long)__double_as_longlong(sc);  // non-negative doubles order like their bits
-    }
-    // Chords are index ranges, so the lanes of a wave mostly share one: then one
-    // atomic per wave carries the wave's maximum (an integer max, order-free).
-    const unsigned long long am = __ballot(act);
-    if (am == 0ull) return;
-    const int first = __ffsll(am) - 1;
-    const int s0 = __shfl(s, first);
-    if (__ballot(act && s == s0) == am) {
-        unsigned long long m = bits;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const unsigned long long o = __shfl_xor(m, off);
-            m = o > m ? o : m;
-        }
-        if ((int)(threadIdx.x & 63) == first) atomicMax(segmax + s0, m);
-    } else if (act) {
-        atomicMax(segmax + s, bits);
-    }
+    score_point(xy, i, act, act ? lo[i] : -1, act ? hi[i] : -1, score, segmax);
 }
 
 __global__ __launch_bounds__(256) void dp_argmax_kernel(int64_t n, const int *__restrict__ lo,
@@ -170,21 +180,41 @@ __global__ __launch_bounds__(256) void dp_decide_kernel(const double2 *__restric
     if (split) *splits = 1u;  // only "some chord split" is needed: same value from every writer
 }
 
-__global__ __launch_bounds__(256) void dp_update_kernel(int64_t n, int *__restrict__ lo, int *__restrict__ hi,
-                                                        uint8_t *__restrict__ active,
-                                                        const unsigned long long *__restrict__ segarg,
-                                                        const uint8_t *__restrict__ segdec) {
+// End of a level and start of the next, per point: a point of a final chord is
+// dropped, the splitting point itself is kept (and leaves), every other point
+// moves to the half chord on its side of it; then it is scored against that
+// chord into the next level's slots.  (The update needs only the point's own
+// chord's decision, so no level-wide barrier separates the two.)
+__global__ __launch_bounds__(256) void dp_update_score_kernel(const double2 *__restrict__ xy, int64_t n,
+                                                              int *__restrict__ lo, int *__restrict__ hi,
+                                                              uint8_t *__restrict__ active,
+                                                              const unsigned long long *__restrict__ segarg,
+                                                              const uint8_t *__restrict__ segdec,
+                                                              double *__restrict__ score,
+                                                              unsigned long long *__restrict__ next_max) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || !active[i]) return;
-    const int s = lo[i];
-    if (segdec[s] == 2) {
-        active[i] = 0;  // within eps of its final chord: dropped
-        return;
+    bool act = i < n && active[i];
+    int l = -1, h = -1;
+    if (act) {
+        l = lo[i];
+        h = hi[i];
+        if (segdec[l] == 2) {
+            act = false;  // within eps of its final chord: dropped
+        } else {
+            const int k = (int)segarg[l];
+            if (k == i) {
+                act = false;  // kept
+            } else if (i < k) {
+                h = k;
+                hi[i] = k;
+            } else {
+                l = k;
+                lo[i] = k;
+            }
+        }
+        if (!act) active[i] = 0;
     }
-    const int k = (int)segarg[s];
-    if (k == i) active[i] = 0;  // kept
-    else if (i < k) hi[i] = k;
-    else lo[i] = k;
+    score_point(xy, i, act, l, h, score, next_max);
 }
 
 __global__ __launch_bounds__(256) void zero_u32_kernel(unsigned *p, int64_t count) {
@@ -281,13 +311,14 @@ hipError_t run_dp(const DpArgs &a, void *ws, hipStream_t s, int64_t *n_kept) {
     // Every level either splits a chord or leaves all remaining ones final, so
     // no track needs more levels than it has points.
     int64_t level = 0;
+    hipLaunchKernelGGL(dp_score_kernel, grid, block, 0, s, a.xy, a.n, static_cast<const int *>(lo),
+                       static_cast<const int *>(hi), static_cast<const uint8_t *>(active), score, segmax);
     for (int64_t group = 0; group <= a.n / kLevelsPerCheck + 1; ++group) {
         hipLaunchKernelGGL(zero_u32_kernel, dim3(1), block, 0, s, splits, (int64_t)1);
         for (int l = 0; l < kLevelsPerCheck; ++l, ++level) {
+            // level's scores are in segmax + cur; the update of its chords also
+            // scores the next level into segmax + nxt
             const int64_t cur = (level & 1) * a.n, nxt = ((level + 1) & 1) * a.n;
-            hipLaunchKernelGGL(dp_score_kernel, grid, block, 0, s, a.xy, a.n, static_cast<const int *>(lo),
-                               static_cast<const int *>(hi), static_cast<const uint8_t *>(active), score,
-                               segmax + cur);
             hipLaunchKernelGGL(dp_argmax_kernel, grid, block, 0, s, a.n, static_cast<const int *>(lo),
                                static_cast<const uint8_t *>(active), static_cast<const double *>(score),
                                static_cast<const unsigned long long *>(segmax + cur), segarg + cur);
@@ -296,9 +327,9 @@ hipError_t run_dp(const DpArgs &a, void *ws, hipStream_t s, int64_t *n_kept) {
                                static_cast<const double *>(score),
                                static_cast<const unsigned long long *>(segarg + cur), segdec, a.keep, segmax + nxt,
                                segarg + nxt, splits);
-            hipLaunchKernelGGL(dp_update_kernel, grid, block, 0, s, a.n, lo, hi, active,
+            hipLaunchKernelGGL(dp_update_score_kernel, grid, block, 0, s, a.xy, a.n, lo, hi, active,
                                static_cast<const unsigned long long *>(segarg + cur),
-                               static_cast<const uint8_t *>(segdec));
+                               static_cast<const uint8_t *>(segdec), score, segmax + nxt);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
         unsigned got = 0;
