@@ -177,7 +177,13 @@ __global__ __launch_bounds__(256) void dp_decide_kernel(const double2 *__restric
             next_arg[i] = kNoIndex;
         }
     }
-    if (split) *splits = 1u;  // only "some chord split" is needed: same value from every writer
+    // Only "some chord split" is needed: one lane per wave that saw a split
+    // sets the flag, and skips the store once it reads the flag already set
+    // (many concurrent stores to one line would serialise in the cache).
+    const uint64_t any = __ballot(split);
+    if (any != 0ull && (int)(threadIdx.x & 63) == __ffsll((unsigned long long)any) - 1 &&
+        __atomic_load_n(splits, __ATOMIC_RELAXED) == 0u)
+        *splits = 1u;
 }
 
 // End of a level and start of the next, per point: a point of a final chord is
