@@ -145,6 +145,15 @@ def bench_adjoint(torch, kde, synth, steps: int):
                       "vjp_with_h_ms": ms_vjp_h, "lscv_ms": ms_lscv,
                       "lscv_pairs_per_s": n * n / (ms_lscv * 1e-3)}
         log(f"adjoint {kname}: vjp {ms_vjp:.2f} ms, lscv {ms_lscv:.2f} ms")
+    # LSCV of the other six kernels on the same points (one timed call each)
+    other = {}
+    for kname in ("uniform", "triangular", "quartic", "triweight", "tricube", "cosine"):
+        kde.lscv(pts, kname, 0.004, 0.004, g)
+        t0 = time.perf_counter()
+        kde.lscv(pts, kname, 0.004, 0.004, g)
+        other[kname] = (time.perf_counter() - t0) * 1e3
+    res["lscv_other_kernels_ms"] = other
+    log("lscv, other kernels: " + ", ".join(f"{k} {v:.1f} ms" for k, v in other.items()))
     return res
 
 

@@ -218,6 +218,7 @@ struct LscvLaunch {
     const float2 *pts;
     int64_t n;
     float ix2, iy2;   // 1/H^2 (grid units)
+    float ix, iy;     // 1/H
     double *part;     // [gridDim.x][6]
 };
 
@@ -228,7 +229,8 @@ __device__ __forceinline__ float hp(float t, float acc, float c, C... rest) {
     return hp(t, fmaf(acc, t, c), rest...);
 }
 
-// Per pair and axis: squared scaled distance w = (d/H)^2 and the four factors
+// Per pair and axis, from the grid-unit difference d (scaled u = d/H: the
+// Gaussian through u^2 = d^2/H^2, the compact kernels through |u| = |d|/H) the four factors
 // kb, kb + u kb', g, g + u g' (without normalising constants).  g is the Table I
 // factor scaled to g(0) = 1 and kb its autoconvolution g * g (support |u| < 2)
 // up to a constant; the launch's host code applies the constants.
@@ -240,15 +242,15 @@ __device__ __forceinline__ float hp(float t, float acc, float c, C... rest) {
 // midpoint (t = a - 1/2 or a - 3/2), where the terms stay within a few times
 // the result; the coefficients below are those expansions, rounded to FP32.
 template <int K>
-__device__ __forceinline__ void lscv_axis(float d, float i2, float &kb, float &kbd, float &g, float &gd) {
-    const float w = fminf(d * d * i2, 1.0e4f);  // u^2, capped: every factor is 0 there and stays finite
+__device__ __forceinline__ void lscv_axis(float d, float ih, float i2, float &kb, float &kbd, float &g, float &gd) {
     if constexpr (K == kGaussian) {
+        const float w = fminf(d * d * i2, 1.0e4f);  // u^2, capped: every factor is 0 there and stays finite
         kb = __builtin_amdgcn_exp2f(-0.36067376022224085f * w);  // exp(-u^2/4)
         g = kb * kb;                                              // exp(-u^2/2)
         kbd = kb * fmaf(-0.5f, w, 1.0f);                          // (1 - u^2/2) kb
         gd = g * (1.0f - w);                                      // (1 - u^2) g
     } else if constexpr (K == kEpanechnikov) {  // kb ~ (2-a)^3 (a^2 + 6a + 4) on a <= 2, g = 1 - u^2 on a <= 1
-        const float a = sqrtf(w);
+        const float a = fminf(fabsf(d) * ih, 100.0f), w = a * a;  // |u|, capped: every factor is 0 there
         const float b = fmaxf(2.0f - a, 0.0f);
         const float b2 = b * b;
         kb = b2 * b * (w + 6.0f * a + 4.0f);
@@ -257,7 +259,7 @@ __device__ __forceinline__ void lscv_axis(float d, float i2, float &kb, float &k
         g = in ? 1.0f - w : 0.0f;
         gd = in ? 1.0f - 3.0f * w : 0.0f;
     } else {
-        const float a = sqrtf(w);
+        const float a = fminf(fabsf(d) * ih, 100.0f), w = a * a;
         const bool reach = a < 2.0f, lo = a <= 1.0f, in = w <= 1.0f;
         float klo, khi, dlo, dhi;  // kb and kb + a kb' on each piece
         if constexpr (K == kUniform) {  // kb = 2 - a
@@ -355,8 +357,8 @@ __global__ __launch_bounds__(kAdjThreads) void lscv_kernel(LscvLaunch p) {
         for (int k = 0; k < kAdjThreads; ++k) {
             const float2 o = qs[k];
             float kbx, kbdx, gx, gdx, kby, kbdy, gy, gdy;
-            lscv_axis<K>(me.x - o.x, p.ix2, kbx, kbdx, gx, gdx);
-            lscv_axis<K>(me.y - o.y, p.iy2, kby, kbdy, gy, gdy);
+            lscv_axis<K>(me.x - o.x, p.ix, p.ix2, kbx, kbdx, gx, gdx);
+            lscv_axis<K>(me.y - o.y, p.iy, p.iy2, kby, kbdy, gy, gdy);
             sa = fmaf(kbx, kby, sa);
             sax = fmaf(kbdx, kby, sax);
             say = fmaf(kbx, kbdy, say);
@@ -411,7 +413,8 @@ int64_t lscv_blocks(int64_t n) { return (n + kAdjThreads - 1) / kAdjThreads; }
 
 hipError_t launch_lscv(const float2 *pts, int64_t n, int kernel_id, float Hx, float Hy, double *part,
                        hipStream_t stream) {
-    LscvLaunch p{pts, n, (float)(1.0 / ((double)Hx * Hx)), (float)(1.0 / ((double)Hy * Hy)), part};
+    LscvLaunch p{pts, n, (float)(1.0 / ((double)Hx * Hx)), (float)(1.0 / ((double)Hy * Hy)), (float)(1.0 / (double)Hx),
+                 (float)(1.0 / (double)Hy), part};
     const dim3 grid((unsigned)lscv_blocks(n));
     switch (kernel_id) {
     case kUniform: hipLaunchKernelGGL(lscv_kernel<kUniform>, grid, dim3(kAdjThreads), 0, stream, p); break;
