@@ -27,6 +27,8 @@
 //    exactly 1 to SB, SBX and SBY).
 #include "kde_internal.h"
 
+#include <algorithm>
+
 #include <cmath>
 
 namespace kde {
@@ -339,22 +341,49 @@ __device__ __forceinline__ void lscv_axis(float d, float ih, float i2, float &kb
     }
 }
 
+// LSCV work plan.  Every pair term is symmetric in (p, q) (it depends on |dx|
+// and |dy| only), so only the tiles (p-block, q-block) with q-block >= p-block
+// are visited: an off-diagonal tile counts twice, and in a diagonal tile the
+// pairs q > p count twice and p = q once, which gives the sums over all ordered
+// pairs with half the work.  The row of tiles of p-block b is paired with that of
+// p-block nb - 1 - b (together nb + 1 tiles, the same for every pair; the middle
+// row of an odd nb stands alone), and each pair of rows is cut into `chunks`
+// equal runs of tiles, one workgroup each.
+struct LscvPlan {
+    int64_t nb, units, chunks;
+};
+
+LscvPlan lscv_plan(int64_t n) {
+    LscvPlan pl;
+    pl.nb = (n + kAdjThreads - 1) / kAdjThreads;
+    pl.units = (pl.nb + 1) / 2;
+    const int64_t want = (2048 + pl.units - 1) / pl.units;                 // aim at ~2048 workgroups
+    pl.chunks = std::max<int64_t>(1, std::min<int64_t>(want, (pl.nb + 1) / 4));  // at least ~4 tiles each
+    return pl;
+}
+
 template <int K>
-__global__ __launch_bounds__(kAdjThreads) void lscv_kernel(LscvLaunch p) {
+__global__ __launch_bounds__(kAdjThreads) void lscv_kernel(LscvLaunch p, int64_t nb, int64_t chunks) {
     __shared__ float2 qs[kAdjThreads];
     __shared__ double red[6][kAdjThreads];
     const int tid = threadIdx.x;
-    const int64_t pi = (int64_t)blockIdx.x * kAdjThreads + tid;
-    const bool active = pi < p.n;
-    const float2 me = active ? p.pts[pi] : make_float2(0.0f, 0.0f);
+    const int64_t u = blockIdx.x / chunks, c = blockIdx.x % chunks;
+    const int64_t b1 = u, b2 = nb - 1 - u;
+    const int64_t len1 = nb - b1, len2 = b2 == b1 ? 0 : nb - b2;
+    const int64_t L = len1 + len2, t0 = L * c / chunks, t1 = L * (c + 1) / chunks;
     double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int64_t base = 0; base < p.n; base += kAdjThreads) {
-        __syncthreads();
-        const int64_t qi = base + tid;
+    for (int64_t t = t0; t < t1; ++t) {
+        const int64_t pb = t < len1 ? b1 : b2, qb = t < len1 ? b1 + t : b2 + (t - len1);
+        const int64_t pi = pb * kAdjThreads + tid, qi = qb * kAdjThreads + tid;
+        const bool valid = pi < p.n;
+        const float2 me = valid ? p.pts[pi] : make_float2(0.0f, 0.0f);
+        __syncthreads();  // previous tile fully consumed
         qs[tid] = qi < p.n ? p.pts[qi] : make_float2(kFarAdj, kFarAdj);
         __syncthreads();
+        if (!valid) continue;
+        const bool diag = qb == pb;
         float sa = 0.0f, sax = 0.0f, say = 0.0f, sb = 0.0f, sbx = 0.0f, sby = 0.0f;
-        for (int k = 0; k < kAdjThreads; ++k) {
+        for (int k = diag ? tid + 1 : 0; k < kAdjThreads; ++k) {  // diagonal tile: q > p only
             const float2 o = qs[k];
             float kbx, kbdx, gx, gdx, kby, kbdy, gy, gdy;
             lscv_axis<K>(me.x - o.x, p.ix, p.ix2, kbx, kbdx, gx, gdx);
@@ -366,15 +395,26 @@ __global__ __launch_bounds__(kAdjThreads) void lscv_kernel(LscvLaunch p) {
             sbx = fmaf(gdx, gy, sbx);
             sby = fmaf(gx, gdy, sby);
         }
-        S[0] += sa;
-        S[1] += sax;
-        S[2] += say;
-        S[3] += sb;
-        S[4] += sbx;
-        S[5] += sby;
+        S[0] += 2.0 * sa;
+        S[1] += 2.0 * sax;
+        S[2] += 2.0 * say;
+        S[3] += 2.0 * sb;
+        S[4] += 2.0 * sbx;
+        S[5] += 2.0 * sby;
+        if (diag) {  // p = q, once
+            float kbx, kbdx, gx, gdx, kby, kbdy, gy, gdy;
+            lscv_axis<K>(0.0f, p.ix, p.ix2, kbx, kbdx, gx, gdx);
+            lscv_axis<K>(0.0f, p.iy, p.iy2, kby, kbdy, gy, gdy);
+            S[0] += kbx * kby;
+            S[1] += kbdx * kby;
+            S[2] += kbx * kbdy;
+            S[3] += gx * gy;
+            S[4] += gdx * gy;
+            S[5] += gx * gdy;
+        }
     }
 #pragma unroll
-    for (int k = 0; k < 6; ++k) red[k][tid] = active ? S[k] : 0.0;
+    for (int k = 0; k < 6; ++k) red[k][tid] = S[k];
     __syncthreads();
     for (int w = kAdjThreads / 2; w > 0; w >>= 1) {
         if (tid < w) {
@@ -409,22 +449,28 @@ hipError_t launch_vjp(const float2 *pts, int64_t n, int kernel_id, float Hx, flo
     return hipGetLastError();
 }
 
-int64_t lscv_blocks(int64_t n) { return (n + kAdjThreads - 1) / kAdjThreads; }
+int64_t lscv_blocks(int64_t n) {
+    const LscvPlan pl = lscv_plan(n);
+    return pl.units * pl.chunks;
+}
 
 hipError_t launch_lscv(const float2 *pts, int64_t n, int kernel_id, float Hx, float Hy, double *part,
                        hipStream_t stream) {
     LscvLaunch p{pts, n, (float)(1.0 / ((double)Hx * Hx)), (float)(1.0 / ((double)Hy * Hy)), (float)(1.0 / (double)Hx),
                  (float)(1.0 / (double)Hy), part};
-    const dim3 grid((unsigned)lscv_blocks(n));
+    const LscvPlan pl = lscv_plan(n);
+    const dim3 grid((unsigned)(pl.units * pl.chunks)), block(kAdjThreads);
     switch (kernel_id) {
-    case kUniform: hipLaunchKernelGGL(lscv_kernel<kUniform>, grid, dim3(kAdjThreads), 0, stream, p); break;
-    case kTriangular: hipLaunchKernelGGL(lscv_kernel<kTriangular>, grid, dim3(kAdjThreads), 0, stream, p); break;
-    case kEpanechnikov: hipLaunchKernelGGL(lscv_kernel<kEpanechnikov>, grid, dim3(kAdjThreads), 0, stream, p); break;
-    case kQuartic: hipLaunchKernelGGL(lscv_kernel<kQuartic>, grid, dim3(kAdjThreads), 0, stream, p); break;
-    case kTriweight: hipLaunchKernelGGL(lscv_kernel<kTriweight>, grid, dim3(kAdjThreads), 0, stream, p); break;
-    case kTricube: hipLaunchKernelGGL(lscv_kernel<kTricube>, grid, dim3(kAdjThreads), 0, stream, p); break;
-    case kGaussian: hipLaunchKernelGGL(lscv_kernel<kGaussian>, grid, dim3(kAdjThreads), 0, stream, p); break;
-    case kCosine: hipLaunchKernelGGL(lscv_kernel<kCosine>, grid, dim3(kAdjThreads), 0, stream, p); break;
+    case kUniform: hipLaunchKernelGGL(lscv_kernel<kUniform>, grid, block, 0, stream, p, pl.nb, pl.chunks); break;
+    case kTriangular: hipLaunchKernelGGL(lscv_kernel<kTriangular>, grid, block, 0, stream, p, pl.nb, pl.chunks); break;
+    case kEpanechnikov:
+        hipLaunchKernelGGL(lscv_kernel<kEpanechnikov>, grid, block, 0, stream, p, pl.nb, pl.chunks);
+        break;
+    case kQuartic: hipLaunchKernelGGL(lscv_kernel<kQuartic>, grid, block, 0, stream, p, pl.nb, pl.chunks); break;
+    case kTriweight: hipLaunchKernelGGL(lscv_kernel<kTriweight>, grid, block, 0, stream, p, pl.nb, pl.chunks); break;
+    case kTricube: hipLaunchKernelGGL(lscv_kernel<kTricube>, grid, block, 0, stream, p, pl.nb, pl.chunks); break;
+    case kGaussian: hipLaunchKernelGGL(lscv_kernel<kGaussian>, grid, block, 0, stream, p, pl.nb, pl.chunks); break;
+    case kCosine: hipLaunchKernelGGL(lscv_kernel<kCosine>, grid, block, 0, stream, p, pl.nb, pl.chunks); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
