@@ -174,7 +174,7 @@ struct GatherLaunch {
     int64_t plane;
 };
 
-template <int K, int RC>
+template <int K, int RC, bool kRuns>
 __global__ __launch_bounds__(tile::kThreads) void bin_gather_kernel(GatherLaunch p) {
     using S = tile::Shape<K, RC>;
     __shared__ float2 sp[tile::kPointTile];
@@ -187,8 +187,9 @@ __global__ __launch_bounds__(tile::kThreads) void bin_gather_kernel(GatherLaunch
     const int x0 = (t % p.tiles_x) * S::TW, y0 = (t / p.tiles_x) * S::TH;
     const int ib = x0 + (tid & 15) * S::C, jb = y0 + (tid >> 4) * S::R;
     float tot[S::R][S::C];
-    tile::tile_sums<K, S::R, S::C, false>(p.bins, lo, hi, p.Hx, p.Hy, p.ax, p.ay, ib, jb, 0.0f, 0.0f, 0.0f, 0.0f,
-                                          sp, swave, tot);
+    tile::tile_sums<K, S::R, S::C, false, kRuns>(p.bins, lo, hi, p.Hx, p.Hy, p.ax, p.ay, ib, jb, 0.0f, 0.0f, 0.0f,
+                                                 0.0f, sp, swave, tot);
+    if constexpr (kRuns) tile::apply_run_q<S::R, S::C>(tot, p.ax, p.ay);
     tile::store_block<S::R, S::C>(tot, p.dst + (int64_t)blockIdx.y * p.plane, p.nx, p.ny, ib, jb,
                                   gridDim.y == 1 ? p.scale : 1.0f);
 }
@@ -231,7 +232,12 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 template <int K, int RC>
 hipError_t launch_gather_r(const GatherLaunch &p, int tiles, int splits, hipStream_t s) {
     main_kernel_begin(s);
-    hipLaunchKernelGGL((bin_gather_kernel<K, RC>), dim3(tiles, splits), dim3(tile::kThreads), 0, s, p);
+    // the truncated Gaussian takes the runs of the Gaussian (two exp2 per run, then the support mask)
+    if (K == kGaussTrunc && p.ax <= kMaxRunScale && p.ay <= kMaxRunScale)
+        hipLaunchKernelGGL((bin_gather_kernel<K, RC, K == kGaussTrunc>), dim3(tiles, splits), dim3(tile::kThreads), 0,
+                           s, p);
+    else
+        hipLaunchKernelGGL((bin_gather_kernel<K, RC, false>), dim3(tiles, splits), dim3(tile::kThreads), 0, s, p);
     main_kernel_end(s);
     return hipGetLastError();
 }

@@ -109,8 +109,9 @@ hipError_t launch_kr(const MapArgs &a, const Plan &pl, float *dst, hipStream_t s
                    (int64_t)a.nx * a.ny};
     dim3 grid(pl.tiles, pl.splits);
     main_kernel_begin(stream);
-    if (K == kGaussian && a.ax <= kMaxRunScale && a.ay <= kMaxRunScale)
-        hipLaunchKernelGGL((direct_fp32_kernel<K, RC, K == kGaussian>), grid, dim3(kThreads), 0, stream, p);
+    constexpr bool kGauss = K == kGaussian || K == kGaussTrunc;
+    if (kGauss && a.ax <= kMaxRunScale && a.ay <= kMaxRunScale)
+        hipLaunchKernelGGL((direct_fp32_kernel<K, RC, kGauss>), grid, dim3(kThreads), 0, stream, p);
     else
         hipLaunchKernelGGL((direct_fp32_kernel<K, RC, false>), grid, dim3(kThreads), 0, stream, p);
     main_kernel_end(stream);

@@ -111,7 +111,8 @@ __device__ __forceinline__ void store_block(float (&v)[R][C], float *dst, int nx
 // columns starting at (jb, ib); tile reach x0..x1, y0..y1 (nodes) for culling.
 // Each LDS tile of points is summed into a fresh block before joining the total.
 // sp: LDS [kPointTile] float2; swave: LDS [kThreads / 64] int.
-// kRuns (Gaussian): factors as Gaussian runs; the caller applies apply_run_q.
+// kRuns (Gaussian, truncated Gaussian): factors as Gaussian runs (the truncated
+// one then masked to its support); the caller applies apply_run_q.
 template <int K, int R, int C, bool kCull, bool kRuns = false>
 __device__ __forceinline__ void tile_sums(const float2 *__restrict__ pts, int64_t beg, int64_t end, float Hx,
                                           float Hy, float ax, float ay, int ib, int jb, float bx0, float bx1,
@@ -166,6 +167,13 @@ __device__ __forceinline__ void tile_sums(const float2 *__restrict__ pts, int64_
                 // run centres: half-integer nodes, so (centre - X) is exact like dx0 below
                 gauss_run<C>((fib + 0.5f * (float)(C - 1) - pt.x) * ax, ax, kx);
                 gauss_run<R>((fjb + 0.5f * (float)(R - 1) - pt.y) * ay, ay, ky);
+                if constexpr (K == kGaussTrunc) {  // the support test of factor<kGaussTrunc> (q_r > 0 keeps zeros)
+                    const float dx0 = fib - pt.x, dy0 = fjb - pt.y;
+#pragma unroll
+                    for (int c = 0; c < C; ++c) kx[c] = fabsf(dx0 + (float)c) <= Hx ? kx[c] : 0.0f;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) ky[r] = fabsf(dy0 + (float)r) <= Hy ? ky[r] : 0.0f;
+                }
             } else {
                 const float dx0 = fib - pt.x, dy0 = fjb - pt.y;
 #pragma unroll
