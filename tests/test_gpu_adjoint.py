@@ -156,6 +156,28 @@ def test_lscv_other_kernels(kernel, hdeg):
     assert np.all(np.abs(np.array(gh) - ref_g) <= GRAD_GATE * np.abs(ref_g))
 
 
+@pytest.mark.parametrize("n", [3, 255, 256, 257, 513, 1000, 2049])
+def test_lscv_ragged_point_counts(n):
+    """Point counts around the 256-point tiles (one to nine p-blocks, odd and
+    even, so the paired rows of tiles, the lone middle row and the diagonal
+    tiles all occur), Gaussian and tricube, against the oracle."""
+    import torch
+    rng = np.random.default_rng(n)
+    g = kde.Grid(0.0, 1.0, 0.0, 1.0, 128, 128)
+    og = oracle.Grid(0.0, 1.0, 0.0, 1.0, 128, 128)
+    XY = rng.uniform(20.0, 60.0, (n, 2)).astype(np.float32)
+    for kernel, h in ((6, 0.03), (5, 0.05)):
+        Hx, Hy = oracle.bandwidth_units(h, 1.2 * h, og)
+        vu, gu = oracle.lscv_units(XY, kernel, Hx, Hy)
+        ref_v = vu * float(Hx) * float(Hy) / (h * 1.2 * h)
+        v, gh = kde.lscv(kt.to_device(XY), kernel, h, 1.2 * h, g)
+        torch.cuda.synchronize()
+        assert abs(v - ref_v) <= GRAD_GATE * abs(ref_v), (kernel, v, ref_v)
+        ref_g = np.array([gu[0] * float(Hx) ** 2 * float(Hy) / (h * h * 1.2 * h),
+                          gu[1] * float(Hx) * float(Hy) ** 2 / (h * 1.2 * h * 1.2 * h)])
+        assert np.all(np.abs(np.array(gh) - ref_g) <= GRAD_GATE * np.abs(ref_g)), (kernel, gh, ref_g)
+
+
 def test_lscv_autograd_and_edge_cases():
     import torch
     g = kde.Grid(0.0, 1.0, 0.0, 1.0, 64, 64)
