@@ -32,7 +32,7 @@ N_TRACKS, PTS_PER_TRACK, SIDE, H_DEG = 8000, 500, 2048, 0.002
 # two rocprofv3 counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors a
 # plain 256 MiB elementwise copy gives), profiles/kde_map_gaussian_4M_2048_fp16_traffic.txt.
 # Set to None whenever that kernel changes until the counters are taken again.
-TRAFFIC_FP16 = 339.0e6
+TRAFFIC_FP16 = 146.9e6
 
 
 def log(msg: str) -> None:

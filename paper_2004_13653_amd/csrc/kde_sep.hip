@@ -357,6 +357,7 @@ __global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p) {
     // and points (workgroups past the last item leave at once).
     const bool banded = p.items != nullptr;
     int tile_idx = blockIdx.x;
+    int64_t split = 0;
     int64_t count;
     const float2 *qbase;
     if (banded) {
@@ -366,9 +367,18 @@ __global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p) {
         count = it.len;
         qbase = p.pts + it.pad_off;
     } else {
-        const int64_t beg = (int64_t)blockIdx.y * p.per_split;
+        // Workgroups go to the 8 XCDs in turn (dispatch index mod 8), each XCD
+        // with its own L2.  Numbering the (tile, split) items split-major and
+        // giving each XCD one contiguous eighth of them keeps every split's points
+        // in the L2s of the few XCDs that sweep it, instead of streaming every
+        // split through all eight (a bijection, so any dispatch order stays correct).
+        const int64_t L = blockIdx.x + (int64_t)blockIdx.y * gridDim.x, TS = (int64_t)gridDim.x * gridDim.y;
+        const int64_t w = TS % 8 == 0 ? (L % 8) * (TS / 8) + L / 8 : L;
+        tile_idx = (int)(w % gridDim.x);
+        split = w / gridDim.x;
+        const int64_t beg = split * p.per_split;
         count = min(p.n, beg + p.per_split) - beg;
-        qbase = p.pts + blockIdx.y * p.pad_stride;
+        qbase = p.pts + split * p.pad_stride;
     }
     const int tx = tile_idx % p.tiles_x, ty = tile_idx / p.tiles_x;
     const int col0 = tx * kTile, row0 = ty * kTile;
@@ -547,7 +557,7 @@ __global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p) {
                          (lane & 31)] = acc[a][b][r];
         return;
     }
-    float *dst = p.dst + (int64_t)blockIdx.y * p.plane;
+    float *dst = p.dst + split * p.plane;
     const float sc = gridDim.y == 1 ? p.scale : 1.0f;
     float qcol = 1.0f, qrow[4] = {1.0f, 1.0f, 1.0f, 1.0f};
     if constexpr (kRecur) {
