@@ -90,3 +90,14 @@ def test_invalid_offsets_rejected():
         st = torch.tensor(bad, dtype=torch.int64, device=kt.device())
         with pytest.raises(kde.KDEError):
             kde.dp_compress(x, st, 1.0)
+
+
+def test_empty_input_offsets():
+    """No points and no tracks: nothing kept, and the compressed offsets are [0]."""
+    import torch
+    x = torch.zeros((0, 2), dtype=torch.float64, device=kt.device())
+    st = torch.zeros(1, dtype=torch.int64, device=kt.device())
+    keep, out, lens, cst = kde.dp_compress(x, st, 10.0)
+    torch.cuda.synchronize()
+    assert keep.numel() == 0 and out.shape[0] == 0 and lens.numel() == 0
+    assert cst.cpu().tolist() == [0]

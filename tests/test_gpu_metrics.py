@@ -177,3 +177,22 @@ def test_invalid_offsets_rejected():
             kde.compression_metrics(x, _dev(np.array([0] * (len(bad) - 1) + [10], np.int64)), x, st)
     with pytest.raises(ValueError):
         kde.compression_metrics(x, good, x, _dev(np.array([0, 10], np.int64)))
+
+
+def test_totals_without_per_track_outputs():
+    """per_track=False (the per-track arrays live in library workspace) gives
+    the same totals bit for bit."""
+    import torch
+    rng = np.random.default_rng(31)
+    lo = [int(v) for v in rng.integers(1, 300, 50)]
+    lc = [int(v) for v in rng.integers(1, 300, 50)]
+    xo = np.cumsum(rng.normal(0, 5, (sum(lo), 2)), axis=0)
+    xc = np.cumsum(rng.normal(0, 5, (sum(lc), 2)), axis=0)
+    args = (_dev(xo), _dev(_starts(lo)), _dev(xc), _dev(_starts(lc)))
+    a = kde.compression_metrics(*args)
+    b = kde.compression_metrics(*args, per_track=False)
+    torch.cuda.synchronize()
+    for k in ("n_original", "n_compressed", "cr_percent", "length_original", "length_compressed", "rll",
+              "dtw_mean", "dtw_std"):
+        assert a[k] == b[k], k
+    assert "dtw" not in b
