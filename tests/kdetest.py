@@ -92,3 +92,31 @@ def peak_error(y, r) -> float:
     y = np.asarray(y, np.float64)
     r = np.asarray(r, np.float64)
     return float(np.max(np.abs(y - r)) / np.max(np.abs(r)))
+
+
+def mass_window(XY: np.ndarray, nx: int, ny: int, side: int = 256, stride: int = 64) -> tuple:
+    """The side x side window, corners on multiples of stride, that holds the
+    most points (the crop with the largest mass), as (i0, i1, j0, j1).  Chosen
+    from the inputs alone, so every path is compared on the same window."""
+    bx, by = nx // stride, ny // stride
+    cnt, _, _ = np.histogram2d(XY[:, 1], XY[:, 0], bins=[by, bx], range=[[0, by * stride], [0, bx * stride]])
+    w = side // stride
+    best, arg = -1.0, (0, 0)
+    for b in range(by - w + 1):
+        for a in range(bx - w + 1):
+            s = cnt[b:b + w, a:a + w].sum()
+            if s > best:
+                best, arg = s, (a, b)
+    i0, j0 = arg[0] * stride, arg[1] * stride
+    return (i0, i0 + side, j0, j0 + side)
+
+
+_ORACLE_CACHE: dict = {}
+
+
+def cached(key, compute):
+    """Oracle results shared by several tests of one session (the large windows
+    take tens of seconds on the host)."""
+    if key not in _ORACLE_CACHE:
+        _ORACLE_CACHE[key] = compute()
+    return _ORACLE_CACHE[key]

@@ -57,20 +57,78 @@ def _gpu_vjp(XY, kernel, hx, hy, g, gbar, raw=False, grid_units=False):
 
 @pytest.mark.parametrize("kernel", list(range(8)))
 @pytest.mark.parametrize("raw", [False, True])
-def test_vjp_all_kernels(kernel, raw):
-    """2,000 lane points, 150 x 97 grid (ragged strips), random cotangent."""
+@pytest.mark.parametrize("shape", [(150, 97), (180, 530)])
+def test_vjp_all_kernels(kernel, raw, shape):
+    """2,000 lane points, random cotangent, on a 150 x 97 grid (ragged strips) and
+    on a 180 x 530 grid, whose row sweep crosses the 256-row chunks twice (rows
+    0-255, 256-511, 512-529)."""
+    nx, ny = shape
     t = kt.lanes(20, 100)
-    g, og = kt.grids(synth.BOX_C2, 150, 97)
+    g, og = kt.grids(synth.BOX_C2, nx, ny)
     XY = kde.to_grid_units(t.xy, g)
     rng = np.random.default_rng(kernel)
-    gbar = rng.standard_normal((97, 150))
+    gbar = rng.standard_normal((ny, nx))
     h = 0.02
     gp, gh = _gpu_vjp(XY, kernel, h, 0.7 * h, g, gbar, raw=raw)
     rp, rh = _expected_vjp(XY, kernel, h, 0.7 * h, og, gbar, raw)
     e_p = _rel_l2(gp, rp)
     e_h = _rel(gh, rh)
-    kt.log(f"kernel={kernel} raw={raw}: points rel-L2 {e_p:.2e}, h rel {e_h}")
+    kt.log(f"kernel={kernel} raw={raw} {nx}x{ny}: points rel-L2 {e_p:.2e}, h rel {e_h}")
     assert e_p <= GRAD_GATE
+    assert np.all(e_h <= GRAD_GATE)
+
+
+def _sample_points(XY, ny, nx, seed):
+    """Indices of >= 256 points for full-size gradient checks: points in the rows
+    around the 256-row chunk edge, past it, below it, near the grid's edges, and
+    uniform ones."""
+    rng = np.random.default_rng(seed)
+    X, Y = XY[:, 0], XY[:, 1]
+    pick = []
+    for mask, m in (((Y >= 240) & (Y <= 272), 64), ((Y > 300) & (Y < ny), 64), ((Y >= 0) & (Y < 200), 32),
+                    ((X < 6) | (X > nx - 7) | (Y < 6) | (Y > ny - 7), 32)):
+        idx = np.flatnonzero(mask)
+        if idx.size:
+            pick.append(rng.choice(idx, size=min(m, idx.size), replace=False))
+    pick.append(rng.choice(XY.shape[0], size=96, replace=False))
+    return np.unique(np.concatenate(pick))
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("kernel", [6, 2])
+def test_vjp_full_size_against_oracle(kernel):
+    """250,000 points on 512 x 512 at h = 0.004 deg, L2 loss against the map of
+    the same tracks Douglas-Peucker-compressed at 50 m: gbar = 2 (f - T), f and T
+    from the oracle.  dL/d(x_p, y_p) of >= 256 sampled points (rows around and
+    past the 256-row chunk edge, the grid's edges, uniform) against the oracle's
+    plain loops, and both bandwidth gradients (sums over every point) against
+    its factored form; gate relative L2 / relative error <= 1e-4."""
+    t = kt.lanes(500, 500)
+    tc = kt.lanes_dp(500, 500, 50.0)
+    g, og = kt.grids(synth.BOX_C2, 512, 512)
+    XY = kde.to_grid_units(t.xy, g)
+    XYc = kde.to_grid_units(tc.xy, g)
+    h = 0.004
+    Hx, Hy = oracle.bandwidth_units(h, h, og)
+    full = (0, 512, 0, 512)
+    S = oracle.map_units_separable(XY, kernel, Hx, Hy, full)
+    sigma = oracle.density_scale(XY.shape[0], h, h)
+    T = oracle.map_units_separable(XYc, kernel, Hx, Hy, full) * oracle.density_scale(XYc.shape[0], h, h)
+    gbar = (2.0 * (S * sigma - T)).astype(np.float32).astype(np.float64)
+    kt.log(f"kernel={kernel}: n={XY.shape[0]}, compressed {XYc.shape[0]}, |gbar|max={np.abs(gbar).max():.3e}")
+    gp, gh = _gpu_vjp(XY, kernel, h, h, g, gbar)
+    sel = _sample_points(XY, 512, 512, seed=kernel)
+    rp, _ = oracle.vjp_units(XY, kernel, Hx, Hy, gbar, sel=sel)
+    rp = np.column_stack([rp[:, 0] * sigma / og.dx, rp[:, 1] * sigma / og.dy])
+    e_p = _rel_l2(gp[sel], rp)
+    kt.log(f"  {sel.size} sampled points ({int((XY[sel, 1] >= 256).sum())} in rows >= 256): rel-L2 {e_p:.2e}")
+    assert sel.size >= 256
+    assert e_p <= GRAD_GATE
+    _, ghs = oracle.vjp_units_separable(XY, kernel, Hx, Hy, gbar)
+    q = float((gbar * S).sum())
+    rh = np.array([sigma * ghs[:, 0].sum() / og.dx - sigma * q / h, sigma * ghs[:, 1].sum() / og.dy - sigma * q / h])
+    e_h = _rel(gh, rh)
+    kt.log(f"  bandwidth gradient {gh} ref {rh}: rel {e_h}")
     assert np.all(e_h <= GRAD_GATE)
 
 
@@ -111,26 +169,41 @@ def test_autograd_function_matches_backward():
     assert abs(hy.grad.item() - rh[1]) <= GRAD_GATE * abs(rh[1])
 
 
-@pytest.mark.parametrize("kernel", [6, 2])
-@pytest.mark.parametrize("hdeg", [0.001, 0.004, 0.01])
-def test_lscv_value_and_gradient(kernel, hdeg):
-    """20,000 lane points, LSCV over all ordered pairs against the oracle in
-    parity mode (FP32 grid-unit inputs, FP64 arithmetic)."""
+def _lscv_against_oracle(XY, kernel, hx, hy, g, og):
+    """kde_lscv against the oracle in parity mode (FP32 grid-unit inputs, FP64
+    arithmetic), converted to world units: value relative error and both
+    gradient components' relative errors <= 1e-4."""
     import torch
-    t = kt.lanes(100, 200)
-    g, og = kt.grids(synth.BOX_C2, 512, 512)
-    XY = kde.to_grid_units(t.xy, g)
-    Hx, Hy = oracle.bandwidth_units(hdeg, 1.3 * hdeg, og)
+    Hx, Hy = oracle.bandwidth_units(hx, hy, og)
     vu, gu = oracle.lscv_units(XY, kernel, Hx, Hy)
-    hx, hy = hdeg, 1.3 * hdeg
     ref_v = vu * float(Hx) * float(Hy) / (hx * hy)
     ref_g = np.array([gu[0] * float(Hx) ** 2 * float(Hy) / (hx * hx * hy),
                       gu[1] * float(Hx) * float(Hy) ** 2 / (hx * hy * hy)])
     v, gh = kde.lscv(kt.to_device(XY), kernel, hx, hy, g)
     torch.cuda.synchronize()
-    kt.log(f"lscv kernel={kernel} h={hdeg}: value {v:.6e} ref {ref_v:.6e}; grad {gh} ref {ref_g}")
+    kt.log(f"lscv kernel={kernel} n={XY.shape[0]} h=({hx}, {hy}): value {v:.6e} ref {ref_v:.6e}; "
+           f"grad {gh} ref {ref_g}")
     assert abs(v - ref_v) <= GRAD_GATE * abs(ref_v)
     assert np.all(np.abs(np.array(gh) - ref_g) <= GRAD_GATE * np.abs(ref_g))
+
+
+@pytest.mark.parametrize("kernel", [6, 2])
+@pytest.mark.parametrize("hdeg", [0.001, 0.004, 0.01])
+def test_lscv_value_and_gradient(kernel, hdeg):
+    """20,000 lane points, LSCV over all ordered pairs against the oracle."""
+    t = kt.lanes(100, 200)
+    g, og = kt.grids(synth.BOX_C2, 512, 512)
+    _lscv_against_oracle(kde.to_grid_units(t.xy, g), kernel, hdeg, 1.3 * hdeg, g, og)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("kernel", [6, 2])
+def test_lscv_50k_points(kernel):
+    """50,000 lane points (100 tracks x 500) at h = (0.004, 0.0052) deg on the
+    512 x 512 grid's units: 2.5*10^9 ordered pairs against the oracle."""
+    t = kt.lanes(100, 500)
+    g, og = kt.grids(synth.BOX_C2, 512, 512)
+    _lscv_against_oracle(kde.to_grid_units(t.xy, g), kernel, 0.004, 1.3 * 0.004, g, og)
 
 
 @pytest.mark.parametrize("kernel", [0, 1, 3, 4, 5, 7])

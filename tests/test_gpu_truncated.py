@@ -97,22 +97,33 @@ def test_banded_matrix_core_truncated_matches_oracle(prec, H):
     assert e["e_2"] <= GATE_E2[prec]
 
 
+@pytest.mark.timeout(600)
 @pytest.mark.parametrize("prec", ["fp16", "bf16x3"])
-def test_banded_full_size_against_dense_and_oracle(prec):
+def test_banded_full_size_against_oracle(prec):
     """4*10^6 lane points on 2048^2 at h = 0.002 deg (support 32.8 px): the banded
-    truncated map against the dense map of the same precision (within twice the
-    precision's gate) and against the oracle at sampled pixels; repeat calls
-    are bit-identical."""
-    t = kt.lanes(8000, 500, 2)
+    truncated map against the oracle's truncated Gaussian (kernel 8) on the
+    256 x 256 crop holding the most points and at sampled pixels (plain loops),
+    each at the precision's own e_2 gate; the dense map of the same precision
+    against the full Gaussian on the same crop at that gate (the two references
+    differ by less than n e^-32 of the peak pair value, far below it); repeat
+    calls are bit-identical."""
+    t = kt.lanes(8000, 500)
     g, og = kt.grids(synth.BOX_C2, 2048, 2048)
     XY = kde.to_grid_units(t.xy, g)
     yb = _gpu_sep(XY, 0.002, 0.002, g, prec)
     yb2 = _gpu_sep(XY, 0.002, 0.002, g, prec)
     np.testing.assert_array_equal(yb, yb2)
     yd = _gpu_sep(XY, 0.002, 0.002, g, prec, truncate=False)
-    e = oracle.errors(yb, yd)
-    kt.log(f"{prec}: banded vs dense e_2={e['e_2']:.2e}")
-    assert e["e_2"] <= 2 * GATE_E2[prec]
+    win = kt.mass_window(XY, 2048, 2048)
+    crop = (slice(win[2], win[3]), slice(win[0], win[1]))
+    for kernel, y in ((oracle.GAUSS_TRUNC, yb), (oracle.GAUSSIAN, yd)):
+        r = kt.cached(("c3", kernel, win),
+                      lambda: kt.oracle_density_window(XY, kernel, 0.002, 0.002, og, win, separable=True))
+        e = oracle.errors(y[crop], r)
+        kt.log(f"{prec} kernel={kernel} crop {win}: e_2={e['e_2']:.2e} e_inf={e['e_inf']:.2e}")
+        assert e["e_2"] <= GATE_E2[prec]
     ij = kt.sample_pixels(yb, 32, seed=11)
     r = kt.oracle_density_at(XY, oracle.GAUSS_TRUNC, 0.002, 0.002, og, ij)
-    assert kt.peak_error(yb[ij[:, 1], ij[:, 0]], r) <= 10 * GATE_E2[prec]
+    e = oracle.errors(yb[ij[:, 1], ij[:, 0]], r)
+    kt.log(f"{prec}: {ij.shape[0]} sampled pixels e_2={e['e_2']:.2e}")
+    assert e["e_2"] <= GATE_E2[prec]

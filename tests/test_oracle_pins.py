@@ -408,6 +408,32 @@ def test_lscv_gradient_against_finite_differences(kernel):
     assert grad[1] == pytest.approx(fy, rel=1e-6)
 
 
+@pytest.mark.parametrize("kernel", K)
+def test_lscv_units_mode_equals_world_mode(kernel):
+    """Grid-unit LSCV (the parity reference of the GPU) against world-unit LSCV
+    (pinned above) on a grid with power-of-two spacings dx = 1/2, dy = 1/4 and
+    points on a 1/256 lattice, so X = x/dx, Hx = hx/dx are exact: the value
+    scales by 1/(dx dy) and the gradient by 1/(dx^2 dy), 1/(dx dy^2).  Hx != Hy
+    and the point cloud is longer in x than in y, so swapped bandwidths or axes
+    in the unit conversion change the result (checked)."""
+    rng = np.random.default_rng(170 + kernel)
+    dx, dy = 0.5, 0.25
+    g = Grid(0.0, dx * 63, 0.0, dy * 47, 64, 48)
+    xy = np.column_stack([rng.integers(0, 20 * 256, 30) / 256.0, rng.integers(0, 5 * 256, 30) / 256.0])
+    hx, hy = 2.75, 0.625
+    XY = oracle.to_units(xy, g)
+    np.testing.assert_array_equal(XY.astype(np.float64), xy / np.array([dx, dy]))
+    Hx, Hy = oracle.bandwidth_units(hx, hy, g)
+    assert (float(Hx), float(Hy)) == (hx / dx, hy / dy)
+    vw, gw = oracle.lscv_world(xy, kernel, hx, hy)
+    vu, gu = oracle.lscv_units(XY, kernel, Hx, Hy)
+    assert vu / (dx * dy) == pytest.approx(vw, rel=1e-13)
+    assert gu[0] / (dx * dx * dy) == pytest.approx(gw[0], rel=1e-13)
+    assert gu[1] / (dx * dy * dy) == pytest.approx(gw[1], rel=1e-13)
+    vs, _ = oracle.lscv_units(XY, kernel, Hy, Hx)
+    assert abs(vs / (dx * dy) - vw) > 1e-6 * abs(vw)
+
+
 def test_lscv_two_points_gaussian_closed_form():
     """n = 2 Gaussian: int f^2 is a sum of N(0, 2h^2) densities and the
     leave-one-out density of each point is the other point's kernel."""
