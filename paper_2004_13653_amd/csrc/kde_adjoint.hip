@@ -25,6 +25,23 @@
 //    FP64 accumulators and reduced per workgroup in FP64 in a fixed order.  The
 //    p == q terms are included here and removed on the host (each contributes
 //    exactly 1 to SB, SBX and SBY).
+//
+// 3. Support-culled LSCV for the compact kernels.  kb vanishes for |u| >= 2 and
+//    g for |u| > 1, so a pair (p, q) adds nothing once |X_p - X_q| >= 2 Hx or
+//    |Y_p - Y_q| >= 2 Hy; at vessel-track densities only a few per mille of the
+//    pairs are that close.  The points are first put in spatial (Z-order) order
+//    (kde_sort.hip), so that each 256-point block covers a small region; each
+//    block's bounding box is taken, and a tile (p-block, q-block >= p-block) is
+//    visited only if the boxes are closer than 2H on both axes.  The test is on
+//    the FP32 values the pair terms use (gap * (1/H) >= 2 implies |d| * (1/H)
+//    >= 2 for every pair of the two blocks, rounding being monotone), so a
+//    skipped tile is one whose every term is exactly zero.  The visited tiles,
+//    counted per p-block row and prefix-summed, form one sequence in row order
+//    that a fixed grid of workgroups cuts into equal runs; each workgroup finds
+//    its first tile by a binary search over the row offsets and walks the rows'
+//    candidate q-blocks 256 at a time (a ballot compaction of the box tests).
+//    Per tile the pair loop is that of (2).  All orders are fixed: the sums are
+//    bitwise reproducible.
 #include "kde_internal.h"
 
 #include <algorithm>
@@ -362,6 +379,60 @@ LscvPlan lscv_plan(int64_t n) {
     return pl;
 }
 
+// Pair terms of one tile: thread tid holds point p of p-block pb (me, valid),
+// the q-block's points are staged in qs; adds the tile's FP32 sums, doubled
+// (symmetry), to S, and for a diagonal tile the pairs q > p only plus p = q once.
+template <int K>
+__device__ __forceinline__ void lscv_tile(const LscvLaunch &p, float2 me, bool diag, const float2 *qs, int tid,
+                                          double (&S)[6]) {
+    float sa = 0.0f, sax = 0.0f, say = 0.0f, sb = 0.0f, sbx = 0.0f, sby = 0.0f;
+    for (int k = diag ? tid + 1 : 0; k < kAdjThreads; ++k) {
+        const float2 o = qs[k];
+        float kbx, kbdx, gx, gdx, kby, kbdy, gy, gdy;
+        lscv_axis<K>(me.x - o.x, p.ix, p.ix2, kbx, kbdx, gx, gdx);
+        lscv_axis<K>(me.y - o.y, p.iy, p.iy2, kby, kbdy, gy, gdy);
+        sa = fmaf(kbx, kby, sa);
+        sax = fmaf(kbdx, kby, sax);
+        say = fmaf(kbx, kbdy, say);
+        sb = fmaf(gx, gy, sb);
+        sbx = fmaf(gdx, gy, sbx);
+        sby = fmaf(gx, gdy, sby);
+    }
+    S[0] += 2.0 * sa;
+    S[1] += 2.0 * sax;
+    S[2] += 2.0 * say;
+    S[3] += 2.0 * sb;
+    S[4] += 2.0 * sbx;
+    S[5] += 2.0 * sby;
+    if (diag) {
+        float kbx, kbdx, gx, gdx, kby, kbdy, gy, gdy;
+        lscv_axis<K>(0.0f, p.ix, p.ix2, kbx, kbdx, gx, gdx);
+        lscv_axis<K>(0.0f, p.iy, p.iy2, kby, kbdy, gy, gdy);
+        S[0] += kbx * kby;
+        S[1] += kbdx * kby;
+        S[2] += kbx * kbdy;
+        S[3] += gx * gy;
+        S[4] += gdx * gy;
+        S[5] += gx * gdy;
+    }
+}
+
+// Workgroup sums of S in FP64, fixed order, into part[blockIdx.x][6].
+__device__ __forceinline__ void lscv_store(double (&S)[6], double (*red)[kAdjThreads], double *part, int tid) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) red[k][tid] = S[k];
+    __syncthreads();
+    for (int w = kAdjThreads / 2; w > 0; w >>= 1) {
+        if (tid < w) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) red[k][tid] += red[k][tid + w];
+        }
+        __syncthreads();
+    }
+    if (tid < 6) part[6 * blockIdx.x + tid] = red[tid][0];
+}
+
+// All-pairs LSCV (used for the Gaussian, whose every pair counts).
 template <int K>
 __global__ __launch_bounds__(kAdjThreads) void lscv_kernel(LscvLaunch p, int64_t nb, int64_t chunks) {
     __shared__ float2 qs[kAdjThreads];
@@ -380,50 +451,135 @@ __global__ __launch_bounds__(kAdjThreads) void lscv_kernel(LscvLaunch p, int64_t
         __syncthreads();  // previous tile fully consumed
         qs[tid] = qi < p.n ? p.pts[qi] : make_float2(kFarAdj, kFarAdj);
         __syncthreads();
-        if (!valid) continue;
-        const bool diag = qb == pb;
-        float sa = 0.0f, sax = 0.0f, say = 0.0f, sb = 0.0f, sbx = 0.0f, sby = 0.0f;
-        for (int k = diag ? tid + 1 : 0; k < kAdjThreads; ++k) {  // diagonal tile: q > p only
-            const float2 o = qs[k];
-            float kbx, kbdx, gx, gdx, kby, kbdy, gy, gdy;
-            lscv_axis<K>(me.x - o.x, p.ix, p.ix2, kbx, kbdx, gx, gdx);
-            lscv_axis<K>(me.y - o.y, p.iy, p.iy2, kby, kbdy, gy, gdy);
-            sa = fmaf(kbx, kby, sa);
-            sax = fmaf(kbdx, kby, sax);
-            say = fmaf(kbx, kbdy, say);
-            sb = fmaf(gx, gy, sb);
-            sbx = fmaf(gdx, gy, sbx);
-            sby = fmaf(gx, gdy, sby);
-        }
-        S[0] += 2.0 * sa;
-        S[1] += 2.0 * sax;
-        S[2] += 2.0 * say;
-        S[3] += 2.0 * sb;
-        S[4] += 2.0 * sbx;
-        S[5] += 2.0 * sby;
-        if (diag) {  // p = q, once
-            float kbx, kbdx, gx, gdx, kby, kbdy, gy, gdy;
-            lscv_axis<K>(0.0f, p.ix, p.ix2, kbx, kbdx, gx, gdx);
-            lscv_axis<K>(0.0f, p.iy, p.iy2, kby, kbdy, gy, gdy);
-            S[0] += kbx * kby;
-            S[1] += kbdx * kby;
-            S[2] += kbx * kbdy;
-            S[3] += gx * gy;
-            S[4] += gdx * gy;
-            S[5] += gx * gdy;
-        }
+        if (valid) lscv_tile<K>(p, me, qb == pb, qs, tid, S);
     }
-#pragma unroll
-    for (int k = 0; k < 6; ++k) red[k][tid] = S[k];
+    lscv_store(S, red, p.part, tid);
+}
+
+// Bounding box (xmin, xmax, ymin, ymax) of each 256-point block.
+__global__ __launch_bounds__(kAdjThreads) void block_box_kernel(const float2 *__restrict__ pts, int64_t n,
+                                                               float4 *__restrict__ box) {
+    __shared__ float4 wb[kAdjThreads / 64];
+    const int tid = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * kAdjThreads + tid;
+    const bool ok = i < n;
+    const float2 v = ok ? pts[i] : make_float2(0.0f, 0.0f);
+    float x0 = ok ? v.x : 3.0e38f, x1 = ok ? v.x : -3.0e38f, y0 = ok ? v.y : 3.0e38f, y1 = ok ? v.y : -3.0e38f;
+    for (int off = 32; off > 0; off >>= 1) {
+        x0 = fminf(x0, __shfl_xor(x0, off));
+        x1 = fmaxf(x1, __shfl_xor(x1, off));
+        y0 = fminf(y0, __shfl_xor(y0, off));
+        y1 = fmaxf(y1, __shfl_xor(y1, off));
+    }
+    if ((tid & 63) == 0) wb[tid >> 6] = make_float4(x0, x1, y0, y1);
     __syncthreads();
-    for (int w = kAdjThreads / 2; w > 0; w >>= 1) {
-        if (tid < w) {
-#pragma unroll
-            for (int k = 0; k < 6; ++k) red[k][tid] += red[k][tid + w];
+    if (tid == 0) {
+        float4 b = wb[0];
+        for (int w = 1; w < kAdjThreads / 64; ++w) {
+            b.x = fminf(b.x, wb[w].x);
+            b.y = fmaxf(b.y, wb[w].y);
+            b.z = fminf(b.z, wb[w].z);
+            b.w = fmaxf(b.w, wb[w].w);
         }
-        __syncthreads();
+        box[blockIdx.x] = b;
     }
-    if (tid < 6) p.part[6 * blockIdx.x + tid] = red[tid][0];
+}
+
+// Whether some pair of blocks a, b can be closer than 2H on both axes, as the
+// pair terms compute it: false only if every pair has |d| * (1/H) >= 2 on an axis.
+__device__ __forceinline__ bool boxes_meet(float4 a, float4 b, float ix, float iy) {
+    const float gx = fmaxf(b.x - a.y, a.x - b.y);
+    const float gy = fmaxf(b.z - a.w, a.z - b.w);
+    return !(gx * ix >= 2.0f) && !(gy * iy >= 2.0f);
+}
+
+// rowcnt[pb] = number of q-blocks qb >= pb whose box meets pb's.
+__global__ __launch_bounds__(kAdjThreads) void tile_count_kernel(const float4 *__restrict__ box, int64_t nb, float ix,
+                                                                float iy, unsigned *__restrict__ rowcnt) {
+    __shared__ unsigned wsum[kAdjThreads / 64];
+    const int tid = threadIdx.x;
+    const int64_t pb = blockIdx.x;
+    const float4 a = box[pb];
+    unsigned c = 0;
+    for (int64_t qb = pb + tid; qb < nb; qb += kAdjThreads) c += boxes_meet(a, box[qb], ix, iy) ? 1u : 0u;
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    if ((tid & 63) == 0) wsum[tid >> 6] = c;
+    __syncthreads();
+    if (tid == 0) {
+        unsigned t = 0;
+        for (int w = 0; w < kAdjThreads / 64; ++w) t += wsum[w];
+        rowcnt[pb] = t;
+    }
+}
+
+struct CullLaunch {
+    const float4 *box;       // [nb]
+    const unsigned *rowoff;  // [nb + 1]: exclusive prefix of rowcnt, rowoff[nb] = visited tiles
+    int64_t nb;
+};
+
+template <int K>
+__global__ __launch_bounds__(kAdjThreads) void lscv_cull_kernel(LscvLaunch p, CullLaunch c) {
+    __shared__ float2 qs[kAdjThreads];
+    __shared__ double red[6][kAdjThreads];
+    __shared__ int64_t list[kAdjThreads];
+    __shared__ unsigned wsum[kAdjThreads / 64];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const uint64_t total = c.rowoff[c.nb];
+    const uint64_t t0 = total * blockIdx.x / gridDim.x, t1 = total * (blockIdx.x + 1) / gridDim.x;
+    if (t0 < t1) {
+        // Row holding tile t0: the last pb with rowoff[pb] <= t0.
+        int64_t lo = 0, hi = c.nb - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) / 2;
+            if ((uint64_t)c.rowoff[mid] <= t0) lo = mid;
+            else hi = mid - 1;
+        }
+        int64_t pb = lo, cand = pb;
+        uint64_t skip = t0 - c.rowoff[pb], t = t0;
+        float4 a = c.box[pb];
+        int64_t pi = pb * kAdjThreads + tid;
+        float2 me = pi < p.n ? p.pts[pi] : make_float2(0.0f, 0.0f);
+        while (t < t1) {
+            if (cand >= c.nb) {  // row done: the next row starts at its diagonal tile
+                if (++pb >= c.nb) break;  // not reached: every tile of [t0, t1) lies in a row below nb
+                cand = pb;
+                a = c.box[pb];
+                pi = pb * kAdjThreads + tid;
+                me = pi < p.n ? p.pts[pi] : make_float2(0.0f, 0.0f);
+            }
+            // Compact the next 256 candidates of the row that meet the p-block.
+            const int64_t qb = cand + tid;
+            const bool hit = qb < c.nb && boxes_meet(a, c.box[qb], p.ix, p.iy);
+            const uint64_t bal = __ballot(hit);
+            __syncthreads();  // list and wsum of the previous group consumed
+            if (lane == 0) wsum[wave] = (unsigned)__popcll(bal);
+            __syncthreads();
+            unsigned before = 0, count = 0;
+            for (int w = 0; w < kAdjThreads / 64; ++w) {
+                before += w < wave ? wsum[w] : 0u;
+                count += wsum[w];
+            }
+            if (hit) list[before + __popcll(bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))))] = qb;
+            __syncthreads();
+            cand += kAdjThreads;
+            if (skip >= count) {
+                skip -= count;
+                continue;
+            }
+            for (unsigned k = (unsigned)skip; k < count && t < t1; ++k, ++t) {
+                const int64_t q = list[k];
+                const int64_t qi = q * kAdjThreads + tid;
+                __syncthreads();  // previous tile consumed
+                qs[tid] = qi < p.n ? p.pts[qi] : make_float2(kFarAdj, kFarAdj);
+                __syncthreads();
+                if (pi < p.n) lscv_tile<K>(p, me, q == pb, qs, tid, S);
+            }
+            skip = 0;
+        }
+    }
+    lscv_store(S, red, p.part, tid);
 }
 
 }  // namespace
@@ -449,31 +605,113 @@ hipError_t launch_vjp(const float2 *pts, int64_t n, int kernel_id, float Hx, flo
     return hipGetLastError();
 }
 
-int64_t lscv_blocks(int64_t n) {
+namespace {
+
+constexpr int64_t kCullGroups = 2048;  // workgroups of the culled pass (equal runs of the visited tiles)
+
+// Compact kernels use the culled pass while the tile count fits the 32-bit scan.
+bool lscv_culled(int64_t n, int kernel_id) {
+    const int64_t nb = (n + kAdjThreads - 1) / kAdjThreads;
+    return kernel_id != kGaussian && nb * (nb + 1) / 2 < (int64_t(1) << 32);
+}
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Culled-pass workspace: [part][sorted points][boxes][row counts][scan totals][sort scratch].
+struct CullPlan {
+    int64_t nb, groups;
+    size_t part, sorted, box, rowcnt, totals, sort;
+};
+
+CullPlan cull_plan(int64_t n) {
+    CullPlan pl;
+    pl.nb = (n + kAdjThreads - 1) / kAdjThreads;
+    pl.groups = std::max<int64_t>(1, std::min<int64_t>(kCullGroups, pl.nb * (pl.nb + 1) / 2));
+    pl.part = align256((size_t)pl.groups * 6 * sizeof(double));
+    pl.sorted = align256((size_t)n * sizeof(float2));
+    pl.box = align256((size_t)pl.nb * sizeof(float4));
+    pl.rowcnt = align256((size_t)(pl.nb + 1) * sizeof(unsigned));
+    pl.totals = align256(scan_u32_totals_bytes(pl.nb + 1));
+    pl.sort = spatial_sort_bytes(n);
+    return pl;
+}
+
+template <int K>
+void launch_cull_k(const LscvLaunch &p, const CullLaunch &c, int64_t groups, hipStream_t s) {
+    hipLaunchKernelGGL(lscv_cull_kernel<K>, dim3((unsigned)groups), dim3(kAdjThreads), 0, s, p, c);
+}
+
+template <int K>
+void launch_all_k(const LscvLaunch &p, const LscvPlan &pl, hipStream_t s) {
+    hipLaunchKernelGGL(lscv_kernel<K>, dim3((unsigned)(pl.units * pl.chunks)), dim3(kAdjThreads), 0, s, p, pl.nb,
+                       pl.chunks);
+}
+
+template <template <int> class F, class... A>
+hipError_t by_kernel(int kernel_id, A &&...args) {
+    switch (kernel_id) {
+    case kUniform: F<kUniform>::run(args...); break;
+    case kTriangular: F<kTriangular>::run(args...); break;
+    case kEpanechnikov: F<kEpanechnikov>::run(args...); break;
+    case kQuartic: F<kQuartic>::run(args...); break;
+    case kTriweight: F<kTriweight>::run(args...); break;
+    case kTricube: F<kTricube>::run(args...); break;
+    case kGaussian: F<kGaussian>::run(args...); break;
+    case kCosine: F<kCosine>::run(args...); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int K>
+struct CullRun {
+    static void run(const LscvLaunch &p, const CullLaunch &c, int64_t groups, hipStream_t s) {
+        launch_cull_k<K>(p, c, groups, s);
+    }
+};
+
+template <int K>
+struct AllRun {
+    static void run(const LscvLaunch &p, const LscvPlan &pl, hipStream_t s) { launch_all_k<K>(p, pl, s); }
+};
+
+}  // namespace
+
+int64_t lscv_blocks(int64_t n, int kernel_id) {
+    if (lscv_culled(n, kernel_id)) return cull_plan(n).groups;
     const LscvPlan pl = lscv_plan(n);
     return pl.units * pl.chunks;
 }
 
-hipError_t launch_lscv(const float2 *pts, int64_t n, int kernel_id, float Hx, float Hy, double *part,
+size_t lscv_workspace_bytes(int64_t n, int kernel_id) {
+    if (!lscv_culled(n, kernel_id)) return (size_t)lscv_blocks(n, kernel_id) * 6 * sizeof(double);
+    const CullPlan pl = cull_plan(n);
+    return pl.part + pl.sorted + pl.box + pl.rowcnt + pl.totals + pl.sort;
+}
+
+hipError_t launch_lscv(const float2 *pts, int64_t n, int kernel_id, float Hx, float Hy, int nx, int ny, void *ws,
                        hipStream_t stream) {
+    double *part = static_cast<double *>(ws);
     LscvLaunch p{pts, n, (float)(1.0 / ((double)Hx * Hx)), (float)(1.0 / ((double)Hy * Hy)), (float)(1.0 / (double)Hx),
                  (float)(1.0 / (double)Hy), part};
-    const LscvPlan pl = lscv_plan(n);
-    const dim3 grid((unsigned)(pl.units * pl.chunks)), block(kAdjThreads);
-    switch (kernel_id) {
-    case kUniform: hipLaunchKernelGGL(lscv_kernel<kUniform>, grid, block, 0, stream, p, pl.nb, pl.chunks); break;
-    case kTriangular: hipLaunchKernelGGL(lscv_kernel<kTriangular>, grid, block, 0, stream, p, pl.nb, pl.chunks); break;
-    case kEpanechnikov:
-        hipLaunchKernelGGL(lscv_kernel<kEpanechnikov>, grid, block, 0, stream, p, pl.nb, pl.chunks);
-        break;
-    case kQuartic: hipLaunchKernelGGL(lscv_kernel<kQuartic>, grid, block, 0, stream, p, pl.nb, pl.chunks); break;
-    case kTriweight: hipLaunchKernelGGL(lscv_kernel<kTriweight>, grid, block, 0, stream, p, pl.nb, pl.chunks); break;
-    case kTricube: hipLaunchKernelGGL(lscv_kernel<kTricube>, grid, block, 0, stream, p, pl.nb, pl.chunks); break;
-    case kGaussian: hipLaunchKernelGGL(lscv_kernel<kGaussian>, grid, block, 0, stream, p, pl.nb, pl.chunks); break;
-    case kCosine: hipLaunchKernelGGL(lscv_kernel<kCosine>, grid, block, 0, stream, p, pl.nb, pl.chunks); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    if (!lscv_culled(n, kernel_id)) return by_kernel<AllRun>(kernel_id, p, lscv_plan(n), stream);
+    const CullPlan pl = cull_plan(n);
+    char *w = static_cast<char *>(ws) + pl.part;
+    float2 *sorted = reinterpret_cast<float2 *>(w);
+    float4 *box = reinterpret_cast<float4 *>(w + pl.sorted);
+    unsigned *rowcnt = reinterpret_cast<unsigned *>(w + pl.sorted + pl.box);
+    unsigned *totals = reinterpret_cast<unsigned *>(w + pl.sorted + pl.box + pl.rowcnt);
+    void *sort_ws = w + pl.sorted + pl.box + pl.rowcnt + pl.totals;
+    hipError_t e = launch_spatial_sort(pts, n, spatial_sort_cell(Hx, Hy, nx, ny), sort_ws, sorted, stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(block_box_kernel, dim3((unsigned)pl.nb), dim3(kAdjThreads), 0, stream, sorted, n, box);
+    hipLaunchKernelGGL(tile_count_kernel, dim3((unsigned)pl.nb), dim3(kAdjThreads), 0, stream, box, pl.nb, p.ix, p.iy,
+                       rowcnt);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_fill_zero(reinterpret_cast<float *>(rowcnt + pl.nb), 1, stream)) != hipSuccess) return e;
+    if ((e = launch_scan_u32(rowcnt, pl.nb + 1, totals, stream)) != hipSuccess) return e;
+    p.pts = sorted;
+    return by_kernel<CullRun>(kernel_id, p, CullLaunch{box, rowcnt, pl.nb}, pl.groups, stream);
 }
 
 }  // namespace kde

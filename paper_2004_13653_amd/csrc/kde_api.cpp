@@ -727,12 +727,12 @@ int kde_lscv(const float *points, int64_t n, int32_t kernel_id, double hx, doubl
         if (value == nullptr) return fail(KDE_EINVAL, "kde_lscv: value is NULL");
         hipStream_t s = static_cast<hipStream_t>(stream);
         const float Hx = (float)(hx / g->dx), Hy = (float)(hy / g->dy);
-        const int64_t blocks = kde::lscv_blocks(n);
+        const int64_t blocks = kde::lscv_blocks(n, kernel_id);
         void *ws = nullptr;
-        st = get_workspace(s, (size_t)blocks * 6 * sizeof(double), &ws);
+        st = get_workspace(s, kde::lscv_workspace_bytes(n, kernel_id), &ws);
         if (st != KDE_OK) return st;
-        hipError_t e = kde::launch_lscv(reinterpret_cast<const float2 *>(points), n, kernel_id, Hx, Hy,
-                                        static_cast<double *>(ws), s);
+        hipError_t e = kde::launch_lscv(reinterpret_cast<const float2 *>(points), n, kernel_id, Hx, Hy, g->nx, g->ny,
+                                        ws, s);
         if (e != hipSuccess) return hip_fail(e, "kde_lscv");
         std::vector<double> part((size_t)blocks * 6);
         e = hipMemcpyAsync(part.data(), ws, part.size() * sizeof(double), hipMemcpyDeviceToHost, s);

@@ -162,13 +162,26 @@ void release_batched_graphs();
 // Adjoints.  launch_vjp writes grad[n][2] = (fx Tx_p, fy Ty_p) (if grad is not
 // null) and per-workgroup FP64 sums (Ux, Uy, Q) into part[vjp_blocks(n)][3];
 // launch_lscv writes per-workgroup FP64 sums (SA, SAX, SAY, SB, SBX, SBY) into
-// part[lscv_blocks(n)][6].  See kde_adjoint.hip for the definitions.
+// part[lscv_blocks(n, kernel_id)][6].  See kde_adjoint.hip for the definitions.
 int64_t vjp_blocks(int64_t n);
 hipError_t launch_vjp(const float2 *pts, int64_t n, int kernel_id, float Hx, float Hy, const float *gbar, int nx,
                       int ny, float fx, float fy, float *grad, double *part, hipStream_t stream);
-int64_t lscv_blocks(int64_t n);
-hipError_t launch_lscv(const float2 *pts, int64_t n, int kernel_id, float Hx, float Hy, double *part,
+// launch_lscv needs lscv_workspace_bytes of workspace and leaves the
+// lscv_blocks partial rows at its start.  Compact kernels visit only the tiles
+// of spatially sorted points whose pairs can be in support (nx, ny fix the
+// sort's cell grid, a locality heuristic with no effect on the sums).
+int64_t lscv_blocks(int64_t n, int kernel_id);
+size_t lscv_workspace_bytes(int64_t n, int kernel_id);
+hipError_t launch_lscv(const float2 *pts, int64_t n, int kernel_id, float Hx, float Hy, int nx, int ny, void *ws,
                        hipStream_t stream);
+
+// Spatial sort (kde_sort.hip): out[n] = the points ordered by the Z-order code
+// of their cell (square cells of side `cell` grid units, 1024 per axis from the
+// origin, outside points clamped to the border cells), stable, deterministic.
+size_t spatial_sort_bytes(int64_t n);
+hipError_t launch_spatial_sort(const float2 *pts, int64_t n, float cell, void *ws, float2 *out, hipStream_t s);
+// Cell side for bandwidths Hx, Hy on an nx x ny grid: max(Hx, Hy), at least 1/1024 of the grid.
+float spatial_sort_cell(float Hx, float Hy, int nx, int ny);
 
 // out[i] = scale * sum_{s < splits} part[s * plane + i], summed in split order.
 hipError_t launch_reduce_splits(const float *part, int splits, int64_t plane, float scale, float *out,

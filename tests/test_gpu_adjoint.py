@@ -197,10 +197,12 @@ def test_lscv_value_and_gradient(kernel, hdeg):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("kernel", [6, 2])
+@pytest.mark.parametrize("kernel", [6, 2, 5, 0])
 def test_lscv_50k_points(kernel):
     """50,000 lane points (100 tracks x 500) at h = (0.004, 0.0052) deg on the
-    512 x 512 grid's units: 2.5*10^9 ordered pairs against the oracle."""
+    512 x 512 grid's units: 2.5*10^9 ordered pairs against the oracle (the
+    Gaussian over all pairs, the compact kernels over the support-culled tiles
+    of the spatially sorted points)."""
     t = kt.lanes(100, 500)
     g, og = kt.grids(synth.BOX_C2, 512, 512)
     _lscv_against_oracle(kde.to_grid_units(t.xy, g), kernel, 0.004, 1.3 * 0.004, g, og)
@@ -249,6 +251,22 @@ def test_lscv_ragged_point_counts(n):
         ref_g = np.array([gu[0] * float(Hx) ** 2 * float(Hy) / (h * h * 1.2 * h),
                           gu[1] * float(Hx) * float(Hy) ** 2 / (h * 1.2 * h * 1.2 * h)])
         assert np.all(np.abs(np.array(gh) - ref_g) <= GRAD_GATE * np.abs(ref_g)), (kernel, gh, ref_g)
+
+
+@pytest.mark.parametrize("kernel", [5, 2, 7])
+def test_lscv_culled_points_off_grid_and_coincident(kernel):
+    """Support culling with points far outside the grid (their sort cells are
+    clamped to the border cells), with all points coincident (every tile in
+    support) and with two distant clusters (most tiles skipped), against the
+    oracle."""
+    rng = np.random.default_rng(40 + kernel)
+    g = kde.Grid(0.0, 1.0, 0.0, 1.0, 128, 128)
+    og = oracle.Grid(0.0, 1.0, 0.0, 1.0, 128, 128)
+    spread = rng.uniform(-300.0, 450.0, (3000, 2)).astype(np.float32)
+    same = np.full((700, 2), 17.25, dtype=np.float32)
+    two = np.concatenate([rng.normal(10.0, 1.0, (900, 2)), rng.normal(100.0, 1.0, (1100, 2))]).astype(np.float32)
+    for XY, h in ((spread, 0.2), (same, 0.02), (two, 0.03)):
+        _lscv_against_oracle(XY, kernel, h, 1.3 * h, g, og)
 
 
 def test_lscv_autograd_and_edge_cases():
