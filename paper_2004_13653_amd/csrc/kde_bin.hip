@@ -6,20 +6,24 @@
 // counting-sorted into per-tile bins:
 //
 //   1. count:   every point adds 1 to cnt[tile][w] for each tile it reaches,
-//               where w is its 64-point wave block (integer atomics: the counts
-//               do not depend on their order);
+//               where w is its block of 1024 consecutive points (integer
+//               atomics: the counts do not depend on their order);
 //   2. scan:    exclusive prefix sum over cnt in tile-major order gives each
 //               (tile, wave block) its first slot (the paper's work-efficient
 //               scan pattern, Sec. IV-A: per-block scans, a scan of the block
 //               totals, then a propagation pass);
-//   3. scatter: each wave walks its 64 points and their tiles in a fixed order
-//               and assigns slots with ballots (lanes with the same tile take
-//               consecutive slots in lane order), so the bin contents and their
-//               order are the same on every run;
-//   4. gather:  one workgroup per (tile, split) sums its share of the tile's bin
+//   3. scatter: one wave per block walks its points 64 at a time, and each
+//               64's tiles in a fixed order, assigning slots with ballots (lanes
+//               with the same tile take consecutive slots in lane order), so the
+//               bin contents and their order (point order) are the same on every
+//               run;
+//   4. gather:  each tile's bin is cut into items of at most M entries (dense
+//               tiles, e.g. at anchorages, get many; M from the bound on all
+//               entries, aiming at ~2048 items), one workgroup per item sums it
 //               with the register-tiled kernel of the direct path (no culling
-//               needed; the per-pair support test remains), partial maps are
-//               added in split order.
+//               needed; the per-pair support test remains); a tile with one item
+//               writes the map directly, the others write partial tiles that a
+//               last pass adds in item order.
 #include "kde_tile.h"
 
 #include <algorithm>
@@ -29,12 +33,14 @@ namespace kde {
 namespace {
 
 constexpr int kScanBlock = 1024;
+constexpr int kColBlock = 1024;   // points per count column (one wave each in the scatter)
+constexpr int kTargetItems = 2048;
 
 struct BinGeom {
     int nx, ny, tiles_x, tiles_y;
     int tile;  // tile side in nodes
     float Hx, Hy;
-    int64_t n, wblocks;  // points, 64-point wave blocks
+    int64_t n, wblocks;  // points, kColBlock-point blocks (count columns)
 };
 
 // Tile rectangle a point reaches (empty when tx0 > tx1 or ty0 > ty1).
@@ -56,7 +62,7 @@ __global__ __launch_bounds__(256) void bin_count_kernel(BinGeom g, const float2 
                                                         unsigned *__restrict__ cnt) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= g.n) return;
-    const int64_t w = p >> 6;
+    const int64_t w = p / kColBlock;
     int tx0, tx1, ty0, ty1;
     reach(g, pts[p], tx0, tx1, ty0, ty1);
     for (int ty = ty0; ty <= ty1; ++ty)
@@ -127,51 +133,74 @@ __global__ __launch_bounds__(256) void scan_add_kernel(unsigned *__restrict__ a,
     if (i < len) a[i] += totals[i / kScanBlock];
 }
 
-// Scatter: one wave per 64-point block.  off[] holds the (tile, block) start
-// slots and is advanced in place (each column belongs to one wave), so that
-// afterwards off[t][w] is the end of segment (t, w).
+// Scatter: one wave per kColBlock-point block, 64 points per step in point
+// order.  off[] holds the (tile, block) start slots and is advanced in place
+// (each column belongs to one wave), so that afterwards off[t][w] is the end of
+// segment (t, w).
 __global__ __launch_bounds__(256) void bin_scatter_kernel(BinGeom g, const float2 *__restrict__ pts,
                                                           unsigned *__restrict__ off, float2 *__restrict__ bins) {
     const int lane = threadIdx.x & 63;
     const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (w >= g.wblocks) return;  // whole wave
-    const int64_t p = w * 64 + lane;
-    const bool valid = p < g.n;
-    const float2 v = valid ? pts[p] : make_float2(0.0f, 0.0f);
-    int tx0 = 1, tx1 = 0, ty0 = 1, ty1 = 0;
-    if (valid) reach(g, v, tx0, tx1, ty0, ty1);
-    const int ncols = tx1 >= tx0 ? tx1 - tx0 + 1 : 0;
-    const int ntl = ncols > 0 && ty1 >= ty0 ? ncols * (ty1 - ty0 + 1) : 0;
-    int most = ntl;
-    for (int o = 32; o > 0; o >>= 1) most = max(most, __shfl_xor(most, o));
-    for (int j = 0; j < most; ++j) {  // j-th tile of every lane, raster order within its rectangle
-        int key = -1;
-        if (j < ntl) key = (ty0 + j / ncols) * g.tiles_x + tx0 + j % ncols;
-        uint64_t pending = __ballot(key >= 0);
-        while (pending) {
-            const int leader = __ffsll((unsigned long long)pending) - 1;
-            const int lkey = __shfl(key, leader);
-            const uint64_t same = __ballot(key == lkey);
-            // Only this wave touches column w, so the atomic just returns the
-            // current cursor and advances it, in this wave's program order.
-            unsigned base = 0;
-            if (lane == leader) base = atomicAdd(&off[(int64_t)lkey * g.wblocks + w], (unsigned)__popcll(same));
-            base = __shfl(base, leader);
-            if (key == lkey) bins[base + (unsigned)__popcll(same & ((1ull << lane) - 1ull))] = v;
-            pending &= ~same;
+    const uint64_t below = (1ull << lane) - 1ull;
+    for (int step = 0; step < kColBlock / 64; ++step) {
+        const int64_t p = w * kColBlock + step * 64 + lane;
+        if (w * kColBlock + step * 64 >= g.n) break;  // whole wave
+        const bool valid = p < g.n;
+        const float2 v = valid ? pts[p] : make_float2(0.0f, 0.0f);
+        int tx0 = 1, tx1 = 0, ty0 = 1, ty1 = 0;
+        if (valid) reach(g, v, tx0, tx1, ty0, ty1);
+        const int ncols = tx1 >= tx0 ? tx1 - tx0 + 1 : 0;
+        const int ntl = ncols > 0 && ty1 >= ty0 ? ncols * (ty1 - ty0 + 1) : 0;
+        int most = ntl;
+        for (int o = 32; o > 0; o >>= 1) most = max(most, __shfl_xor(most, o));
+        for (int j = 0; j < most; ++j) {  // j-th tile of every lane, raster order within its rectangle
+            int key = -1;
+            if (j < ntl) key = (ty0 + j / ncols) * g.tiles_x + tx0 + j % ncols;
+            uint64_t pending = __ballot(key >= 0);
+            while (pending) {
+                const int leader = __ffsll((unsigned long long)pending) - 1;
+                const int lkey = __shfl(key, leader);
+                const uint64_t same = __ballot(key == lkey);
+                // Only this wave touches column w, so the atomic just returns the
+                // current cursor and advances it, in this wave's program order.
+                unsigned base = 0;
+                if (lane == leader) base = atomicAdd(&off[(int64_t)lkey * g.wblocks + w], (unsigned)__popcll(same));
+                base = __shfl(base, leader);
+                if (key == lkey) bins[base + (unsigned)__popcll(same & below)] = v;
+                pending &= ~same;
+            }
         }
     }
 }
 
+// Items: item_off[t] (exclusive prefix over tiles, item_off[tiles] = all items)
+// is the first item of tile t; tile t's bin is cut into item_off[t+1] -
+// item_off[t] equal parts.
+__global__ __launch_bounds__(256) void item_count_kernel(const unsigned *__restrict__ end, int64_t wblocks, int tiles,
+                                                         int64_t per_item, unsigned *__restrict__ cnt) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > tiles) return;
+    if (t == tiles) {
+        cnt[t] = 0u;
+        return;
+    }
+    const int64_t e = end[(int64_t)t * wblocks + wblocks - 1];
+    const int64_t b = t > 0 ? (int64_t)end[(int64_t)t * wblocks - 1] : 0;
+    const int64_t c = (e - b + per_item - 1) / per_item;
+    cnt[t] = (unsigned)(c > 1 ? c : 1);
+}
+
 struct GatherLaunch {
     const float2 *bins;
-    const unsigned *end;  // after the scatter, end[t * wblocks + wblocks - 1] is the end of tile t's bin
+    const unsigned *end;       // after the scatter, end[t * wblocks + wblocks - 1] is the end of tile t's bin
+    const unsigned *item_off;  // [tiles + 1]
     int64_t wblocks;
     float Hx, Hy, ax, ay;
-    int nx, ny, tiles_x;
-    float *dst;   // final map (one split) or partials [splits][ny][nx]
+    int nx, ny, tiles_x, tiles;
+    float *out;                // the map
+    float *part;               // [items][TH][TW] partial tiles of tiles with several items
     float scale;
-    int64_t plane;
 };
 
 template <int K, int RC, bool kRuns>
@@ -179,26 +208,54 @@ __global__ __launch_bounds__(tile::kThreads) void bin_gather_kernel(GatherLaunch
     using S = tile::Shape<K, RC>;
     __shared__ float2 sp[tile::kPointTile];
     __shared__ int swave[tile::kThreads / 64];
-    const int t = blockIdx.x, tid = threadIdx.x;
+    const int64_t item = blockIdx.x;
+    if (item >= (int64_t)p.item_off[p.tiles]) return;  // whole workgroup: beyond the items of this map
+    int lo_t = 0, hi_t = p.tiles - 1;  // tile of this item: the last t with item_off[t] <= item
+    while (lo_t < hi_t) {
+        const int mid = (lo_t + hi_t + 1) / 2;
+        if ((int64_t)p.item_off[mid] <= item) lo_t = mid;
+        else hi_t = mid - 1;
+    }
+    const int t = lo_t, tid = threadIdx.x;
+    const int64_t k = item - p.item_off[t], parts = (int64_t)p.item_off[t + 1] - p.item_off[t];
     const int64_t e = p.end[(int64_t)t * p.wblocks + p.wblocks - 1];
     const int64_t b = t > 0 ? (int64_t)p.end[(int64_t)t * p.wblocks - 1] : 0;
-    const int64_t len = e - b, parts = gridDim.y;
-    const int64_t lo = b + len * blockIdx.y / parts, hi = b + len * (blockIdx.y + 1) / parts;
+    const int64_t len = e - b;
+    const int64_t lo = b + len * k / parts, hi = b + len * (k + 1) / parts;
     const int x0 = (t % p.tiles_x) * S::TW, y0 = (t / p.tiles_x) * S::TH;
     const int ib = x0 + (tid & 15) * S::C, jb = y0 + (tid >> 4) * S::R;
     float tot[S::R][S::C];
     tile::tile_sums<K, S::R, S::C, false, kRuns>(p.bins, lo, hi, p.Hx, p.Hy, p.ax, p.ay, ib, jb, 0.0f, 0.0f, 0.0f,
                                                  0.0f, sp, swave, tot);
     if constexpr (kRuns) tile::apply_run_q<S::R, S::C>(tot, p.ax, p.ay);
-    tile::store_block<S::R, S::C>(tot, p.dst + (int64_t)blockIdx.y * p.plane, p.nx, p.ny, ib, jb,
-                                  gridDim.y == 1 ? p.scale : 1.0f);
+    if (parts == 1)
+        tile::store_block<S::R, S::C>(tot, p.out, p.nx, p.ny, ib, jb, p.scale);
+    else
+        tile::store_block<S::R, S::C>(tot, p.part + item * (S::TW * S::TH), S::TW, S::TH, ib - x0, jb - y0, 1.0f);
+}
+
+// Tiles with several items: the partial tiles added in item order, scaled.
+__global__ __launch_bounds__(256) void item_reduce_kernel(const float *__restrict__ part,
+                                                          const unsigned *__restrict__ item_off, int tw, int th,
+                                                          int tiles_x, int nx, int ny, float scale,
+                                                          float *__restrict__ out) {
+    const int t = blockIdx.x;
+    const int64_t i0 = item_off[t], i1 = item_off[t + 1];
+    if (i1 - i0 <= 1) return;
+    const int x0 = (t % tiles_x) * tw, y0 = (t / tiles_x) * th;
+    for (int e = threadIdx.x; e < tw * th; e += blockDim.x) {
+        const int i = x0 + e % tw, j = y0 + e / tw;
+        float s = 0.0f;
+        for (int64_t it = i0; it < i1; ++it) s += part[it * (tw * th) + e];
+        if (i < nx && j < ny) out[(int64_t)j * nx + i] = s * scale;
+    }
 }
 
 struct BinPlan {
     BinGeom g;
     int64_t cnt_len, scan_blocks, max_entries;
-    int splits;
-    size_t off_bytes, totals_bytes, bins_bytes, part_bytes;
+    int64_t per_item, max_items;
+    size_t off_bytes, totals_bytes, bins_bytes, item_bytes, item_totals_bytes, part_bytes;
 };
 
 BinPlan bin_plan(const MapArgs &a, int T) {
@@ -211,7 +268,7 @@ BinPlan bin_plan(const MapArgs &a, int T) {
     pl.g.Hx = a.Hx;
     pl.g.Hy = a.Hy;
     pl.g.n = a.n;
-    pl.g.wblocks = (a.n + 63) / 64;
+    pl.g.wblocks = (a.n + kColBlock - 1) / kColBlock;
     pl.cnt_len = (int64_t)pl.g.tiles_x * pl.g.tiles_y * pl.g.wblocks;
     pl.scan_blocks = (pl.cnt_len + kScanBlock - 1) / kScanBlock;
     // Tiles a point can reach per axis: its support spans at most 2H + 1 nodes.
@@ -219,35 +276,40 @@ BinPlan bin_plan(const MapArgs &a, int T) {
     const int64_t ry = std::min<int64_t>(pl.g.tiles_y, (int64_t)(2.0f * a.Hy) / T + 2);
     pl.max_entries = a.n * rx * ry;
     const int64_t tiles = (int64_t)pl.g.tiles_x * pl.g.tiles_y;
-    pl.splits = (int)std::max<int64_t>(1, std::min<int64_t>(8, 2048 / std::max<int64_t>(1, tiles)));
+    // Items of at most per_item entries: each tile has max(1, ceil(len / per_item))
+    // <= 1 + len / per_item of them, so at most tiles + max_entries / per_item.
+    pl.per_item = std::max<int64_t>(1024, (pl.max_entries / kTargetItems + 255) / 256 * 256);
+    pl.max_items = tiles + pl.max_entries / pl.per_item;
     pl.off_bytes = (size_t)pl.cnt_len * sizeof(unsigned);
     pl.totals_bytes = (size_t)(pl.scan_blocks + 1) * sizeof(unsigned);
     pl.bins_bytes = (size_t)pl.max_entries * sizeof(float2);
-    pl.part_bytes = pl.splits > 1 ? (size_t)pl.splits * a.nx * a.ny * sizeof(float) : 0;
+    pl.item_bytes = (size_t)(tiles + 1) * sizeof(unsigned);
+    pl.item_totals_bytes = scan_u32_totals_bytes(tiles + 1);
+    pl.part_bytes = (size_t)pl.max_items * T * T * sizeof(float);
     return pl;
 }
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 template <int K, int RC>
-hipError_t launch_gather_r(const GatherLaunch &p, int tiles, int splits, hipStream_t s) {
+hipError_t launch_gather_r(const GatherLaunch &p, int64_t items, hipStream_t s) {
     main_kernel_begin(s);
     // the truncated Gaussian takes the runs of the Gaussian (two exp2 per run, then the support mask)
     if (K == kGaussTrunc && p.ax <= kMaxRunScale && p.ay <= kMaxRunScale)
-        hipLaunchKernelGGL((bin_gather_kernel<K, RC, K == kGaussTrunc>), dim3(tiles, splits), dim3(tile::kThreads), 0,
-                           s, p);
+        hipLaunchKernelGGL((bin_gather_kernel<K, RC, K == kGaussTrunc>), dim3((unsigned)items), dim3(tile::kThreads),
+                           0, s, p);
     else
-        hipLaunchKernelGGL((bin_gather_kernel<K, RC, false>), dim3(tiles, splits), dim3(tile::kThreads), 0, s, p);
+        hipLaunchKernelGGL((bin_gather_kernel<K, RC, false>), dim3((unsigned)items), dim3(tile::kThreads), 0, s, p);
     main_kernel_end(s);
     return hipGetLastError();
 }
 
 template <int K>
-hipError_t launch_gather(const GatherLaunch &p, int rc, int tiles, int splits, hipStream_t s) {
+hipError_t launch_gather(const GatherLaunch &p, int rc, int64_t items, hipStream_t s) {
     switch (rc) {
-    case 2: return launch_gather_r<K, 2>(p, tiles, splits, s);
-    case 4: return launch_gather_r<K, 4>(p, tiles, splits, s);
-    case 8: return launch_gather_r<K, 8>(p, tiles, splits, s);
+    case 2: return launch_gather_r<K, 2>(p, items, s);
+    case 4: return launch_gather_r<K, 4>(p, items, s);
+    case 8: return launch_gather_r<K, 8>(p, items, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -301,7 +363,7 @@ bool binning_applies(const MapArgs &a) {
 
 size_t binned_workspace_bytes(const MapArgs &a) {
     const BinPlan pl = bin_plan(a, 16 * a.rc);
-    return scatter_bytes(pl) + pl.part_bytes;
+    return scatter_bytes(pl) + align256(pl.item_bytes) + align256(pl.item_totals_bytes) + pl.part_bytes;
 }
 
 bool tile_bins_fit(const MapArgs &a, int tile) {
@@ -328,15 +390,25 @@ hipError_t launch_tile_bins(const MapArgs &a, int tile, void *ws, hipStream_t s,
 
 hipError_t launch_binned(const MapArgs &a, void *ws, hipStream_t s) {
     const BinPlan pl = bin_plan(a, 16 * a.rc);
+    const int T = 16 * a.rc;
     char *w = static_cast<char *>(ws);
-    float *part = reinterpret_cast<float *>(w + scatter_bytes(pl));
+    unsigned *item_off = reinterpret_cast<unsigned *>(w + scatter_bytes(pl));
+    unsigned *item_totals = reinterpret_cast<unsigned *>(w + scatter_bytes(pl) + align256(pl.item_bytes));
+    float *part = reinterpret_cast<float *>(w + scatter_bytes(pl) + align256(pl.item_bytes) +
+                                            align256(pl.item_totals_bytes));
     unsigned *off = nullptr;
     float2 *bins = nullptr;
     hipError_t e = scatter_bins(a, pl, w, &off, &bins, s);
     if (e != hipSuccess) return e;
+    const int tiles = pl.g.tiles_x * pl.g.tiles_y;
+    hipLaunchKernelGGL(item_count_kernel, dim3((unsigned)((tiles + 1 + 255) / 256)), dim3(256), 0, s, off,
+                       pl.g.wblocks, tiles, pl.per_item, item_off);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_scan_u32(item_off, tiles + 1, item_totals, s)) != hipSuccess) return e;
     GatherLaunch p;
     p.bins = bins;
     p.end = off;
+    p.item_off = item_off;
     p.wblocks = pl.g.wblocks;
     p.Hx = a.Hx;
     p.Hy = a.Hy;
@@ -345,23 +417,25 @@ hipError_t launch_binned(const MapArgs &a, void *ws, hipStream_t s) {
     p.nx = a.nx;
     p.ny = a.ny;
     p.tiles_x = pl.g.tiles_x;
-    p.dst = pl.splits > 1 ? part : a.out;
+    p.tiles = tiles;
+    p.out = a.out;
+    p.part = part;
     p.scale = a.scale;
-    p.plane = (int64_t)a.nx * a.ny;
-    const int tiles = pl.g.tiles_x * pl.g.tiles_y;
     switch (a.kernel_id) {
-    case kUniform: e = launch_gather<kUniform>(p, a.rc, tiles, pl.splits, s); break;
-    case kTriangular: e = launch_gather<kTriangular>(p, a.rc, tiles, pl.splits, s); break;
-    case kEpanechnikov: e = launch_gather<kEpanechnikov>(p, a.rc, tiles, pl.splits, s); break;
-    case kQuartic: e = launch_gather<kQuartic>(p, a.rc, tiles, pl.splits, s); break;
-    case kTriweight: e = launch_gather<kTriweight>(p, a.rc, tiles, pl.splits, s); break;
-    case kTricube: e = launch_gather<kTricube>(p, a.rc, tiles, pl.splits, s); break;
-    case kCosine: e = launch_gather<kCosine>(p, a.rc, tiles, pl.splits, s); break;
-    case kGaussTrunc: e = launch_gather<kGaussTrunc>(p, a.rc, tiles, pl.splits, s); break;
+    case kUniform: e = launch_gather<kUniform>(p, a.rc, pl.max_items, s); break;
+    case kTriangular: e = launch_gather<kTriangular>(p, a.rc, pl.max_items, s); break;
+    case kEpanechnikov: e = launch_gather<kEpanechnikov>(p, a.rc, pl.max_items, s); break;
+    case kQuartic: e = launch_gather<kQuartic>(p, a.rc, pl.max_items, s); break;
+    case kTriweight: e = launch_gather<kTriweight>(p, a.rc, pl.max_items, s); break;
+    case kTricube: e = launch_gather<kTricube>(p, a.rc, pl.max_items, s); break;
+    case kCosine: e = launch_gather<kCosine>(p, a.rc, pl.max_items, s); break;
+    case kGaussTrunc: e = launch_gather<kGaussTrunc>(p, a.rc, pl.max_items, s); break;
     default: return hipErrorInvalidValue;
     }
-    if (e != hipSuccess || pl.splits == 1) return e;
-    return launch_reduce_splits(part, pl.splits, (int64_t)a.nx * a.ny, a.scale, a.out, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(item_reduce_kernel, dim3((unsigned)tiles), dim3(256), 0, s, part,
+                       static_cast<const unsigned *>(item_off), T, T, pl.g.tiles_x, a.nx, a.ny, a.scale, a.out);
+    return hipGetLastError();
 }
 
 }  // namespace kde
