@@ -68,9 +68,26 @@ def timed_steps(torch, fn, steps: int, warmup: int, kde=None):
     return ev[0].elapsed_time(ev[-1]), per, kern
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+# Unit roundoff of the factor formats: FP16 has 11 significant bits, BF16 8.
+UNIT_ROUNDOFF = {"fp16": 2.0 ** -11, "bf16": 2.0 ** -8}
+
+
 def cpu_baseline(XY, y_maps, og, budget_s: float):
     """The FP64 oracle on the host cores over a bounded pixel sample of the same
-    workload (all 4M points per pixel), plus the GPU maps' errors there."""
+    workload (all 4M points per pixel), on every core and on one; the GPU maps'
+    errors there; and the rounding-error model of the single-pass matrix-core
+    maps on the peak crop."""
     import numpy as np
 
     import oracle
@@ -95,6 +112,15 @@ def cpu_baseline(XY, y_maps, og, budget_s: float):
     ij = np.concatenate(done_ij)
     r = np.concatenate(vals)
     pairs = ij.shape[0] * XY.shape[0]
+    threads = oracle.num_threads()
+    # one core: the peak 7 x 7 neighbourhood
+    oracle.set_num_threads(1)
+    try:
+        t1 = time.perf_counter()
+        oracle.map_units_at(XY, oracle.GAUSSIAN, Hx, Hy, np.array(pix, dtype=np.int32))
+        dt1 = time.perf_counter() - t1
+    finally:
+        oracle.set_num_threads(threads)
     errs = {}
     for name, y in y_maps.items():
         yy = y[ij[:, 1], ij[:, 0]].astype(np.float64)
@@ -102,26 +128,96 @@ def cpu_baseline(XY, y_maps, og, budget_s: float):
     # relative L2 on a 64 x 64 crop at the peak, separable oracle
     i0, j0 = int(min(max(ip - 32, 0), SIDE - 64)), int(min(max(jp - 32, 0), SIDE - 64))
     win = (i0, i0 + 64, j0, j0 + 64)
-    rc = oracle.map_units_separable(XY, oracle.GAUSSIAN, Hx, Hy, win) * scale
+    raw = oracle.map_units_separable(XY, oracle.GAUSSIAN, Hx, Hy, win)
+    rc = raw * scale
     crop = {}
     for name, y in y_maps.items():
         e = oracle.errors(y[win[2]:win[3], win[0]:win[1]], rc)
         crop[name] = {"e_2": e["e_2"], "e_inf": e["e_inf"]}
-    base = {"value": pairs / dt, "unit": UNIT, "cores": oracle.num_threads(), "kind": "oracle",
+    # Rounding model of the single-pass paths: each factor rounded to nearest
+    # carries an independent relative error of RMS u/sqrt(3), a pair product
+    # u sqrt(2/3); a pixel's error then has RMS u sqrt(2/3) sqrt(sum_p w_p^2)
+    # against its sum S = sum_p w_p (w_p = k(s) k(t)), i.e. relative
+    # u sqrt(2/3) / sqrt(n_eff) with n_eff = S^2 / sum_p w_p^2.  For the
+    # Gaussian, w_p^2 = k(s') k(t') / (2 pi) with s' = s sqrt(2): the raw map at
+    # bandwidth H / sqrt(2).
+    w2 = oracle.map_units_separable(XY, oracle.GAUSSIAN, np.float32(Hx / np.sqrt(2.0)),
+                                    np.float32(Hy / np.sqrt(2.0)), win) / (2.0 * np.pi)
+    n_eff = raw * raw / w2
+    model = {"n_eff_median": float(np.median(n_eff)), "n_eff_min": float(n_eff.min())}
+    for name, u in UNIT_ROUNDOFF.items():
+        pred = u * np.sqrt(2.0 / 3.0) * np.sqrt(w2.sum()) / np.linalg.norm(raw)
+        model[name] = {"predicted_e_2": float(pred), "measured_e_2": crop[name]["e_2"],
+                       "measured_over_predicted": crop[name]["e_2"] / float(pred)}
+    base = {"value": pairs / dt, "unit": UNIT, "cores": threads, "kind": "oracle",
             "sample": f"FP64 direct sum over all {XY.shape[0]} points at {ij.shape[0]} pixels "
-                      f"(peak 7x7 neighbourhood + random), {dt:.1f} s"}
-    return base, errs, crop, win
+                      f"(peak 7x7 neighbourhood + random), {dt:.1f} s",
+            "one_core": {"value": len(pix) * XY.shape[0] / dt1, "cores": 1,
+                         "sample": f"the peak 7x7 neighbourhood ({len(pix)} pixels x {XY.shape[0]} points), "
+                                   f"{dt1:.1f} s"},
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "host_cpus_usable": len(os.sched_getaffinity(0))}
+    return base, errs, crop, win, model
+
+
+def transfers(torch, XY, out, map_fn, map_ms: float, pairs: float, reps: int = 5):
+    """Host <-> device copies around one map, the paper's speed-up convention
+    (both transfers counted): the points up (FP32 grid units, from pinned and
+    from pageable host memory) and the map down (into pinned memory), each the
+    median of `reps` timed copies on the current stream; end-to-end = upload
+    from pinned memory + map + download."""
+    import numpy as np
+    stream = torch.cuda.current_stream()
+    dev_pts = torch.empty(XY.shape, dtype=torch.float32, device=out.device)
+    pinned = torch.from_numpy(XY).pin_memory()
+    pageable = torch.from_numpy(np.ascontiguousarray(XY))
+    host_map = torch.empty(out.shape, dtype=torch.float32).pin_memory()
+
+    def timed(fn):
+        ms = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            a.record(stream)
+            fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        return statistics.median(ms)
+
+    up_pinned = timed(lambda: dev_pts.copy_(pinned, non_blocking=True))
+    up_pageable = timed(lambda: dev_pts.copy_(pageable))
+    down = timed(lambda: host_map.copy_(out, non_blocking=True))
+    e2e = up_pinned + map_ms + down
+    return {"points_bytes": int(XY.nbytes), "map_bytes": int(out.numel() * 4), "h2d_pinned_ms": up_pinned,
+            "h2d_pageable_ms": up_pageable, "d2h_pinned_ms": down, "map_ms": map_ms, "end_to_end_ms": e2e,
+            "end_to_end_pairs_per_s": pairs / (e2e * 1e-3)}
+
+
+def lscv_support_pairs(XY, Hx: float, Hy: float) -> float:
+    """Ordered point pairs (p = q included) with |X_p - X_q| < 2 Hx and
+    |Y_p - Y_q| < 2 Hy: the pairs whose LSCV terms can be non-zero for the
+    compact kernels (the autoconvolution's support), counted on the host."""
+    import numpy as np
+    from scipy.spatial import cKDTree
+    z = np.column_stack([XY[:, 0].astype(np.float64) / (2.0 * Hx), XY[:, 1].astype(np.float64) / (2.0 * Hy)])
+    tree = cKDTree(z)
+    return float(tree.count_neighbors(tree, 1.0 - 1e-9, p=np.inf))
 
 
 def bench_adjoint(torch, kde, synth, steps: int):
-    """Adjoint workload: 250,000 points on 512 x 512, Gaussian and Epanechnikov,
-    hx = hy = 0.004 degrees: the map VJP (L2 loss against the map of the
-    Douglas-Peucker-compressed points) and the LSCV score with its gradient."""
+    """Adjoint workload: 250,000 points on 512 x 512, hx = hy = 0.004 degrees: the
+    map VJP for the Gaussian and the Epanechnikov (L2 loss against the map of
+    the Douglas-Peucker-compressed points) and the LSCV score with its gradient
+    for all eight kernels.  LSCV work: the Gaussian evaluates every ordered pair;
+    the compact kernels' algorithmic work is the ordered pairs closer than 2H on
+    both axes (in-support pairs), reported beside the logical n^2."""
     t = synth.workload_lanes(n_tracks=500, pts=500, seed_index=3)
     tc = synth.dp_compress(t, 50.0)
     b = synth.BOX_C2
     g = kde.Grid(b.lon0, b.lon1, b.lat0, b.lat1, 512, 512)
-    pts = torch.from_numpy(kde.to_grid_units(t.xy, g)).cuda()
+    XY = kde.to_grid_units(t.xy, g)
+    pts = torch.from_numpy(XY).cuda()
     ptc = torch.from_numpy(kde.to_grid_units(tc.xy, g)).cuda()
     n = pts.shape[0]
     res = {"points": n, "grid": [512, 512], "h_deg": 0.004, "target_points": int(ptc.shape[0])}
@@ -137,23 +233,27 @@ def bench_adjoint(torch, kde, synth, steps: int):
         for _ in range(steps):
             kde.backward(pts, kname, 0.004, 0.004, g, gbar)
         ms_vjp_h = (time.perf_counter() - t0) * 1e3 / steps
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            kde.lscv(pts, kname, 0.004, 0.004, g)
-        ms_lscv = (time.perf_counter() - t0) * 1e3 / steps
         res[kname] = {"vjp_ms": ms_vjp, "vjp_pairs_per_s": n * 512 * 512 / (ms_vjp * 1e-3),
-                      "vjp_with_h_ms": ms_vjp_h, "lscv_ms": ms_lscv,
-                      "lscv_pairs_per_s": n * n / (ms_lscv * 1e-3)}
-        log(f"adjoint {kname}: vjp {ms_vjp:.2f} ms, lscv {ms_lscv:.2f} ms")
-    # LSCV of the other six kernels on the same points (one timed call each)
-    other = {}
-    for kname in ("uniform", "triangular", "quartic", "triweight", "tricube", "cosine"):
+                      "vjp_with_h_ms": ms_vjp_h}
+        log(f"adjoint {kname}: vjp {ms_vjp:.2f} ms")
+    Hx, Hy = kde.bandwidth_units(0.004, 0.004, g)
+    support = lscv_support_pairs(XY, float(Hx), float(Hy))
+    lscv = {"ordered_pairs": float(n) * n, "in_support_pairs": support}
+    for kname in kde.KERNELS:
         kde.lscv(pts, kname, 0.004, 0.004, g)
-        t0 = time.perf_counter()
-        kde.lscv(pts, kname, 0.004, 0.004, g)
-        other[kname] = (time.perf_counter() - t0) * 1e3
-    res["lscv_other_kernels_ms"] = other
-    log("lscv, other kernels: " + ", ".join(f"{k} {v:.1f} ms" for k, v in other.items()))
+        ms = []
+        for _ in range(steps):  # each call synchronises (host scalars)
+            t0 = time.perf_counter()
+            kde.lscv(pts, kname, 0.004, 0.004, g)
+            ms.append((time.perf_counter() - t0) * 1e3)
+        m = statistics.median(ms)
+        ent = {"ms": m, "logical_pairs_per_s": float(n) * n / (m * 1e-3)}
+        if kname != "gaussian":
+            ent["in_support_pairs_per_s"] = support / (m * 1e-3)
+        lscv[kname] = ent
+    res["lscv"] = lscv
+    log(f"lscv ({support:.3e} of {float(n) * n:.3e} ordered pairs within 2H): " +
+        ", ".join(f"{k} {v['ms']:.2f} ms" for k, v in lscv.items() if isinstance(v, dict)))
     return res
 
 
@@ -335,6 +435,16 @@ def metrics_cpu_baseline(synth, t, eps: float = 50.0):
             "kind": "oracle", "dtw_mean": r["dtw_mean"]}
 
 
+def map_support_pairs(XY, Hx: float, Hy: float, nx: int, ny: int) -> float:
+    """(node, point) pairs with |i - X| <= Hx and |j - Y| <= Hy on the grid: the
+    pairs a compact kernel's map evaluates (exact in FP64 from the FP32 inputs)."""
+    import numpy as np
+    X, Y = XY[:, 0].astype(np.float64), XY[:, 1].astype(np.float64)
+    cx = np.clip(np.minimum(nx - 1, np.floor(X + Hx)) - np.maximum(0, np.ceil(X - Hx)) + 1, 0, None)
+    cy = np.clip(np.minimum(ny - 1, np.floor(Y + Hy)) - np.maximum(0, np.ceil(Y - Hy)) + 1, 0, None)
+    return float(np.sum(cx * cy))
+
+
 def bench_compact(torch, kde, synth, steps: int):
     """The eight kernels on the FP32 direct path: 1,000,000 points (2,000 tracks x
     500) on 1024 x 1024, h = 0.002 degrees, raw and Douglas-Peucker-compressed at
@@ -353,13 +463,18 @@ def bench_compact(torch, kde, synth, steps: int):
         keep = kde.dp_compress(xy_m, start, eps, compact=False).keep.cpu().numpy().astype(bool)
         inputs[f"dp_{eps:g}m"] = t.xy[keep]
     res = {}
+    Hx, Hy = kde.bandwidth_units(0.002, 0.002, g)
     for name, xy in inputs.items():
-        pts = torch.from_numpy(kde.to_grid_units(xy, g)).cuda()
-        ent = {"points": int(pts.shape[0])}
+        XY = kde.to_grid_units(xy, g)
+        pts = torch.from_numpy(XY).cuda()
+        support = map_support_pairs(XY, float(Hx), float(Hy), 1024, 1024)
+        ent = {"points": int(pts.shape[0]), "in_support_pairs": support}
         for kname, kid in kde.KERNELS.items():
             tot, _, _ = timed_steps(torch, lambda: kde.eval(pts, kid, 0.002, 0.002, g, out=out), steps, 1)
             ms = tot / steps
             ent[kname] = {"ms": ms, "logical_pairs_per_s": pts.shape[0] * 1024 * 1024 / (ms * 1e-3)}
+            if kname != "gaussian":
+                ent[kname]["in_support_pairs_per_s"] = support / (ms * 1e-3)
         res[name] = ent
         log(f"kernels ({name}, {ent['points']} points): " + ", ".join(
             f"{k} {v['ms']:.2f} ms" for k, v in ent.items() if isinstance(v, dict)))
@@ -430,6 +545,7 @@ def main() -> int:
         log(f"{prec}: {ms:.3f} ms/step  {pairs / (ms * 1e-3):.3e} pairs/s")
 
     head = results["fp16"]
+    line_transfers = transfers(torch, XY, out, run("fp16"), head["ms_per_step"], pairs)
     mult = {"fp16": 1, "bf16": 1, "fp16x3": 3, "bf16x3": 3}
     for prec in mult:
         tfl = 2.0 * mult[prec] * pairs / (results[prec]["main_kernel_ms"] * 1e-3) / 1e12
@@ -460,6 +576,7 @@ def main() -> int:
                         "roofline": {"bound": "alu", "achieved": d["fp32_tflops"], "peak": PEAK_FP32_VECTOR_TFLOPS,
                                      "unit": "TFLOP/s", "frac": d["fp32_tflops"] / PEAK_FP32_VECTOR_TFLOPS}},
         "paths": results,
+        "transfers": line_transfers,
     }
     extra = [x for x in args.sections.split(",") if x and x != "none"]
     if "adjoint" in extra:
@@ -480,8 +597,9 @@ def main() -> int:
     if not args.no_cpu_baseline:
         og_mod = __import__("oracle")
         og = og_mod.Grid(b.lon0, b.lon1, b.lat0, b.lat1, SIDE, SIDE)
-        base, errs, crop, win = cpu_baseline(XY, maps, og, args.cpu_budget)
+        base, errs, crop, win, model = cpu_baseline(XY, maps, og, args.cpu_budget)
         line["cpu_baseline"] = base
+        line["mfma_error_model"] = model
         if "dp" in extra:
             line["dp"]["cpu_baseline"] = dp_cpu_baseline(synth, t)
             line["dp"]["speedup_vs_cpu_eps_50m"] = line["dp"]["cpu_baseline"]["ms"] / line["dp"]["eps_50m"]["ms"]

@@ -56,6 +56,8 @@ def lib():
         f = ctypes.c_float
         L.ko_num_threads.restype = ctypes.c_int
         L.ko_num_threads.argtypes = []
+        L.ko_set_num_threads.restype = None
+        L.ko_set_num_threads.argtypes = [ctypes.c_int]
         L.ko_k.restype = d
         L.ko_k.argtypes = [i, d]
         L.ko_dk.restype = d
@@ -89,6 +91,11 @@ def lib():
 def num_threads() -> int:
     """Threads the oracle's parallel loops use (OpenMP)."""
     return int(lib().ko_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads for the oracle's parallel loops (results do not depend on it)."""
+    lib().ko_set_num_threads(int(n))
 
 
 def _ptr(a: np.ndarray) -> int:

@@ -69,6 +69,17 @@ int ko_num_threads(void)
 #endif
 }
 
+/* Sets the number of threads of the parallel loops (n >= 1); the per-output
+ * sums do not depend on it. */
+void ko_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* One-dimensional factor k(u) of the Table I product kernels, in Table I order.
  * The indicator I(u) is 1 for |u| <= 1 (inclusive) and the Gaussian has none. */
 double ko_k(int kernel, double u)
