@@ -136,6 +136,27 @@ int kde_bandwidth_units(const kde_grid *g, double hx, double hy, float *Hx, floa
 int kde_eval(const float *points, int64_t n, int32_t kernel_id, double hx, double hy, const kde_grid *g,
              float *out, int32_t precision, uint32_t flags, void *stream);
 
+/* Allocation-free kde_eval, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, validation, paths and results as kde_eval; the
+ * workspace is a fixed device array of KDE_NOALLOC_SCRATCH_BYTES that every GPU
+ * the library runs on holds until the process ends, and the call makes no
+ * hipMalloc, hipFree or other allocating call.  Differences from kde_eval:
+ *  - a map whose workspace would exceed KDE_NOALLOC_SCRATCH_BYTES is rejected
+ *    with KDE_EINVAL before any launch (dense matrix-core maps need 64 MiB of
+ *    split partial planes plus 8 bytes per point, e.g. 4*10^6 points on 2048^2
+ *    fit; FP32 direct and banded maps need less);
+ *  - the FP32 direct path uses the cached, forced or default tile shape and
+ *    never runs tuning launches.
+ * All calls on one GPU share that GPU's array and leave it holding the last
+ * call's contents (every launch sequence clears what it needs zeroed with its
+ * own fill kernel): calls on one GPU that overlap in time (different streams or
+ * host threads, not ordered by the caller) race on it and give undefined maps.
+ * Calls ordered on one stream are safe. */
+#define KDE_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int kde_eval_noalloc(const float *points, int64_t n, int32_t kernel_id, double hx, double hy, const kde_grid *g,
+                     float *out, int32_t precision, uint32_t flags, void *stream);
+
 /* One map of a batch: the arguments of kde_eval except precision and stream. */
 typedef struct kde_map {
     const float *points; /* device [n][2] grid units of `grid` */

@@ -69,6 +69,7 @@ def lib() -> ctypes.CDLL:
             "kde_to_grid_units": (ctypes.c_int, [p, p, i64, p]),
             "kde_bandwidth_units": (ctypes.c_int, [p, d, d, p, p]),
             "kde_eval": (ctypes.c_int, [p, i64, i32, d, d, p, p, i32, u32, p]),
+            "kde_eval_noalloc": (ctypes.c_int, [p, i64, i32, d, d, p, p, i32, u32, p]),
             "kde_eval_batched": (ctypes.c_int, [p, i32, u32, p]),
             "kde_backward": (ctypes.c_int, [p, i64, i32, d, d, p, p, p, p, u32, p]),
             "kde_lscv": (ctypes.c_int, [p, i64, i32, d, d, p, p, p, p]),
@@ -171,6 +172,22 @@ def eval(points, kernel, hx: float, hy: float, grid: Grid, out=None, precision: 
     returns (or fills) an [ny, nx] FP32 tensor (kde_eval).  truncate: the
     Gaussian cut at 8 bandwidths (binned on the FP32 path, banded on the
     matrix-core paths)."""
+    return _eval("kde_eval", points, kernel, hx, hy, grid, out, precision, raw, truncate)
+
+
+# Device scratch of the allocation-free entry point (KDE_NOALLOC_SCRATCH_BYTES).
+NOALLOC_SCRATCH_BYTES = 128 << 20
+
+
+def eval_noalloc(points, kernel, hx: float, hy: float, grid: Grid, out, precision: str = "fp32",
+                 raw: bool = False, truncate: bool = False):
+    """eval through kde_eval_noalloc: fills the caller's `out` using the
+    library's fixed per-GPU scratch array instead of allocated workspace (no
+    device allocation in the call; maps needing more scratch are rejected)."""
+    return _eval("kde_eval_noalloc", points, kernel, hx, hy, grid, out, precision, raw, truncate)
+
+
+def _eval(entry, points, kernel, hx, hy, grid, out, precision, raw, truncate):
     import torch
     _check_points(points, torch)
     if out is None:
@@ -178,10 +195,10 @@ def eval(points, kernel, hx: float, hy: float, grid: Grid, out=None, precision: 
     elif not (out.is_cuda and out.dtype == torch.float32 and out.is_contiguous() and out.numel() == grid.nx * grid.ny):
         raise ValueError("out must be a contiguous CUDA float32 tensor with ny*nx elements")
     with torch.cuda.device(points.device):
-        _check(lib().kde_eval(points.data_ptr() if points.numel() else None, points.shape[0], _kernel_id(kernel),
-                              hx, hy, grid.handle, out.data_ptr(), PRECISIONS[precision],
-                              (RAW_SUM if raw else 0) | (TRUNCATE if truncate else 0),
-                              _stream(torch, points.device)))
+        _check(getattr(lib(), entry)(points.data_ptr() if points.numel() else None, points.shape[0],
+                                     _kernel_id(kernel), hx, hy, grid.handle, out.data_ptr(), PRECISIONS[precision],
+                                     (RAW_SUM if raw else 0) | (TRUNCATE if truncate else 0),
+                                     _stream(torch, points.device)))
     return out
 
 

@@ -17,6 +17,9 @@
 
 #include "kde_internal.h"
 
+// Workspace of kde_eval_noalloc: one copy per GPU, held until the process ends.
+static __device__ __align__(256) unsigned char scratch[KDE_NOALLOC_SCRATCH_BYTES];
+
 struct kde_grid {
     uint64_t magic;
     double xmin, xmax, ymin, ymax;
@@ -336,6 +339,98 @@ int pick_batch_rc(std::vector<kde::MapArgs> &args, hipStream_t s) {
     return KDE_OK;
 }
 
+// ------------------------------------------------------------ allocation-free maps
+// kde_eval_noalloc runs the same launches as kde_eval with a fixed device array
+// as its workspace instead of the (device, stream) cache, so it never allocates.
+// In host code the array's name stands for a host-side shadow: its device
+// address, one per GPU, comes from hipGetSymbolAddress on that GPU and is the
+// only form in which it reaches a kernel or a HIP call.
+
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_dev;  // device ordinal -> address of `scratch` there
+
+int noalloc_scratch(void **out) {
+    *out = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_dev.find(dev);
+    if (it != g_scratch_dev.end()) {
+        *out = it->second;
+        return KDE_OK;
+    }
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr)
+        return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    g_scratch_dev[dev] = ptr;
+    *out = ptr;
+    return KDE_OK;
+}
+
+// Register-block side without tuning runs: forced, cached or default.
+int untuned_rc(const kde::MapArgs &a) {
+    if (const int forced = kde::tune::forced()) return forced;
+    int rc = a.kernel_id == KDE_GAUSSIAN ? kRcGauss : kRcCompact;
+    if (a.kernel_id == kde::kGaussTrunc) {
+        const float reach = std::max(a.Hx, a.Hy);
+        rc = reach <= 32.0f ? 2 : reach <= 64.0f ? 4 : 8;
+    }
+    std::string choice;
+    if (kde::tune::enabled() && kde::tune::lookup(eval_key(a), &choice)) rc = choice[0] - '0';
+    return rc;
+}
+
+// The body of kde_eval and kde_eval_noalloc.
+int eval_map(const float *points, int64_t n, int32_t kernel_id, double hx, double hy, const kde_grid *g, float *out,
+             int32_t precision, uint32_t flags, void *stream, bool noalloc, const char *who) {
+    int st = check_map(points, n, kernel_id, hx, hy, g, who);
+    if (st != KDE_OK) return st;
+    if (out == nullptr) return fail(KDE_EINVAL, "%s: out is NULL", who);
+    if (flags & ~(KDE_RAW_SUM | KDE_TRUNCATE)) return fail(KDE_EINVAL, "%s: unknown flags 0x%x", who, flags);
+    if (precision < KDE_FP32_DIRECT || precision > KDE_BF16X3_SEP)
+        return fail(KDE_EINVAL, "%s: unknown precision %d", who, (int)precision);
+    const bool truncate = (flags & KDE_TRUNCATE) != 0;
+    if (truncate && kernel_id != KDE_GAUSSIAN)
+        return fail(KDE_EINVAL, "%s: KDE_TRUNCATE applies to the Gaussian kernel only", who);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t plane = (int64_t)g->nx * g->ny;
+    if (n == 0) {
+        hipError_t e = kde::launch_fill_zero(out, plane, s);
+        return e == hipSuccess ? KDE_OK : hip_fail(e, who);
+    }
+    kde::MapArgs a = make_args(points, n, kernel_id, hx, hy, g, out, flags);
+    if (truncate) {  // support 8 bandwidths, Gaussian argument scale and constant
+        a.kernel_id = kde::kGaussTrunc;
+        a.Hx *= kde::kTruncSigmas;
+        a.Hy *= kde::kTruncSigmas;
+    }
+    const bool direct = precision == KDE_FP32_DIRECT;
+    if (direct) {
+        if (noalloc) {
+            a.rc = untuned_rc(a);
+        } else {
+            st = pick_rc(a, s, &a.rc);
+            if (st != KDE_OK) return st;
+        }
+    }
+    const size_t bytes = direct ? kde::direct_workspace_bytes(a) : kde::sep_workspace_bytes(a, precision);
+    void *ws = nullptr;
+    if (noalloc) {
+        if (bytes > KDE_NOALLOC_SCRATCH_BYTES)
+            return fail(KDE_EINVAL, "%s: this map needs %zu bytes of scratch, more than the %zu bytes the "
+                        "allocation-free entry point holds (use kde_eval)", who, bytes,
+                        (size_t)KDE_NOALLOC_SCRATCH_BYTES);
+        if (bytes > 0) st = noalloc_scratch(&ws);
+    } else {
+        st = get_workspace(s, bytes, &ws);
+    }
+    if (st != KDE_OK) return st;
+    hipError_t e = direct ? kde::launch_direct(a, ws, s) : kde::launch_sep(a, precision, ws, s);
+    return e == hipSuccess ? KDE_OK : hip_fail(e, who);
+}
+
 }  // namespace
 
 extern "C" {
@@ -406,39 +501,19 @@ int kde_eval(const float *points, int64_t n, int32_t kernel_id, double hx, doubl
              int32_t precision, uint32_t flags, void *stream) {
     ConsumeTimer consume_timer;
     try {
-        int st = check_map(points, n, kernel_id, hx, hy, g, "kde_eval");
-        if (st != KDE_OK) return st;
-        if (out == nullptr) return fail(KDE_EINVAL, "kde_eval: out is NULL");
-        if (flags & ~(KDE_RAW_SUM | KDE_TRUNCATE)) return fail(KDE_EINVAL, "kde_eval: unknown flags 0x%x", flags);
-        if (precision < KDE_FP32_DIRECT || precision > KDE_BF16X3_SEP)
-            return fail(KDE_EINVAL, "kde_eval: unknown precision %d", (int)precision);
-        const bool truncate = (flags & KDE_TRUNCATE) != 0;
-        if (truncate && kernel_id != KDE_GAUSSIAN)
-            return fail(KDE_EINVAL, "kde_eval: KDE_TRUNCATE applies to the Gaussian kernel only");
-        hipStream_t s = static_cast<hipStream_t>(stream);
-        const int64_t plane = (int64_t)g->nx * g->ny;
-        if (n == 0) {
-            hipError_t e = kde::launch_fill_zero(out, plane, s);
-            return e == hipSuccess ? KDE_OK : hip_fail(e, "kde_eval");
-        }
-        kde::MapArgs a = make_args(points, n, kernel_id, hx, hy, g, out, flags);
-        if (truncate) {  // support 8 bandwidths, Gaussian argument scale and constant
-            a.kernel_id = kde::kGaussTrunc;
-            a.Hx *= kde::kTruncSigmas;
-            a.Hy *= kde::kTruncSigmas;
-        }
-        const bool direct = precision == KDE_FP32_DIRECT;
-        if (direct) {
-            st = pick_rc(a, s, &a.rc);
-            if (st != KDE_OK) return st;
-        }
-        void *ws = nullptr;
-        st = get_workspace(s, direct ? kde::direct_workspace_bytes(a) : kde::sep_workspace_bytes(a, precision), &ws);
-        if (st != KDE_OK) return st;
-        hipError_t e = direct ? kde::launch_direct(a, ws, s) : kde::launch_sep(a, precision, ws, s);
-        return e == hipSuccess ? KDE_OK : hip_fail(e, "kde_eval");
+        return eval_map(points, n, kernel_id, hx, hy, g, out, precision, flags, stream, false, "kde_eval");
     } catch (...) {
         return fail(KDE_EHIP, "kde_eval: internal error");
+    }
+}
+
+int kde_eval_noalloc(const float *points, int64_t n, int32_t kernel_id, double hx, double hy, const kde_grid *g,
+                     float *out, int32_t precision, uint32_t flags, void *stream) {
+    ConsumeTimer consume_timer;
+    try {
+        return eval_map(points, n, kernel_id, hx, hy, g, out, precision, flags, stream, true, "kde_eval_noalloc");
+    } catch (...) {
+        return fail(KDE_EHIP, "kde_eval_noalloc: internal error");
     }
 }
 

@@ -213,3 +213,25 @@ def test_single_hip_runtime_in_process():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_noalloc_entry_point_validates_before_launch():
+    """kde_eval_noalloc validates like kde_eval, and refuses a map whose
+    workspace exceeds its fixed scratch array before anything is launched
+    (dense FP16 at 2*10^7 points on 512^2: 64 MiB of split planes plus 160 MB
+    of padded points)."""
+    g = kde.Grid(0.0, 1.0, 0.0, 1.0, 512, 512)
+    L = kde.lib()
+    for args in ((FAKE, -1, 6, 0.05, 0.05, g.handle, FAKE, 0, 0, None),
+                 (None, 10, 6, 0.05, 0.05, g.handle, FAKE, 0, 0, None),
+                 (FAKE, 10, 9, 0.05, 0.05, g.handle, FAKE, 0, 0, None),
+                 (FAKE, 10, 6, 0.0, 0.05, g.handle, FAKE, 0, 0, None),
+                 (FAKE, 10, 6, 0.05, 0.05, None, FAKE, 0, 0, None),
+                 (FAKE, 10, 6, 0.05, 0.05, g.handle, None, 0, 0, None),
+                 (FAKE, 10, 6, 0.05, 0.05, g.handle, FAKE, 7, 0, None),
+                 (FAKE, 10, 2, 0.05, 0.05, g.handle, FAKE, 0, 8, None)):
+        assert L.kde_eval_noalloc(*args) == kde.KDE_EINVAL, args
+        assert L.kde_last_error().decode().startswith("kde_eval_noalloc")
+    assert L.kde_eval_noalloc(FAKE, 20_000_000, 6, 0.004, 0.004, g.handle, FAKE, 1, 0, None) == kde.KDE_EINVAL
+    assert "scratch" in L.kde_last_error().decode()
+    assert kde.NOALLOC_SCRATCH_BYTES == 128 << 20
