@@ -28,11 +28,12 @@ UNIT = "pixel×point evals/s"
 PEAK_MFMA_TFLOPS = {"fp16": 2500.0, "bf16": 2500.0, "fp16x3": 2500.0, "bf16x3": 2500.0}
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 N_TRACKS, PTS_PER_TRACK, SIDE, H_DEG = 8000, 500, 2048, 0.002
-# HBM-side bytes per launch of the FP16 contraction kernel at this workload, from
-# two rocprofv3 counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors a
-# plain 256 MiB elementwise copy gives), profiles/kde_map_gaussian_4M_2048_fp16_traffic.txt.
-# Set to None whenever that kernel changes until the counters are taken again.
-TRAFFIC_FP16 = 146.9e6
+# HBM-side bytes per launch of the FP16 contraction kernel (sep_mfma8_kernel) at this
+# workload, from two rocprofv3 counter runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the
+# factors a plain 256 MiB elementwise copy gives),
+# profiles/kde_map_gaussian_4M_2048_fp16_traffic.txt.  Set to None whenever that kernel
+# changes until the counters are taken again.
+TRAFFIC_FP16 = 131.5e6
 
 
 def log(msg: str) -> None:
@@ -559,7 +560,7 @@ def main() -> int:
     achieved = 2.0 * pairs / (head["main_kernel_ms"] * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_TFLOPS["fp16"], "unit": "TFLOP/s",
                 "frac": achieved / PEAK_MFMA_TFLOPS["fp16"], "traffic": TRAFFIC_FP16,
-                "kernel": "sep_mfma_kernel<gaussian, fp16>", "kernel_ms": head["main_kernel_ms"],
+                "kernel": "sep_mfma8_kernel<fp16> (dense Gaussian runs)", "kernel_ms": head["main_kernel_ms"],
                 "flops_per_launch": 2.0 * pairs}
 
     line = {

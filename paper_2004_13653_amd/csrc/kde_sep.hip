@@ -27,6 +27,9 @@
 // Points are split across workgroups (split-K) so that a launch has about one
 // workgroup per CU; per-split partial maps are added in split order by the
 // reduction kernel of the direct path's file, which also applies the scale.
+//
+// Dense single-precision Gaussian maps (the common case) run an 8-wave variant,
+// sep_mfma8_kernel, with two waves per SIMD; see there.
 #include "kde_internal.h"
 
 #include <algorithm>
@@ -80,7 +83,7 @@ struct SepLaunch {
     const float2 *pts;  // padded copy: split s owns [s * pad_stride, (s + 1) * pad_stride)
     int64_t n;
     int64_t per_split;  // points per split, multiple of the chunk size
-    int64_t pad_stride; // per_split + 3 chunks of far-away points
+    int64_t pad_stride; // per_split + 4 chunks of far-away points
     float ax, ay;       // Gaussian argument scales sqrt(log2(e)/2)/H
     float Hx, Hy;       // compact kernels: support half-widths
     float ix, iy;       // compact kernels: 1/H
@@ -585,6 +588,177 @@ __global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p) {
     }
 }
 
+// Dense single-precision Gaussian maps with multiplicative runs: 8 waves, two
+// per SIMD, so that one wave's factor generation (VALU) overlaps the other's
+// MFMAs (a single wave per SIMD issues its VALU work mostly between its own
+// MFMAs and leaves the matrix core idle meanwhile).  Wave w owns the 128 x 64
+// block (w / 4, w % 4) of the 256 x 256 tile: 4 x 2 MFMA tiles, 128
+// accumulator registers per lane, which leaves room for two waves per SIMD.
+// Threads 0-255 generate the row factors (A, from Y), threads 256-511 the
+// column factors (B, from X): per chunk one 8-node run of 8 points each.  Every
+// phase (one MFMA k-step) emits two rows of the next chunk's run and starts two
+// points of the run after it, so the VALU work is spread evenly over the
+// phases; the fragments of phase kk + 1 are read during phase kk.  Same LDS
+// layout, chunking, split-K and tile order as sep_mfma_kernel; the point loads
+// run three chunks ahead (the padded copy holds four chunks of far-away points
+// past each split).
+constexpr int kThreads8 = 512;
+
+template <int P>
+__global__ __launch_bounds__(kThreads8, 1) void sep_mfma8_kernel(SepLaunch p) {
+    using Cfg = SepConfig<P>;
+    static_assert(!Cfg::kSplit, "single precision only");
+    constexpr bool kBf16 = PrecTraits<P>::kBf16;
+    constexpr int W = Cfg::kWords;
+    constexpr int KK = Cfg::KK;
+    static_assert(Cfg::R == 8 && KK == 4, "two rows and two points per phase");
+    __shared__ uint4 lds0[2 * W];
+    __shared__ uint4 lds1[2 * W];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // XCD-aware order of the (tile, split) items, as in sep_mfma_kernel.
+    const int64_t L = blockIdx.x + (int64_t)blockIdx.y * gridDim.x, TS = (int64_t)gridDim.x * gridDim.y;
+    const int64_t wl = TS % 8 == 0 ? (L % 8) * (TS / 8) + L / 8 : L;
+    const int tile_idx = (int)(wl % gridDim.x);
+    const int64_t split = wl / gridDim.x;
+    const int64_t beg = split * p.per_split;
+    const int64_t count = min(p.n, beg + p.per_split) - beg;
+    const float2 *qbase = p.pts + split * p.pad_stride;
+    const int tx = tile_idx % p.tiles_x, ty = tile_idx / p.tiles_x;
+    const int col0 = tx * kTile, row0 = ty * kTile;
+
+    // Generation role: A (rows, Y) for threads 0-255, B (columns, X) for 256-511.
+    const bool genB = tid >= 256;
+    const int gt = tid & 255;
+    const int g8 = gt % Cfg::G, mrun = Cfg::R * (gt / Cfg::G);
+    const float a = genB ? p.ax : p.ay;
+    const float origin = genB ? (float)col0 : (float)row0;
+    const float m0 = (float)mrun * a;
+    const int word0 = mrun * Cfg::kRowWords + g8;
+    const int slice = genB ? W : 0;
+    const float mc = m0 + 0.5f * (float)(Cfg::R - 1) * a, span = (float)(Cfg::R - 1) * a;
+
+    f32x16 acc[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+    const int64_t nch = ((count + Cfg::KC - 1) / Cfg::KC + 1) & ~int64_t(1);
+    const float2 *qg = qbase + 8 * g8;
+    const int ta0 = 4 * (wave >> 2), tb0 = 2 * (wave & 3);  // first 32-row / 32-column MFMA tile
+    const int frag0 = (lane & 31) * Cfg::kRowWords + (lane >> 5);
+    auto frag = [&](int t, int kk) { return frag0 + 32 * t * Cfg::kRowWords + 2 * kk; };
+
+    // This thread's coordinate of 8 points, scaled and tile-relative.
+    auto coords = [&](const float2 (&v)[8], float (&pc)[8]) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) pc[k] = ((genB ? v[k].x : v[k].y) - origin) * a;
+    };
+    // Run start (see gen_slice) for points k0 .. k1-1, and the emission of one row.
+    auto start_pts = [&](float (&e)[8], float (&ratio)[8], const float (&pc)[8], int k0, int k1) {
+#pragma unroll
+        for (int k = k0; k < k1; ++k) {
+            const float tc = mc - pc[k];
+            e[k] = __builtin_amdgcn_exp2f(tc * (span - tc));
+            ratio[k] = __builtin_amdgcn_exp2f(fminf(-2.0f * a * tc, 126.0f));
+        }
+    };
+    auto emit = [&](float (&e)[8], const float (&ratio)[8], uint4 *hi, int word) {
+        put8<P>(e, hi, nullptr, word);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) e[k] *= ratio[k];
+    };
+
+    float2 raw[8];  // points of the chunk whose run starts next
+    float eA[8], rA[8], eB[8], rB[8];
+    {
+        float2 v[8];
+        float pc[8];
+        load_points(qg, v);
+        coords(v, pc);
+        start_pts(eA, rA, pc, 0, 8);
+#pragma unroll
+        for (int r = 0; r < Cfg::R; ++r) emit(eA, rA, lds0 + slice, word0 + r * Cfg::kRowWords);
+        load_points(qg + Cfg::KC, v);
+        coords(v, pc);
+        start_pts(eA, rA, pc, 0, 8);          // chunk 1's run
+        load_points(qg + 2 * Cfg::KC, raw);  // chunk 2's points
+    }
+    __syncthreads();
+
+    // Step c: MFMAs on chunk c (use), emission of chunk c + 1 (run e, r) into
+    // gen, start of chunk c + 2's run (en, rn); raw then takes chunk c + 3.
+    auto step = [&](int64_t c, uint4 *gen, const uint4 *use, float (&e)[8], float (&r)[8], float (&en)[8],
+                    float (&rn)[8]) {
+        float pc[8];
+        coords(raw, pc);
+        load_points(qg + (c + 3) * Cfg::KC, raw);
+        const uint4 *Ah = use, *Bh = use + W;
+        uint4 na[4], nb[2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) na[i] = Ah[frag(ta0 + i, 0)];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) nb[j] = Bh[frag(tb0 + j, 0)];
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) {
+            uint4 fa[4], fb[2];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) fa[i] = na[i];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) fb[j] = nb[j];
+            if (kk + 1 < KK) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) na[i] = Ah[frag(ta0 + i, kk + 1)];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) nb[j] = Bh[frag(tb0 + j, kk + 1)];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = mfma<kBf16>(fa[i], fb[j], acc[i][j]);
+#pragma unroll
+            for (int q = 0; q < 2; ++q) emit(e, r, gen + slice, word0 + (2 * kk + q) * Cfg::kRowWords);
+            start_pts(en, rn, pc, 2 * kk, 2 * kk + 2);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        __syncthreads();
+    };
+    for (int64_t c = 0; c < nch; c += 2) {
+        step(c, lds1, lds0, eA, rA, eB, rB);
+        step(c + 1, lds0, lds1, eB, rB, eA, rA);
+    }
+
+    // Epilogue: register r of lane l in a 32 x 32 tile holds row 8 (r / 4) + 4 (l / 32) + r % 4,
+    // column l % 32; the runs' position factors q(row mod 8) q(column mod 8).
+    float *dst = p.dst + split * p.plane;
+    const float sc = gridDim.y == 1 ? p.scale : 1.0f;
+    constexpr float hc = 0.5f * (float)(Cfg::R - 1);
+    const float rcq = ((float)(lane % Cfg::R) - hc) * p.ax;
+    const float qcol = __builtin_amdgcn_exp2f(-rcq * rcq);
+    float qrow[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const float rr = ((float)((4 * (lane >> 5) + r) % Cfg::R) - hc) * p.ay;
+        qrow[r] = __builtin_amdgcn_exp2f(-rr * rr);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int col = col0 + 32 * (tb0 + j) + (lane & 31);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = row0 + 32 * (ta0 + i) + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                if (row < p.ny && col < p.nx)
+                    dst[(int64_t)row * p.nx + col] = acc[i][j][r] * (qrow[r & 3] * qcol * sc);
+            }
+        }
+    }
+}
+
 struct SepPlan {
     int tiles_x, tiles, splits;
     int64_t per_split;
@@ -603,9 +777,9 @@ SepPlan sep_plan(const MapArgs &a, int kc) {
     per = (per + kc - 1) / kc * kc;
     pl.splits = (int)std::max<int64_t>(1, (a.n + per - 1) / per);
     pl.per_split = per;
-    // Three extra chunks: the chunk count is rounded up to even and the point
-    // loads run two chunks ahead of the MFMAs.
-    pl.pad_stride = per + 3 * kc;
+    // Four extra chunks: the chunk count is rounded up to even and the point
+    // loads run up to three chunks ahead of the MFMAs (sep_mfma8_kernel).
+    pl.pad_stride = per + 4 * kc;
     pl.partial_bytes = pl.splits > 1 ? ((size_t)pl.splits * a.nx * a.ny * sizeof(float) + 255) / 256 * 256 : 0;
     return pl;
 }
@@ -664,6 +838,14 @@ hipError_t launch_sep_kp(const MapArgs &a, const SepPlan &pl, const float2 *padd
     // bandwidths evaluate every factor with its own exp2.
     bool recur = false;
     if constexpr (K == kGaussian) recur = p.ax <= kMaxRunScale && p.ay <= kMaxRunScale;
+    if constexpr (K == kGaussian && !PrecTraits<P>::kSplit) {
+        if (recur && bi == nullptr) {  // dense single-precision runs: the 8-wave kernel
+            main_kernel_begin(stream);
+            hipLaunchKernelGGL((sep_mfma8_kernel<P>), grid, dim3(kThreads8), 0, stream, p);
+            main_kernel_end(stream);
+            return hipGetLastError();
+        }
+    }
     if constexpr (K == kGaussian) {
         if (recur) {
             main_kernel_begin(stream);
