@@ -28,8 +28,8 @@
 // workgroup per CU; per-split partial maps are added in split order by the
 // reduction kernel of the direct path's file, which also applies the scale.
 //
-// Dense single-precision Gaussian maps (the common case) run an 8-wave variant,
-// sep_mfma8_kernel, with two waves per SIMD; see there.
+// Dense Gaussian maps with multiplicative runs (the common case) run an 8-wave
+// variant, sep_mfma8_kernel, with two waves per SIMD; see there.
 #include "kde_internal.h"
 
 #include <algorithm>
@@ -187,17 +187,6 @@ struct SepConfig {
     static constexpr int kRowWords = G + 1;
     static constexpr int kWords = kTile * kRowWords;  // 16-byte LDS words per operand slice
     static constexpr int R = G;                            // consecutive rows (and columns) per thread
-    // VALU instructions the scheduler places after each MFMA in the Gaussian
-    // runs' phases (0: no placement hints).
-#ifndef KDE_SEP_HINT_SINGLE
-#define KDE_SEP_HINT_SINGLE 0
-#endif
-#ifndef KDE_SEP_HINT_SPLIT
-    static constexpr int kHintSplit = PrecTraits<P>::kBf16 ? 4 : 2;
-#else
-    static constexpr int kHintSplit = KDE_SEP_HINT_SPLIT;
-#endif
-    static constexpr int kHintValu = kSplit ? kHintSplit : KDE_SEP_HINT_SINGLE;
 };
 
 // The 8 points of one group: 64 contiguous bytes of the padded copy (points
@@ -239,88 +228,24 @@ __device__ __forceinline__ void put8(const float (&v)[8], uint4 *hi, uint4 *lo, 
 
 // Factors of one operand slice for this thread: R consecutive nodes m0 .. m0+R-1
 // (rows of A or columns of B) against the 8 points `pr` (tile-relative; Gaussian
-// scaled by a).
-//
-// kRecur (Gaussian, a <= 0.8): with the run centre c = m0 + (R-1)/2, t_c =
-// (c - X) a and offsets rho_r = r - (R-1)/2,
-//     g(m0 + r) = exp2(-(t_c + rho_r a)^2) = P_r q_r,
-//     P_r = exp2(-t_c^2 - 2 t_c a rho_r),   q_r = exp2(-(rho_r a)^2).
-// q_r depends only on the node's position in its run (row or column index mod
-// R), so it factors out of the contraction and is applied once per output in
-// the epilogue; the operands carry P_r = P_0 B^r, B = exp2(-2 a t_c): two exp2
-// per point and run, then one multiply per factor.  P_r <= g q_r^-1 <= 2^((R-1)^2
-// a^2 / 4) stays inside FP16 range; a start value P_0 that underflows implies
-// every factor of the run is below 2^-31 of the peak, and B is clamped to stay
-// finite, so a run never turns a zero into a non-zero or produces NaN.
-template <int K, int P, bool kRecur>
+// scaled by a), each evaluated on its own.
+template <int K, int P>
 __device__ __forceinline__ void gen_slice(const float (&pr)[8], float m0, float a, float H, float inv, uint4 *hi,
                                           uint4 *lo, int word0, int stride) {
     constexpr int R = SepConfig<P>::R;
-    if constexpr (kRecur) {
-        const float mc = m0 + 0.5f * (float)(R - 1) * a;  // centre node (times a)
-        const float span = (float)(R - 1) * a;
-        float e[8], ratio[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const float tc = mc - pr[k];
-            e[k] = __builtin_amdgcn_exp2f(tc * (span - tc));  // -t_c^2 + (R-1) a t_c
-            ratio[k] = __builtin_amdgcn_exp2f(fminf(-2.0f * a * tc, 126.0f));
-        }
+    for (int r = 0; r < R; ++r) {
+        const float m = K == kGaussian ? m0 + (float)r * a : m0 + (float)r;
+        float v[8];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            put8<P>(e, hi, lo, word0 + r * stride);
-            if (r + 1 < R) {
-#pragma unroll
-                for (int k = 0; k < 8; ++k) e[k] *= ratio[k];
-            }
-        }
-    } else {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const float m = K == kGaussian ? m0 + (float)r * a : m0 + (float)r;
-            float v[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) v[k] = sep_factor<K>(m, pr[k], H, inv);
-            put8<P>(v, hi, lo, word0 + r * stride);
-        }
+        for (int k = 0; k < 8; ++k) v[k] = sep_factor<K>(m, pr[k], H, inv);
+        put8<P>(v, hi, lo, word0 + r * stride);
     }
 }
 
-// One thread's Gaussian run for one operand slice, emitted row by row so that
-// the emission can be spread over the MFMA phases of a chunk (see gen_slice for
-// the recurrence and why it is safe).
-template <int P>
-struct GaussRun {
-    float e[8], ratio[8];
-    uint4 *hi, *lo;
-    int word, stride;
-
-    __device__ __forceinline__ void start(const float (&pr)[8], float m0, float a, uint4 *h, uint4 *l, int w,
-                                          int st) {
-        constexpr int R = SepConfig<P>::R;
-        const float mc = m0 + 0.5f * (float)(R - 1) * a, span = (float)(R - 1) * a;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const float tc = mc - pr[k];
-            e[k] = __builtin_amdgcn_exp2f(tc * (span - tc));
-            ratio[k] = __builtin_amdgcn_exp2f(fminf(-2.0f * a * tc, 126.0f));
-        }
-        hi = h;
-        lo = l;
-        word = w;
-        stride = st;
-    }
-    __device__ __forceinline__ void emit() {
-        put8<P>(e, hi, lo, word);
-        word += stride;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) e[k] *= ratio[k];
-    }
-};
-
 // Generates one chunk (8 points per thread, given) into an LDS buffer: A (rows,
 // from Y) and B (columns, from X).
-template <int K, int P, bool kRecur>
+template <int K, int P>
 __device__ __forceinline__ void generate_chunk(const SepLaunch &p, const float2 (&v)[8], int tid, float x0,
                                                float y0, float mrow0, float mcol0, uint4 *Ahi, uint4 *Bhi,
                                                uint4 *Alo, uint4 *Blo) {
@@ -340,11 +265,11 @@ __device__ __forceinline__ void generate_chunk(const SepLaunch &p, const float2 
         }
     }
     const float ga_y = K == kGaussian ? p.ay : 1.0f, ga_x = K == kGaussian ? p.ax : 1.0f;
-    gen_slice<K, P, kRecur>(py, mrow0, ga_y, p.Hy, p.iy, Ahi, Alo, word0, Cfg::kRowWords);
-    gen_slice<K, P, kRecur>(px, mcol0, ga_x, p.Hx, p.ix, Bhi, Blo, word0, Cfg::kRowWords);
+    gen_slice<K, P>(py, mrow0, ga_y, p.Hy, p.iy, Ahi, Alo, word0, Cfg::kRowWords);
+    gen_slice<K, P>(px, mcol0, ga_x, p.Hx, p.ix, Bhi, Blo, word0, Cfg::kRowWords);
 }
 
-template <int K, int P, bool kRecur>
+template <int K, int P>
 __global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p) {
     using Cfg = SepConfig<P>;
     constexpr bool kBf16 = PrecTraits<P>::kBf16;
@@ -414,97 +339,16 @@ __global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p) {
     float2 pts[8], nxt[8];
     load_points(qg, pts);
     load_points(qg + Cfg::KC, nxt);
-    generate_chunk<K, P, kRecur>(p, pts, tid, x0, y0, mrow0, mcol0, lds0, lds0 + W, lds0 + 2 * W, lds0 + 3 * W);
+    generate_chunk<K, P>(p, pts, tid, x0, y0, mrow0, mcol0, lds0, lds0 + W, lds0 + 2 * W, lds0 + 3 * W);
     __syncthreads();
 
     // One chunk: generate chunk c + 1 into `gen` while the MFMAs consume chunk c
     // from `use`.
-    // Gaussian runs: the chunk is cut into KK phases, each reading one k-step of
-    // fragments, issuing its MFMAs and emitting a share of the next chunk's
-    // factor rows; scheduling barriers keep the phases apart so that every
-    // MFMA group has generation work to overlap with.
-    auto step_phased = [&](int64_t c, uint4 *gen, const uint4 *use) {
-        // The points of chunk c + 1 (in nxt), scaled; nxt then takes chunk c + 2.
-        // The two orders below leave the register allocator different room: for
-        // the splits, scaling first keeps the chunk loop free of spills.
-        float px[8], py[8];
-        if constexpr (Cfg::kSplit) {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                px[k] = (nxt[k].x - x0) * p.ax;
-                py[k] = (nxt[k].y - y0) * p.ay;
-            }
-            load_points(qg + (c + 2) * Cfg::KC, nxt);  // consumed one chunk later
-        } else {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) pts[k] = nxt[k];
-            load_points(qg + (c + 2) * Cfg::KC, nxt);
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                px[k] = (pts[k].x - x0) * p.ax;
-                py[k] = (pts[k].y - y0) * p.ay;
-            }
-        }
-        const int g8 = tid % Cfg::G, mrun = Cfg::R * (tid / Cfg::G);
-        const int word0 = mrun * Cfg::kRowWords + g8;
-        GaussRun<P> ra, rb;
-        const uint4 *Ah = use, *Bh = use + W, *Al = use + 2 * W, *Bl = use + 3 * W;
-        // Emission plan (rows of A and B per phase), R rows each.
-        constexpr int KKp = Cfg::KK;
-        constexpr int ea[4] = {Cfg::R / KKp, Cfg::R / KKp, Cfg::R / KKp, Cfg::R / KKp};
-        constexpr int eb[4] = {0, KKp == 4 ? 3 : Cfg::R, KKp == 4 ? 3 : 0, KKp == 4 ? 2 : 0};
-#pragma unroll
-        for (int kk = 0; kk < KKp; ++kk) {
-            if (kk == 0) ra.start(py, mrow0, p.ay, gen, gen + 2 * W, word0, Cfg::kRowWords);
-            if (kk == 1) rb.start(px, mcol0, p.ax, gen + W, gen + 3 * W, word0, Cfg::kRowWords);
-            uint4 fa[4], fb[4];
-#pragma unroll
-            for (int a = 0; a < 4; ++a) fa[a] = Ah[frag(ta0 + a, kk)];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) fb[b] = Bh[frag(tb0 + b, kk)];
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] = mfma<kBf16>(fa[a], fb[b], acc[a][b]);
-            if constexpr (Cfg::kSplit) {
-                uint4 la[4], lb[4];
-#pragma unroll
-                for (int a = 0; a < 4; ++a) la[a] = Al[frag(ta0 + a, kk)];
-#pragma unroll
-                for (int b = 0; b < 4; ++b) lb[b] = Bl[frag(tb0 + b, kk)];
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        acc[a][b] = mfma<kBf16>(fa[a], lb[b], acc[a][b]);
-                        acc[a][b] = mfma<kBf16>(la[a], fb[b], acc[a][b]);
-                    }
-            }
-#pragma unroll
-            for (int r = 0; r < ea[kk]; ++r) ra.emit();
-#pragma unroll
-            for (int r = 0; r < eb[kk]; ++r) rb.emit();
-            // Split precisions: fragments first, then each MFMA followed by a
-            // slice of the VALU work (the compiler otherwise bunches the MFMAs).
-            if constexpr (Cfg::kHintValu > 0) {
-                __builtin_amdgcn_sched_group_barrier(0x100, Cfg::kSplit ? 16 : 8, 0);
-#pragma unroll
-                for (int i = 0; i < (Cfg::kSplit ? 48 : 16); ++i) {
-                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                    __builtin_amdgcn_sched_group_barrier(0x002, Cfg::kHintValu, 0);
-                    if (i % 4 == 3) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
-                }
-            }
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        __syncthreads();
-    };
-
     auto step = [&](int64_t c, uint4 *gen, const uint4 *use) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) pts[k] = nxt[k];
         load_points(qg + (c + 2) * Cfg::KC, nxt);  // consumed one chunk later
-        generate_chunk<K, P, kRecur>(p, pts, tid, x0, y0, mrow0, mcol0, gen, gen + W, gen + 2 * W, gen + 3 * W);
+        generate_chunk<K, P>(p, pts, tid, x0, y0, mrow0, mcol0, gen, gen + W, gen + 2 * W, gen + 3 * W);
         const uint4 *Ah = use, *Bh = use + W, *Al = use + 2 * W, *Bl = use + 3 * W;
 #pragma unroll
         for (int kk = 0; kk < Cfg::KK; ++kk) {
@@ -535,19 +379,13 @@ __global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p) {
         __syncthreads();
     };
 
-    constexpr bool kPhased = kRecur;  // phases pace the Gaussian runs' emission
     for (int64_t c = 0; c < nch; c += 2) {
-        if constexpr (kPhased) {
-            step_phased(c, lds1, lds0);
-            step_phased(c + 1, lds0, lds1);
-        } else {
-            step(c, lds1, lds0);
-            step(c + 1, lds0, lds1);
-        }
+        step(c, lds1, lds0);
+        step(c + 1, lds0, lds1);
     }
 
     // Epilogue: register r of lane l in a 32 x 32 tile holds row 8 (r / 4) + 4 (l / 32) + r % 4,
-    // column l % 32.  Gaussian runs: multiply by q(row mod R) q(column mod R).
+    // column l % 32.
     if (banded) {  // raw partial tile, row-major 256 x 256, in the item's slot
         float *slot = p.dst + (int64_t)blockIdx.x * (kTile * kTile);
 #pragma unroll
@@ -562,17 +400,6 @@ __global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p) {
     }
     float *dst = p.dst + split * p.plane;
     const float sc = gridDim.y == 1 ? p.scale : 1.0f;
-    float qcol = 1.0f, qrow[4] = {1.0f, 1.0f, 1.0f, 1.0f};
-    if constexpr (kRecur) {
-        constexpr float hc = 0.5f * (float)(Cfg::R - 1);
-        const float rc = ((float)(lane % Cfg::R) - hc) * p.ax;
-        qcol = __builtin_amdgcn_exp2f(-rc * rc);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const float rr = ((float)((4 * (lane >> 5) + r) % Cfg::R) - hc) * p.ay;
-            qrow[r] = __builtin_amdgcn_exp2f(-rr * rr);
-        }
-    }
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
 #pragma unroll
@@ -581,39 +408,42 @@ __global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int row = row0 + 32 * (ta0 + a) + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                if (row < p.ny && col < p.nx)
-                    dst[(int64_t)row * p.nx + col] = acc[a][b][r] * (qrow[r & 3] * qcol * sc);
+                if (row < p.ny && col < p.nx) dst[(int64_t)row * p.nx + col] = acc[a][b][r] * sc;
             }
         }
     }
 }
 
-// Dense single-precision Gaussian maps with multiplicative runs: 8 waves, two
+// Dense Gaussian maps with multiplicative runs, every precision: 8 waves, two
 // per SIMD, so that one wave's factor generation (VALU) overlaps the other's
 // MFMAs (a single wave per SIMD issues its VALU work mostly between its own
 // MFMAs and leaves the matrix core idle meanwhile).  Wave w owns the 128 x 64
 // block (w / 4, w % 4) of the 256 x 256 tile: 4 x 2 MFMA tiles, 128
 // accumulator registers per lane, which leaves room for two waves per SIMD.
 // Threads 0-255 generate the row factors (A, from Y), threads 256-511 the
-// column factors (B, from X): per chunk one 8-node run of 8 points each.  Every
-// phase (one MFMA k-step) emits two rows of the next chunk's run and starts two
+// column factors (B, from X): per chunk one R-node run of 8 points each (R = 8
+// single, 4 for the hi/lo splits, whose chunks are half as long).  Every phase
+// (one MFMA k-step) emits R / KK rows of the next chunk's run and starts 8 / KK
 // points of the run after it, so the VALU work is spread evenly over the
-// phases; the fragments of phase kk + 1 are read during phase kk.  Same LDS
-// layout, chunking, split-K and tile order as sep_mfma_kernel; the point loads
-// run three chunks ahead (the padded copy holds four chunks of far-away points
-// past each split).
+// phases; single precision reads the fragments of phase kk + 1 during phase kk
+// (the splits have no registers left for that).  Same LDS layout, chunking,
+// split-K and tile order as sep_mfma_kernel; the point loads run three chunks
+// ahead (the padded copy holds four chunks of far-away points past each split).
 constexpr int kThreads8 = 512;
 
 template <int P>
 __global__ __launch_bounds__(kThreads8, 1) void sep_mfma8_kernel(SepLaunch p) {
     using Cfg = SepConfig<P>;
-    static_assert(!Cfg::kSplit, "single precision only");
+    constexpr bool kSplit = Cfg::kSplit;
     constexpr bool kBf16 = PrecTraits<P>::kBf16;
     constexpr int W = Cfg::kWords;
     constexpr int KK = Cfg::KK;
-    static_assert(Cfg::R == 8 && KK == 4, "two rows and two points per phase");
-    __shared__ uint4 lds0[2 * W];
-    __shared__ uint4 lds1[2 * W];
+    constexpr int kOps = kSplit ? 4 : 2;       // operand slices per buffer (hi, and lo for splits)
+    constexpr int kRowsPh = Cfg::R / KK;       // run rows emitted per phase
+    constexpr int kPtsPh = 8 / KK;             // points of the next run started per phase
+    static_assert(Cfg::R == kRowsPh * KK && 8 == kPtsPh * KK, "even spread over the phases");
+    __shared__ uint4 lds0[kOps * W];
+    __shared__ uint4 lds1[kOps * W];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // XCD-aware order of the (tile, split) items, as in sep_mfma_kernel.
@@ -635,7 +465,7 @@ __global__ __launch_bounds__(kThreads8, 1) void sep_mfma8_kernel(SepLaunch p) {
     const float origin = genB ? (float)col0 : (float)row0;
     const float m0 = (float)mrun * a;
     const int word0 = mrun * Cfg::kRowWords + g8;
-    const int slice = genB ? W : 0;
+    const int slice = genB ? W : 0;  // hi slice; lo (splits) at slice + 2 W
     const float mc = m0 + 0.5f * (float)(Cfg::R - 1) * a, span = (float)(Cfg::R - 1) * a;
 
     f32x16 acc[4][2];
@@ -657,7 +487,20 @@ __global__ __launch_bounds__(kThreads8, 1) void sep_mfma8_kernel(SepLaunch p) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) pc[k] = ((genB ? v[k].x : v[k].y) - origin) * a;
     };
-    // Run start (see gen_slice) for points k0 .. k1-1, and the emission of one row.
+    // Gaussian runs.  With the run centre c = m0 + (R-1)/2, t_c = (c - X) a and
+    // offsets rho_r = r - (R-1)/2,
+    //     g(m0 + r) = exp2(-(t_c + rho_r a)^2) = P_r q_r,
+    //     P_r = exp2(-t_c^2 - 2 t_c a rho_r),   q_r = exp2(-(rho_r a)^2).
+    // q_r depends only on the node's position in its run (row or column index
+    // mod R), so it factors out of the contraction and is applied once per
+    // output in the epilogue; the operands carry P_r = P_0 B^r, B = exp2(-2 a
+    // t_c): two exp2 per point and run, then one multiply per factor.  P_r <= g
+    // q_r^-1 <= 2^((R-1)^2 a^2 / 4) stays inside FP16 range for a <= 0.8; a start
+    // value P_0 that underflows implies every factor of the run is below 2^-31 of
+    // the peak, and B is clamped to stay finite, so a run never turns a zero into
+    // a non-zero or produces NaN.
+    // start_pts: the run start for points k0 .. k1-1; emit: one row, then the
+    // next row's values.
     auto start_pts = [&](float (&e)[8], float (&ratio)[8], const float (&pc)[8], int k0, int k1) {
 #pragma unroll
         for (int k = k0; k < k1; ++k) {
@@ -666,8 +509,8 @@ __global__ __launch_bounds__(kThreads8, 1) void sep_mfma8_kernel(SepLaunch p) {
             ratio[k] = __builtin_amdgcn_exp2f(fminf(-2.0f * a * tc, 126.0f));
         }
     };
-    auto emit = [&](float (&e)[8], const float (&ratio)[8], uint4 *hi, int word) {
-        put8<P>(e, hi, nullptr, word);
+    auto emit = [&](float (&e)[8], const float (&ratio)[8], uint4 *buf, int word) {
+        put8<P>(e, buf + slice, buf + slice + 2 * W, word);
 #pragma unroll
         for (int k = 0; k < 8; ++k) e[k] *= ratio[k];
     };
@@ -681,7 +524,7 @@ __global__ __launch_bounds__(kThreads8, 1) void sep_mfma8_kernel(SepLaunch p) {
         coords(v, pc);
         start_pts(eA, rA, pc, 0, 8);
 #pragma unroll
-        for (int r = 0; r < Cfg::R; ++r) emit(eA, rA, lds0 + slice, word0 + r * Cfg::kRowWords);
+        for (int r = 0; r < Cfg::R; ++r) emit(eA, rA, lds0, word0 + r * Cfg::kRowWords);
         load_points(qg + Cfg::KC, v);
         coords(v, pc);
         start_pts(eA, rA, pc, 0, 8);          // chunk 1's run
@@ -696,32 +539,55 @@ __global__ __launch_bounds__(kThreads8, 1) void sep_mfma8_kernel(SepLaunch p) {
         float pc[8];
         coords(raw, pc);
         load_points(qg + (c + 3) * Cfg::KC, raw);
-        const uint4 *Ah = use, *Bh = use + W;
+        const uint4 *Ah = use, *Bh = use + W, *Al = use + 2 * W, *Bl = use + 3 * W;
         uint4 na[4], nb[2];
+        if constexpr (!kSplit) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) na[i] = Ah[frag(ta0 + i, 0)];
+            for (int i = 0; i < 4; ++i) na[i] = Ah[frag(ta0 + i, 0)];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) nb[j] = Bh[frag(tb0 + j, 0)];
+            for (int j = 0; j < 2; ++j) nb[j] = Bh[frag(tb0 + j, 0)];
+        }
 #pragma unroll
         for (int kk = 0; kk < KK; ++kk) {
             uint4 fa[4], fb[2];
+            if constexpr (!kSplit) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) fa[i] = na[i];
+                for (int i = 0; i < 4; ++i) fa[i] = na[i];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) fb[j] = nb[j];
-            if (kk + 1 < KK) {
+                for (int j = 0; j < 2; ++j) fb[j] = nb[j];
+                if (kk + 1 < KK) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i) na[i] = Ah[frag(ta0 + i, kk + 1)];
+                    for (int i = 0; i < 4; ++i) na[i] = Ah[frag(ta0 + i, kk + 1)];
 #pragma unroll
-                for (int j = 0; j < 2; ++j) nb[j] = Bh[frag(tb0 + j, kk + 1)];
+                    for (int j = 0; j < 2; ++j) nb[j] = Bh[frag(tb0 + j, kk + 1)];
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) fa[i] = Ah[frag(ta0 + i, kk)];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) fb[j] = Bh[frag(tb0 + j, kk)];
             }
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j) acc[i][j] = mfma<kBf16>(fa[i], fb[j], acc[i][j]);
+            if constexpr (kSplit) {
+                uint4 la[4], lb[2];
 #pragma unroll
-            for (int q = 0; q < 2; ++q) emit(e, r, gen + slice, word0 + (2 * kk + q) * Cfg::kRowWords);
-            start_pts(en, rn, pc, 2 * kk, 2 * kk + 2);
+                for (int i = 0; i < 4; ++i) la[i] = Al[frag(ta0 + i, kk)];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) lb[j] = Bl[frag(tb0 + j, kk)];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        acc[i][j] = mfma<kBf16>(fa[i], lb[j], acc[i][j]);
+                        acc[i][j] = mfma<kBf16>(la[i], fb[j], acc[i][j]);
+                    }
+            }
+#pragma unroll
+            for (int q = 0; q < kRowsPh; ++q) emit(e, r, gen, word0 + (kRowsPh * kk + q) * Cfg::kRowWords);
+            start_pts(en, rn, pc, kPtsPh * kk, kPtsPh * (kk + 1));
             __builtin_amdgcn_sched_barrier(0);
         }
         __syncthreads();
@@ -838,24 +704,18 @@ hipError_t launch_sep_kp(const MapArgs &a, const SepPlan &pl, const float2 *padd
     // bandwidths evaluate every factor with its own exp2.
     bool recur = false;
     if constexpr (K == kGaussian) recur = p.ax <= kMaxRunScale && p.ay <= kMaxRunScale;
-    if constexpr (K == kGaussian && !PrecTraits<P>::kSplit) {
-        if (recur && bi == nullptr) {  // dense single-precision runs: the 8-wave kernel
+    // (The full Gaussian is never banded: only compact supports and the truncated
+    // Gaussian are, so a dense launch is the only one with runs.)
+    if constexpr (K == kGaussian) {
+        if (recur && bi == nullptr) {  // the 8-wave kernel
             main_kernel_begin(stream);
             hipLaunchKernelGGL((sep_mfma8_kernel<P>), grid, dim3(kThreads8), 0, stream, p);
             main_kernel_end(stream);
             return hipGetLastError();
         }
     }
-    if constexpr (K == kGaussian) {
-        if (recur) {
-            main_kernel_begin(stream);
-            hipLaunchKernelGGL((sep_mfma_kernel<K, P, true>), grid, dim3(kThreadsSep), 0, stream, p);
-            main_kernel_end(stream);
-            return hipGetLastError();
-        }
-    }
     main_kernel_begin(stream);
-    hipLaunchKernelGGL((sep_mfma_kernel<K, P, false>), grid, dim3(kThreadsSep), 0, stream, p);
+    hipLaunchKernelGGL((sep_mfma_kernel<K, P>), grid, dim3(kThreadsSep), 0, stream, p);
     main_kernel_end(stream);
     return hipGetLastError();
 }
