@@ -258,32 +258,70 @@ def bench_adjoint(torch, kde, synth, steps: int):
     return res
 
 
+def batch_window_points(torch, kde, synth, t, spec):
+    """World points of one batch map: the window [start, start + count) of the
+    pool, Douglas-Peucker-compressed on the GPU at the map's threshold (Mercator
+    metres; 0 keeps the raw window)."""
+    import numpy as np
+    w = synth.window_tracks(t, spec.start, spec.count)
+    if spec.eps_m == 0.0:
+        return w.xy
+    mx, my = synth.mercator(w.xy[:, 0], w.xy[:, 1], t.box.center_lat)
+    xy = torch.from_numpy(np.column_stack([mx, my])).cuda()
+    start = torch.from_numpy(np.concatenate([[0], np.cumsum(w.lengths)]).astype(np.int64)).cuda()
+    keep = kde.dp_compress(xy, start, spec.eps_m, compact=False).keep.cpu().numpy().astype(bool)
+    return w.xy[keep]
+
+
 def bench_batched(torch, kde, synth, steps: int):
-    """Batch workload: 256 maps, point counts log-uniform in [1k, 200k] (time
-    windows of a 4M-point pool), grids from {256^2, 512^2, 1024^2}, h ~ U(0.001,
-    0.008) degrees, kernels uniform over the eight: one graph-replayed persistent
-    launch against 256 separate kde_eval launches."""
+    """Batch workload: 256 maps, each a time window of a 4M-point pool with point
+    count log-uniform in [1k, 200k], Douglas-Peucker-compressed at a threshold
+    drawn from {0, 10, 50, 100} m; grids from {256^2, 512^2, 1024^2}, h ~
+    U(0.001, 0.008) degrees, kernels uniform over the eight.  Gaussian maps on
+    the FP16 matrix-core path, the compact kernels on the FP32 persistent launch
+    (graph-replayed), in one kde_eval_batched call, against 256 separate kde_eval
+    launches of the same precisions.  The two parts are also timed alone."""
+    import numpy as np
     t = synth.workload_lanes(n_tracks=N_TRACKS, pts=PTS_PER_TRACK, seed_index=2)
     b = synth.BOX_C2
     grids = {s: kde.Grid(b.lon0, b.lon1, b.lat0, b.lat1, s, s) for s in (256, 512, 1024)}
-    dev_pts = {s: torch.from_numpy(kde.to_grid_units(t.xy, grids[s])).cuda() for s in grids}
     specs = synth.batch_specs(256, t.n)
-    maps = [(dev_pts[sp.side][sp.start:sp.start + sp.count], sp.kernel, sp.h_deg, sp.h_deg, grids[sp.side],
-             torch.empty((sp.side, sp.side), device="cuda")) for sp in specs]
-    pairs = float(sum(sp.count * sp.side * sp.side for sp in specs))
-    gauss_pairs = float(sum(sp.count * sp.side * sp.side for sp in specs if sp.kernel == 6))
+    maps, support = [], 0.0
+    for sp in specs:
+        XY = kde.to_grid_units(batch_window_points(torch, kde, synth, t, sp), grids[sp.side])
+        prec = "fp16" if sp.kernel == 6 else "fp32"
+        maps.append((torch.from_numpy(XY).cuda(), sp.kernel, sp.h_deg, sp.h_deg, grids[sp.side],
+                     torch.empty((sp.side, sp.side), device="cuda"), prec))
+        if sp.kernel != 6:
+            Hx, Hy = kde.bandwidth_units(sp.h_deg, sp.h_deg, grids[sp.side])
+            support += map_support_pairs(XY, float(Hx), float(Hy), sp.side, sp.side)
+    npts = [m[0].shape[0] for m in maps]
+    pairs = float(sum(n * m[4].nx * m[4].ny for n, m in zip(npts, maps)))
+    gauss = [m for m in maps if m[6] == "fp16"]
+    compact = [m for m in maps if m[6] == "fp32"]
+    gauss_pairs = float(sum(m[0].shape[0] * m[4].nx * m[4].ny for m in gauss))
     tot_b, _, _ = timed_steps(torch, lambda: kde.eval_batched(maps), steps, 2)
     ms_b = tot_b / steps
+    tot_c, _, _ = timed_steps(torch, lambda: kde.eval_batched(compact), steps, 2)
+    tot_g, _, _ = timed_steps(torch, lambda: kde.eval_batched(gauss), steps, 2)
+    ms_c, ms_g = tot_c / steps, tot_g / steps
 
     def separate():
-        for (p, k, hx, hy, g, o) in maps:
-            kde.eval(p, k, hx, hy, g, out=o)
+        for (p, k, hx, hy, g, o, prec) in maps:
+            kde.eval(p, k, hx, hy, g, out=o, precision=prec)
     tot_s, _, _ = timed_steps(torch, separate, max(1, steps // 2), 1)
     ms_s = tot_s / max(1, steps // 2)
-    log(f"batched: {ms_b:.2f} ms vs separate {ms_s:.2f} ms")
-    return {"maps": 256, "logical_pairs": pairs, "gaussian_pairs": gauss_pairs, "batched_ms": ms_b,
-            "separate_ms": ms_s, "batched_pairs_per_s": pairs / (ms_b * 1e-3),
-            "separate_pairs_per_s": pairs / (ms_s * 1e-3), "speedup": ms_s / ms_b}
+    mfma = 2.0 * gauss_pairs / (ms_g * 1e-3) / 1e12
+    log(f"batched: {ms_b:.2f} ms vs separate {ms_s:.2f} ms (compact maps alone {ms_c:.2f} ms, "
+        f"Gaussian maps alone {ms_g:.2f} ms = {mfma:.0f} TFLOP/s)")
+    return {"maps": 256, "points_after_compression": int(sum(npts)), "points_before": int(sum(s.count for s in specs)),
+            "eps_m": sorted({s.eps_m for s in specs}), "logical_pairs": pairs, "gaussian_maps": len(gauss),
+            "gaussian_pairs": gauss_pairs, "compact_in_support_pairs": support,
+            "batched_ms": ms_b, "separate_ms": ms_s, "batched_pairs_per_s": pairs / (ms_b * 1e-3),
+            "separate_pairs_per_s": pairs / (ms_s * 1e-3), "speedup": ms_s / ms_b,
+            "compact_part_ms": ms_c, "compact_in_support_pairs_per_s": support / (ms_c * 1e-3),
+            "gaussian_part_ms": ms_g, "gaussian_part_mfma_tflops": mfma,
+            "gaussian_part_mfma_frac": mfma / PEAK_MFMA_TFLOPS["fp16"]}
 
 
 def bench_binned(torch, kde, pts, labels, g, ref_map, steps: int):

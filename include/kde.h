@@ -157,30 +157,36 @@ int kde_eval(const float *points, int64_t n, int32_t kernel_id, double hx, doubl
 int kde_eval_noalloc(const float *points, int64_t n, int32_t kernel_id, double hx, double hy, const kde_grid *g,
                      float *out, int32_t precision, uint32_t flags, void *stream);
 
-/* One map of a batch: the arguments of kde_eval except precision and stream. */
+/* One map of a batch: the arguments of kde_eval except stream. */
 typedef struct kde_map {
     const float *points; /* device [n][2] grid units of `grid` */
     int64_t n;
     int32_t kernel_id;
-    int32_t reserved; /* must be 0 */
-    double hx, hy;    /* world units */
+    int32_t precision; /* KDE_FP32_DIRECT or one of the *_SEP matrix-core paths */
+    double hx, hy;     /* world units */
     const kde_grid *grid;
-    float *out; /* device [ny][nx] */
+    float *out;        /* device [ny][nx] */
+    uint32_t flags;    /* 0 or KDE_TRUNCATE (Gaussian only) */
+    uint32_t reserved; /* must be 0 */
 } kde_map;
 
-/* Evaluates n_maps maps (host array of descriptors) with the FP32 direct path in
- * one persistent launch (not in the paper, which maps one data set at a time):
- * the batch is cut into (map, pixel tile, point range) items, longest first,
- * pulled by persistent workgroups from an atomic counter; each map's output
- * equals what kde_eval(..., KDE_FP32_DIRECT, ...) computes up to FP32 rounding
- * order.  Every descriptor is validated before anything is launched; output
+/* Evaluates n_maps maps (host array of descriptors; not in the paper, which maps
+ * one data set at a time).  The FP32 direct maps without KDE_TRUNCATE run in one
+ * persistent launch: the batch is cut into (map, pixel tile, point range)
+ * items, longest first, pulled by persistent workgroups from an atomic counter;
+ * each such map's output equals what kde_eval(..., KDE_FP32_DIRECT, ...)
+ * computes up to FP32 rounding order.  The other maps (matrix-core precisions,
+ * truncated Gaussians) follow on the same stream as individual launches of the
+ * kde_eval path, sharing one workspace, so their outputs equal kde_eval's bit
+ * for bit.  Every descriptor is validated before anything is launched; output
  * buffers must not overlap each other or any point buffer.  By default the
- * upload + launch sequence is captured into a hipGraph the first time a batch
- * shape (item list, kernels, grid sizes, point counts) is seen and replayed
- * afterwards; the library keeps one device buffer and pinned staging buffer per
- * captured shape until kde_shutdown().  A call on a shape that is still running
- * waits for that run to finish before reusing its staging buffer.  flags:
- * KDE_RAW_SUM, KDE_BATCH_EAGER (no graph; the call synchronises `stream`). */
+ * persistent part's upload + launch sequence is captured into a hipGraph the
+ * first time a batch shape (item list, kernels, grid sizes, point counts) is seen
+ * and replayed afterwards; the library keeps one device buffer and pinned
+ * staging buffer per captured shape until kde_shutdown().  A call on a shape that
+ * is still running waits for that run to finish before reusing its staging
+ * buffer.  flags: KDE_RAW_SUM, KDE_BATCH_EAGER (no graph; the call synchronises
+ * `stream`). */
 int kde_eval_batched(const kde_map *maps, int32_t n_maps, uint32_t flags, void *stream);
 
 /* Adjoint of kde_eval (vector-Jacobian product; not in the paper).  Given

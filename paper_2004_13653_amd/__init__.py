@@ -39,8 +39,9 @@ class MapDesc(ctypes.Structure):
     """ctypes image of struct kde_map (one descriptor of kde_eval_batched)."""
 
     _fields_ = [("points", ctypes.c_void_p), ("n", ctypes.c_int64), ("kernel_id", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("hx", ctypes.c_double), ("hy", ctypes.c_double),
-                ("grid", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+                ("precision", ctypes.c_int32), ("hx", ctypes.c_double), ("hy", ctypes.c_double),
+                ("grid", ctypes.c_void_p), ("out", ctypes.c_void_p), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 _lib = None
@@ -486,13 +487,17 @@ BATCH_EAGER = 4
 
 
 def eval_batched(maps, raw: bool = False, eager: bool = False, stream_device=None):
-    """Many maps in one persistent launch (kde_eval_batched).  `maps` is a list of
-    (points [n, 2] CUDA FP32 grid units, kernel, hx, hy, Grid, out [ny, nx] CUDA
-    FP32) tuples; outputs are written in place."""
+    """Many maps in one call (kde_eval_batched).  `maps` is a list of (points
+    [n, 2] CUDA FP32 grid units, kernel, hx, hy, Grid, out [ny, nx] CUDA FP32)
+    tuples, optionally followed by a precision name (default "fp32": the
+    persistent launch) and a truncate flag; outputs are written in place."""
     import torch
     descs = (MapDesc * len(maps))()
     dev = None
-    for d, (pts, kernel, hx, hy, grid, out) in zip(descs, maps):
+    for d, m in zip(descs, maps):
+        pts, kernel, hx, hy, grid, out = m[:6]
+        precision = m[6] if len(m) > 6 else "fp32"
+        truncate = bool(m[7]) if len(m) > 7 else False
         _check_points(pts, torch)
         if not (out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()
                 and out.numel() == grid.nx * grid.ny):
@@ -501,10 +506,12 @@ def eval_batched(maps, raw: bool = False, eager: bool = False, stream_device=Non
         d.points = pts.data_ptr() if pts.numel() else None
         d.n = pts.shape[0]
         d.kernel_id = _kernel_id(kernel)
-        d.reserved = 0
+        d.precision = PRECISIONS[precision]
         d.hx, d.hy = float(hx), float(hy)
         d.grid = grid.handle.value
         d.out = out.data_ptr()
+        d.flags = TRUNCATE if truncate else 0
+        d.reserved = 0
     if dev is None:
         return
     flags = (RAW_SUM if raw else 0) | (BATCH_EAGER if eager else 0)

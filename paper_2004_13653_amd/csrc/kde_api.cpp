@@ -528,27 +528,52 @@ int kde_eval_batched(const kde_map *maps, int32_t n_maps, uint32_t flags, void *
             if (st != KDE_OK) return fail(st, "kde_eval_batched: map %d: %s", m, g_err.c_str());
             if (d.out == nullptr || d.reserved != 0)
                 return fail(KDE_EINVAL, "kde_eval_batched: map %d: out is NULL or reserved != 0", m);
+            if (d.precision < KDE_FP32_DIRECT || d.precision > KDE_BF16X3_SEP)
+                return fail(KDE_EINVAL, "kde_eval_batched: map %d: unknown precision %d", m, (int)d.precision);
+            if (d.flags & ~KDE_TRUNCATE)
+                return fail(KDE_EINVAL, "kde_eval_batched: map %d: unknown map flags 0x%x", m, d.flags);
+            if ((d.flags & KDE_TRUNCATE) && d.kernel_id != KDE_GAUSSIAN)
+                return fail(KDE_EINVAL, "kde_eval_batched: map %d: KDE_TRUNCATE applies to the Gaussian only", m);
         }
         if (n_maps == 0) return KDE_OK;
-        std::vector<kde::MapArgs> args((size_t)n_maps);
+        // FP32 direct maps share the persistent launch; the others run one by one.
+        std::vector<kde::MapArgs> args;
+        std::vector<int32_t> single;
         for (int32_t m = 0; m < n_maps; ++m) {
             const kde_map &d = maps[m];
-            args[m] = make_args(d.points, d.n, d.kernel_id, d.hx, d.hy, d.grid, d.out, flags);
-            if (d.n == 0) args[m].scale = 0.0f;  // zero map
+            if (d.precision != KDE_FP32_DIRECT || (d.flags & KDE_TRUNCATE)) {
+                single.push_back(m);
+                continue;
+            }
+            args.push_back(make_args(d.points, d.n, d.kernel_id, d.hx, d.hy, d.grid, d.out, flags));
+            if (d.n == 0) args.back().scale = 0.0f;  // zero map
         }
         hipStream_t s = static_cast<hipStream_t>(stream);
         const bool eager = (flags & KDE_BATCH_EAGER) != 0;
-        int st = pick_batch_rc(args, s);
-        if (st != KDE_OK) return st;
-        void *ws = nullptr;
-        size_t bytes = 0;
-        if (eager) {
-            bytes = kde::batched_workspace_bytes(args.data(), n_maps);
-            st = get_workspace(s, bytes, &ws);
+        if (!args.empty()) {
+            int st = pick_batch_rc(args, s);
+            if (st != KDE_OK) return st;
+            void *ws = nullptr;
+            size_t bytes = 0;
+            if (eager) {
+                bytes = kde::batched_workspace_bytes(args.data(), (int)args.size());
+                st = get_workspace(s, bytes, &ws);
+                if (st != KDE_OK) return st;
+            }
+            hipError_t e = kde::run_batched(args.data(), (int)args.size(), !eager, ws, bytes, s);
+            if (e != hipSuccess) return hip_fail(e, "kde_eval_batched");
+        }
+        for (int32_t m : single) {
+            const kde_map &d = maps[m];
+            int st = eval_map(d.points, d.n, d.kernel_id, d.hx, d.hy, d.grid, d.out, d.precision,
+                              d.flags | (flags & KDE_RAW_SUM), stream, false, "kde_eval_batched");
             if (st != KDE_OK) return st;
         }
-        hipError_t e = kde::run_batched(args.data(), n_maps, !eager, ws, bytes, s);
-        return e == hipSuccess ? KDE_OK : hip_fail(e, "kde_eval_batched");
+        if (eager && !single.empty()) {
+            hipError_t e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return hip_fail(e, "kde_eval_batched");
+        }
+        return KDE_OK;
     } catch (const std::bad_alloc &) {
         return fail(KDE_ENOMEM, "kde_eval_batched: out of host memory");
     } catch (...) {

@@ -248,19 +248,35 @@ class MapSpec:
     side: int       # grid is side x side over the pool's box
     h_deg: float    # hx = hy
     kernel: int     # Table I kernel id
+    eps_m: float = 0.0  # Douglas-Peucker threshold the window is compressed at (0: raw)
 
 
 def batch_specs(n_maps: int, pool_points: int, seed: int = SEED0 + 4, min_points: int = 1000,
-                max_points: int = 200_000, sides=(256, 512, 1024), h_range=(0.001, 0.008)) -> list[MapSpec]:
+                max_points: int = 200_000, sides=(256, 512, 1024), h_range=(0.001, 0.008),
+                eps_choices=(0.0, 10.0, 50.0, 100.0)) -> list[MapSpec]:
     """Per-map point counts log-uniform in [min_points, max_points], grid sides
     drawn uniformly from `sides`, bandwidth U(h_range), kernel uniform over the
-    eight; each map is a contiguous slice (a time window) of the pool."""
+    eight; each map is a contiguous slice (a time window) of the pool, to be
+    Douglas-Peucker-compressed at a threshold drawn uniformly from eps_choices
+    (a second generator, so the other draws do not depend on it)."""
     rng = np.random.Generator(np.random.PCG64(seed))
+    rng_eps = np.random.Generator(np.random.PCG64(seed + 1))
     specs = []
     for _ in range(n_maps):
         count = int(round(math.exp(rng.uniform(math.log(min_points), math.log(max_points)))))
         count = min(count, pool_points)
         start = int(rng.integers(0, pool_points - count + 1))
         specs.append(MapSpec(start, count, int(rng.choice(sides)), float(rng.uniform(*h_range)),
-                             int(rng.integers(0, 8))))
+                             int(rng.integers(0, 8)), float(rng_eps.choice(eps_choices))))
     return specs
+
+
+def window_tracks(pool: Tracks, start: int, count: int) -> Tracks:
+    """The points [start, start + count) of the pool's merged buffer as tracks:
+    the pool's tracks cut at the window's two ends."""
+    ends = np.cumsum(np.asarray(pool.lengths, dtype=np.int64))
+    begins = ends - pool.lengths
+    lo = np.maximum(begins, start)
+    hi = np.minimum(ends, start + count)
+    lens = (hi - lo)[hi > lo]
+    return Tracks(pool.xy[start:start + count].copy(), lens.astype(np.int64), pool.box)

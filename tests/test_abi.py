@@ -91,6 +91,14 @@ def test_other_entry_points_validate():
     m[1].kernel_id = 11
     assert L.kde_eval_batched(m, 2, 0, None) == kde.KDE_EINVAL
     assert "kernel" in L.kde_last_error().decode()
+    m[1].kernel_id = 2
+    for field, value, words in (("precision", 5, "precision"), ("precision", -1, "precision"),
+                                ("flags", 2, "flags"), ("flags", 8, "KDE_TRUNCATE"), ("reserved", 1, "reserved")):
+        setattr(m[1], field, value)
+        assert L.kde_eval_batched(m, 2, 0, None) == kde.KDE_EINVAL, (field, value)
+        assert words in L.kde_last_error().decode(), (field, value)
+        setattr(m[1], field, 0)
+    assert ctypes.sizeof(kde.MapDesc) == 64
 
 
 def test_main_kernel_timer_arguments():

@@ -82,34 +82,114 @@ def test_graph_replays_track_new_inputs():
             assert kt.peak_error(out.cpu().numpy(), ref.cpu().numpy()) <= 2e-6, (rep, s)
 
 
+PREC_GATE = {"fp32": ("e_inf", kt.FP32_GATE), "fp16": ("e_2", 2e-3), "bf16x3": ("e_2", 2e-3)}
+
+
+def _window_points(pool, spec):
+    """World points of the batch map: the window [start, start + count) of the
+    pool, Douglas-Peucker-compressed (the oracle's, on Mercator metres) at the
+    map's threshold; 0 keeps the raw window."""
+    w = synth.window_tracks(pool, spec.start, spec.count)
+    if spec.eps_m == 0.0:
+        return w.xy
+    mx, my = synth.mercator(w.xy[:, 0], w.xy[:, 1], pool.box.center_lat)
+    keep = oracle.dp_keep(np.column_stack([mx, my]), w.lengths, spec.eps_m).astype(bool)
+    return w.xy[keep]
+
+
+def _c5_precision(k, spec):
+    """Gaussian maps on the matrix cores (FP16, every fourth on the BF16 hi/lo
+    split), the compact kernels on the FP32 persistent launch."""
+    if spec.kernel != oracle.GAUSSIAN:
+        return "fp32"
+    return "bf16x3" if k % 4 == 0 else "fp16"
+
+
+@pytest.mark.timeout(900)
 def test_batch_of_256_time_windows():
-    """256 maps: point counts log-uniform in [1k, 200k] (slices of a 4M-point
-    pool), grids from {256^2, 512^2, 1024^2}, h ~ U(0.001, 0.008) degrees, kernels
-    uniform over the eight.  Every map against a separate kde_eval call; a few
-    against the oracle at sampled pixels."""
+    """256 maps: windows of a 4M-point pool with point counts log-uniform in
+    [1k, 200k], each Douglas-Peucker-compressed at a threshold from {0, 10, 50,
+    100} m, grids from {256^2, 512^2, 1024^2}, h ~ U(0.001, 0.008) degrees,
+    kernels uniform over the eight; Gaussian maps on the matrix cores.  Every map
+    against a separate kde_eval call of its precision (bit-identical for the
+    matrix-core maps), and for every precision some maps against the oracle at
+    sampled pixels, each at its precision's gate."""
     import torch
     t = kt.lanes(8000, 500, 2)
     b = synth.BOX_C2
     grids = {s: kde.Grid(b.lon0, b.lon1, b.lat0, b.lat1, s, s) for s in (256, 512, 1024)}
-    units = {s: kde.to_grid_units(t.xy, g) for s, g in grids.items()}
+    ogrids = {s: oracle.Grid(b.lon0, b.lon1, b.lat0, b.lat1, s, s) for s in (256, 512, 1024)}
     specs = synth.batch_specs(256, t.n)
-    maps = _batch(specs, units, grids)
+    assert {s.eps_m for s in specs} == {0.0, 10.0, 50.0, 100.0}
+    maps, units = [], []
+    for k, s in enumerate(specs):
+        XY = kde.to_grid_units(_window_points(t, s), grids[s.side])
+        units.append(XY)
+        out = torch.full((s.side, s.side), float("nan"), device=kt.device())
+        maps.append((kt.to_device(XY), s.kernel, s.h_deg, s.h_deg, grids[s.side], out, _c5_precision(k, s)))
+    kt.log(f"256 windows: {sum(u.shape[0] for u in units)} points after compression "
+           f"(of {sum(s.count for s in specs)}), precisions "
+           f"{ {p: sum(1 for m in maps if m[6] == p) for p in PREC_GATE} }")
     kde.eval_batched(maps)
     torch.cuda.synchronize()
-    worst = 0.0
-    for k, (s, (pts, kernel, hx, hy, g, out)) in enumerate(zip(specs, maps)):
-        ref = kde.eval(pts, kernel, hx, hy, g)
+    worst, checked = 0.0, {p: 0 for p in PREC_GATE}
+    for k, (s, (pts, kernel, hx, hy, g, out, prec)) in enumerate(zip(specs, maps)):
+        ref = kde.eval(pts, kernel, hx, hy, g, precision=prec)
         torch.cuda.synchronize()
-        e = kt.peak_error(out.cpu().numpy(), ref.cpu().numpy())
-        worst = max(worst, e)
-        assert e <= 2e-6, (k, s)
-        if k % 64 == 0:
-            y = out.cpu().numpy().astype(np.float64)
-            og = oracle.Grid(*g.bounds, g.nx, g.ny)
-            ij = kt.sample_pixels(y, 16, seed=k)
-            r = kt.oracle_density_at(units[s.side][s.start:s.start + s.count], kernel, hx, hy, og, ij)
-            assert kt.peak_error(y[ij[:, 1], ij[:, 0]], r) <= kt.FP32_GATE, (k, s)
-    kt.log(f"256 maps: worst peak-normalised difference to separate calls {worst:.2e}")
+        y, r = out.cpu().numpy(), ref.cpu().numpy()
+        if prec == "fp32":
+            e = kt.peak_error(y, r)
+            worst = max(worst, e)
+            assert e <= 2e-6, (k, s)
+        else:
+            np.testing.assert_array_equal(y, r)
+        if checked[prec] < 3 and (prec != "fp32" or k % 32 == 0):
+            checked[prec] += 1
+            yy = y.astype(np.float64)
+            ij = kt.sample_pixels(yy, 16, seed=k)
+            ro = kt.oracle_density_at(units[k], kernel, hx, hy, ogrids[s.side], ij)
+            e = oracle.errors(yy[ij[:, 1], ij[:, 0]], ro)
+            name, gate = PREC_GATE[prec]
+            kt.log(f"map {k} ({prec}, kernel {kernel}, eps {s.eps_m} m, n {units[k].shape[0]}): "
+                   f"e_inf {e['e_inf']:.2e} e_2 {e['e_2']:.2e}")
+            assert e[name] <= gate, (k, s)
+    assert all(v >= 2 for v in checked.values()), checked
+    kt.log(f"256 maps: worst peak-normalised FP32 difference to separate calls {worst:.2e}")
+
+
+@pytest.mark.parametrize("eager", [True, False])
+def test_mixed_precision_batch(eager):
+    """FP32, matrix-core and truncated maps in one call: the persistent launch
+    for the FP32 maps, the others one by one after it; each equals kde_eval of
+    its precision (bit for bit for the single launches), empty maps are zero."""
+    import torch
+    t, grids, units = _pool(100)
+    cases = [(synth.MapSpec(100, 20000, 256, 0.004, 6), "fp16", False),
+             (synth.MapSpec(3000, 7000, 100, 0.015, 6), "bf16", False),
+             (synth.MapSpec(0, 30000, 256, 0.003, 2), "fp16x3", False),
+             (synth.MapSpec(500, 9000, 256, 0.004, 6), "fp32", True),
+             (synth.MapSpec(900, 15000, 100, 0.01, 6), "bf16x3", True),
+             (synth.MapSpec(0, 0, 64, 0.01, 6), "fp16", False),
+             (synth.MapSpec(1000, 6000, 64, 0.02, 3), "fp32", False),
+             (synth.MapSpec(2000, 8000, 256, 0.004, 6), "fp32", False)]
+    maps = []
+    for s, prec, trunc in cases:
+        XY = units[s.side][s.start:s.start + s.count]
+        pts = kt.to_device(XY) if s.count else torch.empty((0, 2), device=kt.device())
+        out = torch.full((s.side, s.side), float("nan"), device=kt.device())
+        maps.append((pts, s.kernel, s.h_deg, s.h_deg, grids[s.side], out, prec, trunc))
+    kde.eval_batched(maps, eager=eager)
+    torch.cuda.synchronize()
+    for (s, prec, trunc), (pts, kernel, hx, hy, g, out, _, _) in zip(cases, maps):
+        y = out.cpu().numpy()
+        if s.count == 0:
+            assert np.all(y == 0.0)
+            continue
+        ref = kde.eval(pts, kernel, hx, hy, g, precision=prec, truncate=trunc).cpu().numpy()
+        if prec == "fp32" and not trunc:
+            assert kt.peak_error(y, ref) <= 2e-6, (s, prec)
+        else:
+            np.testing.assert_array_equal(y, ref)
 
 
 @pytest.mark.parametrize("rc", [2, 4, 8])

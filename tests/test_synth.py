@@ -94,3 +94,21 @@ def test_dp_compress_counts():
     assert c10.lengths.sum() == c10.n and c100.n < c10.n < t.n
     assert (c100.lengths >= 2).all()
     assert 0.0 < synth.compression_ratio(t, c10) < synth.compression_ratio(t, c100) < 100.0
+
+
+def test_window_tracks_cuts_the_pool_at_both_ends():
+    t = synth.workload_lanes(n_tracks=7, pts=10, seed_index=1)
+    w = synth.window_tracks(t, 13, 25)
+    np.testing.assert_array_equal(w.xy, t.xy[13:38])
+    assert list(w.lengths) == [7, 10, 8]
+    assert synth.window_tracks(t, 20, 10).lengths.tolist() == [10]
+    assert synth.window_tracks(t, 0, 70).lengths.tolist() == [10] * 7
+
+
+def test_batch_specs_thresholds_do_not_move_other_draws():
+    a = synth.batch_specs(50, 10**6)
+    b = synth.batch_specs(50, 10**6, eps_choices=(0.0,))
+    assert [(s.start, s.count, s.side, s.h_deg, s.kernel) for s in a] == \
+           [(s.start, s.count, s.side, s.h_deg, s.kernel) for s in b]
+    assert {s.eps_m for s in a} == {0.0, 10.0, 50.0, 100.0}
+    assert {s.eps_m for s in b} == {0.0}
