@@ -58,15 +58,32 @@ __device__ __forceinline__ void reach(const BinGeom &g, float2 v, int &tx0, int 
     ty1 = (int)j1 / g.tile;
 }
 
+// Counts per (tile, column); lanes of a wave that register in the same tile
+// combine into one atomic (tracks are stored in order, so neighbouring points
+// mostly share their tiles).
 __global__ __launch_bounds__(256) void bin_count_kernel(BinGeom g, const float2 *__restrict__ pts,
                                                         unsigned *__restrict__ cnt) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= g.n) return;
-    const int64_t w = p / kColBlock;
-    int tx0, tx1, ty0, ty1;
-    reach(g, pts[p], tx0, tx1, ty0, ty1);
-    for (int ty = ty0; ty <= ty1; ++ty)
-        for (int tx = tx0; tx <= tx1; ++tx) atomicAdd(&cnt[(int64_t)(ty * g.tiles_x + tx) * g.wblocks + w], 1u);
+    const int lane = threadIdx.x & 63;
+    if (p - lane >= g.n) return;  // whole wave past the end
+    const int64_t w = p / kColBlock;  // one column per wave (kColBlock is a multiple of 64)
+    int tx0 = 1, tx1 = 0, ty0 = 1, ty1 = 0;
+    if (p < g.n) reach(g, pts[p], tx0, tx1, ty0, ty1);
+    const int ncols = tx1 >= tx0 ? tx1 - tx0 + 1 : 0;
+    const int ntl = ncols > 0 && ty1 >= ty0 ? ncols * (ty1 - ty0 + 1) : 0;
+    int most = ntl;
+    for (int o = 32; o > 0; o >>= 1) most = max(most, __shfl_xor(most, o));
+    for (int j = 0; j < most; ++j) {
+        const int key = j < ntl ? (ty0 + j / ncols) * g.tiles_x + tx0 + j % ncols : -1;
+        uint64_t pending = __ballot(key >= 0);
+        while (pending) {
+            const int leader = __ffsll((unsigned long long)pending) - 1;
+            const int lkey = __shfl(key, leader);
+            const uint64_t same = __ballot(key == lkey);
+            if (lane == leader) atomicAdd(&cnt[(int64_t)lkey * g.wblocks + w], (unsigned)__popcll(same));
+            pending &= ~same;
+        }
+    }
 }
 
 // Exclusive scan, pass 1: each block scans kScanBlock entries in place and
