@@ -520,6 +520,35 @@ def bench_compact(torch, kde, synth, steps: int):
     return res
 
 
+def calibration_copy(torch, dev) -> int:
+    """A plain elementwise copy of 2^26 floats: the HBM byte counters of a
+    kernel that reads and writes 256 MiB each."""
+    src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    return src.numel() * 4
+
+
+def profile_compact(torch, kde, synth) -> int:
+    """Counter run for the support-binned FP32 maps: the 10^6-point workload of
+    bench_compact (raw points), two maps each of the uniform, Epanechnikov and
+    cosine kernels, then the calibration copy."""
+    t = synth.workload_lanes(n_tracks=2000, pts=500, seed_index=1)
+    b = synth.BOX_C2
+    g = kde.Grid(b.lon0, b.lon1, b.lat0, b.lat1, 1024, 1024)
+    out = torch.empty((1024, 1024), device="cuda")
+    pts = torch.from_numpy(kde.to_grid_units(t.xy, g)).cuda()
+    for kname in ("uniform", "epanechnikov", "cosine"):
+        for _ in range(2):
+            kde.eval(pts, kname, 0.002, 0.002, g, out=out)
+    torch.cuda.synchronize()
+    nb = calibration_copy(torch, out.device)
+    log(f"profile run: 2 maps each of uniform, epanechnikov, cosine ({pts.shape[0]} points, 1024x1024), "
+        f"then a copy of {nb} bytes read + written")
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -528,9 +557,11 @@ def main() -> int:
     ap.add_argument("--direct-steps", type=int, default=3, help="timed steps of the FP32 direct path")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--profile-once", action="store_true",
-                    help="for counter runs: two FP16 maps and one FP32 direct map, then a 256 MiB "
-                         "elementwise copy (torch.neg) as the byte-count calibration; prints no JSON")
+    ap.add_argument("--profile-once", nargs="?", const="headline", choices=("headline", "compact"),
+                    help="for counter runs, prints no JSON: 'headline' (the default) runs two FP16 maps and one "
+                         "FP32 direct map of the 4M-point workload, 'compact' two uniform, Epanechnikov and "
+                         "cosine maps each of 10^6 points on 1024 x 1024; then a 256 MiB elementwise copy "
+                         "(torch.neg) as the byte-count calibration")
     ap.add_argument("--sections", default="adjoint,batched,kernels,binned,truncated,dp,metrics",
                     help="extra measured sections beside the headline: adjoint, batched, kernels, binned, "
                          "truncated, dp, metrics (or none)")
@@ -546,6 +577,8 @@ def main() -> int:
     import paper_2004_13653_amd as kde
     import synth
 
+    if args.profile_once == "compact":
+        return profile_compact(torch, kde, synth)
     t = synth.workload_lanes(n_tracks=N_TRACKS, pts=PTS_PER_TRACK, seed_index=2)
     b = synth.BOX_C2
     g = kde.Grid(b.lon0, b.lon1, b.lat0, b.lat1, SIDE, SIDE)
@@ -565,11 +598,8 @@ def main() -> int:
         f()
         f()
         run("fp32")()
-        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        torch.neg(src, out=dst)
-        torch.cuda.synchronize()
-        log(f"profile run: 2 FP16 maps, 1 FP32 direct map, then a copy of {src.numel() * 4} bytes read + written")
+        nb = calibration_copy(torch, dev)
+        log(f"profile run: 2 FP16 maps, 1 FP32 direct map, then a copy of {nb} bytes read + written")
         return 0
 
     results, maps = {}, {}
