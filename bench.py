@@ -226,17 +226,30 @@ def bench_adjoint(torch, kde, synth, steps: int):
         f = kde.eval(pts, kname, 0.004, 0.004, g)
         T = kde.eval(ptc, kname, 0.004, 0.004, g)
         gbar = (2.0 * (f - T)).contiguous()
-        tot, _, _ = timed_steps(torch, lambda: kde.backward(pts, kname, 0.004, 0.004, g, gbar, want_h=False),
-                                steps, 1)
+        mfma = kname == "gaussian"  # the Gaussian VJP runs on matrix cores, with one main kernel
+        tot, _, kern = timed_steps(torch, lambda: kde.backward(pts, kname, 0.004, 0.004, g, gbar, want_h=False),
+                                   steps, 1, kde if mfma else None)
         ms_vjp = tot / steps
         # with the bandwidth gradient (synchronises for the two host scalars)
         t0 = time.perf_counter()
         for _ in range(steps):
             kde.backward(pts, kname, 0.004, 0.004, g, gbar)
         ms_vjp_h = (time.perf_counter() - t0) * 1e3 / steps
-        res[kname] = {"vjp_ms": ms_vjp, "vjp_pairs_per_s": n * 512 * 512 / (ms_vjp * 1e-3),
-                      "vjp_with_h_ms": ms_vjp_h}
-        log(f"adjoint {kname}: vjp {ms_vjp:.2f} ms")
+        ent = {"vjp_ms": ms_vjp, "vjp_pairs_per_s": n * 512 * 512 / (ms_vjp * 1e-3), "vjp_with_h_ms": ms_vjp_h}
+        if mfma:
+            # Two contractions (Gbar^T Gy and Gbar Gx, 2 n nx ny flop each), three
+            # BF16 products each (hi/lo split).
+            k_ms = sum(kern) / len(kern)
+            tfl = 3 * 4.0 * n * 512 * 512 / (k_ms * 1e-3) / 1e12
+            tot32, _, _ = timed_steps(torch, lambda: kde.backward(pts, kname, 0.004, 0.004, g, gbar, want_h=False,
+                                                                  fp32=True), steps, 1)
+            ent.update({"precision": "bf16x3", "mfma_kernel_ms": k_ms, "mfma_tflops": tfl,
+                        "mfma_frac": tfl / PEAK_MFMA_TFLOPS["bf16x3"], "vjp_fp32_ms": tot32 / steps})
+            log(f"adjoint {kname}: vjp {ms_vjp:.2f} ms on matrix cores (main kernel {k_ms:.2f} ms, "
+                f"{tfl / PEAK_MFMA_TFLOPS['bf16x3'] * 100:.1f} % of MFMA peak), FP32 {tot32 / steps:.2f} ms")
+        else:
+            log(f"adjoint {kname}: vjp {ms_vjp:.2f} ms")
+        res[kname] = ent
     Hx, Hy = kde.bandwidth_units(0.004, 0.004, g)
     support = lscv_support_pairs(XY, float(Hx), float(Hy))
     lscv = {"ordered_pairs": float(n) * n, "in_support_pairs": support}

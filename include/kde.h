@@ -89,6 +89,7 @@ enum {
 #define KDE_GRID_UNIT_GRADS 2u  /* kde_backward: grad_points as dL/dX_p, dL/dY_p in grid units */
 #define KDE_BATCH_EAGER 4u      /* kde_eval_batched: launch directly instead of replaying a graph */
 #define KDE_TRUNCATE 8u         /* kde_eval, Gaussian, KDE_FP32_DIRECT: drop pairs beyond 8 bandwidths */
+#define KDE_VJP_FP32 16u        /* kde_backward, Gaussian: per-pair FP32 sums instead of matrix cores */
 
 typedef struct kde_grid kde_grid; /* opaque, immutable, library-owned */
 
@@ -198,7 +199,12 @@ int kde_eval_batched(const kde_map *maps, int32_t n_maps, uint32_t flags, void *
  *                non-NULL the call synchronises `stream`
  * Per pair FP32; bandwidth sums reduced in FP64 in a fixed order.  The
  * derivative of k is taken from its formula inside the support (at the kink
- * u = 0 of the triangular kernel, 0).  flags: KDE_RAW_SUM | KDE_GRID_UNIT_GRADS. */
+ * u = 0 of the triangular kernel, 0).  The Gaussian uses its separability
+ * (Sec. III-C): the sums become the contractions Gbar^T Gy and Gbar Gx on
+ * matrix cores with BF16 hi/lo operands (three products, FP32 accumulation;
+ * relative errors of a few 1e-6), unless KDE_VJP_FP32 asks for the per-pair
+ * FP32 evaluation or the matrix-core workspace would exceed 4 GiB.
+ * flags: KDE_RAW_SUM | KDE_GRID_UNIT_GRADS | KDE_VJP_FP32. */
 int kde_backward(const float *points, int64_t n, int32_t kernel_id, double hx, double hy, const kde_grid *g,
                  const float *grad_out, float *grad_points, double *grad_h, uint32_t flags, void *stream);
 
@@ -350,18 +356,19 @@ int kde_autotune_dump(char *buf, size_t cap, size_t *needed);
 /* Empties the in-memory cache. */
 int kde_autotune_clear(void);
 
-/* Measurement hook.  The next kde_eval, kde_conv_counts, kde_eval_binned or
- * kde_compression_metrics call made by this thread records start_event on its
- * stream right before it launches its main kernel (the separable contraction,
- * the FP32 direct evaluation, the support-binned gather, the two convolution
- * passes, or the per-track length and DTW pass) and
- * stop_event right after, so that the elapsed time between the two events is
- * that work alone, without the point padding, split reduction, support-binning
- * or counting passes.  Both are hipEvent_t handles owned by the caller, created on
- * the device of that call with timing enabled; the request is consumed by that
- * call (also by one that fails or has n = 0, which records nothing).  NULL,
- * NULL cancels a pending request.  Returns KDE_OK, or KDE_EINVAL if exactly
- * one event is NULL. */
+/* Measurement hook.  The next kde_eval, kde_eval_noalloc, kde_backward,
+ * kde_conv_counts, kde_eval_binned or kde_compression_metrics call made by this
+ * thread records start_event on its stream right before it launches its main
+ * kernel (the separable contraction, the FP32 direct evaluation, the
+ * support-binned gather, the VJP kernel, the two convolution passes, or the
+ * per-track length and DTW pass) and stop_event right after, so that the
+ * elapsed time between the two events is that work alone, without the point
+ * padding, split reduction, support-binning or counting passes.  Both are
+ * hipEvent_t handles owned by the caller, created on the device of that call
+ * with timing enabled; the request is consumed by that call (also by one that
+ * fails or has n = 0, which records nothing).  NULL, NULL cancels a pending
+ * request, and so does kde_eval_batched.  Returns KDE_OK, or KDE_EINVAL if
+ * exactly one event is NULL. */
 int kde_time_next_main_kernel(void *start_event, void *stop_event);
 
 /* Thread-local text of the last failure on this thread ("" if none). */

@@ -394,12 +394,14 @@ def time_next_main_kernel(start, stop) -> None:
 
 
 GRID_UNIT_GRADS = 2
+VJP_FP32 = 16
 
 
 def backward(points, kernel, hx: float, hy: float, grid: Grid, grad_out, raw: bool = False,
-             grid_units: bool = False, want_points: bool = True, want_h: bool = True):
+             grid_units: bool = False, want_points: bool = True, want_h: bool = True, fp32: bool = False):
     """Vector-Jacobian product of `eval` (kde_backward).  Returns (grad_points
-    [n, 2] FP32 tensor or None, (dL/dhx, dL/dhy) floats or None)."""
+    [n, 2] FP32 tensor or None, (dL/dhx, dL/dhy) floats or None).  fp32: the
+    Gaussian's sums pair by pair in FP32 instead of on matrix cores."""
     import torch
     _check_points(points, torch)
     if not (grad_out.is_cuda and grad_out.dtype == torch.float32 and grad_out.is_contiguous()
@@ -407,7 +409,7 @@ def backward(points, kernel, hx: float, hy: float, grid: Grid, grad_out, raw: bo
         raise ValueError("grad_out must be a contiguous CUDA float32 tensor with ny*nx elements")
     gp = torch.empty_like(points) if want_points else None
     gh = (ctypes.c_double * 2)() if want_h else None
-    flags = (RAW_SUM if raw else 0) | (GRID_UNIT_GRADS if grid_units else 0)
+    flags = (RAW_SUM if raw else 0) | (GRID_UNIT_GRADS if grid_units else 0) | (VJP_FP32 if fp32 else 0)
     with torch.cuda.device(points.device):
         _check(lib().kde_backward(points.data_ptr() if points.numel() else None, points.shape[0],
                                   _kernel_id(kernel), hx, hy, grid.handle, grad_out.data_ptr(),

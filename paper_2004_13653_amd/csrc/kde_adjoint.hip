@@ -591,6 +591,7 @@ hipError_t launch_vjp(const float2 *pts, int64_t n, int kernel_id, float Hx, flo
     VjpLaunch p{pts, n, gbar, nx, ny, Hx, Hy, (float)(1.0 / (double)Hx), (float)(1.0 / (double)Hy), fx, fy, grad,
                 part};
     const dim3 grid((unsigned)vjp_blocks(n));
+    main_kernel_begin(stream);
     switch (kernel_id) {
     case kUniform: hipLaunchKernelGGL(vjp_kernel<kUniform>, grid, dim3(kAdjThreads), 0, stream, p); break;
     case kTriangular: hipLaunchKernelGGL(vjp_kernel<kTriangular>, grid, dim3(kAdjThreads), 0, stream, p); break;
@@ -602,6 +603,7 @@ hipError_t launch_vjp(const float2 *pts, int64_t n, int kernel_id, float Hx, flo
     case kCosine: hipLaunchKernelGGL(vjp_kernel<kCosine>, grid, dim3(kAdjThreads), 0, stream, p); break;
     default: return hipErrorInvalidValue;
     }
+    main_kernel_end(stream);
     return hipGetLastError();
 }
 

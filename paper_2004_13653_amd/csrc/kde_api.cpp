@@ -518,6 +518,9 @@ int kde_eval_noalloc(const float *points, int64_t n, int32_t kernel_id, double h
 }
 
 int kde_eval_batched(const kde_map *maps, int32_t n_maps, uint32_t flags, void *stream) {
+    // A pending main-kernel timing request is cancelled, not served: the batch
+    // has no single main kernel.
+    g_timer = MainTimer{};
     try {
         if (n_maps < 0 || (n_maps > 0 && maps == nullptr)) return fail(KDE_EINVAL, "kde_eval_batched: bad map array");
         if (flags & ~(KDE_RAW_SUM | KDE_BATCH_EAGER))
@@ -768,11 +771,12 @@ int kde_compression_metrics(const double *xy_o, int64_t n_o, const int64_t *star
 
 int kde_backward(const float *points, int64_t n, int32_t kernel_id, double hx, double hy, const kde_grid *g,
                  const float *grad_out, float *grad_points, double *grad_h, uint32_t flags, void *stream) {
+    ConsumeTimer consume_timer;
     try {
         int st = check_map(points, n, kernel_id, hx, hy, g, "kde_backward");
         if (st != KDE_OK) return st;
         if (grad_out == nullptr) return fail(KDE_EINVAL, "kde_backward: grad_out is NULL");
-        if (flags & ~(KDE_RAW_SUM | KDE_GRID_UNIT_GRADS))
+        if (flags & ~(KDE_RAW_SUM | KDE_GRID_UNIT_GRADS | KDE_VJP_FP32))
             return fail(KDE_EINVAL, "kde_backward: unknown flags 0x%x", flags);
         if (grad_points == nullptr && grad_h == nullptr) return KDE_OK;
         if (n == 0) {
@@ -790,11 +794,16 @@ int kde_backward(const float *points, int64_t n, int32_t kernel_id, double hx, d
         const double fx = -sigma / (double)Hx / (grid_units ? 1.0 : g->dx);
         const double fy = -sigma / (double)Hy / (grid_units ? 1.0 : g->dy);
         const int64_t blocks = kde::vjp_blocks(n);
+        const size_t mfma_bytes = kde::vjp_mfma_workspace_bytes(n, g->nx, g->ny);
+        const bool mfma = kernel_id == KDE_GAUSSIAN && !(flags & KDE_VJP_FP32) && mfma_bytes <= (size_t(4) << 30);
         void *ws = nullptr;
-        st = get_workspace(s, (size_t)blocks * 3 * sizeof(double), &ws);
+        st = get_workspace(s, mfma ? mfma_bytes : (size_t)blocks * 3 * sizeof(double), &ws);
         if (st != KDE_OK) return st;
-        hipError_t e = kde::launch_vjp(reinterpret_cast<const float2 *>(points), n, kernel_id, Hx, Hy, grad_out,
-                                       g->nx, g->ny, (float)fx, (float)fy, grad_points, static_cast<double *>(ws), s);
+        const float2 *pts = reinterpret_cast<const float2 *>(points);
+        hipError_t e = mfma ? kde::launch_vjp_mfma(pts, n, Hx, Hy, grad_out, g->nx, g->ny, (float)fx, (float)fy,
+                                                   grad_points, ws, s)
+                            : kde::launch_vjp(pts, n, kernel_id, Hx, Hy, grad_out, g->nx, g->ny, (float)fx,
+                                              (float)fy, grad_points, static_cast<double *>(ws), s);
         if (e != hipSuccess) return hip_fail(e, "kde_backward");
         if (grad_h != nullptr) {
             std::vector<double> part((size_t)blocks * 3);

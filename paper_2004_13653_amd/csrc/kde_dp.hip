@@ -19,9 +19,15 @@
 //      chord's decision).
 // Scores are FP64 with no fused multiply-add (the decision is taken exactly as
 // the reference does), and all cross-thread combination is integer atomics:
-// the keep mask does not depend on thread order.  The host checks after each
-// group of levels whether any chord still split (the paper synchronises with
-// the host every level).
+// the keep mask does not depend on thread order.
+//
+// Tracks are independent, so each track of at most kTrackMax points runs all
+// its levels inside one workgroup (dp_track_kernel): the track's points in
+// LDS, the chord slots as LDS atomics, the four steps separated by workgroup
+// barriers, until a level splits no chord.  Only longer tracks take the
+// level-synchronous kernels below, three launches per level over the points of
+// those tracks, the host checking after each group of levels whether any chord
+// still split (the paper synchronises with the host every level).
 #include "kde_internal.h"
 
 #include <algorithm>
@@ -57,20 +63,124 @@ __device__ __forceinline__ bool dp_split(const double2 *__restrict__ xy, int64_t
     return score * score > eps2 * c2;
 }
 
-// bad = 1 unless start[0] = 0, start[n_tracks] = n and the offsets never decrease.
+constexpr int kTrackThreads = 256;
+constexpr int kTrackMax = 1024;                       // longest track one workgroup takes
+constexpr int kTrackPer = kTrackMax / kTrackThreads;  // points per thread
+
+// counters[0] = 1 unless start[0] = 0, start[n_tracks] = n and the offsets
+// never decrease; counters[1] = number of tracks longer than kTrackMax.
 __global__ __launch_bounds__(256) void dp_check_kernel(const int64_t *__restrict__ start, int64_t n_tracks, int64_t n,
-                                                       unsigned *__restrict__ bad) {
+                                                       unsigned *__restrict__ counters) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t > n_tracks) return;
     bool ok = true;
     if (t == 0) ok = start[0] == 0;
     if (t == n_tracks) ok = ok && start[n_tracks] == n;
-    if (t < n_tracks) ok = ok && start[t] <= start[t + 1];
-    if (!ok) atomicOr(bad, 1u);
+    if (t < n_tracks) {
+        ok = ok && start[t] <= start[t + 1];
+        if (start[t + 1] - start[t] > kTrackMax) atomicAdd(counters + 1, 1u);
+    }
+    if (!ok) atomicOr(counters, 1u);
+}
+
+// One track of at most kTrackMax points per workgroup, every level in LDS.
+// Point i of the track (local index) belongs to thread i % 256, which keeps its
+// chord (lo, hi), score and activity in registers; the slots of level L (chord
+// maximum and argmax, indexed by the chord's first point) are buffer L % 2, as
+// in the level-synchronous form.  Per level: [scores into the slots] barrier,
+// argmax, barrier, decide, barrier, stop if no chord split, else update and
+// score the next level.  Longer tracks are left to the level-synchronous path.
+__global__ __launch_bounds__(kTrackThreads) void dp_track_kernel(const double2 *__restrict__ xy,
+                                                                 const int64_t *__restrict__ start, double eps2,
+                                                                 uint8_t *__restrict__ keep) {
+    __shared__ double2 pxy[kTrackMax];
+    __shared__ unsigned long long smax[2][kTrackMax];
+    __shared__ unsigned sarg[2][kTrackMax];
+    __shared__ uint8_t sdec[kTrackMax];
+    __shared__ int sflag[2];
+    const int64_t s0 = start[blockIdx.x], len64 = start[blockIdx.x + 1] - s0;
+    if (len64 <= 0 || len64 > kTrackMax) return;  // uniform over the workgroup
+    const int len = (int)len64, tid = threadIdx.x;
+    for (int i = tid; i < len; i += kTrackThreads) {
+        pxy[i] = xy[s0 + i];
+        keep[s0 + i] = (i == 0 || i == len - 1) ? 1 : 0;
+    }
+    if (len <= 2) return;
+    int lo[kTrackPer], hi[kTrackPer];
+    double sc[kTrackPer];
+    bool act[kTrackPer];
+#pragma unroll
+    for (int q = 0; q < kTrackPer; ++q) {
+        const int i = tid + q * kTrackThreads;
+        act[q] = i > 0 && i < len - 1;
+        lo[q] = 0;
+        hi[q] = len - 1;
+    }
+    if (tid == 0) {
+        smax[0][0] = 0ull;
+        sarg[0][0] = UINT_MAX;
+        sflag[0] = sflag[1] = 0;
+    }
+    __syncthreads();
+    auto score_into = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < kTrackPer; ++q) {
+            if (!act[q]) continue;
+            bool zero;
+            sc[q] = dp_score(pxy, lo[q], hi[q], tid + q * kTrackThreads, zero);
+            atomicMax(&smax[buf][lo[q]], (unsigned long long)__double_as_longlong(sc[q]));
+        }
+    };
+    score_into(0);
+    for (int level = 0;; ++level) {
+        const int cur = level & 1, nxt = cur ^ 1;
+        __syncthreads();  // this level's chord maxima are complete
+        if (tid == 0) sflag[nxt] = 0;  // read by every thread before the barrier above
+#pragma unroll
+        for (int q = 0; q < kTrackPer; ++q)
+            if (act[q] && (unsigned long long)__double_as_longlong(sc[q]) == smax[cur][lo[q]])
+                atomicMin(&sarg[cur][lo[q]], (unsigned)(tid + q * kTrackThreads));
+        __syncthreads();  // argmax complete
+#pragma unroll
+        for (int q = 0; q < kTrackPer; ++q) {
+            const int i = tid + q * kTrackThreads;
+            if (!act[q] || sarg[cur][lo[q]] != (unsigned)i) continue;
+            bool zero;
+            (void)dp_score(pxy, lo[q], hi[q], i, zero);  // the zero-chord case, decided as the score was
+            const bool split = dp_split(pxy, lo[q], hi[q], sc[q], zero, eps2);
+            sdec[lo[q]] = split ? 1 : 2;
+            if (split) {
+                keep[s0 + i] = 1;
+                smax[nxt][lo[q]] = 0ull;
+                sarg[nxt][lo[q]] = UINT_MAX;
+                smax[nxt][i] = 0ull;
+                sarg[nxt][i] = UINT_MAX;
+                sflag[cur] = 1;
+            }
+        }
+        __syncthreads();  // decisions and the next level's slot resets complete
+        if (sflag[cur] == 0) break;  // no chord split: every chord is final
+#pragma unroll
+        for (int q = 0; q < kTrackPer; ++q) {
+            if (!act[q]) continue;
+            const int i = tid + q * kTrackThreads;
+            if (sdec[lo[q]] == 2) {
+                act[q] = false;  // within eps of its final chord: dropped
+                continue;
+            }
+            const int k = (int)sarg[cur][lo[q]];
+            if (k == i) act[q] = false;  // kept
+            else if (i < k) hi[q] = k;
+            else lo[q] = k;
+        }
+        score_into(nxt);
+    }
 }
 
 // Track of point i (binary search in the offsets), its end points kept; the
 // slots of the first chords (at the track starts) are reset for level 0.
+// Points of tracks of at most kTrackMax points (done by dp_track_kernel) are
+// left inactive and their keep entries untouched.
 __global__ __launch_bounds__(256) void dp_init_kernel(const int64_t *__restrict__ start, int64_t n_tracks, int64_t n,
                                                       int *__restrict__ lo, int *__restrict__ hi,
                                                       uint8_t *__restrict__ keep, uint8_t *__restrict__ active,
@@ -85,6 +195,10 @@ __global__ __launch_bounds__(256) void dp_init_kernel(const int64_t *__restrict_
         else b = m;
     }
     const int64_t s = start[a], e = start[a + 1] - 1;
+    if (e - s + 1 <= kTrackMax) {
+        active[i] = 0;
+        return;
+    }
     lo[i] = (int)s;
     hi[i] = (int)e;
     const bool end_point = i == s || i == e;
@@ -303,23 +417,30 @@ hipError_t run_dp(const DpArgs &a, void *ws, hipStream_t s, int64_t *n_kept) {
     const dim3 grid((unsigned)((a.n + 255) / 256)), block(256);
     const double eps2 = a.eps * a.eps;
     *n_kept = -1;
-    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), block, 0, s, splits, (int64_t)1);
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), block, 0, s, splits, (int64_t)2);
     hipLaunchKernelGGL(dp_check_kernel, dim3((unsigned)((a.n_tracks + 1 + 255) / 256)), block, 0, s, a.start,
                        a.n_tracks, a.n, splits);
-    unsigned bad = 0;
-    hipError_t e = hipMemcpyAsync(&bad, splits, sizeof bad, hipMemcpyDeviceToHost, s);
+    unsigned chk[2] = {0u, 0u};  // invalid offsets, tracks longer than kTrackMax
+    hipError_t e = hipMemcpyAsync(chk, splits, sizeof chk, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return e;
-    if (bad) return hipErrorInvalidValue;  // *n_kept stays -1: invalid offsets
-    hipLaunchKernelGGL(dp_init_kernel, grid, block, 0, s, a.start, a.n_tracks, a.n, lo, hi, a.keep, active, segmax,
-                       segarg);
+    if (chk[0]) return hipErrorInvalidValue;  // *n_kept stays -1: invalid offsets
+    if (a.n_tracks > 0)
+        hipLaunchKernelGGL(dp_track_kernel, dim3((unsigned)a.n_tracks), dim3(kTrackThreads), 0, s, a.xy, a.start,
+                           eps2, a.keep);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int64_t long_groups = chk[1] > 0 ? a.n / kLevelsPerCheck + 1 : -1;  // no long track: no level loop
+    if (chk[1] > 0) {
+        hipLaunchKernelGGL(dp_init_kernel, grid, block, 0, s, a.start, a.n_tracks, a.n, lo, hi, a.keep, active,
+                           segmax, segarg);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(dp_score_kernel, grid, block, 0, s, a.xy, a.n, static_cast<const int *>(lo),
+                           static_cast<const int *>(hi), static_cast<const uint8_t *>(active), score, segmax);
+    }
     // Every level either splits a chord or leaves all remaining ones final, so
     // no track needs more levels than it has points.
     int64_t level = 0;
-    hipLaunchKernelGGL(dp_score_kernel, grid, block, 0, s, a.xy, a.n, static_cast<const int *>(lo),
-                       static_cast<const int *>(hi), static_cast<const uint8_t *>(active), score, segmax);
-    for (int64_t group = 0; group <= a.n / kLevelsPerCheck + 1; ++group) {
+    for (int64_t group = 0; group <= long_groups; ++group) {
         hipLaunchKernelGGL(zero_u32_kernel, dim3(1), block, 0, s, splits, (int64_t)1);
         for (int l = 0; l < kLevelsPerCheck; ++l, ++level) {
             // level's scores are in segmax + cur; the update of its chords also

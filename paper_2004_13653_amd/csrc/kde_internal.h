@@ -166,6 +166,13 @@ void release_batched_graphs();
 int64_t vjp_blocks(int64_t n);
 hipError_t launch_vjp(const float2 *pts, int64_t n, int kernel_id, float Hx, float Hy, const float *gbar, int nx,
                       int ny, float fx, float fy, float *grad, double *part, hipStream_t stream);
+// Gaussian VJP on matrix cores (kde_vjp_mfma.hip): the same outputs as
+// launch_vjp (grad, and the per-workgroup sums at the start of ws in the
+// vjp_blocks(n) x 3 layout), from BF16 hi/lo contractions; ws holds
+// vjp_mfma_workspace_bytes.
+size_t vjp_mfma_workspace_bytes(int64_t n, int nx, int ny);
+hipError_t launch_vjp_mfma(const float2 *pts, int64_t n, float Hx, float Hy, const float *gbar, int nx, int ny,
+                           float fx, float fy, float *grad, void *ws, hipStream_t stream);
 // launch_lscv needs lscv_workspace_bytes of workspace and leaves the
 // lscv_blocks partial rows at its start.  Compact kernels visit only the tiles
 // of spatially sorted points whose pairs can be in support (nx, ny fix the

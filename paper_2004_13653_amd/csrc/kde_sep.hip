@@ -31,6 +31,7 @@
 // Dense Gaussian maps with multiplicative runs (the common case) run an 8-wave
 // variant, sep_mfma8_kernel, with two waves per SIMD; see there.
 #include "kde_internal.h"
+#include "kde_mfma.h"
 
 #include <algorithm>
 #include <cmath>
@@ -42,11 +43,6 @@ namespace {
 constexpr int kTile = 256;     // output tile side (rows and columns)
 constexpr int kThreadsSep = 256;
 constexpr float kFar = 1.0e30f;
-
-typedef _Float16 half8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef float float8v __attribute__((ext_vector_type(8)));
 
 template <int P>
 struct PrecTraits;
@@ -127,47 +123,6 @@ __device__ __forceinline__ float sep_factor(float m, float pr, float H, float in
         }
         return fabsf(d) <= H ? v : 0.0f;
     }
-}
-
-template <bool kBf16>
-__device__ __forceinline__ uint4 pack8(const float (&v)[8]) {
-    uint4 r;
-    if constexpr (kBf16) {
-        bf16x8 h;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) h[k] = (__bf16)v[k];
-        r = __builtin_bit_cast(uint4, h);
-    } else {
-        half8 h;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) h[k] = (_Float16)v[k];
-        r = __builtin_bit_cast(uint4, h);
-    }
-    return r;
-}
-
-// Residual v - (float)round16(v), for the lo half of a split.
-template <bool kBf16>
-__device__ __forceinline__ void residual8(const float (&v)[8], uint4 hi, float (&lo)[8]) {
-    if constexpr (kBf16) {
-        const bf16x8 h = __builtin_bit_cast(bf16x8, hi);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) lo[k] = v[k] - (float)h[k];
-    } else {
-        const half8 h = __builtin_bit_cast(half8, hi);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) lo[k] = v[k] - (float)h[k];
-    }
-}
-
-template <bool kBf16>
-__device__ __forceinline__ f32x16 mfma(uint4 a, uint4 b, f32x16 c) {
-    if constexpr (kBf16)
-        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
-                                                       c, 0, 0, 0);
-    else
-        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(half8, a), __builtin_bit_cast(half8, b), c,
-                                                      0, 0, 0);
 }
 
 template <int P>

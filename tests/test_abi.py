@@ -81,6 +81,8 @@ def test_other_entry_points_validate():
     L = kde.lib()
     assert L.kde_backward(FAKE, 10, 6, 0.05, 0.05, g.handle, None, FAKE, None, 0, None) == kde.KDE_EINVAL
     assert L.kde_backward(FAKE, 10, 9, 0.05, 0.05, g.handle, FAKE, FAKE, None, 0, None) == kde.KDE_EINVAL
+    assert L.kde_backward(FAKE, 10, 6, 0.05, 0.05, g.handle, FAKE, FAKE, None, 32, None) == kde.KDE_EINVAL
+    assert "unknown flags" in L.kde_last_error().decode()
     v = ctypes.c_double()
     assert L.kde_lscv(FAKE, 1, 6, 0.05, 0.05, g.handle, ctypes.byref(v), None, None) == kde.KDE_EINVAL
     assert L.kde_lscv(FAKE, 10, 6, 0.05, 0.05, g.handle, None, None, None) == kde.KDE_EINVAL

@@ -46,11 +46,11 @@ def _expected_vjp(XY, kernel, hx, hy, og, gbar, raw):
     return gp, np.array([dhx, dhy])
 
 
-def _gpu_vjp(XY, kernel, hx, hy, g, gbar, raw=False, grid_units=False):
+def _gpu_vjp(XY, kernel, hx, hy, g, gbar, raw=False, grid_units=False, fp32=False):
     import torch
     pts = kt.to_device(XY)
     go = torch.from_numpy(np.ascontiguousarray(gbar, dtype=np.float32)).to(kt.device())
-    gp, gh = kde.backward(pts, kernel, hx, hy, g, go, raw=raw, grid_units=grid_units)
+    gp, gh = kde.backward(pts, kernel, hx, hy, g, go, raw=raw, grid_units=grid_units, fp32=fp32)
     torch.cuda.synchronize()
     return gp.cpu().numpy().astype(np.float64), np.array(gh)
 
@@ -76,6 +76,33 @@ def test_vjp_all_kernels(kernel, raw, shape):
     kt.log(f"kernel={kernel} raw={raw} {nx}x{ny}: points rel-L2 {e_p:.2e}, h rel {e_h}")
     assert e_p <= GRAD_GATE
     assert np.all(e_h <= GRAD_GATE)
+
+
+@pytest.mark.parametrize("shape,n", [((96, 80), 1), ((96, 80), 255), ((300, 257), 257), ((513, 33), 2000),
+                                     ((40, 700), 700)])
+@pytest.mark.parametrize("raw", [False, True])
+def test_gaussian_vjp_matrix_cores(shape, n, raw):
+    """The Gaussian VJP on matrix cores (the default) and per pair in FP32
+    (KDE_VJP_FP32), both against the oracle, on ragged shapes: point counts
+    around the 256-point blocks, grids with 1-3 tiles of 256 nodes along either
+    axis and contraction lengths that are not multiples of the 32-node chunks,
+    some points outside the grid.  Matrix-core results are bitwise reproducible."""
+    nx, ny = shape
+    rng = np.random.default_rng(n + nx)
+    XY = np.column_stack([rng.uniform(-3, nx + 3, n), rng.uniform(-3, ny + 3, n)]).astype(np.float32)
+    g, og = kt.grids(synth.BOX_C2, nx, ny)
+    gbar = rng.standard_normal((ny, nx))
+    hx, hy = 3.1 * og.dx, 1.7 * og.dy
+    rp, rh = _expected_vjp(XY.astype(np.float64), 6, hx, hy, og, gbar, raw)
+    gp, gh = _gpu_vjp(XY, 6, hx, hy, g, gbar, raw=raw)
+    gp2, gh2 = _gpu_vjp(XY, 6, hx, hy, g, gbar, raw=raw)
+    fp, fh = _gpu_vjp(XY, 6, hx, hy, g, gbar, raw=raw, fp32=True)
+    e_m, e_f = _rel_l2(gp, rp), _rel_l2(fp, rp)
+    kt.log(f"{nx}x{ny} n={n} raw={raw}: matrix cores rel-L2 {e_m:.2e}, h {_rel(gh, rh)}; "
+           f"FP32 rel-L2 {e_f:.2e}, h {_rel(fh, rh)}")
+    assert np.array_equal(gp, gp2) and np.array_equal(gh, gh2)
+    assert e_m <= GRAD_GATE and e_f <= GRAD_GATE
+    assert np.all(_rel(gh, rh) <= GRAD_GATE) and np.all(_rel(fh, rh) <= GRAD_GATE)
 
 
 def _sample_points(XY, ny, nx, seed):
@@ -315,3 +342,28 @@ def test_full_size_adjoint_runs_and_is_deterministic():
             c, _ = kde.backward(pts, kernel, h, h, g, rnd, raw=True, grid_units=True, want_h=False)
             torch.cuda.synchronize()
             assert np.abs(a.cpu().numpy()[inside]).max() < 1e-4 * np.abs(c.cpu().numpy()).max()
+
+
+def test_backward_serves_and_consumes_the_timing_request():
+    """kde_backward records an armed main-kernel timing request (the VJP kernel,
+    on both paths) and consumes it: events released afterwards are never
+    touched by later calls."""
+    import gc
+
+    import torch
+    rng = np.random.default_rng(5)
+    XY = rng.uniform(0, 64, (3000, 2)).astype(np.float32)
+    g, og = kt.grids(synth.BOX_C2, 64, 64)
+    pts = kt.to_device(XY)
+    go = torch.from_numpy(rng.standard_normal((64, 64)).astype(np.float32)).to(kt.device())
+    for fp32 in (False, True):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        kde.time_next_main_kernel(a, b)
+        kde.backward(pts, "gaussian", 2 * og.dx, 2 * og.dy, g, go, fp32=fp32)
+        torch.cuda.synchronize()
+        assert a.elapsed_time(b) > 0.0
+        del a, b
+        gc.collect()
+        gp, gh = kde.backward(pts, "gaussian", 2 * og.dx, 2 * og.dy, g, go, fp32=fp32)
+        torch.cuda.synchronize()
+        assert np.all(np.isfinite(gp.cpu().numpy()))

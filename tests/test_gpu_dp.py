@@ -64,6 +64,24 @@ def test_track_shapes_and_degenerate_chords():
         _check(xy, lens, eps)
 
 
+def test_long_and_short_tracks():
+    """Tracks of up to 1024 points run whole in one workgroup each; longer ones
+    (1025, 3000 and 5000 points here) take the level-synchronous kernels.  A mix
+    of both, including one exactly 1024 long, in one call."""
+    rng = np.random.default_rng(11)
+    lens = [5000, 12, 1024, 1025, 0, 300, 3000, 2, 1023]
+    parts = []
+    for L in lens:
+        p = np.cumsum(rng.normal(0, 20.0, (L, 2)), axis=0)
+        if L >= 300:
+            p[L // 2] = p[L // 2 - 1]  # a repeated point
+        parts.append(p)
+    xy = np.concatenate([p for p in parts if len(p)])
+    for eps in (0.0, 10.0, 50.0):
+        keep = _check(xy, lens, eps)
+        kt.log(f"eps={eps}: kept {int(keep.sum())} of {keep.size}")
+
+
 @pytest.mark.parametrize("eps", [0.0, 10.0, 50.0, 100.0])
 def test_lane_tracks_match_oracle(eps):
     """2,000 lane tracks x 500 reports in Mercator metres."""
