@@ -68,7 +68,8 @@ constexpr int kTrackMax = 1024;                       // longest track one workg
 constexpr int kTrackPer = kTrackMax / kTrackThreads;  // points per thread
 
 // counters[0] = 1 unless start[0] = 0, start[n_tracks] = n and the offsets
-// never decrease; counters[1] = number of tracks longer than kTrackMax.
+// never decrease; counters[1] = number of tracks longer than kTrackMax;
+// counters[2] = the longest of the other tracks.
 __global__ __launch_bounds__(256) void dp_check_kernel(const int64_t *__restrict__ start, int64_t n_tracks, int64_t n,
                                                        unsigned *__restrict__ counters) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -78,7 +79,9 @@ __global__ __launch_bounds__(256) void dp_check_kernel(const int64_t *__restrict
     if (t == n_tracks) ok = ok && start[n_tracks] == n;
     if (t < n_tracks) {
         ok = ok && start[t] <= start[t + 1];
-        if (start[t + 1] - start[t] > kTrackMax) atomicAdd(counters + 1, 1u);
+        const int64_t len = start[t + 1] - start[t];
+        if (len > kTrackMax) atomicAdd(counters + 1, 1u);
+        else if (len > 0) atomicMax(counters + 2, (unsigned)len);
     }
     if (!ok) atomicOr(counters, 1u);
 }
@@ -90,16 +93,24 @@ __global__ __launch_bounds__(256) void dp_check_kernel(const int64_t *__restrict
 // in the level-synchronous form.  Per level: [scores into the slots] barrier,
 // argmax, barrier, decide, barrier, stop if no chord split, else update and
 // score the next level.  Longer tracks are left to the level-synchronous path.
+// The LDS arrays are sized at launch for `cap` points (the call's longest short
+// track, dp_track_lds_bytes), so that short tracks leave room for more
+// workgroups per CU.
+constexpr size_t dp_track_lds_bytes(int cap) { return (size_t)41 * cap + 16; }
+
 __global__ __launch_bounds__(kTrackThreads) void dp_track_kernel(const double2 *__restrict__ xy,
                                                                  const int64_t *__restrict__ start, double eps2,
-                                                                 uint8_t *__restrict__ keep) {
-    __shared__ double2 pxy[kTrackMax];
-    __shared__ unsigned long long smax[2][kTrackMax];
-    __shared__ unsigned sarg[2][kTrackMax];
-    __shared__ uint8_t sdec[kTrackMax];
-    __shared__ int sflag[2];
+                                                                 int cap, uint8_t *__restrict__ keep) {
+    extern __shared__ __align__(16) unsigned char dp_lds[];
+    unsigned long long *smax0 = reinterpret_cast<unsigned long long *>(dp_lds);  // [2][cap]
+    double2 *pxy = reinterpret_cast<double2 *>(dp_lds + 16 * (size_t)cap);      // [cap]
+    unsigned *sarg0 = reinterpret_cast<unsigned *>(dp_lds + 32 * (size_t)cap);   // [2][cap]
+    uint8_t *sdec = dp_lds + 40 * (size_t)cap;                                    // [cap]
+    int *sflag = reinterpret_cast<int *>(dp_lds + ((41 * (size_t)cap + 3) & ~(size_t)3));  // [2]
+    auto SMAX = [&](int b, int i) -> unsigned long long & { return smax0[b * cap + i]; };
+    auto SARG = [&](int b, int i) -> unsigned & { return sarg0[b * cap + i]; };
     const int64_t s0 = start[blockIdx.x], len64 = start[blockIdx.x + 1] - s0;
-    if (len64 <= 0 || len64 > kTrackMax) return;  // uniform over the workgroup
+    if (len64 <= 0 || len64 > cap) return;  // uniform over the workgroup; longer tracks: level loop
     const int len = (int)len64, tid = threadIdx.x;
     for (int i = tid; i < len; i += kTrackThreads) {
         pxy[i] = xy[s0 + i];
@@ -117,8 +128,8 @@ __global__ __launch_bounds__(kTrackThreads) void dp_track_kernel(const double2 *
         hi[q] = len - 1;
     }
     if (tid == 0) {
-        smax[0][0] = 0ull;
-        sarg[0][0] = UINT_MAX;
+        SMAX(0, 0) = 0ull;
+        SARG(0, 0) = UINT_MAX;
         sflag[0] = sflag[1] = 0;
     }
     __syncthreads();
@@ -128,7 +139,7 @@ __global__ __launch_bounds__(kTrackThreads) void dp_track_kernel(const double2 *
             if (!act[q]) continue;
             bool zero;
             sc[q] = dp_score(pxy, lo[q], hi[q], tid + q * kTrackThreads, zero);
-            atomicMax(&smax[buf][lo[q]], (unsigned long long)__double_as_longlong(sc[q]));
+            atomicMax(&SMAX(buf, lo[q]), (unsigned long long)__double_as_longlong(sc[q]));
         }
     };
     score_into(0);
@@ -138,23 +149,23 @@ __global__ __launch_bounds__(kTrackThreads) void dp_track_kernel(const double2 *
         if (tid == 0) sflag[nxt] = 0;  // read by every thread before the barrier above
 #pragma unroll
         for (int q = 0; q < kTrackPer; ++q)
-            if (act[q] && (unsigned long long)__double_as_longlong(sc[q]) == smax[cur][lo[q]])
-                atomicMin(&sarg[cur][lo[q]], (unsigned)(tid + q * kTrackThreads));
+            if (act[q] && (unsigned long long)__double_as_longlong(sc[q]) == SMAX(cur, lo[q]))
+                atomicMin(&SARG(cur, lo[q]), (unsigned)(tid + q * kTrackThreads));
         __syncthreads();  // argmax complete
 #pragma unroll
         for (int q = 0; q < kTrackPer; ++q) {
             const int i = tid + q * kTrackThreads;
-            if (!act[q] || sarg[cur][lo[q]] != (unsigned)i) continue;
+            if (!act[q] || SARG(cur, lo[q]) != (unsigned)i) continue;
             bool zero;
             (void)dp_score(pxy, lo[q], hi[q], i, zero);  // the zero-chord case, decided as the score was
             const bool split = dp_split(pxy, lo[q], hi[q], sc[q], zero, eps2);
             sdec[lo[q]] = split ? 1 : 2;
             if (split) {
                 keep[s0 + i] = 1;
-                smax[nxt][lo[q]] = 0ull;
-                sarg[nxt][lo[q]] = UINT_MAX;
-                smax[nxt][i] = 0ull;
-                sarg[nxt][i] = UINT_MAX;
+                SMAX(nxt, lo[q]) = 0ull;
+                SARG(nxt, lo[q]) = UINT_MAX;
+                SMAX(nxt, i) = 0ull;
+                SARG(nxt, i) = UINT_MAX;
                 sflag[cur] = 1;
             }
         }
@@ -168,7 +179,7 @@ __global__ __launch_bounds__(kTrackThreads) void dp_track_kernel(const double2 *
                 act[q] = false;  // within eps of its final chord: dropped
                 continue;
             }
-            const int k = (int)sarg[cur][lo[q]];
+            const int k = (int)SARG(cur, lo[q]);
             if (k == i) act[q] = false;  // kept
             else if (i < k) hi[q] = k;
             else lo[q] = k;
@@ -417,17 +428,19 @@ hipError_t run_dp(const DpArgs &a, void *ws, hipStream_t s, int64_t *n_kept) {
     const dim3 grid((unsigned)((a.n + 255) / 256)), block(256);
     const double eps2 = a.eps * a.eps;
     *n_kept = -1;
-    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), block, 0, s, splits, (int64_t)2);
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), block, 0, s, splits, (int64_t)3);
     hipLaunchKernelGGL(dp_check_kernel, dim3((unsigned)((a.n_tracks + 1 + 255) / 256)), block, 0, s, a.start,
                        a.n_tracks, a.n, splits);
-    unsigned chk[2] = {0u, 0u};  // invalid offsets, tracks longer than kTrackMax
+    unsigned chk[3] = {0u, 0u, 0u};  // invalid offsets, tracks longer than kTrackMax, longest other track
     hipError_t e = hipMemcpyAsync(chk, splits, sizeof chk, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return e;
     if (chk[0]) return hipErrorInvalidValue;  // *n_kept stays -1: invalid offsets
-    if (a.n_tracks > 0)
-        hipLaunchKernelGGL(dp_track_kernel, dim3((unsigned)a.n_tracks), dim3(kTrackThreads), 0, s, a.xy, a.start,
-                           eps2, a.keep);
+    if (a.n_tracks > 0 && chk[2] > 0) {
+        const int cap = (int)((chk[2] + 63) / 64 * 64);
+        hipLaunchKernelGGL(dp_track_kernel, dim3((unsigned)a.n_tracks), dim3(kTrackThreads),
+                           (unsigned)dp_track_lds_bytes(cap), s, a.xy, a.start, eps2, cap, a.keep);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int64_t long_groups = chk[1] > 0 ? a.n / kLevelsPerCheck + 1 : -1;  // no long track: no level loop
     if (chk[1] > 0) {
