@@ -12,6 +12,13 @@
 // partials in split order and writes the scaled tile: results do not depend on
 // which workgroup finishes last.
 //
+// Compact maps are whole-tile items over all of the map's points; a first
+// kernel of the launch takes the bounding box of every 256-point chunk of those
+// points, and a tile item loads only the chunks whose box reaches the tile
+// (tile::tile_sums_boxed, the same sums bit for bit).  Tracks are stored in
+// order, so a chunk is a short stretch of one or two tracks and most chunks miss
+// most tiles.
+//
 // Host side: the descriptors and the item list live in one pinned staging
 // buffer that a single copy moves to the device, followed by a counter reset
 // kernel and the persistent kernel.  That sequence is captured once per batch
@@ -42,6 +49,7 @@ struct BMap {
     const float2 *pts;
     float *out;
     int64_t n;
+    int64_t box0;     // first of this map's chunk boxes (compact maps; running count)
     int kernel, rc;   // kernel id, register-block side (tile side 16 rc)
     int nx, ny, tiles_x;
     float Hx, Hy, ax, ay, scale;
@@ -58,14 +66,51 @@ struct BItem {
 struct BatchLaunch {
     const BMap *maps;
     const BItem *items;
-    int n_items;
+    int n_items, n_maps;
     int *counter;   // [1 + n_split_tiles]: next item, then per-tile finish counts
     float *partials;
+    float4 *boxes;  // [n_boxes]: (x min, x max, y min, y max) per 256-point chunk of the compact maps
+    int64_t n_boxes;
 };
+
+// One wave per chunk box: its map is the last whose box0 is at most the box
+// index (maps without chunks repeat the next map's box0).
+__global__ __launch_bounds__(256) void batch_box_kernel(BatchLaunch b) {
+    const int64_t gc = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (gc >= b.n_boxes) return;  // uniform per wave
+    int lo = 0, hi = b.n_maps - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (b.maps[mid].box0 <= gc) lo = mid;
+        else hi = mid - 1;
+    }
+    const BMap m = b.maps[lo];
+    const int64_t base = (gc - m.box0) * kPointTile;
+    const int lane = threadIdx.x & 63;
+    float x0 = 3.0e38f, x1 = -3.0e38f, y0 = 3.0e38f, y1 = -3.0e38f;
+#pragma unroll
+    for (int k = 0; k < kPointTile / 64; ++k) {
+        const int64_t q = base + lane + 64 * k;
+        if (q < m.n) {
+            const float2 v = m.pts[q];
+            x0 = fminf(x0, v.x);
+            x1 = fmaxf(x1, v.x);
+            y0 = fminf(y0, v.y);
+            y1 = fmaxf(y1, v.y);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        x0 = fminf(x0, __shfl_xor(x0, off));
+        x1 = fmaxf(x1, __shfl_xor(x1, off));
+        y0 = fminf(y0, __shfl_xor(y0, off));
+        y1 = fmaxf(y1, __shfl_xor(y1, off));
+    }
+    if (lane == 0) b.boxes[gc] = make_float4(x0, x1, y0, y1);
+}
 
 template <int K, int RC, bool kRuns>
 __device__ __forceinline__ void run_item(const BMap &m, const BItem &w, const BatchLaunch &b, float2 *sp,
-                                         int *swave, int *s_last) {
+                                         int *swave, int *slist, int *s_last) {
     using S = tile::Shape<K, RC>;
     const int tid = threadIdx.x;
     const int tx = w.tile % m.tiles_x, ty = w.tile / m.tiles_x;
@@ -73,9 +118,14 @@ __device__ __forceinline__ void run_item(const BMap &m, const BItem &w, const Ba
     const int lib = (tid & 15) * S::C, ljb = (tid >> 4) * S::R;  // tile-local block origin
     const int ib = x0 + lib, jb = y0 + ljb;
     float tot[S::R][S::C];
-    tile::tile_sums<K, S::R, S::C, S::kCull, kRuns>(m.pts, w.p0, w.p1, m.Hx, m.Hy, m.ax, m.ay, ib, jb, (float)x0,
-                                                    (float)(min(x0 + S::TW, m.nx) - 1), (float)y0,
-                                                    (float)(min(y0 + S::TH, m.ny) - 1), sp, swave, tot);
+    const float bx0 = (float)x0, bx1 = (float)(min(x0 + S::TW, m.nx) - 1);
+    const float by0 = (float)y0, by1 = (float)(min(y0 + S::TH, m.ny) - 1);
+    if constexpr (S::kCull)  // whole-tile item over all the map's points
+        tile::tile_sums_boxed<K, S::R, S::C>(m.pts, m.n, b.boxes + m.box0, m.Hx, m.Hy, m.ax, m.ay, ib, jb, bx0, bx1,
+                                             by0, by1, sp, swave, slist, tot);
+    else
+        tile::tile_sums<K, S::R, S::C, false, kRuns>(m.pts, w.p0, w.p1, m.Hx, m.Hy, m.ax, m.ay, ib, jb, bx0, bx1,
+                                                     by0, by1, sp, swave, tot);
     if constexpr (kRuns) tile::apply_run_q<S::R, S::C>(tot, m.ax, m.ay);
     if (w.nsplit == 1) {
         tile::store_block<S::R, S::C>(tot, m.out, m.nx, m.ny, ib, jb, m.scale);
@@ -108,29 +158,30 @@ __device__ __forceinline__ void run_item(const BMap &m, const BItem &w, const Ba
 
 template <int K>
 __device__ __forceinline__ void run_shape(const BMap &m, const BItem &w, const BatchLaunch &b, float2 *sp,
-                                          int *swave, int *s_last) {
+                                          int *swave, int *slist, int *s_last) {
     if constexpr (K == kGaussian) {
         if (m.ax <= kMaxRunScale && m.ay <= kMaxRunScale) {
             if (m.rc == 2)
-                run_item<K, 2, true>(m, w, b, sp, swave, s_last);
+                run_item<K, 2, true>(m, w, b, sp, swave, slist, s_last);
             else if (m.rc == 4)
-                run_item<K, 4, true>(m, w, b, sp, swave, s_last);
+                run_item<K, 4, true>(m, w, b, sp, swave, slist, s_last);
             else
-                run_item<K, 8, true>(m, w, b, sp, swave, s_last);
+                run_item<K, 8, true>(m, w, b, sp, swave, slist, s_last);
             return;
         }
     }
     if (m.rc == 2)
-        run_item<K, 2, false>(m, w, b, sp, swave, s_last);
+        run_item<K, 2, false>(m, w, b, sp, swave, slist, s_last);
     else if (m.rc == 4)
-        run_item<K, 4, false>(m, w, b, sp, swave, s_last);
+        run_item<K, 4, false>(m, w, b, sp, swave, slist, s_last);
     else
-        run_item<K, 8, false>(m, w, b, sp, swave, s_last);
+        run_item<K, 8, false>(m, w, b, sp, swave, slist, s_last);
 }
 
 __global__ __launch_bounds__(kThreads) void batched_kernel(BatchLaunch b) {
     __shared__ float2 sp[kPointTile];
     __shared__ int swave[kThreads / 64];
+    __shared__ int slist[kThreads];
     __shared__ int s_item, s_last;
     for (;;) {
         __syncthreads();  // every thread has read the previous s_item
@@ -141,14 +192,14 @@ __global__ __launch_bounds__(kThreads) void batched_kernel(BatchLaunch b) {
         const BItem w = b.items[it];
         const BMap m = b.maps[w.map];
         switch (m.kernel) {
-        case kUniform: run_shape<kUniform>(m, w, b, sp, swave, &s_last); break;
-        case kTriangular: run_shape<kTriangular>(m, w, b, sp, swave, &s_last); break;
-        case kEpanechnikov: run_shape<kEpanechnikov>(m, w, b, sp, swave, &s_last); break;
-        case kQuartic: run_shape<kQuartic>(m, w, b, sp, swave, &s_last); break;
-        case kTriweight: run_shape<kTriweight>(m, w, b, sp, swave, &s_last); break;
-        case kTricube: run_shape<kTricube>(m, w, b, sp, swave, &s_last); break;
-        case kGaussian: run_shape<kGaussian>(m, w, b, sp, swave, &s_last); break;
-        default: run_shape<kCosine>(m, w, b, sp, swave, &s_last); break;
+        case kUniform: run_shape<kUniform>(m, w, b, sp, swave, slist, &s_last); break;
+        case kTriangular: run_shape<kTriangular>(m, w, b, sp, swave, slist, &s_last); break;
+        case kEpanechnikov: run_shape<kEpanechnikov>(m, w, b, sp, swave, slist, &s_last); break;
+        case kQuartic: run_shape<kQuartic>(m, w, b, sp, swave, slist, &s_last); break;
+        case kTriweight: run_shape<kTriweight>(m, w, b, sp, swave, slist, &s_last); break;
+        case kTricube: run_shape<kTricube>(m, w, b, sp, swave, slist, &s_last); break;
+        case kGaussian: run_shape<kGaussian>(m, w, b, sp, swave, slist, &s_last); break;
+        default: run_shape<kCosine>(m, w, b, sp, swave, slist, &s_last); break;
         }
     }
 }
@@ -165,6 +216,7 @@ struct Plan {
     std::vector<BItem> items;
     int n_split_tiles = 0;
     int64_t n_slots = 0;  // floats of partial tiles
+    int64_t n_boxes = 0;  // chunk boxes of the compact maps
     std::string signature;  // item list and static map fields
 };
 
@@ -196,6 +248,8 @@ Plan make_plan(const MapArgs *args, int n_maps) {
         bm.scale = a.scale;
         const int tiles = bm.tiles_x * ((a.ny + TH - 1) / TH);
         const bool dense = a.kernel_id == kGaussian;
+        bm.box0 = pl.n_boxes;
+        if (!dense) pl.n_boxes += (a.n + kPointTile - 1) / kPointTile;
         int64_t per = a.n;
         if (dense) {
             per = std::max<int64_t>(kPointTile, kPairsPerItem / ((int64_t)TW * TH));
@@ -218,10 +272,12 @@ Plan make_plan(const MapArgs *args, int n_maps) {
                     pl.n_slots += (int64_t)TW * TH;
                 }
                 it.tile_global = tg;
-                // Dense tiles cost pairs; culled tiles cost the scan plus a small
-                // share of in-support work.
+                // Dense tiles cost pairs; compact tiles the box scan (about one
+                // 256-pixel pass per chunk box) plus their mean share of the
+                // points, each against the whole tile.
                 const double npts = (double)(it.p1 - it.p0);
-                const double cost = dense ? npts * TW * TH : npts * 64.0;
+                const double cost = dense ? npts * TW * TH
+                                          : npts / kPointTile * 256.0 + npts / tiles * TW * TH;
                 cs.push_back({cost, (int)cs.size(), it});
             }
         }
@@ -243,7 +299,7 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 struct Layout {
     size_t maps_off, items_off, stage_bytes;  // staged (copied) part
-    size_t counters_off, partials_off, total;
+    size_t counters_off, partials_off, boxes_off, total;
     int n_counters;
 };
 
@@ -255,7 +311,8 @@ Layout layout_of(const Plan &pl) {
     L.counters_off = L.stage_bytes;
     L.n_counters = 1 + pl.n_split_tiles;
     L.partials_off = align256(L.counters_off + (size_t)L.n_counters * sizeof(int));
-    L.total = align256(L.partials_off + (size_t)pl.n_slots * sizeof(float));
+    L.boxes_off = align256(L.partials_off + (size_t)pl.n_slots * sizeof(float));
+    L.total = align256(L.boxes_off + (size_t)pl.n_boxes * sizeof(float4));
     return L;
 }
 
@@ -282,8 +339,15 @@ hipError_t enqueue(const Plan &pl, const Layout &L, const void *host_stage, char
     b.maps = reinterpret_cast<const BMap *>(dev + L.maps_off);
     b.items = reinterpret_cast<const BItem *>(dev + L.items_off);
     b.n_items = (int)pl.items.size();
+    b.n_maps = (int)pl.maps.size();
     b.counter = reinterpret_cast<int *>(dev + L.counters_off);
     b.partials = reinterpret_cast<float *>(dev + L.partials_off);
+    b.boxes = reinterpret_cast<float4 *>(dev + L.boxes_off);
+    b.n_boxes = pl.n_boxes;
+    if (pl.n_boxes > 0) {
+        hipLaunchKernelGGL(batch_box_kernel, dim3((unsigned)((pl.n_boxes + 3) / 4)), dim3(256), 0, s, b);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(batched_kernel, dim3(persistent_grid(b.n_items)), dim3(kThreads), 0, s, b);
     return hipGetLastError();
 }

@@ -106,18 +106,90 @@ __device__ __forceinline__ void store_block(float (&v)[R][C], float *dst, int nx
     }
 }
 
-// Raw sums of one pixel tile over points [beg, end): workgroup of 256 threads
-// (16 x 16), each an R x C register block of R consecutive rows and C consecutive
-// columns starting at (jb, ib); tile reach x0..x1, y0..y1 (nodes) for culling.
-// Each LDS tile of points is summed into a fresh block before joining the total.
+// Adds the points [base, end) (at most kPointTile, one LDS tile) to tot, for
+// the R x C register block at (jb, ib) of a 256-thread workgroup (16 x 16
+// threads); tile reach x0..x1, y0..y1 (nodes) for culling.  The tile's points
+// are summed into a fresh block before joining the total.  Every thread calls
+// it (it contains workgroup barriers).
 // sp: LDS [kPointTile] float2; swave: LDS [kThreads / 64] int.
 // kRuns (Gaussian, truncated Gaussian): factors as Gaussian runs (the truncated
 // one then masked to its support); the caller applies apply_run_q.
 template <int K, int R, int C, bool kCull, bool kRuns = false>
+__device__ __forceinline__ void chunk_sums(const float2 *__restrict__ pts, int64_t base, int64_t end, float Hx,
+                                           float Hy, float ax, float ay, float fib, float fjb, float bx0, float bx1,
+                                           float by0, float by1, float2 *sp, int *swave, float (&tot)[R][C]) {
+    const int tid = threadIdx.x;
+    const int64_t q = base + tid;
+    float2 v = make_float2(0.0f, 0.0f);
+    if (q < end) v = pts[q];
+    int cnt;
+    __syncthreads();  // previous tile fully consumed
+    if constexpr (kCull) {
+        const bool keep = q < end && v.x + Hx >= bx0 && v.x - Hx <= bx1 && v.y + Hy >= by0 && v.y - Hy <= by1;
+        const uint64_t m = __ballot(keep);
+        const int lane = tid & 63, w = tid >> 6;
+        const int before = __popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0) swave[w] = __popcll(m);
+        __syncthreads();
+        int off = 0;
+        cnt = 0;
+#pragma unroll
+        for (int k = 0; k < kThreads / 64; ++k) {
+            off += (k < w) ? swave[k] : 0;
+            cnt += swave[k];
+        }
+        if (keep) sp[off + before] = v;  // survivors keep their index order
+    } else {
+        sp[tid] = v;
+        cnt = (int)min((int64_t)kPointTile, end - base);
+    }
+    __syncthreads();
+    if (cnt == 0) return;
+
+    float acc[R][C];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[r][c] = 0.0f;
+
+    for (int k = 0; k < cnt; ++k) {
+        const float2 pt = sp[k];
+        float kx[C], ky[R];
+        if constexpr (kRuns) {
+            // run centres: half-integer nodes, so (centre - X) is exact like dx0 below
+            gauss_run<C>((fib + 0.5f * (float)(C - 1) - pt.x) * ax, ax, kx);
+            gauss_run<R>((fjb + 0.5f * (float)(R - 1) - pt.y) * ay, ay, ky);
+            if constexpr (K == kGaussTrunc) {  // the support test of factor<kGaussTrunc> (q_r > 0 keeps zeros)
+                const float dx0 = fib - pt.x, dy0 = fjb - pt.y;
+#pragma unroll
+                for (int c = 0; c < C; ++c) kx[c] = fabsf(dx0 + (float)c) <= Hx ? kx[c] : 0.0f;
+#pragma unroll
+                for (int r = 0; r < R; ++r) ky[r] = fabsf(dy0 + (float)r) <= Hy ? ky[r] : 0.0f;
+            }
+        } else {
+            const float dx0 = fib - pt.x, dy0 = fjb - pt.y;
+#pragma unroll
+            for (int c = 0; c < C; ++c) kx[c] = factor<K>(dx0 + (float)c, ax, Hx);
+#pragma unroll
+            for (int r = 0; r < R; ++r) ky[r] = factor<K>(dy0 + (float)r, ay, Hy);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[r][c] = fmaf(ky[r], kx[c], acc[r][c]);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < C; ++c) tot[r][c] += acc[r][c];
+}
+
+// Raw sums of one pixel tile over points [beg, end), kPointTile at a time (see
+// chunk_sums).
+template <int K, int R, int C, bool kCull, bool kRuns = false>
 __device__ __forceinline__ void tile_sums(const float2 *__restrict__ pts, int64_t beg, int64_t end, float Hx,
                                           float Hy, float ax, float ay, int ib, int jb, float bx0, float bx1,
                                           float by0, float by1, float2 *sp, int *swave, float (&tot)[R][C]) {
-    const int tid = threadIdx.x;
     // Node coordinates of the block's first column and row; the others are these
     // plus small integers, and (node - X) stays exact in FP32 for |X| < 2^24.
     const float fib = (float)ib, fjb = (float)jb;
@@ -125,71 +197,55 @@ __device__ __forceinline__ void tile_sums(const float2 *__restrict__ pts, int64_
     for (int r = 0; r < R; ++r)
 #pragma unroll
         for (int c = 0; c < C; ++c) tot[r][c] = 0.0f;
+    for (int64_t base = beg; base < end; base += kPointTile)
+        chunk_sums<K, R, C, kCull, kRuns>(pts, base, end, Hx, Hy, ax, ay, fib, fjb, bx0, bx1, by0, by1, sp, swave,
+                                          tot);
+}
 
-    for (int64_t base = beg; base < end; base += kPointTile) {
-        const int64_t q = base + tid;
-        float2 v = make_float2(0.0f, 0.0f);
-        if (q < end) v = pts[q];
-        int cnt;
-        __syncthreads();  // previous tile fully consumed
-        if constexpr (kCull) {
-            const bool keep = q < end && v.x + Hx >= bx0 && v.x - Hx <= bx1 && v.y + Hy >= by0 && v.y - Hy <= by1;
-            const uint64_t m = __ballot(keep);
-            const int lane = tid & 63, w = tid >> 6;
-            const int before = __popcll(m & ((1ull << lane) - 1ull));
-            if (lane == 0) swave[w] = __popcll(m);
-            __syncthreads();
-            int off = 0;
-            cnt = 0;
+// Compact kernels over points [0, n) whose kPointTile-point chunks have
+// bounding boxes (x min, x max, y min, y max) in boxes[]: the chunks are tested
+// kThreads at a time, and only those whose box reaches the tile are loaded, in
+// index order.  A chunk whose box misses the tile has no point that passes the
+// per-point test of chunk_sums (x max + Hx >= x0 follows from x + Hx >= x0 by
+// the monotonicity of rounding, and likewise for the other sides), so the sums
+// equal tile_sums' bit for bit.  slist: LDS [kThreads] int.
+template <int K, int R, int C>
+__device__ __forceinline__ void tile_sums_boxed(const float2 *__restrict__ pts, int64_t n,
+                                                const float4 *__restrict__ boxes, float Hx, float Hy, float ax,
+                                                float ay, int ib, int jb, float bx0, float bx1, float by0, float by1,
+                                                float2 *sp, int *swave, int *slist, float (&tot)[R][C]) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const float fib = (float)ib, fjb = (float)jb;
 #pragma unroll
-            for (int k = 0; k < kThreads / 64; ++k) {
-                off += (k < w) ? swave[k] : 0;
-                cnt += swave[k];
-            }
-            if (keep) sp[off + before] = v;  // survivors keep their index order
-        } else {
-            sp[tid] = v;
-            cnt = (int)min((int64_t)kPointTile, end - base);
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < C; ++c) tot[r][c] = 0.0f;
+    const int64_t nch = (n + kPointTile - 1) / kPointTile;
+    for (int64_t g0 = 0; g0 < nch; g0 += kThreads) {
+        const int64_t c = g0 + tid;
+        bool hit = false;
+        if (c < nch) {
+            const float4 b = boxes[c];
+            hit = b.y + Hx >= bx0 && b.x - Hx <= bx1 && b.w + Hy >= by0 && b.z - Hy <= by1;
         }
+        const uint64_t m = __ballot(hit);
+        const int before = __popcll(m & ((1ull << lane) - 1ull));
+        __syncthreads();  // the previous group's list and counts are consumed
+        if (lane == 0) swave[w] = __popcll(m);
         __syncthreads();
-        if (cnt == 0) continue;
-
-        float acc[R][C];
+        int off = 0, cnt = 0;
 #pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-            for (int c = 0; c < C; ++c) acc[r][c] = 0.0f;
-
-        for (int k = 0; k < cnt; ++k) {
-            const float2 pt = sp[k];
-            float kx[C], ky[R];
-            if constexpr (kRuns) {
-                // run centres: half-integer nodes, so (centre - X) is exact like dx0 below
-                gauss_run<C>((fib + 0.5f * (float)(C - 1) - pt.x) * ax, ax, kx);
-                gauss_run<R>((fjb + 0.5f * (float)(R - 1) - pt.y) * ay, ay, ky);
-                if constexpr (K == kGaussTrunc) {  // the support test of factor<kGaussTrunc> (q_r > 0 keeps zeros)
-                    const float dx0 = fib - pt.x, dy0 = fjb - pt.y;
-#pragma unroll
-                    for (int c = 0; c < C; ++c) kx[c] = fabsf(dx0 + (float)c) <= Hx ? kx[c] : 0.0f;
-#pragma unroll
-                    for (int r = 0; r < R; ++r) ky[r] = fabsf(dy0 + (float)r) <= Hy ? ky[r] : 0.0f;
-                }
-            } else {
-                const float dx0 = fib - pt.x, dy0 = fjb - pt.y;
-#pragma unroll
-                for (int c = 0; c < C; ++c) kx[c] = factor<K>(dx0 + (float)c, ax, Hx);
-#pragma unroll
-                for (int r = 0; r < R; ++r) ky[r] = factor<K>(dy0 + (float)r, ay, Hy);
-            }
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-#pragma unroll
-                for (int c = 0; c < C; ++c) acc[r][c] = fmaf(ky[r], kx[c], acc[r][c]);
+        for (int k = 0; k < kThreads / 64; ++k) {
+            off += (k < w) ? swave[k] : 0;
+            cnt += swave[k];
         }
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-            for (int c = 0; c < C; ++c) tot[r][c] += acc[r][c];
+        if (hit) slist[off + before] = (int)(c - g0);
+        __syncthreads();
+        for (int k = 0; k < cnt; ++k) {
+            const int64_t base = (g0 + slist[k]) * kPointTile;
+            chunk_sums<K, R, C, true, false>(pts, base, min(n, base + kPointTile), Hx, Hy, ax, ay, fib, fjb, bx0,
+                                             bx1, by0, by1, sp, swave, tot);
+        }
     }
 }
 
