@@ -94,7 +94,8 @@ enum {
 typedef struct kde_grid kde_grid; /* opaque, immutable, library-owned */
 
 /* Creates a grid of nx x ny nodes spanning [xmin, xmax] x [ymin, ymax] (world
- * units, both edges on nodes).  Requires finite bounds with xmin < xmax,
+ * units, both edges on nodes): the node spacing dx = (xmax - xmin)/(nx - 1),
+ * dy = (ymax - ymin)/(ny - 1) of Eq. (5)-(6), on which every map is evaluated.  Requires finite bounds with xmin < xmax,
  * ymin < ymax, and 2 <= nx, ny <= 65536 (the node spacing divides by nx - 1).
  * *out receives the handle; release it with kde_destroy_grid. */
 int kde_create_grid(double xmin, double xmax, double ymin, double ymax, int32_t nx, int32_t ny,

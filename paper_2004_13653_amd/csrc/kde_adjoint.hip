@@ -386,17 +386,36 @@ template <int K>
 __device__ __forceinline__ void lscv_tile(const LscvLaunch &p, float2 me, bool diag, const float2 *qs, int tid,
                                           double (&S)[6]) {
     float sa = 0.0f, sax = 0.0f, say = 0.0f, sb = 0.0f, sbx = 0.0f, sby = 0.0f;
-    for (int k = diag ? tid + 1 : 0; k < kAdjThreads; ++k) {
-        const float2 o = qs[k];
-        float kbx, kbdx, gx, gdx, kby, kbdy, gy, gdy;
-        lscv_axis<K>(me.x - o.x, p.ix, p.ix2, kbx, kbdx, gx, gdx);
-        lscv_axis<K>(me.y - o.y, p.iy, p.iy2, kby, kbdy, gy, gdy);
-        sa = fmaf(kbx, kby, sa);
-        sax = fmaf(kbdx, kby, sax);
-        say = fmaf(kbx, kbdy, say);
-        sb = fmaf(gx, gy, sb);
-        sbx = fmaf(gdx, gy, sbx);
-        sby = fmaf(gx, gdy, sby);
+    if constexpr (K == kGaussian) {
+        // kb(u) kb(v) = exp(-(u^2 + v^2)/4) is one exp2 per pair, and g(u) g(v) =
+        // exp(-(u^2 + v^2)/2) its square; the derivative factors are those of
+        // lscv_axis, (1 - u^2/2) for kb and (1 - u^2) for g.
+        for (int k = diag ? tid + 1 : 0; k < kAdjThreads; ++k) {
+            const float2 o = qs[k];
+            const float dx = me.x - o.x, dy = me.y - o.y;
+            const float wx = fminf(dx * dx * p.ix2, 1.0e4f), wy = fminf(dy * dy * p.iy2, 1.0e4f);  // u^2, v^2, capped
+            const float e = __builtin_amdgcn_exp2f(-0.36067376022224085f * (wx + wy));
+            const float e2 = e * e;
+            sa += e;
+            sb += e2;
+            sax = fmaf(fmaf(-0.5f, wx, 1.0f), e, sax);
+            say = fmaf(fmaf(-0.5f, wy, 1.0f), e, say);
+            sbx = fmaf(1.0f - wx, e2, sbx);
+            sby = fmaf(1.0f - wy, e2, sby);
+        }
+    } else {
+        for (int k = diag ? tid + 1 : 0; k < kAdjThreads; ++k) {
+            const float2 o = qs[k];
+            float kbx, kbdx, gx, gdx, kby, kbdy, gy, gdy;
+            lscv_axis<K>(me.x - o.x, p.ix, p.ix2, kbx, kbdx, gx, gdx);
+            lscv_axis<K>(me.y - o.y, p.iy, p.iy2, kby, kbdy, gy, gdy);
+            sa = fmaf(kbx, kby, sa);
+            sax = fmaf(kbdx, kby, sax);
+            say = fmaf(kbx, kbdy, say);
+            sb = fmaf(gx, gy, sb);
+            sbx = fmaf(gdx, gy, sbx);
+            sby = fmaf(gx, gdy, sby);
+        }
     }
     S[0] += 2.0 * sa;
     S[1] += 2.0 * sax;

@@ -150,10 +150,11 @@ def test_raw_sum_and_determinism():
 
 
 @pytest.mark.parametrize("kernel", [0, 1, 5, 7])
-@pytest.mark.parametrize("H", [1.3, 60.0, 70.0])
+@pytest.mark.parametrize("H", [1.3, 3.5, 10.0, 60.0, 70.0])
 def test_binned_and_scanned_compact_paths(kernel, H):
     """Compact kernels with n >= 4096 go through support binning when H is at
-    most the tile side and through per-tile culling scans otherwise (the tile
+    most the tile side (H = 1.3 to 60 here) and through per-tile culling scans
+    otherwise (the tile
     side follows the tuned shape); points also lie outside the grid on every
     side."""
     rng = np.random.default_rng(int(H) + 10 * kernel)
