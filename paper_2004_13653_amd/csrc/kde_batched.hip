@@ -156,9 +156,16 @@ __device__ __forceinline__ void run_item(const BMap &m, const BItem &w, const Ba
     tile::store_block<S::R, S::C>(tot, m.out, m.nx, m.ny, ib, jb, m.scale);
 }
 
-template <int K>
+template <int K, int kMaxRc>
 __device__ __forceinline__ void run_shape(const BMap &m, const BItem &w, const BatchLaunch &b, float2 *sp,
                                           int *swave, int *slist, int *s_last) {
+    if constexpr (kMaxRc < 8) {  // lean variant: register blocks of side 2 and 4 only
+        if (m.rc == 2)
+            run_item<K, 2, false>(m, w, b, sp, swave, slist, s_last);
+        else
+            run_item<K, 4, false>(m, w, b, sp, swave, slist, s_last);
+        return;
+    }
     if constexpr (K == kGaussian) {
         if (m.ax <= kMaxRunScale && m.ay <= kMaxRunScale) {
             if (m.rc == 2)
@@ -178,7 +185,14 @@ __device__ __forceinline__ void run_shape(const BMap &m, const BItem &w, const B
         run_item<K, 8, false>(m, w, b, sp, swave, slist, s_last);
 }
 
+// The general variant (kLean false) runs every kernel and register-block side.
+// Batches of compact maps with blocks of side 2 or 4 (the usual case: Gaussian
+// maps go to the matrix cores) use the lean variant, built without the Gaussian
+// paths and the 8 x 8 blocks that set the register count of the general one,
+// so that more workgroups fit on a CU.
+template <bool kLean>
 __global__ __launch_bounds__(kThreads) void batched_kernel(BatchLaunch b) {
+    constexpr int R = kLean ? 4 : 8;
     __shared__ float2 sp[kPointTile];
     __shared__ int swave[kThreads / 64];
     __shared__ int slist[kThreads];
@@ -192,14 +206,16 @@ __global__ __launch_bounds__(kThreads) void batched_kernel(BatchLaunch b) {
         const BItem w = b.items[it];
         const BMap m = b.maps[w.map];
         switch (m.kernel) {
-        case kUniform: run_shape<kUniform>(m, w, b, sp, swave, slist, &s_last); break;
-        case kTriangular: run_shape<kTriangular>(m, w, b, sp, swave, slist, &s_last); break;
-        case kEpanechnikov: run_shape<kEpanechnikov>(m, w, b, sp, swave, slist, &s_last); break;
-        case kQuartic: run_shape<kQuartic>(m, w, b, sp, swave, slist, &s_last); break;
-        case kTriweight: run_shape<kTriweight>(m, w, b, sp, swave, slist, &s_last); break;
-        case kTricube: run_shape<kTricube>(m, w, b, sp, swave, slist, &s_last); break;
-        case kGaussian: run_shape<kGaussian>(m, w, b, sp, swave, slist, &s_last); break;
-        default: run_shape<kCosine>(m, w, b, sp, swave, slist, &s_last); break;
+        case kUniform: run_shape<kUniform, R>(m, w, b, sp, swave, slist, &s_last); break;
+        case kTriangular: run_shape<kTriangular, R>(m, w, b, sp, swave, slist, &s_last); break;
+        case kEpanechnikov: run_shape<kEpanechnikov, R>(m, w, b, sp, swave, slist, &s_last); break;
+        case kQuartic: run_shape<kQuartic, R>(m, w, b, sp, swave, slist, &s_last); break;
+        case kTriweight: run_shape<kTriweight, R>(m, w, b, sp, swave, slist, &s_last); break;
+        case kTricube: run_shape<kTricube, R>(m, w, b, sp, swave, slist, &s_last); break;
+        case kGaussian:
+            if constexpr (!kLean) run_shape<kGaussian, R>(m, w, b, sp, swave, slist, &s_last);
+            break;
+        default: run_shape<kCosine, R>(m, w, b, sp, swave, slist, &s_last); break;
         }
     }
 }
@@ -217,6 +233,7 @@ struct Plan {
     int n_split_tiles = 0;
     int64_t n_slots = 0;  // floats of partial tiles
     int64_t n_boxes = 0;  // chunk boxes of the compact maps
+    bool lean = true;     // no Gaussian map and no register block of side 8
     std::string signature;  // item list and static map fields
 };
 
@@ -250,6 +267,7 @@ Plan make_plan(const MapArgs *args, int n_maps) {
         const bool dense = a.kernel_id == kGaussian;
         bm.box0 = pl.n_boxes;
         if (!dense) pl.n_boxes += (a.n + kPointTile - 1) / kPointTile;
+        pl.lean = pl.lean && !dense && a.rc <= 4;
         int64_t per = a.n;
         if (dense) {
             per = std::max<int64_t>(kPointTile, kPairsPerItem / ((int64_t)TW * TH));
@@ -316,16 +334,22 @@ Layout layout_of(const Plan &pl) {
     return L;
 }
 
+// Workgroups of the persistent launch: as many as can be resident at once
+// (occupancy of the kernel variant times the CUs), at most one per item.
+template <bool kLean>
 int persistent_grid(int n_items) {
-    // Workgroups of 256 threads; the kernel's register use allows about 3 per CU.
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
-                                                                        dev) != hipSuccess || cus <= 0)
+    static int resident = 0;
+    if (resident == 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
             cus = 256;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_kernel<kLean>, kThreads, 0) !=
+                hipSuccess || per_cu <= 0)
+            per_cu = 2;
+        resident = per_cu * cus;
     }
-    return std::max(1, std::min(n_items, 3 * cus));
+    return std::max(1, std::min(n_items, resident));
 }
 
 hipError_t enqueue(const Plan &pl, const Layout &L, const void *host_stage, char *dev, hipStream_t s) {
@@ -348,7 +372,10 @@ hipError_t enqueue(const Plan &pl, const Layout &L, const void *host_stage, char
         hipLaunchKernelGGL(batch_box_kernel, dim3((unsigned)((pl.n_boxes + 3) / 4)), dim3(256), 0, s, b);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(batched_kernel, dim3(persistent_grid(b.n_items)), dim3(kThreads), 0, s, b);
+    if (pl.lean)
+        hipLaunchKernelGGL(batched_kernel<true>, dim3(persistent_grid<true>(b.n_items)), dim3(kThreads), 0, s, b);
+    else
+        hipLaunchKernelGGL(batched_kernel<false>, dim3(persistent_grid<false>(b.n_items)), dim3(kThreads), 0, s, b);
     return hipGetLastError();
 }
 
