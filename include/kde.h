@@ -177,10 +177,15 @@ typedef struct kde_map {
  * persistent launch: the batch is cut into (map, pixel tile, point range)
  * items, longest first, pulled by persistent workgroups from an atomic counter;
  * each such map's output equals what kde_eval(..., KDE_FP32_DIRECT, ...)
- * computes up to FP32 rounding order.  The other maps (matrix-core precisions,
- * truncated Gaussians) follow on the same stream as individual launches of the
- * kde_eval path, sharing one workspace, so their outputs equal kde_eval's bit
- * for bit.  Every descriptor is validated before anything is launched; output
+ * computes up to FP32 rounding order.  The other maps follow on the same
+ * stream: the Gaussian maps of each matrix-core precision (bandwidths of at
+ * least 1.05 node spacings, n > 0) as one launch of the contraction kernel over
+ * all their tiles and point splits, the rest (truncated Gaussians, narrower
+ * bandwidths) as individual launches of the kde_eval path; each map is split
+ * and summed exactly as kde_eval splits and sums it, so these outputs equal
+ * kde_eval's bit for bit.  A small table of the maps goes up from one of a few
+ * pinned buffers the library keeps per device until kde_shutdown().  Every
+ * descriptor is validated before anything is launched; output
  * buffers must not overlap each other or any point buffer.  By default the
  * persistent part's upload + launch sequence is captured into a hipGraph the
  * first time a batch shape (item list, kernels, grid sizes, point counts) is seen

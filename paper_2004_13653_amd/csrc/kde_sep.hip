@@ -35,6 +35,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <vector>
 
 namespace kde {
 
@@ -384,10 +388,64 @@ __global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p) {
 // (the splits have no registers left for that).  Same LDS layout, chunking,
 // split-K and tile order as sep_mfma_kernel; the point loads run three chunks
 // ahead (the padded copy holds four chunks of far-away points past each split).
+// kBatch: the launch runs the (tile, split) items of several maps, each
+// workgroup taking its map's arguments from a table (DenseEntry) instead of the
+// kernel argument; every map is split and summed as its own launch would.
 constexpr int kThreads8 = 512;
 
-template <int P>
-__global__ __launch_bounds__(kThreads8, 1) void sep_mfma8_kernel(SepLaunch p) {
+// A batch of dense maps in one launch: map m owns workgroups [wg0, wg0 + tiles
+// x splits) of the grid (tile fastest), found by binary search.
+struct DenseEntry {
+    SepLaunch p;          // dst: the map (one split) or its partial planes
+    int64_t wg0;          // first workgroup of the map
+    int64_t tiles;
+    int splits;           // point splits of the map
+    // padding: split s of the map's points -> p.pts + s * p.pad_stride
+    const float2 *src;
+    int64_t pad0;         // first padded point of the map in the batch's padded array
+    // split reduction (maps with more than one split; 0 cells otherwise)
+    int64_t red0;         // first cell of the map in the batch's reduction range
+    float *out;
+};
+
+__device__ __forceinline__ int find_entry(const DenseEntry *e, int n, int64_t key, int which) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        const int64_t v = which == 0 ? e[mid].wg0 : which == 1 ? e[mid].pad0 : e[mid].red0;
+        if (v <= key) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// pad_points_kernel over every map of the batch.
+__global__ __launch_bounds__(256) void pad_batch_kernel(const DenseEntry *__restrict__ e, int n, int64_t total,
+                                                        float2 *__restrict__ padded) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int m = find_entry(e, n, i, 1);
+    const SepLaunch &p = e[m].p;
+    const int64_t k0 = i - e[m].pad0, s = k0 / p.pad_stride, k = k0 - s * p.pad_stride;
+    const int64_t q = s * p.per_split + k;
+    padded[i] = (k < p.per_split && q < p.n) ? e[m].src[q] : make_float2(kFar, kFar);
+}
+
+// reduce_splits_kernel over the maps of the batch with more than one split.
+__global__ __launch_bounds__(256) void reduce_batch_kernel(const DenseEntry *__restrict__ e, int n, int64_t total) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int m = find_entry(e, n, i, 2);
+    const SepLaunch &p = e[m].p;
+    const int64_t c = i - e[m].red0;
+    float v = 0.0f;
+    for (int k = 0; k < e[m].splits; ++k) v += p.dst[(int64_t)k * p.plane + c];
+    e[m].out[c] = v * p.scale;
+}
+
+template <int P, bool kBatch>
+__global__ __launch_bounds__(kThreads8, 1) void sep_mfma8_kernel(SepLaunch p, const DenseEntry *__restrict__ batch,
+                                                                  int n_batch) {
     using Cfg = SepConfig<P>;
     constexpr bool kSplit = Cfg::kSplit;
     constexpr bool kBf16 = PrecTraits<P>::kBf16;
@@ -401,11 +459,24 @@ __global__ __launch_bounds__(kThreads8, 1) void sep_mfma8_kernel(SepLaunch p) {
     __shared__ uint4 lds1[kOps * W];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    // XCD-aware order of the (tile, split) items, as in sep_mfma_kernel.
-    const int64_t L = blockIdx.x + (int64_t)blockIdx.y * gridDim.x, TS = (int64_t)gridDim.x * gridDim.y;
-    const int64_t wl = TS % 8 == 0 ? (L % 8) * (TS / 8) + L / 8 : L;
-    const int tile_idx = (int)(wl % gridDim.x);
-    const int64_t split = wl / gridDim.x;
+    int tile_idx;
+    int64_t split;
+    bool one_split;  // the map has a single point split: write it scaled
+    if constexpr (kBatch) {  // the item's map, tile and split from the batch table
+        const int m = find_entry(batch, n_batch, blockIdx.x, 0);
+        p = batch[m].p;
+        const int64_t local = (int64_t)blockIdx.x - batch[m].wg0;
+        tile_idx = (int)(local % batch[m].tiles);
+        split = local / batch[m].tiles;
+        one_split = batch[m].splits == 1;
+    } else {
+        // XCD-aware order of the (tile, split) items, as in sep_mfma_kernel.
+        const int64_t L = blockIdx.x + (int64_t)blockIdx.y * gridDim.x, TS = (int64_t)gridDim.x * gridDim.y;
+        const int64_t wl = TS % 8 == 0 ? (L % 8) * (TS / 8) + L / 8 : L;
+        tile_idx = (int)(wl % gridDim.x);
+        split = wl / gridDim.x;
+        one_split = gridDim.y == 1;
+    }
     const int64_t beg = split * p.per_split;
     const int64_t count = min(p.n, beg + p.per_split) - beg;
     const float2 *qbase = p.pts + split * p.pad_stride;
@@ -555,7 +626,7 @@ __global__ __launch_bounds__(kThreads8, 1) void sep_mfma8_kernel(SepLaunch p) {
     // Epilogue: register r of lane l in a 32 x 32 tile holds row 8 (r / 4) + 4 (l / 32) + r % 4,
     // column l % 32; the runs' position factors q(row mod 8) q(column mod 8).
     float *dst = p.dst + split * p.plane;
-    const float sc = gridDim.y == 1 ? p.scale : 1.0f;
+    const float sc = one_split ? p.scale : 1.0f;
     constexpr float hc = 0.5f * (float)(Cfg::R - 1);
     const float rcq = ((float)(lane % Cfg::R) - hc) * p.ax;
     const float qcol = __builtin_amdgcn_exp2f(-rcq * rcq);
@@ -664,7 +735,8 @@ hipError_t launch_sep_kp(const MapArgs &a, const SepPlan &pl, const float2 *padd
     if constexpr (K == kGaussian) {
         if (recur && bi == nullptr) {  // the 8-wave kernel
             main_kernel_begin(stream);
-            hipLaunchKernelGGL((sep_mfma8_kernel<P>), grid, dim3(kThreads8), 0, stream, p);
+            hipLaunchKernelGGL((sep_mfma8_kernel<P, false>), grid, dim3(kThreads8), 0, stream, p,
+                               static_cast<const DenseEntry *>(nullptr), 0);
             main_kernel_end(stream);
             return hipGetLastError();
         }
@@ -896,6 +968,158 @@ size_t sep_workspace_bytes(const MapArgs &a, int precision) {
     if (banded_applies(a)) return band_plan(a, chunk_for(precision)).total;
     const SepPlan pl = sep_plan(a, chunk_for(precision));
     return pl.partial_bytes + padded_bytes(pl);
+}
+
+// ------------------------------------------------------------------ dense batches
+
+namespace {
+
+// Library-owned pinned staging for the batch tables: a ring of kStageSlots
+// buffers per device, each with an event marking the completion of the last
+// copy out of it, so that a call waits only for the copy issued kStageSlots
+// calls earlier.
+constexpr int kStageSlots = 4;
+struct DenseStage {
+    char *host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+};
+struct DenseRing {
+    DenseStage slot[kStageSlots];
+    int next = 0;
+};
+std::mutex g_stage_mu;
+std::map<int, DenseRing> g_stage;
+
+struct DenseLayout {
+    std::vector<DenseEntry> entries;
+    int64_t wgs = 0, padded = 0, cells = 0;
+    size_t table_bytes = 0, padded_off = 0, part_off = 0, total = 0;
+};
+
+DenseLayout dense_layout(const MapArgs *maps, int n, int precision) {
+    DenseLayout L;
+    const int kc = chunk_for(precision);
+    L.entries.resize(n);
+    size_t part = 0;
+    for (int m = 0; m < n; ++m) {
+        const MapArgs &a = maps[m];
+        const SepPlan pl = sep_plan(a, kc);
+        DenseEntry &e = L.entries[m];
+        e.wg0 = L.wgs;
+        e.tiles = pl.tiles;
+        L.wgs += (int64_t)pl.tiles * pl.splits;
+        e.src = a.pts;
+        e.pad0 = L.padded;
+        L.padded += (int64_t)pl.splits * pl.pad_stride;
+        e.red0 = L.cells;
+        if (pl.splits > 1) L.cells += (int64_t)a.nx * a.ny;
+        e.out = a.out;
+        SepLaunch &p = e.p;
+        p = SepLaunch{};
+        p.n = a.n;
+        p.per_split = pl.per_split;
+        p.pad_stride = pl.pad_stride;
+        p.ax = arg_scale(kGaussian, a.Hx);
+        p.ay = arg_scale(kGaussian, a.Hy);
+        p.Hx = a.Hx;
+        p.Hy = a.Hy;
+        p.ix = (float)(1.0 / (double)a.Hx);
+        p.iy = (float)(1.0 / (double)a.Hy);
+        p.nx = a.nx;
+        p.ny = a.ny;
+        p.tiles_x = pl.tiles_x;
+        p.scale = a.scale;
+        p.plane = (int64_t)a.nx * a.ny;
+        e.splits = pl.splits;
+        p.pts = reinterpret_cast<const float2 *>((uintptr_t)e.pad0);  // offsets until the base is known
+        p.dst = pl.splits > 1 ? reinterpret_cast<float *>((uintptr_t)part) : a.out;
+        part += pl.partial_bytes;
+    }
+    L.table_bytes = ((size_t)n * sizeof(DenseEntry) + 255) / 256 * 256;
+    L.padded_off = L.table_bytes;
+    L.part_off = L.padded_off + (((size_t)L.padded * sizeof(float2) + 255) / 256 * 256);
+    L.total = L.part_off + part;
+    return L;
+}
+
+template <int P>
+hipError_t launch_dense_batch_p(const DenseEntry *dev, int n, const DenseLayout &L, hipStream_t s) {
+    hipLaunchKernelGGL((sep_mfma8_kernel<P, true>), dim3((unsigned)L.wgs), dim3(kThreads8), 0, s, SepLaunch{}, dev, n);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool sep_dense_batchable(const MapArgs &a) {
+    return a.kernel_id == kGaussian && a.n > 0 && arg_scale(kGaussian, a.Hx) <= kMaxRunScale &&
+           arg_scale(kGaussian, a.Hy) <= kMaxRunScale;
+}
+
+size_t sep_dense_batch_bytes(const MapArgs *maps, int n, int precision) {
+    return n > 0 ? dense_layout(maps, n, precision).total : 0;
+}
+
+hipError_t launch_sep_dense_batch(const MapArgs *maps, int n, int precision, void *ws, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    DenseLayout L = dense_layout(maps, n, precision);
+    char *w = static_cast<char *>(ws);
+    for (DenseEntry &e : L.entries) {  // offsets -> device addresses
+        e.p.pts = reinterpret_cast<const float2 *>(w + L.padded_off) + (uintptr_t)e.p.pts;
+        if (e.splits > 1) e.p.dst = reinterpret_cast<float *>(w + L.part_off + (uintptr_t)e.p.dst);
+    }
+    int dev = 0;
+    hipError_t err = hipGetDevice(&dev);
+    if (err != hipSuccess) return err;
+    const size_t bytes = (size_t)n * sizeof(DenseEntry);
+    {
+        std::lock_guard<std::mutex> lock(g_stage_mu);
+        DenseRing &ring = g_stage[dev];
+        DenseStage &st = ring.slot[ring.next];
+        ring.next = (ring.next + 1) % kStageSlots;
+        if (st.done == nullptr && (err = hipEventCreateWithFlags(&st.done, hipEventDisableTiming)) != hipSuccess)
+            return err;
+        if ((err = hipEventSynchronize(st.done)) != hipSuccess) return err;  // the last copy has read the buffer
+        if (st.cap < bytes) {
+            if (st.host) (void)hipHostFree(st.host);
+            st.host = nullptr;
+            st.cap = 0;
+            if ((err = hipHostMalloc(&st.host, bytes, hipHostMallocDefault)) != hipSuccess) return err;
+            st.cap = bytes;
+        }
+        std::memcpy(st.host, L.entries.data(), bytes);
+        if ((err = hipMemcpyAsync(w, st.host, bytes, hipMemcpyHostToDevice, s)) != hipSuccess) return err;
+        if ((err = hipEventRecord(st.done, s)) != hipSuccess) return err;
+    }
+    const DenseEntry *table = reinterpret_cast<const DenseEntry *>(w);
+    hipLaunchKernelGGL(pad_batch_kernel, dim3((unsigned)((L.padded + 255) / 256)), dim3(256), 0, s, table, n,
+                       L.padded, reinterpret_cast<float2 *>(w + L.padded_off));
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    switch (precision) {
+    case kPrecFp16: err = launch_dense_batch_p<kPrecFp16>(table, n, L, s); break;
+    case kPrecBf16: err = launch_dense_batch_p<kPrecBf16>(table, n, L, s); break;
+    case kPrecFp16x3: err = launch_dense_batch_p<kPrecFp16x3>(table, n, L, s); break;
+    case kPrecBf16x3: err = launch_dense_batch_p<kPrecBf16x3>(table, n, L, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    if (err != hipSuccess || L.cells == 0) return err;
+    hipLaunchKernelGGL(reduce_batch_kernel, dim3((unsigned)((L.cells + 255) / 256)), dim3(256), 0, s, table, n,
+                       L.cells);
+    return hipGetLastError();
+}
+
+void release_dense_stage() {
+    std::lock_guard<std::mutex> lock(g_stage_mu);
+    for (auto &kv : g_stage) {
+        for (DenseStage &st : kv.second.slot) {
+            if (st.done) {
+                (void)hipEventSynchronize(st.done);
+                (void)hipEventDestroy(st.done);
+            }
+            if (st.host) (void)hipHostFree(st.host);
+        }
+    }
+    g_stage.clear();
 }
 
 // Workspace: [split partial planes][padded points] (dense) or the banded layout.

@@ -192,6 +192,43 @@ def test_mixed_precision_batch(eager):
             np.testing.assert_array_equal(y, ref)
 
 
+@pytest.mark.parametrize("eager", [True, False])
+def test_dense_gaussian_maps_share_one_launch(eager):
+    """Several Gaussian maps per matrix-core precision go out as one launch of
+    the contraction kernel (plus one padding and one split-reduction launch):
+    maps of one and of several point splits, one to nine 256-node tiles, ragged
+    grids, and a bandwidth too narrow for multiplicative runs (which takes the
+    single-map path) in the same call.  Each map equals kde_eval bit for bit,
+    and sampled maps match the oracle at their precision's gate."""
+    import torch
+    t, grids, units = _pool(100)
+    cases = []
+    for prec in ("fp16", "bf16", "fp16x3", "bf16x3"):
+        cases += [(synth.MapSpec(0, 45000, 512, 0.003, 6), prec),    # four tiles, several splits
+                  (synth.MapSpec(2000, 300, 100, 0.02, 6), prec),    # one ragged tile, one split
+                  (synth.MapSpec(7000, 9000, 1024, 0.002, 6), prec),  # sixteen tiles
+                  (synth.MapSpec(100, 5000, 256, 0.0004, 6), prec)]  # H < 1.05 px: no runs, single path
+    maps = []
+    for s, prec in cases:
+        XY = units[s.side][s.start:s.start + s.count]
+        out = torch.full((s.side, s.side), float("nan"), device=kt.device())
+        maps.append((kt.to_device(XY), s.kernel, s.h_deg, s.h_deg, grids[s.side], out, prec))
+    for _ in range(2):  # the second call reuses the staged table buffer
+        kde.eval_batched(maps, eager=eager)
+        torch.cuda.synchronize()
+        for (s, prec), (pts, kernel, hx, hy, g, out, _) in zip(cases, maps):
+            ref = kde.eval(pts, kernel, hx, hy, g, precision=prec).cpu().numpy()
+            np.testing.assert_array_equal(out.cpu().numpy(), ref, err_msg=f"{s} {prec}")
+    og = oracle.Grid(*grids[100].bounds, 100, 100)
+    for k in (1, 5, 9, 13):  # the 100 x 100 map of every precision
+        s, prec = cases[k]
+        r = kt.oracle_density_window(units[100][s.start:s.start + s.count], 6, s.h_deg, s.h_deg, og,
+                                     (0, 100, 0, 100))
+        e = oracle.errors(maps[k][5].cpu().numpy().astype(np.float64).ravel(), r.ravel())
+        kt.log(f"{prec}: e_2 {e['e_2']:.2e} e_inf {e['e_inf']:.2e}")
+        assert e["e_2"] <= 2e-3, (s, prec, e)
+
+
 @pytest.mark.parametrize("rc", [2, 4, 8])
 def test_forced_tile_shapes_match_oracle(rc):
     """The persistent kernel with every register-block shape forced (Gaussian
