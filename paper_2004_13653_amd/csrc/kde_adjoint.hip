@@ -390,9 +390,8 @@ __device__ __forceinline__ void lscv_tile(const LscvLaunch &p, float2 me, bool d
         // kb(u) kb(v) = exp(-(u^2 + v^2)/4) is one exp2 per pair, and g(u) g(v) =
         // exp(-(u^2 + v^2)/2) its square; the derivative factors are those of
         // lscv_axis, (1 - u^2/2) for kb and (1 - u^2) for g.
-        for (int k = diag ? tid + 1 : 0; k < kAdjThreads; ++k) {
-            const float2 o = qs[k];
-            const float dx = me.x - o.x, dy = me.y - o.y;
+        auto pair = [&](float ox, float oy) {
+            const float dx = me.x - ox, dy = me.y - oy;
             const float wx = fminf(dx * dx * p.ix2, 1.0e4f), wy = fminf(dy * dy * p.iy2, 1.0e4f);  // u^2, v^2, capped
             const float e = __builtin_amdgcn_exp2f(-0.36067376022224085f * (wx + wy));
             const float e2 = e * e;
@@ -402,6 +401,17 @@ __device__ __forceinline__ void lscv_tile(const LscvLaunch &p, float2 me, bool d
             say = fmaf(fmaf(-0.5f, wy, 1.0f), e, say);
             sbx = fmaf(1.0f - wx, e2, sbx);
             sby = fmaf(1.0f - wy, e2, sby);
+        };
+        if (!diag) {  // the same q for every lane: a uniform loop, two points per LDS read
+            const float4 *q2 = reinterpret_cast<const float4 *>(qs);
+#pragma unroll 4
+            for (int k = 0; k < kAdjThreads / 2; ++k) {
+                const float4 o = q2[k];
+                pair(o.x, o.y);
+                pair(o.z, o.w);
+            }
+        } else {
+            for (int k = tid + 1; k < kAdjThreads; ++k) pair(qs[k].x, qs[k].y);
         }
     } else {
         for (int k = diag ? tid + 1 : 0; k < kAdjThreads; ++k) {
@@ -454,7 +464,7 @@ __device__ __forceinline__ void lscv_store(double (&S)[6], double (*red)[kAdjThr
 // All-pairs LSCV (used for the Gaussian, whose every pair counts).
 template <int K>
 __global__ __launch_bounds__(kAdjThreads) void lscv_kernel(LscvLaunch p, int64_t nb, int64_t chunks) {
-    __shared__ float2 qs[kAdjThreads];
+    __shared__ __align__(16) float2 qs[kAdjThreads];
     __shared__ double red[6][kAdjThreads];
     const int tid = threadIdx.x;
     const int64_t u = blockIdx.x / chunks, c = blockIdx.x % chunks;
@@ -539,7 +549,7 @@ struct CullLaunch {
 
 template <int K>
 __global__ __launch_bounds__(kAdjThreads) void lscv_cull_kernel(LscvLaunch p, CullLaunch c) {
-    __shared__ float2 qs[kAdjThreads];
+    __shared__ __align__(16) float2 qs[kAdjThreads];
     __shared__ double red[6][kAdjThreads];
     __shared__ int64_t list[kAdjThreads];
     __shared__ unsigned wsum[kAdjThreads / 64];
