@@ -27,6 +27,7 @@
 #include "kde_tile.h"
 
 #include <algorithm>
+#include <cmath>
 
 namespace kde {
 
@@ -251,6 +252,74 @@ __global__ __launch_bounds__(tile::kThreads) void bin_gather_kernel(GatherLaunch
         tile::store_block<S::R, S::C>(tot, p.part + item * (S::TW * S::TH), S::TW, S::TH, ib - x0, jb - y0, 1.0f);
 }
 
+// Compact kernels with small supports: each binned point adds its own terms
+// g(s) g(t) at the nodes of its support inside the tile, instead of every
+// thread of the tile testing every point (the gather above spends hundreds of
+// lane operations per in-support pair when the support covers a few percent of
+// the tile).  The tile accumulates in LDS as 64-bit fixed-point integers: each
+// FP32 term v in [0, 1] becomes round(v 2^32) and is added with an integer
+// atomic, so the sums are exact in the rounded terms and do not depend on the
+// order the points arrive in (n < 2^31 terms of at most 2^32 cannot overflow).
+// Each thread takes a contiguous run of the item's points, so that the lanes of
+// a wave work on distant stretches of the tracks and seldom hit one node at once.
+// A tile with one item writes scale * acc / 2^32 (one rounding), otherwise the
+// raw FP32 partial tile for item_reduce_kernel.  Nodes are tried from
+// floor(X - H) - 1 over floor(2 H) + 3 per axis with the factor's own support
+// test, so rounding of X - H never drops a node of the support.
+template <int K, int RC>
+__global__ __launch_bounds__(tile::kThreads) void bin_accum_kernel(GatherLaunch p) {
+    constexpr int TW = 16 * RC, TH = 16 * RC;
+    __shared__ unsigned long long acc[TW * TH];
+    const int64_t item = blockIdx.x;
+    if (item >= (int64_t)p.item_off[p.tiles]) return;  // whole workgroup: beyond the items of this map
+    int lo_t = 0, hi_t = p.tiles - 1;  // tile of this item: the last t with item_off[t] <= item
+    while (lo_t < hi_t) {
+        const int mid = (lo_t + hi_t + 1) / 2;
+        if ((int64_t)p.item_off[mid] <= item) lo_t = mid;
+        else hi_t = mid - 1;
+    }
+    const int t = lo_t, tid = threadIdx.x;
+    const int64_t k = item - p.item_off[t], parts = (int64_t)p.item_off[t + 1] - p.item_off[t];
+    const int64_t e = p.end[(int64_t)t * p.wblocks + p.wblocks - 1];
+    const int64_t b = t > 0 ? (int64_t)p.end[(int64_t)t * p.wblocks - 1] : 0;
+    const int64_t len = e - b;
+    const int64_t lo = b + len * k / parts, hi = b + len * (k + 1) / parts;
+    const int x0 = (t % p.tiles_x) * TW, y0 = (t / p.tiles_x) * TH;
+    for (int i = tid; i < TW * TH; i += tile::kThreads) acc[i] = 0ull;
+    __syncthreads();
+    const int rows = (int)floorf(2.0f * p.Hy) + 3, cols = (int)floorf(2.0f * p.Hx) + 3;
+    const int64_t per = (hi - lo + tile::kThreads - 1) / tile::kThreads;
+    const int64_t q0 = lo + per * tid, q1 = min(hi, q0 + per);
+    for (int64_t q = q0; q < q1; ++q) {
+        const float2 v = p.bins[q];  // registered in this tile: its support reaches the tile
+        const int j0 = (int)floorf(v.y - p.Hy) - 1, i0 = (int)floorf(v.x - p.Hx) - 1;
+        for (int r = 0; r < rows; ++r) {
+            const int j = j0 + r;
+            if (j < y0 || j >= y0 + TH || j >= p.ny) continue;
+            const float ty = tile::factor<K>((float)j - v.y, p.ay, p.Hy);
+            if (!(ty > 0.0f)) continue;
+            for (int c = 0; c < cols; ++c) {
+                const int i = i0 + c;
+                if (i < x0 || i >= x0 + TW || i >= p.nx) continue;
+                // the compact factors are >= 0; the FP32 cosine at the support edge can
+                // round to a tiny negative, which the clamp turns into the exact 0
+                const float w = fmaxf(ty * tile::factor<K>((float)i - v.x, p.ax, p.Hx), 0.0f);
+                if (w > 0.0f) atomicAdd(&acc[(j - y0) * TW + (i - x0)], __float2ull_rn(w * 4294967296.0f));
+            }
+        }
+    }
+    __syncthreads();
+    const double raw = 1.0 / 4294967296.0;
+    for (int i = tid; i < TW * TH; i += tile::kThreads) {
+        const int gi = x0 + i % TW, gj = y0 + i / TW;
+        if (parts == 1) {
+            if (gi < p.nx && gj < p.ny) p.out[(int64_t)gj * p.nx + gi] = (float)((double)acc[i] * (raw * p.scale));
+        } else {
+            p.part[item * (TW * TH) + i] = (float)((double)acc[i] * raw);
+        }
+    }
+}
+
 // Tiles with several items: the partial tiles added in item order, scaled.
 __global__ __launch_bounds__(256) void item_reduce_kernel(const float *__restrict__ part,
                                                           const unsigned *__restrict__ item_off, int tw, int th,
@@ -308,9 +377,27 @@ BinPlan bin_plan(const MapArgs &a, int T) {
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
+// Compact kernels whose support is tried over at most this many nodes per point
+// (floor(2 Hx) + 3) (floor(2 Hy) + 3) accumulate per point (bin_accum_kernel) on
+// tiles of side 32 or 64; larger supports and tiles take the gather.
+constexpr int kAccumMaxFootprint = 121;
+
+bool accum_applies(int kernel_id, int rc, float Hx, float Hy) {
+    if (kernel_id == kGaussian || kernel_id == kGaussTrunc || rc > 4) return false;
+    const int64_t foot = (int64_t)(std::floor(2.0 * (double)Hx) + 3) * (int64_t)(std::floor(2.0 * (double)Hy) + 3);
+    return foot <= kAccumMaxFootprint;
+}
+
 template <int K, int RC>
 hipError_t launch_gather_r(const GatherLaunch &p, int64_t items, hipStream_t s) {
     main_kernel_begin(s);
+    if constexpr (K != kGaussian && K != kGaussTrunc && RC <= 4) {
+        if (accum_applies(K, RC, p.Hx, p.Hy)) {
+            hipLaunchKernelGGL((bin_accum_kernel<K, RC>), dim3((unsigned)items), dim3(tile::kThreads), 0, s, p);
+            main_kernel_end(s);
+            return hipGetLastError();
+        }
+    }
     // the truncated Gaussian takes the runs of the Gaussian (two exp2 per run, then the support mask)
     if (K == kGaussTrunc && p.ax <= kMaxRunScale && p.ay <= kMaxRunScale)
         hipLaunchKernelGGL((bin_gather_kernel<K, RC, K == kGaussTrunc>), dim3((unsigned)items), dim3(tile::kThreads),
