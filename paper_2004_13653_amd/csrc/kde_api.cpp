@@ -276,8 +276,10 @@ void set_batch_rc(std::vector<kde::MapArgs> &args, int rc_gauss, int rc_compact)
 }
 
 // Register-block sides for a batch (one for its Gaussian maps, one for its
-// compact maps): forced, cached, tuned now (eager runs of the whole batch) or default.
-int pick_batch_rc(std::vector<kde::MapArgs> &args, hipStream_t s) {
+// compact maps): forced, cached, tuned now (runs of the whole batch, in the mode
+// of the call: graph replays, whose host part is a copy of the descriptors, or
+// eager runs, which rebuild the item list each time) or default.
+int pick_batch_rc(std::vector<kde::MapArgs> &args, bool eager, hipStream_t s) {
     const int forced = kde::tune::forced();
     if (forced) {
         set_batch_rc(args, forced, forced);
@@ -310,12 +312,15 @@ int pick_batch_rc(std::vector<kde::MapArgs> &args, hipStream_t s) {
     for (int g : gs) {
         for (int c : cs) {
             set_batch_rc(args, g, c);
-            const size_t bytes = kde::batched_workspace_bytes(args.data(), (int)args.size());
+            size_t bytes = 0;
             void *ws = nullptr;
-            int st = get_workspace(s, bytes, &ws);
-            if (st != KDE_OK) return st;
+            if (eager) {
+                bytes = kde::batched_workspace_bytes(args.data(), (int)args.size());
+                int st = get_workspace(s, bytes, &ws);
+                if (st != KDE_OK) return st;
+            }
             float ms = 0.0f;
-            e = time_twice([&] { return kde::run_batched(args.data(), (int)args.size(), false, ws, bytes, s); }, s,
+            e = time_twice([&] { return kde::run_batched(args.data(), (int)args.size(), !eager, ws, bytes, s); }, s,
                            ev, &ms);
             if (e != hipSuccess) return hip_fail(e, "kde_eval_batched (tile-shape tuning)");
             char name[8];
@@ -554,7 +559,7 @@ int kde_eval_batched(const kde_map *maps, int32_t n_maps, uint32_t flags, void *
         hipStream_t s = static_cast<hipStream_t>(stream);
         const bool eager = (flags & KDE_BATCH_EAGER) != 0;
         if (!args.empty()) {
-            int st = pick_batch_rc(args, s);
+            int st = pick_batch_rc(args, eager, s);
             if (st != KDE_OK) return st;
             void *ws = nullptr;
             size_t bytes = 0;

@@ -19,11 +19,13 @@
 // order, so a chunk is a short stretch of one or two tracks and most chunks miss
 // most tiles.
 //
-// Host side: the descriptors and the item list live in one pinned staging
-// buffer that a single copy moves to the device, followed by a counter reset
-// kernel and the persistent kernel.  That sequence is captured once per batch
-// shape (the item list and the static map fields) into a hipGraph and replayed
-// for later calls with new pointers and bandwidths.
+// Host side: a batch shape (per map: kernel, tile side, grid, point count)
+// fixes the item list and the static map fields.  The first call of a shape
+// builds them, uploads the item list once and captures into a hipGraph the copy
+// of the map descriptors from a pinned staging buffer, a counter reset kernel,
+// the box kernel and the persistent kernel; later calls of the shape only write
+// the descriptors (new pointers and bandwidths) and replay the graph.  Eager
+// calls copy descriptors and items and launch the same kernels.
 #include "kde_tile.h"
 
 #include <algorithm>
@@ -156,9 +158,132 @@ __device__ __forceinline__ void run_item(const BMap &m, const BItem &w, const Ba
     tile::store_block<S::R, S::C>(tot, m.out, m.nx, m.ny, ib, jb, m.scale);
 }
 
+// Compact maps whose supports span few nodes (tile::accum_footprint_fits): the
+// item's tile is taken as kAccSide x kAccSide sub-tiles.  For each, the chunks
+// whose box reaches it are listed; their points are read (coalesced) and those
+// whose support can reach the sub-tile are gathered into a list in LDS, which,
+// when nearly full, is worked through point by point: each adds its own terms
+// (tile::accum_point) to a fixed-point tile in LDS.  Integer sums depend neither
+// on the order nor on the tiling the points come in, so these maps equal
+// kde_eval's support-binned maps bit for bit.  In the list, the lanes of a wave
+// take entries kThreads / 64 apart (list entries keep track order), so that they
+// seldom start in one node at once and their atomics seldom collide.
+constexpr int kAccSide = 32;
+constexpr int kAccGroup = 4;    // listed chunks read per step
+constexpr int kAccList = 2048;  // float2 entries; the point tile of the gather items shares the array
+
+template <int K>
+__device__ __forceinline__ void accum_list(const BMap &m, const float2 *lst, int cnt, int x0, int y0,
+                                           unsigned long long *acc) {
+    const int spread = (threadIdx.x & 63) * (kThreads / 64) + (threadIdx.x >> 6);
+    for (int e0 = 0; e0 < cnt; e0 += kThreads) {
+        const int e = e0 + spread;
+        if (e < cnt) tile::accum_point<K, kAccSide, kAccSide>(lst[e], x0, y0, m.nx, m.ny, m.Hx, m.Hy, m.ax, m.ay, acc);
+    }
+}
+
+template <int K, int RC, int G>
+__device__ __forceinline__ void run_accum_item(const BMap &m, const BItem &w, const BatchLaunch &b,
+                                               unsigned long long *acc, float2 *lst, int *swave, int *slist,
+                                               int *sgrp) {
+    constexpr int TS = 16 * RC, NS = TS / kAccSide;
+    static_assert(NS >= 1 && TS % kAccSide == 0, "tile side must be a multiple of the accumulation side");
+    static_assert(kPointTile == kThreads && G <= kAccGroup && kAccList >= 2 * G * kThreads, "one point per thread per chunk");
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int tx = w.tile % m.tiles_x, ty = w.tile / m.tiles_x;
+    const int64_t nch = (m.n + kPointTile - 1) / kPointTile;
+    const float4 *boxes = b.boxes + m.box0;
+    const double unit = (1.0 / (double)tile::kFixedOne) * m.scale;
+    for (int sub = 0; sub < NS * NS; ++sub) {
+        const int x0 = tx * TS + (sub % NS) * kAccSide, y0 = ty * TS + (sub / NS) * kAccSide;
+        if (x0 >= m.nx || y0 >= m.ny) continue;  // uniform: the sub-tile lies past the grid
+        // Points reaching the sub-tile lie within H + 1 of its nodes (the margin
+        // of one node covers the rounding of the factors' support tests).
+        const float lx = (float)x0 - m.Hx - 1.0f, hx = (float)(min(x0 + kAccSide, m.nx) - 1) + m.Hx + 1.0f;
+        const float ly = (float)y0 - m.Hy - 1.0f, hy = (float)(min(y0 + kAccSide, m.ny) - 1) + m.Hy + 1.0f;
+        __syncthreads();  // the previous sub-tile has been written out
+        for (int i = tid; i < kAccSide * kAccSide; i += kThreads) acc[i] = 0ull;
+        int fill = 0;  // list entries (the same in every thread)
+        for (int64_t g0 = 0; g0 < nch; g0 += kThreads) {
+            const int64_t c = g0 + tid;
+            bool hit = false;
+            if (c < nch) {
+                const float4 bx = boxes[c];
+                hit = bx.y >= lx && bx.x <= hx && bx.w >= ly && bx.z <= hy;
+            }
+            const uint64_t mk = __ballot(hit);
+            __syncthreads();  // the previous group's list and counts are consumed; acc is cleared
+            if (lane == 0) swave[wv] = __popcll(mk);
+            __syncthreads();
+            int off = 0, cnt = 0;
+#pragma unroll
+            for (int k = 0; k < kThreads / 64; ++k) {
+                off += (k < wv) ? swave[k] : 0;
+                cnt += swave[k];
+            }
+            if (hit) slist[off + __popcll(mk & below)] = (int)(c - g0);
+            __syncthreads();
+            for (int k = 0; k < cnt; k += G) {  // G chunks a step: their loads overlap
+                float2 v[G];
+                bool take[G];
+                uint64_t mt[G];
+#pragma unroll
+                for (int j = 0; j < G; ++j) {
+                    const int64_t q = k + j < cnt ? (g0 + slist[k + j]) * kPointTile + tid : m.n;
+                    v[j] = q < m.n ? m.pts[q] : make_float2(0.0f, 0.0f);
+                    take[j] = q < m.n && v[j].x >= lx && v[j].x <= hx && v[j].y >= ly && v[j].y <= hy;  // NaN fails
+                    mt[j] = __ballot(take[j]);
+                }
+                __syncthreads();  // every thread has read the counts of the previous step
+                if (lane == 0)
+#pragma unroll
+                    for (int j = 0; j < G; ++j) sgrp[j * (kThreads / 64) + wv] = __popcll(mt[j]);
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < G; ++j) {  // list order: chunk by chunk, wave by wave, lane by lane
+                    int at = fill;
+#pragma unroll
+                    for (int kk = 0; kk < kThreads / 64; ++kk) {
+                        const int c = sgrp[j * (kThreads / 64) + kk];
+                        at += (kk < wv) ? c : 0;
+                        fill += c;
+                    }
+                    if (take[j]) lst[at + __popcll(mt[j] & below)] = v[j];
+                }
+                if (fill > kAccList - G * kThreads) {  // no room for another step's points
+                    __syncthreads();
+                    accum_list<K>(m, lst, fill, x0, y0, acc);
+                    fill = 0;  // the next writes to the list follow two barriers
+                }
+            }
+        }
+        __syncthreads();
+        accum_list<K>(m, lst, fill, x0, y0, acc);
+        __syncthreads();
+        for (int i = tid; i < kAccSide * kAccSide; i += kThreads) {
+            const int gi = x0 + i % kAccSide, gj = y0 + i / kAccSide;
+            if (gi < m.nx && gj < m.ny) m.out[(int64_t)gj * m.nx + gi] = (float)((double)acc[i] * unit);
+        }
+    }
+}
+
 template <int K, int kMaxRc>
 __device__ __forceinline__ void run_shape(const BMap &m, const BItem &w, const BatchLaunch &b, float2 *sp,
-                                          int *swave, int *slist, int *s_last) {
+                                          int *swave, int *slist, int *s_last, unsigned long long *acc,
+                                          int *sgrp) {
+    if constexpr (K != kGaussian) {
+        constexpr int kG = kMaxRc < 8 ? kAccGroup : 1;  // the general variant has no registers to spare
+        if (tile::accum_footprint_fits(m.Hx, m.Hy)) {  // compact items are whole tiles over all the points
+            if (m.rc == 2)
+                run_accum_item<K, 2, kG>(m, w, b, acc, sp, swave, slist, sgrp);
+            else if (kMaxRc < 8 || m.rc == 4)
+                run_accum_item<K, 4, kG>(m, w, b, acc, sp, swave, slist, sgrp);
+            else
+                run_accum_item<K, kMaxRc, kG>(m, w, b, acc, sp, swave, slist, sgrp);
+            return;
+        }
+    }
     if constexpr (kMaxRc < 8) {  // lean variant: register blocks of side 2 and 4 only
         if (m.rc == 2)
             run_item<K, 2, false>(m, w, b, sp, swave, slist, s_last);
@@ -191,12 +316,14 @@ __device__ __forceinline__ void run_shape(const BMap &m, const BItem &w, const B
 // paths and the 8 x 8 blocks that set the register count of the general one,
 // so that more workgroups fit on a CU.
 template <bool kLean>
-__global__ __launch_bounds__(kThreads) void batched_kernel(BatchLaunch b) {
+__global__ __launch_bounds__(kThreads, 2) void batched_kernel(BatchLaunch b) {  // at least 2 waves per SIMD
     constexpr int R = kLean ? 4 : 8;
-    __shared__ float2 sp[kPointTile];
+    __shared__ float2 sp[kAccList];  // point tile of the gather items, point list of the accumulating ones
     __shared__ int swave[kThreads / 64];
     __shared__ int slist[kThreads];
+    __shared__ int sgrp[kAccGroup * (kThreads / 64)];
     __shared__ int s_item, s_last;
+    __shared__ unsigned long long acc[kAccSide * kAccSide];
     for (;;) {
         __syncthreads();  // every thread has read the previous s_item
         if (threadIdx.x == 0) s_item = atomicAdd(b.counter, 1);
@@ -206,16 +333,16 @@ __global__ __launch_bounds__(kThreads) void batched_kernel(BatchLaunch b) {
         const BItem w = b.items[it];
         const BMap m = b.maps[w.map];
         switch (m.kernel) {
-        case kUniform: run_shape<kUniform, R>(m, w, b, sp, swave, slist, &s_last); break;
-        case kTriangular: run_shape<kTriangular, R>(m, w, b, sp, swave, slist, &s_last); break;
-        case kEpanechnikov: run_shape<kEpanechnikov, R>(m, w, b, sp, swave, slist, &s_last); break;
-        case kQuartic: run_shape<kQuartic, R>(m, w, b, sp, swave, slist, &s_last); break;
-        case kTriweight: run_shape<kTriweight, R>(m, w, b, sp, swave, slist, &s_last); break;
-        case kTricube: run_shape<kTricube, R>(m, w, b, sp, swave, slist, &s_last); break;
+        case kUniform: run_shape<kUniform, R>(m, w, b, sp, swave, slist, &s_last, acc, sgrp); break;
+        case kTriangular: run_shape<kTriangular, R>(m, w, b, sp, swave, slist, &s_last, acc, sgrp); break;
+        case kEpanechnikov: run_shape<kEpanechnikov, R>(m, w, b, sp, swave, slist, &s_last, acc, sgrp); break;
+        case kQuartic: run_shape<kQuartic, R>(m, w, b, sp, swave, slist, &s_last, acc, sgrp); break;
+        case kTriweight: run_shape<kTriweight, R>(m, w, b, sp, swave, slist, &s_last, acc, sgrp); break;
+        case kTricube: run_shape<kTricube, R>(m, w, b, sp, swave, slist, &s_last, acc, sgrp); break;
         case kGaussian:
-            if constexpr (!kLean) run_shape<kGaussian, R>(m, w, b, sp, swave, slist, &s_last);
+            if constexpr (!kLean) run_shape<kGaussian, R>(m, w, b, sp, swave, slist, &s_last, acc, sgrp);
             break;
-        default: run_shape<kCosine, R>(m, w, b, sp, swave, slist, &s_last); break;
+        default: run_shape<kCosine, R>(m, w, b, sp, swave, slist, &s_last, acc, sgrp); break;
         }
     }
 }
@@ -234,8 +361,37 @@ struct Plan {
     int64_t n_slots = 0;  // floats of partial tiles
     int64_t n_boxes = 0;  // chunk boxes of the compact maps
     bool lean = true;     // no Gaussian map and no register block of side 8
-    std::string signature;  // item list and static map fields
 };
+
+// Everything a batch's item list and static map fields depend on: per map the
+// kernel, register-block side, grid and point count.  Pointers and the
+// bandwidth-dependent scalars are per-call values.
+std::string shape_key(const MapArgs *args, int n_maps) {
+    std::string k;
+    k.reserve((size_t)n_maps * 24);
+    for (int m = 0; m < n_maps; ++m) {
+        const int32_t st[4] = {args[m].kernel_id, args[m].rc, args[m].nx, args[m].ny};
+        k.append(reinterpret_cast<const char *>(st), sizeof st);
+        k.append(reinterpret_cast<const char *>(&args[m].n), sizeof args[m].n);
+    }
+    return k;
+}
+
+// The per-call map descriptors: the plan's static fields, this call's values.
+void fill_maps(const MapArgs *args, const std::vector<BMap> &tmpl, BMap *dst) {
+    for (size_t m = 0; m < tmpl.size(); ++m) {
+        BMap bm = tmpl[m];
+        const MapArgs &a = args[m];
+        bm.pts = a.pts;
+        bm.out = a.out;
+        bm.Hx = a.Hx;
+        bm.Hy = a.Hy;
+        bm.ax = a.ax;
+        bm.ay = a.ay;
+        bm.scale = a.scale;
+        dst[m] = bm;
+    }
+}
 
 Plan make_plan(const MapArgs *args, int n_maps) {
     Plan pl;
@@ -303,13 +459,6 @@ Plan make_plan(const MapArgs *args, int n_maps) {
     std::stable_sort(cs.begin(), cs.end(), [](const Costed &x, const Costed &y) { return x.cost > y.cost; });
     pl.items.reserve(cs.size());
     for (const auto &c : cs) pl.items.push_back(c.item);
-    // Signature: everything the captured launch depends on except the values
-    // re-uploaded each call (pointers, bandwidth-dependent scalars).
-    pl.signature.assign(reinterpret_cast<const char *>(pl.items.data()), pl.items.size() * sizeof(BItem));
-    for (const BMap &bm : pl.maps) {
-        const int32_t st[6] = {bm.kernel, bm.rc, bm.nx, bm.ny, bm.tiles_x, (int32_t)(bm.n & 0x7fffffff)};
-        pl.signature.append(reinterpret_cast<const char *>(st), sizeof st);
-    }
     return pl;
 }
 
@@ -352,8 +501,12 @@ int persistent_grid(int n_items) {
     return std::max(1, std::min(n_items, resident));
 }
 
-hipError_t enqueue(const Plan &pl, const Layout &L, const void *host_stage, char *dev, hipStream_t s) {
-    hipError_t e = hipMemcpyAsync(dev, host_stage, L.stage_bytes, hipMemcpyHostToDevice, s);
+// copy_bytes of the staging buffer go to the device first: the map descriptors
+// and item list (eager runs), or the map descriptors only (graph replays, whose
+// item list was uploaded when the graph was made).
+hipError_t enqueue(const Plan &pl, const Layout &L, const void *host_stage, size_t copy_bytes, char *dev,
+                   hipStream_t s) {
+    hipError_t e = hipMemcpyAsync(dev, host_stage, copy_bytes, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(zero_ints_kernel, dim3((L.n_counters + 255) / 256), dim3(256), 0, s,
                        reinterpret_cast<int *>(dev + L.counters_off), L.n_counters);
@@ -379,18 +532,16 @@ hipError_t enqueue(const Plan &pl, const Layout &L, const void *host_stage, char
     return hipGetLastError();
 }
 
-void fill_stage(const Plan &pl, const Layout &L, char *stage) {
-    std::memcpy(stage + L.maps_off, pl.maps.data(), pl.maps.size() * sizeof(BMap));
-    std::memcpy(stage + L.items_off, pl.items.data(), pl.items.size() * sizeof(BItem));
-}
-
-// A captured batch: device buffer, pinned staging buffer, executable graph.
+// A captured batch: device buffer (item list uploaded once), pinned staging
+// buffer of the map descriptors, executable graph, and the plan's static map
+// fields.
 struct Captured {
     char *dev = nullptr;
     char *stage = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;
     Layout L;
+    std::vector<BMap> maps;
     ~Captured() {
         if (done) (void)hipEventSynchronize(done);
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -409,14 +560,15 @@ hipError_t run_batched(const MapArgs *args, int n_maps, bool use_graph, void *ws
                        hipStream_t stream) {
     for (int m = 0; m < n_maps; ++m)
         if (!valid_rc(args[m].rc)) return hipErrorInvalidValue;
-    const Plan pl = make_plan(args, n_maps);
-    if (pl.items.empty()) return hipSuccess;
-    const Layout L = layout_of(pl);
     if (!use_graph) {
+        const Plan pl = make_plan(args, n_maps);
+        if (pl.items.empty()) return hipSuccess;
+        const Layout L = layout_of(pl);
         if (ws_bytes < L.total) return hipErrorInvalidValue;
         std::vector<char> stage(L.stage_bytes);
-        fill_stage(pl, L, stage.data());
-        hipError_t e = enqueue(pl, L, stage.data(), static_cast<char *>(ws_eager), stream);
+        std::memcpy(stage.data() + L.maps_off, pl.maps.data(), pl.maps.size() * sizeof(BMap));
+        std::memcpy(stage.data() + L.items_off, pl.items.data(), pl.items.size() * sizeof(BItem));
+        hipError_t e = enqueue(pl, L, stage.data(), L.stage_bytes, static_cast<char *>(ws_eager), stream);
         if (e != hipSuccess) return e;
         return hipStreamSynchronize(stream);  // the pageable staging buffer dies here
     }
@@ -424,19 +576,26 @@ hipError_t run_batched(const MapArgs *args, int n_maps, bool use_graph, void *ws
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     std::lock_guard<std::mutex> lock(g_mu);
-    auto &slot = g_graphs[{dev, pl.signature}];
+    auto &slot = g_graphs[{dev, shape_key(args, n_maps)}];
     if (!slot) {
+        const Plan pl = make_plan(args, n_maps);
+        if (pl.items.empty()) return hipSuccess;
         auto c = std::make_unique<Captured>();
-        c->L = L;
-        if ((e = hipMalloc(&c->dev, L.total)) != hipSuccess) return e;
-        if ((e = hipHostMalloc(&c->stage, L.stage_bytes, hipHostMallocDefault)) != hipSuccess) return e;
+        c->L = layout_of(pl);
+        c->maps = pl.maps;
+        const size_t map_bytes = pl.maps.size() * sizeof(BMap);
+        if ((e = hipMalloc(&c->dev, c->L.total)) != hipSuccess) return e;
+        if ((e = hipHostMalloc(&c->stage, map_bytes, hipHostMallocDefault)) != hipSuccess) return e;
         if ((e = hipEventCreateWithFlags(&c->done, hipEventDisableTiming)) != hipSuccess) return e;
+        if ((e = hipMemcpy(c->dev + c->L.items_off, pl.items.data(), pl.items.size() * sizeof(BItem),
+                           hipMemcpyHostToDevice)) != hipSuccess)
+            return e;
         hipStream_t cap = nullptr;
         if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess) return e;
         hipGraph_t graph = nullptr;
         e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            const hipError_t e1 = enqueue(pl, L, c->stage, c->dev, cap);
+            const hipError_t e1 = enqueue(pl, c->L, c->stage, map_bytes, c->dev, cap);
             e = hipStreamEndCapture(cap, &graph);
             if (e1 != hipSuccess) e = e1;
         }
@@ -450,7 +609,7 @@ hipError_t run_batched(const MapArgs *args, int n_maps, bool use_graph, void *ws
     // The previous replay's copy must have read the staging buffer before it is
     // overwritten.
     if ((e = hipEventSynchronize(c.done)) != hipSuccess) return e;
-    fill_stage(pl, c.L, c.stage);
+    fill_maps(args, c.maps, reinterpret_cast<BMap *>(c.stage));
     if ((e = hipGraphLaunch(c.exec, stream)) != hipSuccess) return e;
     return hipEventRecord(c.done, stream);
 }

@@ -218,6 +218,7 @@ struct GatherLaunch {
     int nx, ny, tiles_x, tiles;
     float *out;                // the map
     float *part;               // [items][TH][TW] partial tiles of tiles with several items
+    unsigned long long *part_fixed;  // the same memory, as fixed-point partial tiles (bin_accum_kernel)
     float scale;
 };
 
@@ -252,20 +253,15 @@ __global__ __launch_bounds__(tile::kThreads) void bin_gather_kernel(GatherLaunch
         tile::store_block<S::R, S::C>(tot, p.part + item * (S::TW * S::TH), S::TW, S::TH, ib - x0, jb - y0, 1.0f);
 }
 
-// Compact kernels with small supports: each binned point adds its own terms
-// g(s) g(t) at the nodes of its support inside the tile, instead of every
+// Compact kernels with small supports (tile::accum_applies): each binned point
+// adds its own terms to the tile in LDS (tile::accum_point), instead of every
 // thread of the tile testing every point (the gather above spends hundreds of
 // lane operations per in-support pair when the support covers a few percent of
-// the tile).  The tile accumulates in LDS as 64-bit fixed-point integers: each
-// FP32 term v in [0, 1] becomes round(v 2^32) and is added with an integer
-// atomic, so the sums are exact in the rounded terms and do not depend on the
-// order the points arrive in (n < 2^31 terms of at most 2^32 cannot overflow).
-// Each thread takes a contiguous run of the item's points, so that the lanes of
-// a wave work on distant stretches of the tracks and seldom hit one node at once.
-// A tile with one item writes scale * acc / 2^32 (one rounding), otherwise the
-// raw FP32 partial tile for item_reduce_kernel.  Nodes are tried from
-// floor(X - H) - 1 over floor(2 H) + 3 per axis with the factor's own support
-// test, so rounding of X - H never drops a node of the support.
+// the tile).  Each thread takes a contiguous run of the item's points, so that
+// the lanes of a wave work on distant stretches of the tracks and seldom hit one
+// node at once.  A tile with one item writes scale * acc / 2^32 (one rounding),
+// otherwise its fixed-point partial tile for item_reduce_fixed_kernel, so that
+// the map does not depend on how a tile's points are cut into items.
 template <int K, int RC>
 __global__ __launch_bounds__(tile::kThreads) void bin_accum_kernel(GatherLaunch p) {
     constexpr int TW = 16 * RC, TH = 16 * RC;
@@ -287,35 +283,18 @@ __global__ __launch_bounds__(tile::kThreads) void bin_accum_kernel(GatherLaunch 
     const int x0 = (t % p.tiles_x) * TW, y0 = (t / p.tiles_x) * TH;
     for (int i = tid; i < TW * TH; i += tile::kThreads) acc[i] = 0ull;
     __syncthreads();
-    const int rows = (int)floorf(2.0f * p.Hy) + 3, cols = (int)floorf(2.0f * p.Hx) + 3;
     const int64_t per = (hi - lo + tile::kThreads - 1) / tile::kThreads;
     const int64_t q0 = lo + per * tid, q1 = min(hi, q0 + per);
-    for (int64_t q = q0; q < q1; ++q) {
-        const float2 v = p.bins[q];  // registered in this tile: its support reaches the tile
-        const int j0 = (int)floorf(v.y - p.Hy) - 1, i0 = (int)floorf(v.x - p.Hx) - 1;
-        for (int r = 0; r < rows; ++r) {
-            const int j = j0 + r;
-            if (j < y0 || j >= y0 + TH || j >= p.ny) continue;
-            const float ty = tile::factor<K>((float)j - v.y, p.ay, p.Hy);
-            if (!(ty > 0.0f)) continue;
-            for (int c = 0; c < cols; ++c) {
-                const int i = i0 + c;
-                if (i < x0 || i >= x0 + TW || i >= p.nx) continue;
-                // the compact factors are >= 0; the FP32 cosine at the support edge can
-                // round to a tiny negative, which the clamp turns into the exact 0
-                const float w = fmaxf(ty * tile::factor<K>((float)i - v.x, p.ax, p.Hx), 0.0f);
-                if (w > 0.0f) atomicAdd(&acc[(j - y0) * TW + (i - x0)], __float2ull_rn(w * 4294967296.0f));
-            }
-        }
-    }
+    for (int64_t q = q0; q < q1; ++q)  // binned in this tile: the support reaches it
+        tile::accum_point<K, TW, TH>(p.bins[q], x0, y0, p.nx, p.ny, p.Hx, p.Hy, p.ax, p.ay, acc);
     __syncthreads();
-    const double raw = 1.0 / 4294967296.0;
+    const double raw = 1.0 / (double)tile::kFixedOne;
     for (int i = tid; i < TW * TH; i += tile::kThreads) {
         const int gi = x0 + i % TW, gj = y0 + i / TW;
         if (parts == 1) {
             if (gi < p.nx && gj < p.ny) p.out[(int64_t)gj * p.nx + gi] = (float)((double)acc[i] * (raw * p.scale));
         } else {
-            p.part[item * (TW * TH) + i] = (float)((double)acc[i] * raw);
+            p.part_fixed[item * (TW * TH) + i] = acc[i];
         }
     }
 }
@@ -334,6 +313,24 @@ __global__ __launch_bounds__(256) void item_reduce_kernel(const float *__restric
         float s = 0.0f;
         for (int64_t it = i0; it < i1; ++it) s += part[it * (tw * th) + e];
         if (i < nx && j < ny) out[(int64_t)j * nx + i] = s * scale;
+    }
+}
+
+// The same for fixed-point partial tiles: integer sums, then one rounding.
+__global__ __launch_bounds__(256) void item_reduce_fixed_kernel(const unsigned long long *__restrict__ part,
+                                                                const unsigned *__restrict__ item_off, int tw, int th,
+                                                                int tiles_x, int nx, int ny, float scale,
+                                                                float *__restrict__ out) {
+    const int t = blockIdx.x;
+    const int64_t i0 = item_off[t], i1 = item_off[t + 1];
+    if (i1 - i0 <= 1) return;
+    const int x0 = (t % tiles_x) * tw, y0 = (t / tiles_x) * th;
+    const double raw = 1.0 / (double)tile::kFixedOne;
+    for (int e = threadIdx.x; e < tw * th; e += blockDim.x) {
+        const int i = x0 + e % tw, j = y0 + e / tw;
+        unsigned long long s = 0ull;
+        for (int64_t it = i0; it < i1; ++it) s += part[it * (tw * th) + e];
+        if (i < nx && j < ny) out[(int64_t)j * nx + i] = (float)((double)s * (raw * scale));
     }
 }
 
@@ -371,28 +368,18 @@ BinPlan bin_plan(const MapArgs &a, int T) {
     pl.bins_bytes = (size_t)pl.max_entries * sizeof(float2);
     pl.item_bytes = (size_t)(tiles + 1) * sizeof(unsigned);
     pl.item_totals_bytes = scan_u32_totals_bytes(tiles + 1);
-    pl.part_bytes = (size_t)pl.max_items * T * T * sizeof(float);
+    const bool fixed = T == 16 * a.rc && tile::accum_applies(a.kernel_id, a.rc, a.Hx, a.Hy);
+    pl.part_bytes = (size_t)pl.max_items * T * T * (fixed ? sizeof(unsigned long long) : sizeof(float));
     return pl;
 }
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-// Compact kernels whose support is tried over at most this many nodes per point
-// (floor(2 Hx) + 3) (floor(2 Hy) + 3) accumulate per point (bin_accum_kernel) on
-// tiles of side 32 or 64; larger supports and tiles take the gather.
-constexpr int kAccumMaxFootprint = 121;
-
-bool accum_applies(int kernel_id, int rc, float Hx, float Hy) {
-    if (kernel_id == kGaussian || kernel_id == kGaussTrunc || rc > 4) return false;
-    const int64_t foot = (int64_t)(std::floor(2.0 * (double)Hx) + 3) * (int64_t)(std::floor(2.0 * (double)Hy) + 3);
-    return foot <= kAccumMaxFootprint;
-}
-
 template <int K, int RC>
 hipError_t launch_gather_r(const GatherLaunch &p, int64_t items, hipStream_t s) {
     main_kernel_begin(s);
     if constexpr (K != kGaussian && K != kGaussTrunc && RC <= 4) {
-        if (accum_applies(K, RC, p.Hx, p.Hy)) {
+        if (tile::accum_applies(K, RC, p.Hx, p.Hy)) {
             hipLaunchKernelGGL((bin_accum_kernel<K, RC>), dim3((unsigned)items), dim3(tile::kThreads), 0, s, p);
             main_kernel_end(s);
             return hipGetLastError();
@@ -524,6 +511,7 @@ hipError_t launch_binned(const MapArgs &a, void *ws, hipStream_t s) {
     p.tiles = tiles;
     p.out = a.out;
     p.part = part;
+    p.part_fixed = reinterpret_cast<unsigned long long *>(part);
     p.scale = a.scale;
     switch (a.kernel_id) {
     case kUniform: e = launch_gather<kUniform>(p, a.rc, pl.max_items, s); break;
@@ -537,8 +525,13 @@ hipError_t launch_binned(const MapArgs &a, void *ws, hipStream_t s) {
     default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(item_reduce_kernel, dim3((unsigned)tiles), dim3(256), 0, s, part,
-                       static_cast<const unsigned *>(item_off), T, T, pl.g.tiles_x, a.nx, a.ny, a.scale, a.out);
+    if (tile::accum_applies(a.kernel_id, a.rc, a.Hx, a.Hy))  // the same test as launch_gather_r
+        hipLaunchKernelGGL(item_reduce_fixed_kernel, dim3((unsigned)tiles), dim3(256), 0, s,
+                           static_cast<const unsigned long long *>(p.part_fixed),
+                           static_cast<const unsigned *>(item_off), T, T, pl.g.tiles_x, a.nx, a.ny, a.scale, a.out);
+    else
+        hipLaunchKernelGGL(item_reduce_kernel, dim3((unsigned)tiles), dim3(256), 0, s, part,
+                           static_cast<const unsigned *>(item_off), T, T, pl.g.tiles_x, a.nx, a.ny, a.scale, a.out);
     return hipGetLastError();
 }
 

@@ -249,6 +249,46 @@ __device__ __forceinline__ void tile_sums_boxed(const float2 *__restrict__ pts, 
     }
 }
 
+// Fixed-point accumulation of compact kernels with small supports (support
+// binning and batched tiles): a point adds its own terms g(s) g(t) at the nodes
+// of its support inside a TW x TH tile at (x0, y0), as round(v 2^32) with 64-bit
+// integer atomics into acc (LDS), so the sums are exact in the rounded terms and
+// independent of the order the points arrive in (n < 2^31 terms of at most
+// 2^32 cannot overflow).  Nodes are tried from floor(X - H) - 1 over
+// floor(2 H) + 3 per axis with the factor's own support test, so rounding of
+// X - H never drops a node of the support; the tile's nodes past the grid
+// (nx, ny) are skipped.  The point's support must reach the tile (its
+// coordinates then convert to int safely).
+constexpr float kFixedOne = 4294967296.0f;  // 2^32
+constexpr int kAccumMaxFootprint = 121;     // nodes tried per point, at most
+
+__host__ __device__ inline bool accum_footprint_fits(float Hx, float Hy) {
+    if (!(Hx > 0.0f && Hy > 0.0f && Hx < 64.0f && Hy < 64.0f)) return false;  // NaN fails; int conversions safe
+    return ((int)floorf(2.0f * Hx) + 3) * ((int)floorf(2.0f * Hy) + 3) <= kAccumMaxFootprint;
+}
+
+__host__ __device__ inline bool accum_applies(int kernel_id, int rc, float Hx, float Hy) {
+    return kernel_id != kGaussian && kernel_id != kGaussTrunc && rc <= 4 && accum_footprint_fits(Hx, Hy);
+}
+
+template <int K, int TW, int TH>
+__device__ __forceinline__ void accum_point(float2 v, int x0, int y0, int nx, int ny, float Hx, float Hy, float ax,
+                                            float ay, unsigned long long *acc) {
+    const int j0 = (int)floorf(v.y - Hy) - 1, i0 = (int)floorf(v.x - Hx) - 1;
+    const int jlo = max(j0, y0), jhi = min(min(j0 + (int)floorf(2.0f * Hy) + 3, y0 + TH), ny);
+    const int ilo = max(i0, x0), ihi = min(min(i0 + (int)floorf(2.0f * Hx) + 3, x0 + TW), nx);
+    for (int j = jlo; j < jhi; ++j) {
+        const float ty = factor<K>((float)j - v.y, ay, Hy);
+        if (!(ty > 0.0f)) continue;
+        for (int i = ilo; i < ihi; ++i) {
+            // the compact factors are >= 0; the FP32 cosine at the support edge can
+            // round to a tiny negative, which the clamp turns into the exact 0
+            const float w = fmaxf(ty * factor<K>((float)i - v.x, ax, Hx), 0.0f);
+            if (w > 0.0f) atomicAdd(&acc[(j - y0) * TW + (i - x0)], __float2ull_rn(w * kFixedOne));
+        }
+    }
+}
+
 // Register-block shape: R x C = RC x RC per thread, so a workgroup covers a
 // 16 RC x 16 RC pixel tile.  Larger blocks amortise each factor over more FMAs;
 // smaller tiles waste fewer evaluations on pixels outside a compact kernel's

@@ -60,6 +60,45 @@ def test_small_mixed_batch_matches_separate_and_oracle(eager):
         assert kt.peak_error(y, ro) <= kt.FP32_GATE, s
 
 
+@pytest.mark.parametrize("eager", [True, False])
+def test_small_support_compact_maps_equal_kde_eval_bit_for_bit(eager):
+    """Compact maps whose supports span at most 121 nodes sum in 64-bit fixed
+    point in both paths (support-binned items in kde_eval, chunk-box tiles in the
+    batch), so the maps agree bit for bit whatever tile sides the two take: the
+    batch with 32-, 64- and 128-node tiles against kde_eval with 32-node tiles.
+    The 64 x 64 map puts about 5000 points in each tile, which kde_eval cuts into
+    several items; one map is anisotropic and one sits at the footprint limit."""
+    import math
+    import torch
+    t, grids, units = _pool(100)
+    units[1024] = kde.to_grid_units(t.xy, grids[1024])
+    rows = [(0, 20000, 64, 0.02, 0.02, 0), (5000, 12000, 100, 0.01, 0.01, 2), (0, 30000, 256, 0.005, 0.005, 7),
+            (10000, 25000, 512, 0.003, 0.003, 5), (20000, 30000, 1024, 0.0043, 0.0043, 4),
+            (3000, 9000, 512, 0.004, 0.002, 1), (40000, 8000, 256, 0.006, 0.006, 3)]
+    for (_, _, side, hx, hy, _) in rows:  # every map takes the fixed-point path
+        Hx, Hy = kde.bandwidth_units(hx, hy, grids[side])
+        assert (math.floor(2 * Hx) + 3) * (math.floor(2 * Hy) + 3) <= 121
+    pts = [kt.to_device(units[side][a:a + n]) for (a, n, side, _, _, _) in rows]
+    try:
+        kde.autotune(force=2)
+        refs = [kde.eval(p, k, hx, hy, grids[side]).cpu().numpy()
+                for p, (_, _, side, hx, hy, k) in zip(pts, rows)]
+        for rc in (2, 4, 8):
+            kde.autotune(force=rc)
+            maps = [(p, k, hx, hy, grids[side], torch.full((side, side), float("nan"), device=kt.device()))
+                    for p, (_, _, side, hx, hy, k) in zip(pts, rows)]
+            kde.eval_batched(maps, eager=eager)
+            torch.cuda.synchronize()
+            for m, r, row in zip(maps, refs, rows):
+                np.testing.assert_array_equal(m[5].cpu().numpy(), r, err_msg=f"tile side {16 * rc}, map {row}")
+    finally:
+        kde.autotune(force=0)
+    a, n, side, hx, hy, k = rows[0]
+    og = oracle.Grid(*grids[side].bounds, side, side)
+    ro = kt.oracle_density_window(units[side][a:a + n], k, hx, hy, og, (0, side, 0, side), separable=True)
+    assert kt.peak_error(refs[0].astype(np.float64), ro) <= kt.FP32_GATE
+
+
 def test_graph_replays_track_new_inputs():
     """Same batch shape three times with different points and bandwidth-dependent
     scales (same grids and counts): every replay equals separate calls; eager
