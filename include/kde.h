@@ -181,9 +181,11 @@ typedef struct kde_map {
  * stream: the Gaussian maps of each matrix-core precision (bandwidths of at
  * least 1.05 node spacings, n > 0) as one launch of the contraction kernel over
  * all their tiles and point splits, the rest (truncated Gaussians, narrower
- * bandwidths) as individual launches of the kde_eval path; each map is split
- * and summed exactly as kde_eval splits and sums it, so these outputs equal
- * kde_eval's bit for bit.  A small table of the maps goes up from one of a few
+ * bandwidths) as individual launches of the kde_eval path.  The batched
+ * Gaussian maps fill the GPU together, so a map's points are split only as far
+ * as its share of the batch's work asks for (never further than kde_eval
+ * splits them): its output equals kde_eval's up to the FP32 order of the split
+ * sums; the individual launches equal kde_eval's bit for bit.  A small table of the maps goes up from one of a few
  * pinned buffers the library keeps per device until kde_shutdown().  Every
  * descriptor is validated before anything is launched; output
  * buffers must not overlap each other or any point buffer.  By default the

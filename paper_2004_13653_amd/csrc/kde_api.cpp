@@ -571,28 +571,31 @@ int kde_eval_batched(const kde_map *maps, int32_t n_maps, uint32_t flags, void *
             hipError_t e = kde::run_batched(args.data(), (int)args.size(), !eager, ws, bytes, s);
             if (e != hipSuccess) return hip_fail(e, "kde_eval_batched");
         }
-        // Dense Gaussian maps on the matrix cores: one launch per precision.
-        std::vector<kde::MapArgs> dense[KDE_BF16X3_SEP + 1];
+        // Dense Gaussian maps on the matrix cores: one launch per precision and
+        // kernel (multiplicative runs, or every factor evaluated).
+        std::vector<kde::MapArgs> dense[2][KDE_BF16X3_SEP + 1];
         std::vector<int32_t> rest;
         for (int32_t m : single) {
             const kde_map &d = maps[m];
             if (d.precision != KDE_FP32_DIRECT && !(d.flags & KDE_TRUNCATE) && d.n > 0) {
                 kde::MapArgs a = make_args(d.points, d.n, d.kernel_id, d.hx, d.hy, d.grid, d.out, flags);
-                if (kde::sep_dense_batchable(a)) {
-                    dense[d.precision].push_back(a);
+                if (const int kind = kde::sep_dense_batchable(a)) {
+                    dense[kind - 1][d.precision].push_back(a);
                     continue;
                 }
             }
             rest.push_back(m);
         }
-        for (int prec = KDE_FP16_SEP; prec <= KDE_BF16X3_SEP; ++prec) {
-            const std::vector<kde::MapArgs> &v = dense[prec];
-            if (v.empty()) continue;
-            void *ws = nullptr;
-            int st = get_workspace(s, kde::sep_dense_batch_bytes(v.data(), (int)v.size(), prec), &ws);
-            if (st != KDE_OK) return st;
-            hipError_t e = kde::launch_sep_dense_batch(v.data(), (int)v.size(), prec, ws, s);
-            if (e != hipSuccess) return hip_fail(e, "kde_eval_batched");
+        for (int kind = 0; kind < 2; ++kind) {
+            for (int prec = KDE_FP16_SEP; prec <= KDE_BF16X3_SEP; ++prec) {
+                const std::vector<kde::MapArgs> &v = dense[kind][prec];
+                if (v.empty()) continue;
+                void *ws = nullptr;
+                int st = get_workspace(s, kde::sep_dense_batch_bytes(v.data(), (int)v.size(), prec), &ws);
+                if (st != KDE_OK) return st;
+                hipError_t e = kde::launch_sep_dense_batch(v.data(), (int)v.size(), prec, kind == 0, ws, s);
+                if (e != hipSuccess) return hip_fail(e, "kde_eval_batched");
+            }
         }
         for (int32_t m : rest) {
             const kde_map &d = maps[m];

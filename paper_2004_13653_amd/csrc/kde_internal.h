@@ -152,14 +152,19 @@ hipError_t run_metrics(const MetricsArgs &a, void *ws, hipStream_t stream, Metri
 hipError_t launch_sep(const MapArgs &a, int precision, void *ws, hipStream_t stream);
 size_t sep_workspace_bytes(const MapArgs &a, int precision);
 
-// Dense Gaussian maps of one matrix-core precision (sep_dense_batchable: the
-// 8-wave kernel's multiplicative runs apply) in one launch of that kernel, plus
-// one padding and one split-reduction launch for all of them; each map's
-// result equals launch_sep's bit for bit.  ws holds sep_dense_batch_bytes; the
-// map table goes up from a library-owned pinned buffer (release_dense_stage).
-bool sep_dense_batchable(const MapArgs &a);
+// Dense Gaussian maps of one matrix-core precision in one launch of the 8-wave
+// kernel (runs true: sep_dense_batchable 1, the multiplicative runs apply) or
+// of the kernel that evaluates every factor (runs false: 2, narrower
+// bandwidths), plus one padding and one split-reduction launch for all of
+// them.  A map's points are split only as far as its share of the batch's work
+// asks for, never further than launch_sep splits them, so a result equals
+// launch_sep's up to the FP32 order of the split sums.  ws holds
+// sep_dense_batch_bytes; the map table goes up from a library-owned pinned
+// buffer (release_dense_stage).  sep_dense_batchable is 0 for other maps.
+int sep_dense_batchable(const MapArgs &a);
 size_t sep_dense_batch_bytes(const MapArgs *maps, int n, int precision);
-hipError_t launch_sep_dense_batch(const MapArgs *maps, int n, int precision, void *ws, hipStream_t stream);
+hipError_t launch_sep_dense_batch(const MapArgs *maps, int n, int precision, bool runs, void *ws,
+                                  hipStream_t stream);
 void release_dense_stage();
 
 // Batched maps (FP32 direct path) in one persistent launch; use_graph captures

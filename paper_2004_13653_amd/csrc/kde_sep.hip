@@ -228,8 +228,37 @@ __device__ __forceinline__ void generate_chunk(const SepLaunch &p, const float2 
     gen_slice<K, P>(px, mcol0, ga_x, p.Hx, p.ix, Bhi, Blo, word0, Cfg::kRowWords);
 }
 
-template <int K, int P>
-__global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p) {
+// A batch of dense maps in one launch: map m owns workgroups [wg0, wg0 + tiles
+// x splits) of the grid (tile fastest), found by binary search.
+struct DenseEntry {
+    SepLaunch p;          // dst: the map (one split) or its partial planes
+    int64_t wg0;          // first workgroup of the map
+    int64_t tiles;
+    int splits;           // point splits of the map
+    // padding: split s of the map's points -> p.pts + s * p.pad_stride
+    const float2 *src;
+    int64_t pad0;         // first padded point of the map in the batch's padded array
+    // split reduction (maps with more than one split; 0 cells otherwise)
+    int64_t red0;         // first cell of the map in the batch's reduction range
+    float *out;
+};
+
+__device__ __forceinline__ int find_entry(const DenseEntry *e, int n, int64_t key, int which) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        const int64_t v = which == 0 ? e[mid].wg0 : which == 1 ? e[mid].pad0 : e[mid].red0;
+        if (v <= key) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// kBatch: one launch over the maps of a DenseEntry table (dense Gaussian maps
+// too narrow for multiplicative runs); p is then each workgroup's entry's.
+template <int K, int P, bool kBatch>
+__global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p, const DenseEntry *__restrict__ batch,
+                                                                 int n_batch) {
     using Cfg = SepConfig<P>;
     constexpr bool kBf16 = PrecTraits<P>::kBf16;
     constexpr int W = Cfg::kWords;
@@ -242,12 +271,26 @@ __global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // Dense: tile blockIdx.x, point split blockIdx.y.  Banded: the item's tile
     // and points (workgroups past the last item leave at once).
-    const bool banded = p.items != nullptr;
+    bool one_split = gridDim.y == 1;  // a single point split: write the map scaled
+    int bm = 0;                       // the workgroup's entry (kBatch)
+    if constexpr (kBatch) {
+        bm = find_entry(batch, n_batch, blockIdx.x, 0);
+        p = batch[bm].p;
+        one_split = batch[bm].splits == 1;
+    }
+    const bool banded = !kBatch && p.items != nullptr;
     int tile_idx = blockIdx.x;
     int64_t split = 0;
     int64_t count;
     const float2 *qbase;
-    if (banded) {
+    if constexpr (kBatch) {  // the item's tile and split, tile fastest
+        const int64_t local = (int64_t)blockIdx.x - batch[bm].wg0;
+        tile_idx = (int)(local % batch[bm].tiles);
+        split = local / batch[bm].tiles;
+        const int64_t beg = split * p.per_split;
+        count = min(p.n, beg + p.per_split) - beg;
+        qbase = p.pts + split * p.pad_stride;
+    } else if (banded) {
         if ((int)blockIdx.x >= *p.n_items) return;
         const SepItem it = p.items[blockIdx.x];
         tile_idx = it.tile;
@@ -358,7 +401,7 @@ __global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p) {
         return;
     }
     float *dst = p.dst + split * p.plane;
-    const float sc = gridDim.y == 1 ? p.scale : 1.0f;
+    const float sc = one_split ? p.scale : 1.0f;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
 #pragma unroll
@@ -392,32 +435,6 @@ __global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p) {
 // workgroup taking its map's arguments from a table (DenseEntry) instead of the
 // kernel argument; every map is split and summed as its own launch would.
 constexpr int kThreads8 = 512;
-
-// A batch of dense maps in one launch: map m owns workgroups [wg0, wg0 + tiles
-// x splits) of the grid (tile fastest), found by binary search.
-struct DenseEntry {
-    SepLaunch p;          // dst: the map (one split) or its partial planes
-    int64_t wg0;          // first workgroup of the map
-    int64_t tiles;
-    int splits;           // point splits of the map
-    // padding: split s of the map's points -> p.pts + s * p.pad_stride
-    const float2 *src;
-    int64_t pad0;         // first padded point of the map in the batch's padded array
-    // split reduction (maps with more than one split; 0 cells otherwise)
-    int64_t red0;         // first cell of the map in the batch's reduction range
-    float *out;
-};
-
-__device__ __forceinline__ int find_entry(const DenseEntry *e, int n, int64_t key, int which) {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) / 2;
-        const int64_t v = which == 0 ? e[mid].wg0 : which == 1 ? e[mid].pad0 : e[mid].red0;
-        if (v <= key) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
 
 // pad_points_kernel over every map of the batch.
 __global__ __launch_bounds__(256) void pad_batch_kernel(const DenseEntry *__restrict__ e, int n, int64_t total,
@@ -658,13 +675,15 @@ struct SepPlan {
     size_t partial_bytes; // split partial planes (0 with one split), 256-byte aligned
 };
 
-SepPlan sep_plan(const MapArgs &a, int kc) {
+// max_splits caps the point splits (maps of a batch, which fill the GPU together).
+SepPlan sep_plan(const MapArgs &a, int kc, int64_t max_splits = INT64_MAX) {
     SepPlan pl;
     pl.tiles_x = (a.nx + kTile - 1) / kTile;
     pl.tiles = pl.tiles_x * ((a.ny + kTile - 1) / kTile);
     // One 4-wave workgroup per CU (256 CUs); at least 4 chunks per split.
     int64_t splits = std::max<int64_t>(1, 256 / pl.tiles);
     splits = std::min<int64_t>(splits, std::max<int64_t>(1, a.n / (4 * kc)));
+    splits = std::max<int64_t>(1, std::min<int64_t>(splits, max_splits));
     int64_t per = (a.n + splits - 1) / splits;
     per = (per + kc - 1) / kc * kc;
     pl.splits = (int)std::max<int64_t>(1, (a.n + per - 1) / per);
@@ -742,7 +761,8 @@ hipError_t launch_sep_kp(const MapArgs &a, const SepPlan &pl, const float2 *padd
         }
     }
     main_kernel_begin(stream);
-    hipLaunchKernelGGL((sep_mfma_kernel<K, P>), grid, dim3(kThreadsSep), 0, stream, p);
+    hipLaunchKernelGGL((sep_mfma_kernel<K, P, false>), grid, dim3(kThreadsSep), 0, stream, p,
+                       static_cast<const DenseEntry *>(nullptr), 0);
     main_kernel_end(stream);
     return hipGetLastError();
 }
@@ -997,14 +1017,23 @@ struct DenseLayout {
     size_t table_bytes = 0, padded_off = 0, part_off = 0, total = 0;
 };
 
+// Point splits in a batch: the maps fill the GPU together, so a map is split
+// only as far as its share of the batch's (point, tile) work asks for, about
+// kBatchWgs workgroups in all, never further than alone (split partial planes
+// cost a write and a read of the map each).
+constexpr int64_t kBatchWgs = 1024;
+
 DenseLayout dense_layout(const MapArgs *maps, int n, int precision) {
     DenseLayout L;
     const int kc = chunk_for(precision);
     L.entries.resize(n);
+    double work = 0.0;  // (point, tile) pairs of the batch
+    for (int m = 0; m < n; ++m) work += (double)maps[m].n * (double)sep_plan(maps[m], kc).tiles;
+    const double per_wg = std::max(4.0 * kc, work / (double)kBatchWgs);  // points per workgroup
     size_t part = 0;
     for (int m = 0; m < n; ++m) {
         const MapArgs &a = maps[m];
-        const SepPlan pl = sep_plan(a, kc);
+        const SepPlan pl = sep_plan(a, kc, (int64_t)std::ceil((double)a.n / per_wg));
         DenseEntry &e = L.entries[m];
         e.wg0 = L.wgs;
         e.tiles = pl.tiles;
@@ -1044,23 +1073,28 @@ DenseLayout dense_layout(const MapArgs *maps, int n, int precision) {
 }
 
 template <int P>
-hipError_t launch_dense_batch_p(const DenseEntry *dev, int n, const DenseLayout &L, hipStream_t s) {
-    hipLaunchKernelGGL((sep_mfma8_kernel<P, true>), dim3((unsigned)L.wgs), dim3(kThreads8), 0, s, SepLaunch{}, dev, n);
+hipError_t launch_dense_batch_p(const DenseEntry *dev, int n, const DenseLayout &L, bool runs, hipStream_t s) {
+    if (runs)
+        hipLaunchKernelGGL((sep_mfma8_kernel<P, true>), dim3((unsigned)L.wgs), dim3(kThreads8), 0, s, SepLaunch{},
+                           dev, n);
+    else
+        hipLaunchKernelGGL((sep_mfma_kernel<kGaussian, P, true>), dim3((unsigned)L.wgs), dim3(kThreadsSep), 0, s,
+                           SepLaunch{}, dev, n);
     return hipGetLastError();
 }
 
 }  // namespace
 
-bool sep_dense_batchable(const MapArgs &a) {
-    return a.kernel_id == kGaussian && a.n > 0 && arg_scale(kGaussian, a.Hx) <= kMaxRunScale &&
-           arg_scale(kGaussian, a.Hy) <= kMaxRunScale;
+int sep_dense_batchable(const MapArgs &a) {
+    if (a.kernel_id != kGaussian || a.n <= 0) return 0;
+    return arg_scale(kGaussian, a.Hx) <= kMaxRunScale && arg_scale(kGaussian, a.Hy) <= kMaxRunScale ? 1 : 2;
 }
 
 size_t sep_dense_batch_bytes(const MapArgs *maps, int n, int precision) {
     return n > 0 ? dense_layout(maps, n, precision).total : 0;
 }
 
-hipError_t launch_sep_dense_batch(const MapArgs *maps, int n, int precision, void *ws, hipStream_t s) {
+hipError_t launch_sep_dense_batch(const MapArgs *maps, int n, int precision, bool runs, void *ws, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     DenseLayout L = dense_layout(maps, n, precision);
     char *w = static_cast<char *>(ws);
@@ -1096,10 +1130,10 @@ hipError_t launch_sep_dense_batch(const MapArgs *maps, int n, int precision, voi
                        L.padded, reinterpret_cast<float2 *>(w + L.padded_off));
     if ((err = hipGetLastError()) != hipSuccess) return err;
     switch (precision) {
-    case kPrecFp16: err = launch_dense_batch_p<kPrecFp16>(table, n, L, s); break;
-    case kPrecBf16: err = launch_dense_batch_p<kPrecBf16>(table, n, L, s); break;
-    case kPrecFp16x3: err = launch_dense_batch_p<kPrecFp16x3>(table, n, L, s); break;
-    case kPrecBf16x3: err = launch_dense_batch_p<kPrecBf16x3>(table, n, L, s); break;
+    case kPrecFp16: err = launch_dense_batch_p<kPrecFp16>(table, n, L, runs, s); break;
+    case kPrecBf16: err = launch_dense_batch_p<kPrecBf16>(table, n, L, runs, s); break;
+    case kPrecFp16x3: err = launch_dense_batch_p<kPrecFp16x3>(table, n, L, runs, s); break;
+    case kPrecBf16x3: err = launch_dense_batch_p<kPrecBf16x3>(table, n, L, runs, s); break;
     default: return hipErrorInvalidValue;
     }
     if (err != hipSuccess || L.cells == 0) return err;

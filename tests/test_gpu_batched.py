@@ -122,6 +122,9 @@ def test_graph_replays_track_new_inputs():
 
 
 PREC_GATE = {"fp32": ("e_inf", kt.FP32_GATE), "fp16": ("e_2", 2e-3), "bf16x3": ("e_2", 2e-3)}
+# Batched matrix-core maps against kde_eval: the same products, summed over
+# fewer point splits (FP32 accumulation in another order).
+SPLIT_ORDER_GATE = 1e-5
 
 
 def _window_points(pool, spec):
@@ -150,8 +153,9 @@ def test_batch_of_256_time_windows():
     [1k, 200k], each Douglas-Peucker-compressed at a threshold from {0, 10, 50,
     100} m, grids from {256^2, 512^2, 1024^2}, h ~ U(0.001, 0.008) degrees,
     kernels uniform over the eight; Gaussian maps on the matrix cores.  Every map
-    against a separate kde_eval call of its precision (bit-identical for the
-    matrix-core maps), and for every precision some maps against the oracle at
+    against a separate kde_eval call of its precision (the matrix-core maps
+    split their points more coarsely in the batch: equal up to the FP32 order of
+    the split sums), and for every precision some maps against the oracle at
     sampled pixels, each at its precision's gate."""
     import torch
     t = kt.lanes(8000, 500, 2)
@@ -181,7 +185,7 @@ def test_batch_of_256_time_windows():
             worst = max(worst, e)
             assert e <= 2e-6, (k, s)
         else:
-            np.testing.assert_array_equal(y, r)
+            assert kt.peak_error(y, r) <= SPLIT_ORDER_GATE, (k, s)
         if checked[prec] < 3 and (prec != "fp32" or k % 32 == 0):
             checked[prec] += 1
             yy = y.astype(np.float64)
@@ -200,7 +204,8 @@ def test_batch_of_256_time_windows():
 def test_mixed_precision_batch(eager):
     """FP32, matrix-core and truncated maps in one call: the persistent launch
     for the FP32 maps, the others one by one after it; each equals kde_eval of
-    its precision (bit for bit for the single launches), empty maps are zero."""
+    its precision (bit for bit for the single launches, up to the order of the
+    split sums for the batched matrix-core Gaussian maps), empty maps are zero."""
     import torch
     t, grids, units = _pool(100)
     cases = [(synth.MapSpec(100, 20000, 256, 0.004, 6), "fp16", False),
@@ -227,18 +232,21 @@ def test_mixed_precision_batch(eager):
         ref = kde.eval(pts, kernel, hx, hy, g, precision=prec, truncate=trunc).cpu().numpy()
         if prec == "fp32" and not trunc:
             assert kt.peak_error(y, ref) <= 2e-6, (s, prec)
+        elif kernel == 6 and not trunc:
+            assert kt.peak_error(y, ref) <= SPLIT_ORDER_GATE, (s, prec)
         else:
             np.testing.assert_array_equal(y, ref)
 
 
 @pytest.mark.parametrize("eager", [True, False])
 def test_dense_gaussian_maps_share_one_launch(eager):
-    """Several Gaussian maps per matrix-core precision go out as one launch of
-    the contraction kernel (plus one padding and one split-reduction launch):
-    maps of one and of several point splits, one to nine 256-node tiles, ragged
-    grids, and a bandwidth too narrow for multiplicative runs (which takes the
-    single-map path) in the same call.  Each map equals kde_eval bit for bit,
-    and sampled maps match the oracle at their precision's gate."""
+    """The Gaussian maps of each matrix-core precision go out as one launch of
+    the contraction kernel with multiplicative runs, and those too narrow for
+    runs as one launch of the kernel that evaluates every factor (plus one
+    padding and one split-reduction launch each): maps of one and of several
+    point splits, one to sixteen 256-node tiles, ragged grids.  Each map equals
+    kde_eval up to the order of the split sums, and sampled maps match the
+    oracle at their precision's gate."""
     import torch
     t, grids, units = _pool(100)
     cases = []
@@ -246,7 +254,7 @@ def test_dense_gaussian_maps_share_one_launch(eager):
         cases += [(synth.MapSpec(0, 45000, 512, 0.003, 6), prec),    # four tiles, several splits
                   (synth.MapSpec(2000, 300, 100, 0.02, 6), prec),    # one ragged tile, one split
                   (synth.MapSpec(7000, 9000, 1024, 0.002, 6), prec),  # sixteen tiles
-                  (synth.MapSpec(100, 5000, 256, 0.0004, 6), prec)]  # H < 1.05 px: no runs, single path
+                  (synth.MapSpec(100, 5000, 256, 0.0004, 6), prec)]  # H < 1.05 px: no runs, the other kernel
     maps = []
     for s, prec in cases:
         XY = units[s.side][s.start:s.start + s.count]
@@ -257,7 +265,7 @@ def test_dense_gaussian_maps_share_one_launch(eager):
         torch.cuda.synchronize()
         for (s, prec), (pts, kernel, hx, hy, g, out, _) in zip(cases, maps):
             ref = kde.eval(pts, kernel, hx, hy, g, precision=prec).cpu().numpy()
-            np.testing.assert_array_equal(out.cpu().numpy(), ref, err_msg=f"{s} {prec}")
+            assert kt.peak_error(out.cpu().numpy(), ref) <= SPLIT_ORDER_GATE, (s, prec)
     og = oracle.Grid(*grids[100].bounds, 100, 100)
     for k in (1, 5, 9, 13):  # the 100 x 100 map of every precision
         s, prec = cases[k]
@@ -265,6 +273,15 @@ def test_dense_gaussian_maps_share_one_launch(eager):
                                      (0, 100, 0, 100))
         e = oracle.errors(maps[k][5].cpu().numpy().astype(np.float64).ravel(), r.ravel())
         kt.log(f"{prec}: e_2 {e['e_2']:.2e} e_inf {e['e_inf']:.2e}")
+        assert e["e_2"] <= 2e-3, (s, prec, e)
+    og = oracle.Grid(*grids[256].bounds, 256, 256)
+    for k in (3, 7, 11, 15):  # the narrow 256 x 256 map of every precision, at sampled pixels
+        s, prec = cases[k]
+        y = maps[k][5].cpu().numpy().astype(np.float64)
+        ij = kt.sample_pixels(y, 64, seed=k)
+        r = kt.oracle_density_at(units[256][s.start:s.start + s.count], 6, s.h_deg, s.h_deg, og, ij)
+        e = oracle.errors(y[ij[:, 1], ij[:, 0]], r)
+        kt.log(f"{prec} narrow: e_2 {e['e_2']:.2e} e_inf {e['e_inf']:.2e}")
         assert e["e_2"] <= 2e-3, (s, prec, e)
 
 
