@@ -159,7 +159,7 @@ __device__ __forceinline__ void run_item(const BMap &m, const BItem &w, const Ba
 }
 
 // Compact maps whose supports span few nodes (tile::accum_footprint_fits): the
-// item's tile is taken as kAccSide x kAccSide sub-tiles.  For each, the chunks
+// item's tile is taken as sub-tiles of side at most kAccMaxSide.  For each, the chunks
 // whose box reaches it are listed; their points are read (coalesced) and those
 // whose support can reach the sub-tile are gathered into a list in LDS, which,
 // when nearly full, is worked through point by point: each adds its own terms
@@ -168,17 +168,17 @@ __device__ __forceinline__ void run_item(const BMap &m, const BItem &w, const Ba
 // kde_eval's support-binned maps bit for bit.  In the list, the lanes of a wave
 // take entries kThreads / 64 apart (list entries keep track order), so that they
 // seldom start in one node at once and their atomics seldom collide.
-constexpr int kAccSide = 32;
+constexpr int kAccMaxSide = 32;
 constexpr int kAccGroup = 4;    // listed chunks read per step
 constexpr int kAccList = 2048;  // float2 entries; the point tile of the gather items shares the array
 
-template <int K>
+template <int K, int AS>
 __device__ __forceinline__ void accum_list(const BMap &m, const float2 *lst, int cnt, int x0, int y0,
                                            unsigned long long *acc) {
     const int spread = (threadIdx.x & 63) * (kThreads / 64) + (threadIdx.x >> 6);
     for (int e0 = 0; e0 < cnt; e0 += kThreads) {
         const int e = e0 + spread;
-        if (e < cnt) tile::accum_point<K, kAccSide, kAccSide>(lst[e], x0, y0, m.nx, m.ny, m.Hx, m.Hy, m.ax, m.ay, acc);
+        if (e < cnt) tile::accum_point<K, AS, AS>(lst[e], x0, y0, m.nx, m.ny, m.Hx, m.Hy, m.ax, m.ay, acc);
     }
 }
 
@@ -186,8 +186,8 @@ template <int K, int RC, int G>
 __device__ __forceinline__ void run_accum_item(const BMap &m, const BItem &w, const BatchLaunch &b,
                                                unsigned long long *acc, float2 *lst, int *swave, int *slist,
                                                int *sgrp) {
-    constexpr int TS = 16 * RC, NS = TS / kAccSide;
-    static_assert(NS >= 1 && TS % kAccSide == 0, "tile side must be a multiple of the accumulation side");
+    constexpr int TS = 16 * RC, AS = TS < kAccMaxSide ? TS : kAccMaxSide, NS = TS / AS;
+    static_assert(TS % AS == 0, "tile side must be a multiple of the accumulation side");
     static_assert(kPointTile == kThreads && G <= kAccGroup && kAccList >= 2 * G * kThreads, "one point per thread per chunk");
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const uint64_t below = (1ull << lane) - 1ull;
@@ -196,14 +196,14 @@ __device__ __forceinline__ void run_accum_item(const BMap &m, const BItem &w, co
     const float4 *boxes = b.boxes + m.box0;
     const double unit = (1.0 / (double)tile::kFixedOne) * m.scale;
     for (int sub = 0; sub < NS * NS; ++sub) {
-        const int x0 = tx * TS + (sub % NS) * kAccSide, y0 = ty * TS + (sub / NS) * kAccSide;
+        const int x0 = tx * TS + (sub % NS) * AS, y0 = ty * TS + (sub / NS) * AS;
         if (x0 >= m.nx || y0 >= m.ny) continue;  // uniform: the sub-tile lies past the grid
         // Points reaching the sub-tile lie within H + 1 of its nodes (the margin
         // of one node covers the rounding of the factors' support tests).
-        const float lx = (float)x0 - m.Hx - 1.0f, hx = (float)(min(x0 + kAccSide, m.nx) - 1) + m.Hx + 1.0f;
-        const float ly = (float)y0 - m.Hy - 1.0f, hy = (float)(min(y0 + kAccSide, m.ny) - 1) + m.Hy + 1.0f;
+        const float lx = (float)x0 - m.Hx - 1.0f, hx = (float)(min(x0 + AS, m.nx) - 1) + m.Hx + 1.0f;
+        const float ly = (float)y0 - m.Hy - 1.0f, hy = (float)(min(y0 + AS, m.ny) - 1) + m.Hy + 1.0f;
         __syncthreads();  // the previous sub-tile has been written out
-        for (int i = tid; i < kAccSide * kAccSide; i += kThreads) acc[i] = 0ull;
+        for (int i = tid; i < AS * AS; i += kThreads) acc[i] = 0ull;
         int fill = 0;  // list entries (the same in every thread)
         for (int64_t g0 = 0; g0 < nch; g0 += kThreads) {
             const int64_t c = g0 + tid;
@@ -253,16 +253,16 @@ __device__ __forceinline__ void run_accum_item(const BMap &m, const BItem &w, co
                 }
                 if (fill > kAccList - G * kThreads) {  // no room for another step's points
                     __syncthreads();
-                    accum_list<K>(m, lst, fill, x0, y0, acc);
+                    accum_list<K, AS>(m, lst, fill, x0, y0, acc);
                     fill = 0;  // the next writes to the list follow two barriers
                 }
             }
         }
         __syncthreads();
-        accum_list<K>(m, lst, fill, x0, y0, acc);
+        accum_list<K, AS>(m, lst, fill, x0, y0, acc);
         __syncthreads();
-        for (int i = tid; i < kAccSide * kAccSide; i += kThreads) {
-            const int gi = x0 + i % kAccSide, gj = y0 + i / kAccSide;
+        for (int i = tid; i < AS * AS; i += kThreads) {
+            const int gi = x0 + i % AS, gj = y0 + i / AS;
             if (gi < m.nx && gj < m.ny) m.out[(int64_t)gj * m.nx + gi] = (float)((double)acc[i] * unit);
         }
     }
@@ -323,7 +323,7 @@ __global__ __launch_bounds__(kThreads, 2) void batched_kernel(BatchLaunch b) {  
     __shared__ int slist[kThreads];
     __shared__ int sgrp[kAccGroup * (kThreads / 64)];
     __shared__ int s_item, s_last;
-    __shared__ unsigned long long acc[kAccSide * kAccSide];
+    __shared__ unsigned long long acc[kAccMaxSide * kAccMaxSide];
     for (;;) {
         __syncthreads();  // every thread has read the previous s_item
         if (threadIdx.x == 0) s_item = atomicAdd(b.counter, 1);
