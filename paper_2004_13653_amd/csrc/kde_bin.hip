@@ -12,18 +12,22 @@
 //               (tile, wave block) its first slot (the paper's work-efficient
 //               scan pattern, Sec. IV-A: per-block scans, a scan of the block
 //               totals, then a propagation pass);
-//   3. scatter: one wave per block walks its points 64 at a time, and each
-//               64's tiles in a fixed order, assigning slots with ballots (lanes
-//               with the same tile take consecutive slots in lane order), so the
-//               bin contents and their order (point order) are the same on every
-//               run;
-//   4. gather:  each tile's bin is cut into items of at most M entries (dense
+//   3. scatter: for the gather, one wave per block walks its points 64 at a
+//               time, and each 64's tiles in a fixed order, assigning slots with
+//               ballots (lanes with the same tile take consecutive slots in lane
+//               order), so the bin contents and their order (point order) are
+//               the same on every run; for the fixed-point accumulation, whose
+//               sums do not depend on order, one thread per point takes its
+//               slots with atomics on the same table;
+//   4. items:   each tile's bin is cut into items of at most M entries (dense
 //               tiles, e.g. at anchorages, get many; M from the bound on all
-//               entries, aiming at ~2048 items), one workgroup per item sums it
-//               with the register-tiled kernel of the direct path (no culling
-//               needed; the per-pair support test remains); a tile with one item
-//               writes the map directly, the others write partial tiles that a
-//               last pass adds in item order.
+//               entries, aiming at ~2048 items), one workgroup per item;
+//   5. sums:    small compact supports accumulate per point in 64-bit fixed
+//               point (bin_accum_kernel), the others are gathered with the
+//               register-tiled kernel of the direct path (no culling needed;
+//               the per-pair support test remains); a tile with one item writes
+//               the map directly, the others write partial tiles that a last
+//               pass adds in item order (as integers for the fixed point).
 #include "kde_tile.h"
 
 #include <algorithm>
@@ -192,21 +196,79 @@ __global__ __launch_bounds__(256) void bin_scatter_kernel(BinGeom g, const float
     }
 }
 
+
 // Items: item_off[t] (exclusive prefix over tiles, item_off[tiles] = all items)
 // is the first item of tile t; tile t's bin is cut into item_off[t+1] -
-// item_off[t] equal parts.
-__global__ __launch_bounds__(256) void item_count_kernel(const unsigned *__restrict__ end, int64_t wblocks, int tiles,
-                                                         int64_t per_item, unsigned *__restrict__ cnt) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t > tiles) return;
-    if (t == tiles) {
-        cnt[t] = 0u;
-        return;
+// item_off[t] = max(1, ceil(bin length / per_item)) equal parts.  One
+// workgroup, from the scanned (tile, column) table, whose last column of tile t
+// ends t's bin after the scatter.
+constexpr int kItemScan = 1024;
+
+__global__ __launch_bounds__(kItemScan) void item_scan_kernel(const unsigned *__restrict__ end, int64_t wblocks,
+                                                              int tiles, int64_t per_item,
+                                                              unsigned *__restrict__ item_off) {
+    __shared__ unsigned si[kItemScan];
+    const int tid = threadIdx.x;
+    unsigned carry = 0u;
+    for (int base = 0; base < tiles; base += kItemScan) {
+        const int t = base + tid;
+        unsigned it = 0u;
+        if (t < tiles) {
+            const int64_t e = end[(int64_t)t * wblocks + wblocks - 1];
+            const int64_t b = t > 0 ? (int64_t)end[(int64_t)t * wblocks - 1] : 0;
+            const int64_t need = (e - b + per_item - 1) / per_item;
+            it = (unsigned)(need > 1 ? need : 1);
+        }
+        si[tid] = it;
+        __syncthreads();
+        for (int off = 1; off < kItemScan; off <<= 1) {  // inclusive Hillis-Steele
+            const unsigned a = tid >= off ? si[tid - off] : 0u;
+            __syncthreads();
+            si[tid] += a;
+            __syncthreads();
+        }
+        if (t < tiles) item_off[t] = carry + si[tid] - it;
+        carry += si[kItemScan - 1];
+        __syncthreads();  // every thread has read the total before the next chunk
     }
-    const int64_t e = end[(int64_t)t * wblocks + wblocks - 1];
-    const int64_t b = t > 0 ? (int64_t)end[(int64_t)t * wblocks - 1] : 0;
-    const int64_t c = (e - b + per_item - 1) / per_item;
-    cnt[t] = (unsigned)(c > 1 ? c : 1);
+    if (tid == 0) item_off[tiles] = carry;
+}
+
+// Order-free scatter, for the fixed-point accumulation (whose sums do not
+// depend on the order of a tile's points): one thread per point takes slots
+// from the scanned (tile, column) table with atomics, the lanes of a wave that
+// register in one tile sharing one.  Only the waves of one 1024-point column
+// touch its entries, and the table ends as the ordered scatter leaves it.
+__global__ __launch_bounds__(256) void bin_scatter_free_kernel(BinGeom g, const float2 *__restrict__ pts,
+                                                               unsigned *__restrict__ off,
+                                                               float2 *__restrict__ bins) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    if (p - lane >= g.n) return;  // whole wave past the end
+    const int64_t w = p / kColBlock;  // the wave's column (kColBlock is a multiple of 64)
+    const uint64_t below = (1ull << lane) - 1ull;
+    const bool valid = p < g.n;
+    const float2 v = valid ? pts[p] : make_float2(0.0f, 0.0f);
+    int tx0 = 1, tx1 = 0, ty0 = 1, ty1 = 0;
+    if (valid) reach(g, v, tx0, tx1, ty0, ty1);
+    const int ncols = tx1 >= tx0 ? tx1 - tx0 + 1 : 0;
+    const int ntl = ncols > 0 && ty1 >= ty0 ? ncols * (ty1 - ty0 + 1) : 0;
+    int most = ntl;
+    for (int o = 32; o > 0; o >>= 1) most = max(most, __shfl_xor(most, o));
+    for (int j = 0; j < most; ++j) {
+        const int key = j < ntl ? (ty0 + j / ncols) * g.tiles_x + tx0 + j % ncols : -1;
+        uint64_t pending = __ballot(key >= 0);
+        while (pending) {
+            const int leader = __ffsll((unsigned long long)pending) - 1;
+            const int lkey = __shfl(key, leader);
+            const uint64_t same = __ballot(key == lkey);
+            unsigned slot = 0;
+            if (lane == leader) slot = atomicAdd(&off[(int64_t)lkey * g.wblocks + w], (unsigned)__popcll(same));
+            slot = __shfl(slot, leader);
+            if (key == lkey) bins[slot + (unsigned)__popcll(same & below)] = v;
+            pending &= ~same;
+        }
+    }
 }
 
 struct GatherLaunch {
@@ -338,7 +400,7 @@ struct BinPlan {
     BinGeom g;
     int64_t cnt_len, scan_blocks, max_entries;
     int64_t per_item, max_items;
-    size_t off_bytes, totals_bytes, bins_bytes, item_bytes, item_totals_bytes, part_bytes;
+    size_t off_bytes, totals_bytes, bins_bytes, item_bytes, part_bytes;
 };
 
 BinPlan bin_plan(const MapArgs &a, int T) {
@@ -367,7 +429,6 @@ BinPlan bin_plan(const MapArgs &a, int T) {
     pl.totals_bytes = (size_t)(pl.scan_blocks + 1) * sizeof(unsigned);
     pl.bins_bytes = (size_t)pl.max_entries * sizeof(float2);
     pl.item_bytes = (size_t)(tiles + 1) * sizeof(unsigned);
-    pl.item_totals_bytes = scan_u32_totals_bytes(tiles + 1);
     const bool fixed = T == 16 * a.rc && tile::accum_applies(a.kernel_id, a.rc, a.Hx, a.Hy);
     pl.part_bytes = (size_t)pl.max_items * T * T * (fixed ? sizeof(unsigned long long) : sizeof(float));
     return pl;
@@ -408,7 +469,7 @@ hipError_t launch_gather(const GatherLaunch &p, int rc, int64_t items, hipStream
 // Count, scan and scatter into workspace ws (layout: counts/ends, scan totals,
 // bins); the bins then hold each tile's points contiguously, in tile order.
 hipError_t scatter_bins(const MapArgs &a, const BinPlan &pl, char *w, unsigned **off_out, float2 **bins_out,
-                        hipStream_t s) {
+                        hipStream_t s, bool ordered = true) {
     unsigned *off = reinterpret_cast<unsigned *>(w);
     unsigned *totals = reinterpret_cast<unsigned *>(w + align256(pl.off_bytes));
     float2 *bins = reinterpret_cast<float2 *>(w + align256(pl.off_bytes) + align256(pl.totals_bytes));
@@ -419,8 +480,12 @@ hipError_t scatter_bins(const MapArgs &a, const BinPlan &pl, char *w, unsigned *
     hipLaunchKernelGGL(scan_totals_kernel, dim3(1), dim3(256), 0, s, totals, pl.scan_blocks);
     hipLaunchKernelGGL(scan_add_kernel, dim3((unsigned)((pl.cnt_len + 255) / 256)), dim3(256), 0, s, off,
                        pl.cnt_len, static_cast<const unsigned *>(totals));
-    hipLaunchKernelGGL(bin_scatter_kernel, dim3((unsigned)((pl.g.wblocks + 3) / 4)), dim3(256), 0, s, pl.g, a.pts,
-                       off, bins);
+    if (ordered)
+        hipLaunchKernelGGL(bin_scatter_kernel, dim3((unsigned)((pl.g.wblocks + 3) / 4)), dim3(256), 0, s, pl.g,
+                           a.pts, off, bins);
+    else
+        hipLaunchKernelGGL(bin_scatter_free_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, pl.g,
+                           a.pts, off, bins);
     *off_out = off;
     *bins_out = bins;
     return hipGetLastError();
@@ -454,7 +519,7 @@ bool binning_applies(const MapArgs &a) {
 
 size_t binned_workspace_bytes(const MapArgs &a) {
     const BinPlan pl = bin_plan(a, 16 * a.rc);
-    return scatter_bytes(pl) + align256(pl.item_bytes) + align256(pl.item_totals_bytes) + pl.part_bytes;
+    return scatter_bytes(pl) + align256(pl.item_bytes) + pl.part_bytes;
 }
 
 bool tile_bins_fit(const MapArgs &a, int tile) {
@@ -484,18 +549,17 @@ hipError_t launch_binned(const MapArgs &a, void *ws, hipStream_t s) {
     const int T = 16 * a.rc;
     char *w = static_cast<char *>(ws);
     unsigned *item_off = reinterpret_cast<unsigned *>(w + scatter_bytes(pl));
-    unsigned *item_totals = reinterpret_cast<unsigned *>(w + scatter_bytes(pl) + align256(pl.item_bytes));
-    float *part = reinterpret_cast<float *>(w + scatter_bytes(pl) + align256(pl.item_bytes) +
-                                            align256(pl.item_totals_bytes));
+    float *part = reinterpret_cast<float *>(w + scatter_bytes(pl) + align256(pl.item_bytes));
     unsigned *off = nullptr;
     float2 *bins = nullptr;
-    hipError_t e = scatter_bins(a, pl, w, &off, &bins, s);
+    // The fixed-point accumulation does not need a tile's points in order.
+    const bool fixed = tile::accum_applies(a.kernel_id, a.rc, a.Hx, a.Hy);
+    hipError_t e = scatter_bins(a, pl, w, &off, &bins, s, !fixed);
     if (e != hipSuccess) return e;
     const int tiles = pl.g.tiles_x * pl.g.tiles_y;
-    hipLaunchKernelGGL(item_count_kernel, dim3((unsigned)((tiles + 1 + 255) / 256)), dim3(256), 0, s, off,
+    hipLaunchKernelGGL(item_scan_kernel, dim3(1), dim3(kItemScan), 0, s, static_cast<const unsigned *>(off),
                        pl.g.wblocks, tiles, pl.per_item, item_off);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = launch_scan_u32(item_off, tiles + 1, item_totals, s)) != hipSuccess) return e;
     GatherLaunch p;
     p.bins = bins;
     p.end = off;
@@ -525,7 +589,7 @@ hipError_t launch_binned(const MapArgs &a, void *ws, hipStream_t s) {
     default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
-    if (tile::accum_applies(a.kernel_id, a.rc, a.Hx, a.Hy))  // the same test as launch_gather_r
+    if (fixed)  // the same test as launch_gather_r
         hipLaunchKernelGGL(item_reduce_fixed_kernel, dim3((unsigned)tiles), dim3(256), 0, s,
                            static_cast<const unsigned long long *>(p.part_fixed),
                            static_cast<const unsigned *>(item_off), T, T, pl.g.tiles_x, a.nx, a.ny, a.scale, a.out);
