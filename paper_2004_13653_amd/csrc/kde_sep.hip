@@ -436,28 +436,50 @@ __global__ __launch_bounds__(kThreadsSep, 1) void sep_mfma_kernel(SepLaunch p, c
 // kernel argument; every map is split and summed as its own launch would.
 constexpr int kThreads8 = 512;
 
+// The entry of element i, starting from entry m (elements of a workgroup lie in
+// one or a few consecutive entries: one search per workgroup, then steps).
+__device__ __forceinline__ int advance_entry(const DenseEntry *e, int n, int64_t i, int m, int which) {
+    while (m + 1 < n && (which == 1 ? e[m + 1].pad0 : e[m + 1].red0) <= i) ++m;
+    return m;
+}
+
 // pad_points_kernel over every map of the batch.
 __global__ __launch_bounds__(256) void pad_batch_kernel(const DenseEntry *__restrict__ e, int n, int64_t total,
                                                         float2 *__restrict__ padded) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ int s_m;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x, i = i0 + threadIdx.x;
+    if (threadIdx.x == 0) s_m = find_entry(e, n, i0, 1);
+    __syncthreads();
     if (i >= total) return;
-    const int m = find_entry(e, n, i, 1);
+    const int m = advance_entry(e, n, i, s_m, 1);
     const SepLaunch &p = e[m].p;
     const int64_t k0 = i - e[m].pad0, s = k0 / p.pad_stride, k = k0 - s * p.pad_stride;
     const int64_t q = s * p.per_split + k;
     padded[i] = (k < p.per_split && q < p.n) ? e[m].src[q] : make_float2(kFar, kFar);
 }
 
-// reduce_splits_kernel over the maps of the batch with more than one split.
+// reduce_splits_kernel over the maps of the batch with more than one split,
+// kReduceCells cells per workgroup.
+constexpr int kReduceCells = 1024;
+
 __global__ __launch_bounds__(256) void reduce_batch_kernel(const DenseEntry *__restrict__ e, int n, int64_t total) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= total) return;
-    const int m = find_entry(e, n, i, 2);
-    const SepLaunch &p = e[m].p;
-    const int64_t c = i - e[m].red0;
-    float v = 0.0f;
-    for (int k = 0; k < e[m].splits; ++k) v += p.dst[(int64_t)k * p.plane + c];
-    e[m].out[c] = v * p.scale;
+    __shared__ int s_m;
+    const int64_t i0 = (int64_t)blockIdx.x * kReduceCells;
+    if (threadIdx.x == 0) s_m = find_entry(e, n, i0, 2);
+    __syncthreads();
+    int m = s_m;
+    for (int r = 0; r < kReduceCells / 256; ++r) {
+        const int64_t i = i0 + r * 256 + threadIdx.x;
+        if (i >= total) return;
+        m = advance_entry(e, n, i, m, 2);
+        const SepLaunch &p = e[m].p;
+        const int64_t c = i - e[m].red0;
+        const int splits = e[m].splits;
+        float v = 0.0f;
+#pragma unroll 8
+        for (int k = 0; k < splits; ++k) v += p.dst[(int64_t)k * p.plane + c];
+        e[m].out[c] = v * p.scale;
+    }
 }
 
 template <int P, bool kBatch>
@@ -1137,7 +1159,8 @@ hipError_t launch_sep_dense_batch(const MapArgs *maps, int n, int precision, boo
     default: return hipErrorInvalidValue;
     }
     if (err != hipSuccess || L.cells == 0) return err;
-    hipLaunchKernelGGL(reduce_batch_kernel, dim3((unsigned)((L.cells + 255) / 256)), dim3(256), 0, s, table, n,
+    hipLaunchKernelGGL(reduce_batch_kernel, dim3((unsigned)((L.cells + kReduceCells - 1) / kReduceCells)), dim3(256), 0,
+                       s, table, n,
                        L.cells);
     return hipGetLastError();
 }
