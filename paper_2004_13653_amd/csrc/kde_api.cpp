@@ -271,8 +271,16 @@ int pick_rc(kde::MapArgs a, hipStream_t s, int *rc_out) {
     return KDE_OK;
 }
 
-void set_batch_rc(std::vector<kde::MapArgs> &args, int rc_gauss, int rc_compact) {
-    for (kde::MapArgs &a : args) a.rc = a.kernel_id == KDE_GAUSSIAN ? rc_gauss : rc_compact;
+// Compact maps that a batch sums by fixed-point accumulation take tiles of side
+// 64 (one accumulation pass per item) unless a shape is pinned; the tuned side
+// applies to the other compact maps.
+constexpr int kRcAccumBatch = 4;
+
+void set_batch_rc(std::vector<kde::MapArgs> &args, int rc_gauss, int rc_compact, bool pinned = false) {
+    for (kde::MapArgs &a : args)
+        a.rc = a.kernel_id == KDE_GAUSSIAN                        ? rc_gauss
+               : !pinned && kde::batch_accumulates(a) ? kRcAccumBatch
+                                                      : rc_compact;
 }
 
 // Register-block sides for a batch (one for its Gaussian maps, one for its
@@ -282,7 +290,7 @@ void set_batch_rc(std::vector<kde::MapArgs> &args, int rc_gauss, int rc_compact)
 int pick_batch_rc(std::vector<kde::MapArgs> &args, bool eager, hipStream_t s) {
     const int forced = kde::tune::forced();
     if (forced) {
-        set_batch_rc(args, forced, forced);
+        set_batch_rc(args, forced, forced, true);
         return KDE_OK;
     }
     set_batch_rc(args, kRcGauss, kRcCompactBatch);

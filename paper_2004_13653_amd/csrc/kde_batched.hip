@@ -159,7 +159,9 @@ __device__ __forceinline__ void run_item(const BMap &m, const BItem &w, const Ba
 }
 
 // Compact maps whose supports span few nodes (tile::accum_footprint_fits): the
-// item's tile is taken as sub-tiles of side at most kAccMaxSide.  For each, the chunks
+// item's tile is taken as sub-tiles of side at most kAccMaxSide (such maps get
+// tiles of that side, so one pass; 32 in the general variant, which has no
+// registers to spare).  For each, the chunks
 // whose box reaches it are listed; their points are read (coalesced) and those
 // whose support can reach the sub-tile are gathered into a list in LDS, which,
 // when nearly full, is worked through point by point: each adds its own terms
@@ -168,9 +170,9 @@ __device__ __forceinline__ void run_item(const BMap &m, const BItem &w, const Ba
 // kde_eval's support-binned maps bit for bit.  In the list, the lanes of a wave
 // take entries kThreads / 64 apart (list entries keep track order), so that they
 // seldom start in one node at once and their atomics seldom collide.
-constexpr int kAccMaxSide = 32;
-constexpr int kAccGroup = 4;    // listed chunks read per step
-constexpr int kAccList = 2048;  // float2 entries; the point tile of the gather items shares the array
+constexpr int kAccMaxSide = 64;
+constexpr int kAccGroup = 1;    // listed chunks read per step
+constexpr int kAccList = 768;   // float2 entries; the point tile of the gather items shares the array
 
 template <int K, int AS>
 __device__ __forceinline__ void accum_list(const BMap &m, const float2 *lst, int cnt, int x0, int y0,
@@ -182,13 +184,15 @@ __device__ __forceinline__ void accum_list(const BMap &m, const float2 *lst, int
     }
 }
 
-template <int K, int RC, int G>
+template <int K, int RC, int G, int kMaxSide>
 __device__ __forceinline__ void run_accum_item(const BMap &m, const BItem &w, const BatchLaunch &b,
                                                unsigned long long *acc, float2 *lst, int *swave, int *slist,
                                                int *sgrp) {
-    constexpr int TS = 16 * RC, AS = TS < kAccMaxSide ? TS : kAccMaxSide, NS = TS / AS;
+    constexpr int TS = 16 * RC, AS = TS < kMaxSide ? TS : kMaxSide, NS = TS / AS;
+    static_assert(kMaxSide <= kAccMaxSide, "the accumulation tile holds kAccMaxSide^2 nodes");
     static_assert(TS % AS == 0, "tile side must be a multiple of the accumulation side");
-    static_assert(kPointTile == kThreads && G <= kAccGroup && kAccList >= 2 * G * kThreads, "one point per thread per chunk");
+    // one point per thread per chunk; a flushed list holds more than kThreads points
+    static_assert(kPointTile == kThreads && G <= kAccGroup && kAccList >= (G + 1) * kThreads, "list too short");
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const uint64_t below = (1ull << lane) - 1ull;
     const int tx = w.tile % m.tiles_x, ty = w.tile / m.tiles_x;
@@ -273,14 +277,15 @@ __device__ __forceinline__ void run_shape(const BMap &m, const BItem &w, const B
                                           int *swave, int *slist, int *s_last, unsigned long long *acc,
                                           int *sgrp) {
     if constexpr (K != kGaussian) {
-        constexpr int kG = kMaxRc < 8 ? kAccGroup : 1;  // the general variant has no registers to spare
-        if (tile::accum_footprint_fits(m.Hx, m.Hy)) {  // compact items are whole tiles over all the points
+        // the general variant has no registers to spare: one chunk a step, sub-tiles of 32
+        constexpr int kG = kMaxRc < 8 ? kAccGroup : 1, kSide = kMaxRc < 8 ? kAccMaxSide : 32;
+        if (tile::accum_footprint_fits(m.Hx, m.Hy)) {  // as batch_accumulates; whole-tile items over all points
             if (m.rc == 2)
-                run_accum_item<K, 2, kG>(m, w, b, acc, sp, swave, slist, sgrp);
+                run_accum_item<K, 2, kG, kSide>(m, w, b, acc, sp, swave, slist, sgrp);
             else if (kMaxRc < 8 || m.rc == 4)
-                run_accum_item<K, 4, kG>(m, w, b, acc, sp, swave, slist, sgrp);
+                run_accum_item<K, 4, kG, kSide>(m, w, b, acc, sp, swave, slist, sgrp);
             else
-                run_accum_item<K, kMaxRc, kG>(m, w, b, acc, sp, swave, slist, sgrp);
+                run_accum_item<K, kMaxRc, kG, kSide>(m, w, b, acc, sp, swave, slist, sgrp);
             return;
         }
     }
@@ -612,6 +617,10 @@ hipError_t run_batched(const MapArgs *args, int n_maps, bool use_graph, void *ws
     fill_maps(args, c.maps, reinterpret_cast<BMap *>(c.stage));
     if ((e = hipGraphLaunch(c.exec, stream)) != hipSuccess) return e;
     return hipEventRecord(c.done, stream);
+}
+
+bool batch_accumulates(const MapArgs &a) {
+    return a.kernel_id != kGaussian && tile::accum_footprint_fits(a.Hx, a.Hy);
 }
 
 size_t batched_workspace_bytes(const MapArgs *args, int n_maps) {

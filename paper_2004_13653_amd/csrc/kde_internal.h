@@ -167,6 +167,10 @@ hipError_t launch_sep_dense_batch(const MapArgs *maps, int n, int precision, boo
                                   hipStream_t stream);
 void release_dense_stage();
 
+// A compact map that the persistent launch sums by fixed-point accumulation
+// (supports spanning few nodes) rather than by the gather.
+bool batch_accumulates(const MapArgs &a);
+
 // Batched maps (FP32 direct path) in one persistent launch; use_graph captures
 // the launch sequence once per batch shape and replays it (ws unused then).
 hipError_t run_batched(const MapArgs *args, int n_maps, bool use_graph, void *ws_eager, size_t ws_bytes,
