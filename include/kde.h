@@ -173,29 +173,35 @@ typedef struct kde_map {
 } kde_map;
 
 /* Evaluates n_maps maps (host array of descriptors; not in the paper, which maps
- * one data set at a time).  The FP32 direct maps without KDE_TRUNCATE run in one
- * persistent launch: the batch is cut into (map, pixel tile, point range)
+ * one data set at a time).  The FP32 direct maps without KDE_TRUNCATE run in
+ * one persistent launch: the batch is cut into (map, pixel tile, point range)
  * items, longest first, pulled by persistent workgroups from an atomic counter;
  * each such map's output equals what kde_eval(..., KDE_FP32_DIRECT, ...)
- * computes up to FP32 rounding order.  The other maps follow on the same
- * stream: the Gaussian maps of each matrix-core precision (bandwidths of at
- * least 1.05 node spacings, n > 0) as one launch of the contraction kernel over
- * all their tiles and point splits, the rest (truncated Gaussians, narrower
- * bandwidths) as individual launches of the kde_eval path.  The batched
+ * computes up to FP32 rounding order, and bit for bit for compact kernels whose
+ * supports span at most 121 tried nodes, (floor(2Hx)+3)(floor(2Hy)+3) <= 121,
+ * with n >= 4096 and kde_eval on tiles of side 32 or 64 (its default): both
+ * paths sum those in 64-bit fixed point, exactly.  The other maps follow on the
+ * same stream: the Gaussian maps of each matrix-core precision (n > 0) as one
+ * launch of the contraction kernel over all their tiles and point splits
+ * (bandwidths of at least 1.05 node spacings, with multiplicative runs) and one
+ * of the kernel that evaluates every factor (narrower bandwidths), the
+ * truncated Gaussians as individual launches of the kde_eval path.  The batched
  * Gaussian maps fill the GPU together, so a map's points are split only as far
- * as its share of the batch's work asks for (never further than kde_eval
- * splits them): its output equals kde_eval's up to the FP32 order of the split
- * sums; the individual launches equal kde_eval's bit for bit.  A small table of the maps goes up from one of a few
- * pinned buffers the library keeps per device until kde_shutdown().  Every
- * descriptor is validated before anything is launched; output
- * buffers must not overlap each other or any point buffer.  By default the
- * persistent part's upload + launch sequence is captured into a hipGraph the
- * first time a batch shape (item list, kernels, grid sizes, point counts) is seen
- * and replayed afterwards; the library keeps one device buffer and pinned
- * staging buffer per captured shape until kde_shutdown().  A call on a shape that
- * is still running waits for that run to finish before reusing its staging
- * buffer.  flags: KDE_RAW_SUM, KDE_BATCH_EAGER (no graph; the call synchronises
- * `stream`). */
+ * as its share of the batch's work asks for (never further than kde_eval splits
+ * them): its output equals kde_eval's up to the FP32 order of the split sums;
+ * the individual launches equal kde_eval's bit for bit.  A small table of the
+ * Gaussian maps goes up from one of a few pinned buffers the library keeps per
+ * device until kde_shutdown().  Every descriptor is validated before anything
+ * is launched; output buffers must not overlap each other or any point buffer.
+ * By default the persistent part is captured into a hipGraph the first time a
+ * batch shape (per map: kernel, tile side, grid size, point count) is seen: its
+ * item list goes up once, and the graph copies the map descriptors (pointers,
+ * bandwidths) from a pinned staging buffer, then launches the kernels; later
+ * calls of the shape write the descriptors and replay it.  The library keeps
+ * one device buffer and pinned staging buffer per captured shape until
+ * kde_shutdown().  A call on a shape that is still running waits for that run
+ * to finish before reusing its staging buffer.  flags: KDE_RAW_SUM,
+ * KDE_BATCH_EAGER (no graph; the call synchronises `stream`). */
 int kde_eval_batched(const kde_map *maps, int32_t n_maps, uint32_t flags, void *stream);
 
 /* Adjoint of kde_eval (vector-Jacobian product; not in the paper).  Given
