@@ -331,3 +331,60 @@ def test_batch_shapes_are_tuned_once():
     assert kde.autotune() == ent
     for a, m in zip(first, maps):
         np.testing.assert_array_equal(a, m[5].cpu().numpy())
+
+
+@pytest.mark.parametrize("eager", [True, False])
+def test_non_finite_points_contribute_nothing_to_compact_maps(eager):
+    """Points with NaN or infinite coordinates add nothing to a compact map, as
+    kde_eval's contract states: with raw sums (no 1/n), the map of a point set
+    laced with them equals the map of its finite points, single and batched, on
+    the fixed-point path (small supports), the binned gather (large supports)
+    and the unbinned sums (n < 4096, and the batch's gather).  Bit for bit on
+    the fixed-point path, whose sums do not depend on order or grouping;
+    elsewhere the inserted points shift the 64-point scatter groups and the
+    256-point chunks, so the FP32 partial sums associate differently."""
+    import torch
+    t, grids, units = _pool(100)
+    rng = np.random.default_rng(17)
+    bad_vals = [np.nan, np.inf, -np.inf]
+    # (start, count, side, h, kernel, exact single, exact batched)
+    rows = [(0, 20000, 256, 0.005, 0, True, True),       # fixed point both ways (H = 1.3)
+            (3000, 12000, 512, 0.003, 7, True, True),    # fixed point both ways (H = 1.5)
+            (0, 20000, 256, 0.03, 7, False, False),      # binned gather; chunk-box gather (H = 7.7)
+            (5000, 9000, 100, 0.05, 3, False, False),    # the same on a ragged grid (H = 5.0)
+            (100, 3000, 256, 0.005, 2, False, True)]     # unbinned single map; fixed point batched
+    finite, laced = [], []
+    for (a, n, side, h, k, _, _) in rows:
+        XY = units[side][a:a + n].astype(np.float32)
+        bad = np.empty((n // 50, 2), np.float32)
+        for r in range(bad.shape[0]):  # one or both coordinates non-finite, the other in the grid
+            bad[r] = XY[rng.integers(0, n)]
+            which = rng.integers(0, 3)
+            if which != 1:
+                bad[r, 0] = bad_vals[rng.integers(0, 3)]
+            if which != 0:
+                bad[r, 1] = bad_vals[rng.integers(0, 3)]
+        mixed = np.insert(XY, rng.integers(0, n, bad.shape[0]), bad, axis=0)
+        finite.append(kt.to_device(XY))
+        laced.append(kt.to_device(mixed))
+    def same(got, ref, exact, what):
+        assert np.isfinite(got).all(), what
+        if exact:
+            np.testing.assert_array_equal(got, ref, err_msg=what)
+        else:
+            assert kt.peak_error(got, ref) <= 1e-6, what
+    for row, pf, pl in zip(rows, finite, laced):
+        a, n, side, h, k, exact, _ = row
+        ref = kde.eval(pf, k, h, h, grids[side], raw=True).cpu().numpy()
+        got = kde.eval(pl, k, h, h, grids[side], raw=True).cpu().numpy()
+        same(got, ref, exact, f"kde_eval {row}")
+    for pts in (finite, laced):
+        maps = [(p, k, h, h, grids[side], torch.full((side, side), float("nan"), device=kt.device()))
+                for p, (a, n, side, h, k, _, _) in zip(pts, rows)]
+        kde.eval_batched(maps, raw=True, eager=eager)
+        torch.cuda.synchronize()
+        if pts is finite:
+            ref_b = [m[5].cpu().numpy() for m in maps]
+        else:
+            for m, r, row in zip(maps, ref_b, rows):
+                same(m[5].cpu().numpy(), r, row[6], f"kde_eval_batched {row}")
