@@ -158,18 +158,20 @@ __device__ __forceinline__ void run_item(const BMap &m, const BItem &w, const Ba
     tile::store_block<S::R, S::C>(tot, m.out, m.nx, m.ny, ib, jb, m.scale);
 }
 
-// Compact maps whose supports span few nodes (tile::accum_footprint_fits): the
-// item's tile is taken as sub-tiles of side at most kAccMaxSide (such maps get
-// tiles of that side, so one pass; 32 in the general variant, which has no
-// registers to spare).  For each, the chunks
-// whose box reaches it are listed; their points are read (coalesced) and those
-// whose support can reach the sub-tile are gathered into a list in LDS, which,
-// when nearly full, is worked through point by point: each adds its own terms
-// (tile::accum_point) to a fixed-point tile in LDS.  Integer sums depend neither
-// on the order nor on the tiling the points come in, so these maps equal
-// kde_eval's support-binned maps bit for bit.  In the list, the lanes of a wave
-// take entries kThreads / 64 apart (list entries keep track order), so that they
-// seldom start in one node at once and their atomics seldom collide.
+// Compact maps whose supports span at most tile::kBatchAccumMaxFootprint tried
+// nodes (tile::accum_footprint_fits): the item's tile is taken as sub-tiles of
+// side at most kAccMaxSide (such maps get tiles of that side, so one pass; 32
+// in the general variant, which has no registers to spare).  For each, the
+// chunks whose box reaches it are listed; their points are read (coalesced)
+// and those whose support can reach the sub-tile are gathered into a list in
+// LDS, which, when nearly full, is worked through point by point: each adds its
+// own terms (tile::accum_point) to a fixed-point tile in LDS.  Integer sums
+// depend neither on the order nor on the tiling the points come in, so the maps
+// that kde_eval sums in fixed point too (supports of at most
+// tile::kAccumMaxFootprint nodes) equal its maps bit for bit.  In the list, the
+// lanes of a wave take entries kThreads / 64 apart (list entries keep track
+// order), so that they seldom start in one node at once and their atomics
+// seldom collide.
 constexpr int kAccMaxSide = 64;
 constexpr int kAccGroup = 1;    // listed chunks read per step
 constexpr int kAccList = 768;   // float2 entries; the point tile of the gather items shares the array
@@ -279,7 +281,8 @@ __device__ __forceinline__ void run_shape(const BMap &m, const BItem &w, const B
     if constexpr (K != kGaussian) {
         // the general variant has no registers to spare: one chunk a step, sub-tiles of 32
         constexpr int kG = kMaxRc < 8 ? kAccGroup : 1, kSide = kMaxRc < 8 ? kAccMaxSide : 32;
-        if (tile::accum_footprint_fits(m.Hx, m.Hy)) {  // as batch_accumulates; whole-tile items over all points
+        // as batch_accumulates; whole-tile items over all points
+        if (tile::accum_footprint_fits(m.Hx, m.Hy, tile::kBatchAccumMaxFootprint)) {
             if (m.rc == 2)
                 run_accum_item<K, 2, kG, kSide>(m, w, b, acc, sp, swave, slist, sgrp);
             else if (kMaxRc < 8 || m.rc == 4)
@@ -620,7 +623,7 @@ hipError_t run_batched(const MapArgs *args, int n_maps, bool use_graph, void *ws
 }
 
 bool batch_accumulates(const MapArgs &a) {
-    return a.kernel_id != kGaussian && tile::accum_footprint_fits(a.Hx, a.Hy);
+    return a.kernel_id != kGaussian && tile::accum_footprint_fits(a.Hx, a.Hy, tile::kBatchAccumMaxFootprint);
 }
 
 size_t batched_workspace_bytes(const MapArgs *args, int n_maps) {

@@ -262,9 +262,13 @@ __device__ __forceinline__ void tile_sums_boxed(const float2 *__restrict__ pts, 
 constexpr float kFixedOne = 4294967296.0f;  // 2^32
 constexpr int kAccumMaxFootprint = 121;     // nodes tried per point, at most
 
-__host__ __device__ inline bool accum_footprint_fits(float Hx, float Hy) {
+// Batched tiles: every item already lists the chunks that reach its tile, and
+// the gather there loses to the accumulation up to larger supports.
+constexpr int kBatchAccumMaxFootprint = 441;
+
+__host__ __device__ inline bool accum_footprint_fits(float Hx, float Hy, int limit = kAccumMaxFootprint) {
     if (!(Hx > 0.0f && Hy > 0.0f && Hx < 64.0f && Hy < 64.0f)) return false;  // NaN fails; int conversions safe
-    return ((int)floorf(2.0f * Hx) + 3) * ((int)floorf(2.0f * Hy) + 3) <= kAccumMaxFootprint;
+    return ((int)floorf(2.0f * Hx) + 3) * ((int)floorf(2.0f * Hy) + 3) <= limit;
 }
 
 __host__ __device__ inline bool accum_applies(int kernel_id, int rc, float Hx, float Hy) {
