@@ -178,9 +178,9 @@ typedef struct kde_map {
  * items, longest first, pulled by persistent workgroups from an atomic counter;
  * each such map's output equals what kde_eval(..., KDE_FP32_DIRECT, ...)
  * computes up to FP32 rounding order, and bit for bit for compact kernels whose
- * supports span at most 121 tried nodes, (floor(2Hx)+3)(floor(2Hy)+3) <= 121,
- * with n >= 4096 and kde_eval on tiles of side 32 or 64 (its default): both
- * paths sum those in 64-bit fixed point, exactly.  The other maps follow on the
+ * supports span at most 225 tried nodes, (floor(2Hx)+3)(floor(2Hy)+3) <= 225
+ * (441 for the cosine), with n >= 4096 and kde_eval on tiles of side 32 or 64
+ * (its default): both paths sum those in 64-bit fixed point, exactly.  The other maps follow on the
  * same stream: the Gaussian maps of each matrix-core precision (n > 0) as one
  * launch of the contraction kernel over all their tiles and point splits
  * (bandwidths of at least 1.05 node spacings, with multiplicative runs) and one

@@ -167,8 +167,8 @@ __device__ __forceinline__ void run_item(const BMap &m, const BItem &w, const Ba
 // LDS, which, when nearly full, is worked through point by point: each adds its
 // own terms (tile::accum_point) to a fixed-point tile in LDS.  Integer sums
 // depend neither on the order nor on the tiling the points come in, so the maps
-// that kde_eval sums in fixed point too (supports of at most
-// tile::kAccumMaxFootprint nodes) equal its maps bit for bit.  In the list, the
+// that kde_eval sums in fixed point too (tile::accum_applies) equal its maps bit
+// for bit.  In the list, the
 // lanes of a wave take entries kThreads / 64 apart (list entries keep track
 // order), so that they seldom start in one node at once and their atomics
 // seldom collide.

@@ -260,7 +260,10 @@ __device__ __forceinline__ void tile_sums_boxed(const float2 *__restrict__ pts, 
 // (nx, ny) are skipped.  The point's support must reach the tile (its
 // coordinates then convert to int safely).
 constexpr float kFixedOne = 4294967296.0f;  // 2^32
-constexpr int kAccumMaxFootprint = 121;     // nodes tried per point, at most
+// Nodes tried per point, at most, on the single-map path: beyond, the gather is
+// faster (the cosine's gather, with a transcendental per factor, later).
+constexpr int kAccumMaxFootprint = 225;
+constexpr int kAccumMaxFootprintCosine = 441;
 
 // Batched tiles: every item already lists the chunks that reach its tile, and
 // the gather there loses to the accumulation up to larger supports.
@@ -272,7 +275,8 @@ __host__ __device__ inline bool accum_footprint_fits(float Hx, float Hy, int lim
 }
 
 __host__ __device__ inline bool accum_applies(int kernel_id, int rc, float Hx, float Hy) {
-    return kernel_id != kGaussian && kernel_id != kGaussTrunc && rc <= 4 && accum_footprint_fits(Hx, Hy);
+    return kernel_id != kGaussian && kernel_id != kGaussTrunc && rc <= 4 &&
+           accum_footprint_fits(Hx, Hy, kernel_id == kCosine ? kAccumMaxFootprintCosine : kAccumMaxFootprint);
 }
 
 template <int K, int TW, int TH>

@@ -62,22 +62,23 @@ def test_small_mixed_batch_matches_separate_and_oracle(eager):
 
 @pytest.mark.parametrize("eager", [True, False])
 def test_small_support_compact_maps_equal_kde_eval_bit_for_bit(eager):
-    """Compact maps whose supports span at most 121 nodes sum in 64-bit fixed
-    point in both paths (support-binned items in kde_eval, chunk-box tiles in the
+    """Compact maps whose supports span at most 225 tried nodes (441 for the
+    cosine) sum in 64-bit fixed point in both paths (support-binned items in kde_eval, chunk-box tiles in the
     batch), so the maps agree bit for bit whatever tile sides the two take: the
     batch with 32-, 64- and 128-node tiles against kde_eval with 32-node tiles.
     The 64 x 64 map puts about 5000 points in each tile, which kde_eval cuts into
-    several items; one map is anisotropic and one sits at the footprint limit."""
+    several items; one map is anisotropic and two sit at the footprint limits."""
     import math
     import torch
     t, grids, units = _pool(100)
     units[1024] = kde.to_grid_units(t.xy, grids[1024])
     rows = [(0, 20000, 64, 0.02, 0.02, 0), (5000, 12000, 100, 0.01, 0.01, 2), (0, 30000, 256, 0.005, 0.005, 7),
-            (10000, 25000, 512, 0.003, 0.003, 5), (20000, 30000, 1024, 0.0043, 0.0043, 4),
-            (3000, 9000, 512, 0.004, 0.002, 1), (40000, 8000, 256, 0.006, 0.006, 3)]
-    for (_, _, side, hx, hy, _) in rows:  # every map takes the fixed-point path
+            (10000, 25000, 512, 0.003, 0.003, 5), (20000, 30000, 1024, 0.006, 0.006, 4),
+            (3000, 9000, 512, 0.004, 0.002, 1), (40000, 8000, 256, 0.006, 0.006, 3),
+            (0, 20000, 1024, 0.009, 0.009, 7)]
+    for (_, _, side, hx, hy, k) in rows:  # every map takes the fixed-point path, two at its limits
         Hx, Hy = kde.bandwidth_units(hx, hy, grids[side])
-        assert (math.floor(2 * Hx) + 3) * (math.floor(2 * Hy) + 3) <= 121
+        assert (math.floor(2 * Hx) + 3) * (math.floor(2 * Hy) + 3) <= (441 if k == 7 else 225)
     pts = [kt.to_device(units[side][a:a + n]) for (a, n, side, _, _, _) in rows]
     try:
         kde.autotune(force=2)
