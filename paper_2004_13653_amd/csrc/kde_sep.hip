@@ -1051,12 +1051,33 @@ DenseLayout dense_layout(const MapArgs *maps, int n, int precision) {
     L.entries.resize(n);
     double work = 0.0;  // (point, tile) pairs of the batch
     for (int m = 0; m < n; ++m) work += (double)maps[m].n * (double)sep_plan(maps[m], kc).tiles;
-    const double per_wg = std::max(4.0 * kc, work / (double)kBatchWgs);  // points per workgroup
+    // Points per workgroup: the batch's share of kBatchWgs workgroups, raised
+    // until the rounding of the splits leaves at most kBatchWgs of them (one
+    // workgroup per CU at a time: a few past a multiple of the CU count would
+    // run as a nearly empty last round).
+    double per_wg = std::max(4.0 * kc, work / (double)kBatchWgs);
+    std::vector<SepPlan> plans(n);
+    for (int pass = 0; pass < 64; ++pass) {
+        int64_t wgs = 0;
+        for (int m = 0; m < n; ++m) {
+            plans[m] = sep_plan(maps[m], kc, (int64_t)std::ceil((double)maps[m].n / per_wg));
+            wgs += (int64_t)plans[m].tiles * plans[m].splits;
+        }
+        if (wgs <= kBatchWgs) break;
+        per_wg *= 1.03;
+    }
+    std::vector<int> order(n);
+    for (int m = 0; m < n; ++m) order[m] = m;
+    // Workgroups are dispatched in index order: the maps with the longest
+    // workgroups (most points per split) first, the short ones fill the tail.
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return plans[x].per_split > plans[y].per_split; });
     size_t part = 0;
-    for (int m = 0; m < n; ++m) {
+    for (int k = 0; k < n; ++k) {
+        const int m = order[k];
         const MapArgs &a = maps[m];
-        const SepPlan pl = sep_plan(a, kc, (int64_t)std::ceil((double)a.n / per_wg));
-        DenseEntry &e = L.entries[m];
+        const SepPlan &pl = plans[m];
+        DenseEntry &e = L.entries[k];
         e.wg0 = L.wgs;
         e.tiles = pl.tiles;
         L.wgs += (int64_t)pl.tiles * pl.splits;
