@@ -132,11 +132,7 @@ __device__ __forceinline__ float sep_factor(float m, float pr, float H, float in
 template <int P>
 struct SepConfig {
     static constexpr bool kSplit = PrecTraits<P>::kSplit;
-#ifndef KDE_SEP_KC
     static constexpr int KC = kSplit ? 32 : 64;            // points per chunk
-#else
-    static constexpr int KC = KDE_SEP_KC;
-#endif
     static constexpr int G = KC / 8;                       // 8-point groups per chunk
     static constexpr int KK = KC / 16;                     // MFMA k-steps per chunk
     // Operand slice in LDS: row-major [kTile rows][G + 1] 16-byte words (8 factors
