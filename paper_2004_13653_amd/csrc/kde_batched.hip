@@ -14,10 +14,12 @@
 //
 // Compact maps are whole-tile items over all of the map's points; a first
 // kernel of the launch takes the bounding box of every 256-point chunk of those
-// points, and a tile item loads only the chunks whose box reaches the tile
-// (tile::tile_sums_boxed, the same sums bit for bit).  Tracks are stored in
-// order, so a chunk is a short stretch of one or two tracks and most chunks miss
-// most tiles.
+// points, and a tile item loads only the chunks whose box reaches the tile.
+// Tracks are stored in order, so a chunk is a short stretch of one or two
+// tracks and most chunks miss most tiles.  Small supports accumulate the
+// reaching points' terms in 64-bit fixed point (run_accum_item: exact, so equal
+// to kde_eval's fixed-point maps bit for bit); larger ones are gathered
+// (tile::tile_sums_boxed, the same sums as the full scan bit for bit).
 //
 // Host side: a batch shape (per map: kernel, tile side, grid, point count)
 // fixes the item list and the static map fields.  The first call of a shape
