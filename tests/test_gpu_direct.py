@@ -66,6 +66,30 @@ def test_full_size_lanes_sampled(kernel):
     assert abs(mass - 1.0) < 2e-2
 
 
+@pytest.mark.parametrize("kernel,h", [(0, 0.001), (7, 0.001), (0, 0.004), (7, 0.004), (5, 0.003)])
+def test_binned_maps_with_thousands_of_tiles(kernel, h):
+    """1,000,000 points on 2048 x 2048 with 32-node tiles: 4096 tiles, more than
+    one workgroup's pass of the item scan, on the fixed-point path (H = 2 px;
+    the cosine also at H = 8, tricube at H = 6, both at their footprint limits)
+    and the gather (the uniform at H = 8): sampled pixels against the oracle,
+    repeat calls bit-identical."""
+    t = kt.lanes(2000, 500)
+    g, og = kt.grids(synth.BOX_C2, 2048, 2048)
+    XY = kde.to_grid_units(t.xy, g)
+    kde.autotune(force=2)
+    try:
+        y = kt.gpu_map(XY, kernel, h, h, g)
+        y2 = kt.gpu_map(XY, kernel, h, h, g)
+    finally:
+        kde.autotune(force=0)
+    np.testing.assert_array_equal(y, y2)
+    ij = kt.sample_pixels(y, 48, seed=kernel)
+    r = kt.oracle_density_at(XY, kernel, h, h, og, ij)
+    err = kt.peak_error(y[ij[:, 1], ij[:, 0]], r)
+    kt.log(f"kernel={kernel} h={h}: sampled {ij.shape[0]} pixels, e_inf={err:.3e}")
+    assert err <= kt.FP32_GATE
+
+
 @pytest.mark.parametrize("eps", [10.0, 100.0])
 def test_dp_compressed_inputs(eps):
     """Douglas-Peucker-compressed tracks (eps in metres) as input."""
