@@ -286,15 +286,10 @@ def batch_window_points(torch, kde, synth, t, spec):
     return w.xy[keep]
 
 
-def bench_batched(torch, kde, synth, steps: int):
-    """Batch workload: 256 maps, each a time window of a 4M-point pool with point
-    count log-uniform in [1k, 200k], Douglas-Peucker-compressed at a threshold
-    drawn from {0, 10, 50, 100} m; grids from {256^2, 512^2, 1024^2}, h ~
-    U(0.001, 0.008) degrees, kernels uniform over the eight.  Gaussian maps on
-    the FP16 matrix-core path, the compact kernels on the FP32 persistent launch
-    (graph-replayed), in one kde_eval_batched call, against 256 separate kde_eval
-    launches of the same precisions.  The two parts are also timed alone."""
-    import numpy as np
+def batch_maps(torch, kde, synth, with_support: bool = False):
+    """The 256 maps of the batch workload (see bench_batched) as kde.eval_batched
+    descriptors, their specs, and (with_support) the compact maps' in-support
+    pair count."""
     t = synth.workload_lanes(n_tracks=N_TRACKS, pts=PTS_PER_TRACK, seed_index=2)
     b = synth.BOX_C2
     grids = {s: kde.Grid(b.lon0, b.lon1, b.lat0, b.lat1, s, s) for s in (256, 512, 1024)}
@@ -305,9 +300,21 @@ def bench_batched(torch, kde, synth, steps: int):
         prec = "fp16" if sp.kernel == 6 else "fp32"
         maps.append((torch.from_numpy(XY).cuda(), sp.kernel, sp.h_deg, sp.h_deg, grids[sp.side],
                      torch.empty((sp.side, sp.side), device="cuda"), prec))
-        if sp.kernel != 6:
+        if with_support and sp.kernel != 6:
             Hx, Hy = kde.bandwidth_units(sp.h_deg, sp.h_deg, grids[sp.side])
             support += map_support_pairs(XY, float(Hx), float(Hy), sp.side, sp.side)
+    return maps, specs, support
+
+
+def bench_batched(torch, kde, synth, steps: int):
+    """Batch workload: 256 maps, each a time window of a 4M-point pool with point
+    count log-uniform in [1k, 200k], Douglas-Peucker-compressed at a threshold
+    drawn from {0, 10, 50, 100} m; grids from {256^2, 512^2, 1024^2}, h ~
+    U(0.001, 0.008) degrees, kernels uniform over the eight.  Gaussian maps on
+    the FP16 matrix-core path, the compact kernels on the FP32 persistent launch
+    (graph-replayed), in one kde_eval_batched call, against 256 separate kde_eval
+    launches of the same precisions.  The two parts are also timed alone."""
+    maps, specs, support = batch_maps(torch, kde, synth, with_support=True)
     npts = [m[0].shape[0] for m in maps]
     pairs = float(sum(n * m[4].nx * m[4].ny for n, m in zip(npts, maps)))
     gauss = [m for m in maps if m[6] == "fp16"]
@@ -562,6 +569,19 @@ def profile_compact(torch, kde, synth) -> int:
     return 0
 
 
+def profile_batch(torch, kde, synth) -> int:
+    """Counter run for the batch: the 256-map batch of bench_batched three
+    times (the first tunes its tile sides and captures its graph), then the
+    calibration copy."""
+    maps, _, _ = batch_maps(torch, kde, synth)
+    for _ in range(3):
+        kde.eval_batched(maps)
+    torch.cuda.synchronize()
+    nb = calibration_copy(torch, torch.device("cuda:0"))
+    log(f"profile run: 3 calls of the 256-map batch, then a copy of {nb} bytes read + written")
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -570,11 +590,11 @@ def main() -> int:
     ap.add_argument("--direct-steps", type=int, default=3, help="timed steps of the FP32 direct path")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--profile-once", nargs="?", const="headline", choices=("headline", "compact"),
+    ap.add_argument("--profile-once", nargs="?", const="headline", choices=("headline", "compact", "batch"),
                     help="for counter runs, prints no JSON: 'headline' (the default) runs two FP16 maps and one "
                          "FP32 direct map of the 4M-point workload, 'compact' two uniform, Epanechnikov and "
-                         "cosine maps each of 10^6 points on 1024 x 1024; then a 256 MiB elementwise copy "
-                         "(torch.neg) as the byte-count calibration")
+                         "cosine maps each of 10^6 points on 1024 x 1024, 'batch' three calls of the 256-map "
+                         "batch; then a 256 MiB elementwise copy (torch.neg) as the byte-count calibration")
     ap.add_argument("--sections", default="adjoint,batched,kernels,binned,truncated,dp,metrics",
                     help="extra measured sections beside the headline: adjoint, batched, kernels, binned, "
                          "truncated, dp, metrics (or none)")
@@ -592,6 +612,8 @@ def main() -> int:
 
     if args.profile_once == "compact":
         return profile_compact(torch, kde, synth)
+    if args.profile_once == "batch":
+        return profile_batch(torch, kde, synth)
     t = synth.workload_lanes(n_tracks=N_TRACKS, pts=PTS_PER_TRACK, seed_index=2)
     b = synth.BOX_C2
     g = kde.Grid(b.lon0, b.lon1, b.lat0, b.lat1, SIDE, SIDE)
