@@ -389,7 +389,9 @@ __device__ __forceinline__ void lscv_tile(const LscvLaunch &p, float2 me, bool d
     if constexpr (K == kGaussian) {
         // kb(u) kb(v) = exp(-(u^2 + v^2)/4) is one exp2 per pair, and g(u) g(v) =
         // exp(-(u^2 + v^2)/2) its square; the derivative factors are those of
-        // lscv_axis, (1 - u^2/2) for kb and (1 - u^2) for g.
+        // lscv_axis, (1 - u^2/2) for kb and (1 - u^2) for g, applied after the
+        // loop: the tile keeps sum e and sum u^2 e (sax, say, sbx, sby hold the
+        // u^2- and v^2-weighted sums here), one FMA per derivative sum and pair.
         auto pair = [&](float ox, float oy) {
             const float dx = me.x - ox, dy = me.y - oy;
             const float wx = fminf(dx * dx * p.ix2, 1.0e4f), wy = fminf(dy * dy * p.iy2, 1.0e4f);  // u^2, v^2, capped
@@ -397,10 +399,10 @@ __device__ __forceinline__ void lscv_tile(const LscvLaunch &p, float2 me, bool d
             const float e2 = e * e;
             sa += e;
             sb += e2;
-            sax = fmaf(fmaf(-0.5f, wx, 1.0f), e, sax);
-            say = fmaf(fmaf(-0.5f, wy, 1.0f), e, say);
-            sbx = fmaf(1.0f - wx, e2, sbx);
-            sby = fmaf(1.0f - wy, e2, sby);
+            sax = fmaf(wx, e, sax);
+            say = fmaf(wy, e, say);
+            sbx = fmaf(wx, e2, sbx);
+            sby = fmaf(wy, e2, sby);
         };
         if (!diag) {  // the same q for every lane: a uniform loop, two points per LDS read
             const float4 *q2 = reinterpret_cast<const float4 *>(qs);
@@ -427,12 +429,21 @@ __device__ __forceinline__ void lscv_tile(const LscvLaunch &p, float2 me, bool d
             sby = fmaf(gx, gdy, sby);
         }
     }
-    S[0] += 2.0 * sa;
-    S[1] += 2.0 * sax;
-    S[2] += 2.0 * say;
-    S[3] += 2.0 * sb;
-    S[4] += 2.0 * sbx;
-    S[5] += 2.0 * sby;
+    if constexpr (K == kGaussian) {  // sum (1 - u^2/2) e = sum e - sum u^2 e / 2, and so on, in FP64
+        S[0] += 2.0 * sa;
+        S[1] += 2.0 * ((double)sa - 0.5 * (double)sax);
+        S[2] += 2.0 * ((double)sa - 0.5 * (double)say);
+        S[3] += 2.0 * sb;
+        S[4] += 2.0 * ((double)sb - (double)sbx);
+        S[5] += 2.0 * ((double)sb - (double)sby);
+    } else {
+        S[0] += 2.0 * sa;
+        S[1] += 2.0 * sax;
+        S[2] += 2.0 * say;
+        S[3] += 2.0 * sb;
+        S[4] += 2.0 * sbx;
+        S[5] += 2.0 * sby;
+    }
     if (diag) {
         float kbx, kbdx, gx, gdx, kby, kbdy, gy, gdy;
         lscv_axis<K>(0.0f, p.ix, p.ix2, kbx, kbdx, gx, gdx);
