@@ -392,10 +392,14 @@ __device__ __forceinline__ void lscv_tile(const LscvLaunch &p, float2 me, bool d
         // lscv_axis, (1 - u^2/2) for kb and (1 - u^2) for g, applied after the
         // loop: the tile keeps sum e and sum u^2 e (sax, say, sbx, sby hold the
         // u^2- and v^2-weighted sums here), one FMA per derivative sum and pair.
+        // wx, wy carry the exp2 scale c = log2(e) / 4: wx = c u^2 (capped), and the
+        // derivative sums are divided by c after the loop.
+        constexpr float c = 0.36067376022224085f;  // log2(e) / 4
+        const float cx = c * p.ix2, cy = c * p.iy2, cap = c * 1.0e4f;
         auto pair = [&](float ox, float oy) {
             const float dx = me.x - ox, dy = me.y - oy;
-            const float wx = fminf(dx * dx * p.ix2, 1.0e4f), wy = fminf(dy * dy * p.iy2, 1.0e4f);  // u^2, v^2, capped
-            const float e = __builtin_amdgcn_exp2f(-0.36067376022224085f * (wx + wy));
+            const float wx = fminf(dx * dx * cx, cap), wy = fminf(dy * dy * cy, cap);  // c u^2, c v^2, capped
+            const float e = __builtin_amdgcn_exp2f(-(wx + wy));
             const float e2 = e * e;
             sa += e;
             sb += e2;
@@ -430,12 +434,13 @@ __device__ __forceinline__ void lscv_tile(const LscvLaunch &p, float2 me, bool d
         }
     }
     if constexpr (K == kGaussian) {  // sum (1 - u^2/2) e = sum e - sum u^2 e / 2, and so on, in FP64
+        constexpr double ic = 1.0 / (double)0.36067376022224085f;  // the u^2 sums carry the FP32 c
         S[0] += 2.0 * sa;
-        S[1] += 2.0 * ((double)sa - 0.5 * (double)sax);
-        S[2] += 2.0 * ((double)sa - 0.5 * (double)say);
+        S[1] += 2.0 * ((double)sa - 0.5 * ic * (double)sax);
+        S[2] += 2.0 * ((double)sa - 0.5 * ic * (double)say);
         S[3] += 2.0 * sb;
-        S[4] += 2.0 * ((double)sb - (double)sbx);
-        S[5] += 2.0 * ((double)sb - (double)sby);
+        S[4] += 2.0 * ((double)sb - ic * (double)sbx);
+        S[5] += 2.0 * ((double)sb - ic * (double)sby);
     } else {
         S[0] += 2.0 * sa;
         S[1] += 2.0 * sax;
