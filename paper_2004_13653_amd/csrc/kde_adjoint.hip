@@ -233,6 +233,75 @@ __global__ __launch_bounds__(kAdjThreads) void vjp_kernel(VjpLaunch p) {
     }
 }
 
+// Compact kernels with small supports: one thread per point over the nodes of
+// its own support window (from ceil(X - H) - 1 to floor(X + H) + 1 per axis,
+// clamped to the grid; gdg's support test decides), reading Gbar from the
+// caches, instead of every thread of a workgroup sweeping the bounding box of
+// all its points.  The same sums per point (columns within a row, then rows, in
+// order) and the same FP64 tree for the bandwidth sums.
+constexpr int kVjpLocalMaxWindow = 1024;  // nodes per point, at most
+
+template <int K>
+__global__ __launch_bounds__(kAdjThreads) void vjp_local_kernel(VjpLaunch p) {
+    __shared__ double red[3][kAdjThreads];
+    const int tid = threadIdx.x;
+    const int64_t q = (int64_t)blockIdx.x * kAdjThreads + tid;
+    const bool active = q < p.n;
+    const float2 pt = active ? p.pts[q] : make_float2(kFarAdj, kFarAdj);
+    float Tx = 0.0f, Ty = 0.0f, Ux = 0.0f, Uy = 0.0f, Q = 0.0f;
+    // The window, or an empty one for points whose support misses the grid
+    // (NaN coordinates fail every comparison).
+    const bool near = pt.x + p.Hx >= 0.0f && pt.x - p.Hx <= (float)(p.nx - 1) && pt.y + p.Hy >= 0.0f &&
+                      pt.y - p.Hy <= (float)(p.ny - 1);
+    if (active && near) {
+        const int i0 = max(0, (int)ceilf(pt.x - p.Hx) - 1), i1 = min(p.nx - 1, (int)floorf(pt.x + p.Hx) + 1);
+        const int j0 = max(0, (int)ceilf(pt.y - p.Hy) - 1), j1 = min(p.ny - 1, (int)floorf(pt.y + p.Hy) + 1);
+        for (int j = j0; j <= j1; ++j) {
+            const float dy = (float)j - pt.y;
+            float gy, dgy;
+            gdg<K>(dy, p.Hy, p.iy, gy, dgy);
+            if (gy == 0.0f && dgy == 0.0f) continue;  // outside the support: the row adds nothing
+            const float *row = p.gbar + (int64_t)j * p.nx;
+            float a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+            for (int i = i0; i <= i1; ++i) {
+                const float d = (float)i - pt.x;
+                float gx, dgx;
+                gdg<K>(d, p.Hx, p.ix, gx, dgx);
+                const float gb = row[i];
+                a1 = fmaf(gb, dgx, a1);
+                a2 = fmaf(gb, gx, a2);
+                a3 = fmaf(gb, d * p.ix * dgx, a3);
+            }
+            Tx = fmaf(gy, a1, Tx);
+            Ux = fmaf(gy, a3, Ux);
+            Q = fmaf(gy, a2, Q);
+            Ty = fmaf(dgy, a2, Ty);
+            Uy = fmaf(dy * p.iy * dgy, a2, Uy);
+        }
+    }
+    if (active && p.grad != nullptr) {
+        p.grad[2 * q] = p.fx * Tx;
+        p.grad[2 * q + 1] = p.fy * Ty;
+    }
+    red[0][tid] = active ? (double)Ux : 0.0;
+    red[1][tid] = active ? (double)Uy : 0.0;
+    red[2][tid] = active ? (double)Q : 0.0;
+    __syncthreads();
+    for (int w = kAdjThreads / 2; w > 0; w >>= 1) {
+        if (tid < w) {
+            red[0][tid] += red[0][tid + w];
+            red[1][tid] += red[1][tid + w];
+            red[2][tid] += red[2][tid + w];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        p.part[3 * blockIdx.x + 0] = red[0][0];
+        p.part[3 * blockIdx.x + 1] = red[1][0];
+        p.part[3 * blockIdx.x + 2] = red[2][0];
+    }
+}
+
 struct LscvLaunch {
     const float2 *pts;
     int64_t n;
@@ -637,6 +706,28 @@ hipError_t launch_vjp(const float2 *pts, int64_t n, int kernel_id, float Hx, flo
                 part};
     const dim3 grid((unsigned)vjp_blocks(n));
     main_kernel_begin(stream);
+    // Small compact supports: each point over its own window.
+    const double wx = std::floor(2.0 * (double)Hx) + 3.0, wy = std::floor(2.0 * (double)Hy) + 3.0;
+    if (kernel_id != kGaussian && wx * wy <= (double)kVjpLocalMaxWindow) {
+        switch (kernel_id) {
+        case kUniform: hipLaunchKernelGGL(vjp_local_kernel<kUniform>, grid, dim3(kAdjThreads), 0, stream, p); break;
+        case kTriangular:
+            hipLaunchKernelGGL(vjp_local_kernel<kTriangular>, grid, dim3(kAdjThreads), 0, stream, p);
+            break;
+        case kEpanechnikov:
+            hipLaunchKernelGGL(vjp_local_kernel<kEpanechnikov>, grid, dim3(kAdjThreads), 0, stream, p);
+            break;
+        case kQuartic: hipLaunchKernelGGL(vjp_local_kernel<kQuartic>, grid, dim3(kAdjThreads), 0, stream, p); break;
+        case kTriweight:
+            hipLaunchKernelGGL(vjp_local_kernel<kTriweight>, grid, dim3(kAdjThreads), 0, stream, p);
+            break;
+        case kTricube: hipLaunchKernelGGL(vjp_local_kernel<kTricube>, grid, dim3(kAdjThreads), 0, stream, p); break;
+        case kCosine: hipLaunchKernelGGL(vjp_local_kernel<kCosine>, grid, dim3(kAdjThreads), 0, stream, p); break;
+        default: return hipErrorInvalidValue;
+        }
+        main_kernel_end(stream);
+        return hipGetLastError();
+    }
     switch (kernel_id) {
     case kUniform: hipLaunchKernelGGL(vjp_kernel<kUniform>, grid, dim3(kAdjThreads), 0, stream, p); break;
     case kTriangular: hipLaunchKernelGGL(vjp_kernel<kTriangular>, grid, dim3(kAdjThreads), 0, stream, p); break;
