@@ -78,6 +78,29 @@ def test_vjp_all_kernels(kernel, raw, shape):
     assert np.all(e_h <= GRAD_GATE)
 
 
+@pytest.mark.parametrize("kernel", [0, 2, 5, 7])
+@pytest.mark.parametrize("raw", [False, True])
+def test_vjp_wide_compact_supports(kernel, raw):
+    """Compact supports wider than the per-point windows take (more than 1,024
+    nodes: Hx = 30, Hy = 13 px here) take the workgroup sweep of row strips;
+    2,000 lane points, random cotangent, 150 x 97 grid, against the oracle."""
+    nx, ny = 150, 97
+    t = kt.lanes(20, 100)
+    g, og = kt.grids(synth.BOX_C2, nx, ny)
+    XY = kde.to_grid_units(t.xy, g)
+    Hx, Hy = kde.bandwidth_units(0.2, 0.14, g)
+    assert (np.floor(2 * Hx) + 3) * (np.floor(2 * Hy) + 3) > 1024
+    rng = np.random.default_rng(100 + kernel)
+    gbar = rng.standard_normal((ny, nx))
+    gp, gh = _gpu_vjp(XY, kernel, 0.2, 0.14, g, gbar, raw=raw)
+    rp, rh = _expected_vjp(XY, kernel, 0.2, 0.14, og, gbar, raw)
+    e_p = _rel_l2(gp, rp)
+    e_h = _rel(gh, rh)
+    kt.log(f"kernel={kernel} raw={raw} wide: points rel-L2 {e_p:.2e}, h rel {e_h}")
+    assert e_p <= GRAD_GATE
+    assert np.all(e_h <= GRAD_GATE)
+
+
 @pytest.mark.parametrize("shape,n", [((96, 80), 1), ((96, 80), 255), ((300, 257), 257), ((513, 33), 2000),
                                      ((40, 700), 700)])
 @pytest.mark.parametrize("raw", [False, True])
