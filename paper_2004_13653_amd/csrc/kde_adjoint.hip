@@ -453,7 +453,8 @@ LscvPlan lscv_plan(int64_t n) {
 // (symmetry), to S, and for a diagonal tile the pairs q > p only plus p = q once.
 template <int K>
 __device__ __forceinline__ void lscv_tile(const LscvLaunch &p, float2 me, bool diag, const float2 *qs, int tid,
-                                          double (&S)[6]) {
+                                          double (&S)[6], float4 reach = make_float4(-3.0e38f, 3.0e38f, -3.0e38f,
+                                                                                     3.0e38f)) {
     float sa = 0.0f, sax = 0.0f, say = 0.0f, sb = 0.0f, sbx = 0.0f, sby = 0.0f;
     if constexpr (K == kGaussian) {
         // kb(u) kb(v) = exp(-(u^2 + v^2)/4) is one exp2 per pair, and g(u) g(v) =
@@ -491,6 +492,11 @@ __device__ __forceinline__ void lscv_tile(const LscvLaunch &p, float2 me, bool d
     } else {
         for (int k = diag ? tid + 1 : 0; k < kAdjThreads; ++k) {
             const float2 o = qs[k];
+            // The same q for every lane of the wave: a q beyond the autoconvolution's
+            // reach (2H) of all the wave's points adds exact zeros to every sum (the
+            // uniform kernel's pair terms cost less than the test).
+            if constexpr (K != kUniform)
+                if (o.x < reach.x || o.x > reach.y || o.y < reach.z || o.y > reach.w) continue;
             float kbx, kbdx, gx, gdx, kby, kbdy, gy, gdy;
             lscv_axis<K>(me.x - o.x, p.ix, p.ix2, kbx, kbdx, gx, gdx);
             lscv_axis<K>(me.y - o.y, p.iy, p.iy2, kby, kbdy, gy, gdy);
@@ -655,6 +661,21 @@ __global__ __launch_bounds__(kAdjThreads) void lscv_cull_kernel(LscvLaunch p, Cu
         float4 a = c.box[pb];
         int64_t pi = pb * kAdjThreads + tid;
         float2 me = pi < p.n ? p.pts[pi] : make_float2(0.0f, 0.0f);
+        // The wave's points' box, widened by the autoconvolution's reach 2H (with a
+        // margin for rounding): q outside it meet none of the wave's points.
+        const float rx = 2.0f / p.ix * 1.0001f + 1.0e-3f, ry = 2.0f / p.iy * 1.0001f + 1.0e-3f;
+        auto wave_reach = [&](int64_t i, float2 v) {
+            const bool ok = i < p.n;
+            float x0 = ok ? v.x : 3.0e38f, x1 = ok ? v.x : -3.0e38f, y0 = ok ? v.y : 3.0e38f, y1 = ok ? v.y : -3.0e38f;
+            for (int off = 32; off > 0; off >>= 1) {
+                x0 = fminf(x0, __shfl_xor(x0, off));
+                x1 = fmaxf(x1, __shfl_xor(x1, off));
+                y0 = fminf(y0, __shfl_xor(y0, off));
+                y1 = fmaxf(y1, __shfl_xor(y1, off));
+            }
+            return make_float4(x0 - rx, x1 + rx, y0 - ry, y1 + ry);
+        };
+        float4 reach = wave_reach(pi, me);
         while (t < t1) {
             if (cand >= c.nb) {  // row done: the next row starts at its diagonal tile
                 if (++pb >= c.nb) break;  // not reached: every tile of [t0, t1) lies in a row below nb
@@ -662,6 +683,7 @@ __global__ __launch_bounds__(kAdjThreads) void lscv_cull_kernel(LscvLaunch p, Cu
                 a = c.box[pb];
                 pi = pb * kAdjThreads + tid;
                 me = pi < p.n ? p.pts[pi] : make_float2(0.0f, 0.0f);
+                reach = wave_reach(pi, me);
             }
             // Compact the next 256 candidates of the row that meet the p-block.
             const int64_t qb = cand + tid;
@@ -688,7 +710,7 @@ __global__ __launch_bounds__(kAdjThreads) void lscv_cull_kernel(LscvLaunch p, Cu
                 __syncthreads();  // previous tile consumed
                 qs[tid] = qi < p.n ? p.pts[qi] : make_float2(kFarAdj, kFarAdj);
                 __syncthreads();
-                if (pi < p.n) lscv_tile<K>(p, me, q == pb, qs, tid, S);
+                if (pi < p.n) lscv_tile<K>(p, me, q == pb, qs, tid, S, reach);
             }
             skip = 0;
         }
